@@ -1,0 +1,153 @@
+/*
+ * stern.h - C ABI of the MI355X (gfx950) Sternheimer chi0 library.
+ *
+ * The library evaluates the static density response dn = chi0 dV of a set of
+ * occupied Kohn-Sham-like states without empty states, the route that
+ * Sec. II.A of the WEST paper (arXiv 2607.14025) uses inside its PDEP
+ * diagonalisation of chi0 (eq. pdep): for every occupied band v and field dV_i
+ *
+ *     P_c (H - eps_v) P_c x_{v,i} = -P_c dV_i psi_v,      P_c = 1 - sum_v |psi_v><psi_v|
+ *     dn_i(r) = 4 Re sum_v conj(psi_v(r)) x_{v,i}(r)       (2 spin x 2 c.c.)
+ *
+ * solved by projected preconditioned CG (Teter-Payne-Allan diagonal) from zero.
+ *
+ * Model Hamiltonian (input stand-in for the ground-state code of the paper's
+ * workflow, Sec. II): cubic cell of edge L (bohr), Gamma point, plane waves
+ * G = 2 pi n / L with |G|^2 <= ecut_ry (bohr^-2);
+ *   H = |G|^2/2 + V_loc + D sum_a |beta_a><beta_a|,
+ *   V_loc(q) = A (2 pi s^2)^{3/2} / Omega exp(-s^2 |q|^2 / 2) sum_a exp(-i q.R_a),
+ *   beta_a(G) = Omega^{-1/2} exp(-w^2 |G|^2 / 2) exp(-i G.R_a).
+ *
+ * Conventions shared by every entry point:
+ *   - Coefficient order ("canonical order"): the plane waves sorted by |n|^2,
+ *     then n_x, n_y, n_z ascending. stern_basis_info() returns the triples.
+ *   - Complex arrays are interleaved (re, im) doubles.
+ *   - Real-space arrays are [n][N][N][N] doubles indexed [ix][iy][iz] with iz
+ *     fastest, at r = L (ix, iy, iz) / N; N is the FFT grid of the system.
+ *   - psi(r) = Omega^{-1/2} sum_G c_G exp(i G.r); dn is in electrons / bohr^3.
+ *   - Every call is synchronous with respect to the caller: when it returns,
+ *     outputs are written (host) or the work is complete on the stream (device).
+ *   - The caller owns every pointer it passes; the library copies what it keeps.
+ *   - Errors: a negative return code; stern_last_error() gives the message of
+ *     the last failing call on the calling thread. Nothing throws across the ABI.
+ */
+#ifndef STERN_H
+#define STERN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define STERN_OK 0
+#define STERN_WARN_NOT_CONVERGED 1   /* dn written; some solves missed tol (see stats) */
+#define STERN_ERR_INVALID_ARG (-1)
+#define STERN_ERR_STATE (-2)          /* e.g. apply before set_occupied */
+#define STERN_ERR_OOM (-3)
+#define STERN_ERR_HIP (-4)
+#define STERN_ERR_UNSUPPORTED (-6)    /* e.g. FFT size not of the form 2^a 3^b <= 128 */
+
+/* precision of the inner solver */
+#define STERN_FP64 0
+#define STERN_MIXED 1
+
+/* initial guess */
+#define STERN_GUESS_ZERO 0
+
+/* where pointer arguments live */
+#define STERN_MEM_HOST 0
+#define STERN_MEM_DEVICE 1
+
+typedef struct stern_system stern_system;
+
+/* One cell. pos: [n_atoms][3] bohr, copied. fft_n = 0 selects the smallest
+ * 2^a 3^b >= 2 (floor(2 sqrt(ecut) L / 2 pi) + 1) + 1, which holds the 4 ecut
+ * sphere so that every grid product is exact in the basis. */
+typedef struct {
+  double L;
+  double ecut_ry;
+  int n_atoms;
+  const double* pos;
+  double vloc_amp;    /* A, Ha (e.g. -2) */
+  double vloc_sigma;  /* s, bohr (e.g. 1) */
+  double kb_D;        /* D, Ha (e.g. +1) */
+  double kb_width;    /* w (e.g. 1) */
+  int fft_n;
+} stern_cell;
+
+/* device: HIP ordinal; stream: hipStream_t to run on (NULL = default stream). */
+typedef struct {
+  int device;
+  void* stream;
+} stern_runtime;
+
+typedef struct {
+  double tol;          /* relative FP64 true residual ||b - A x|| / ||b|| to accept */
+  int max_iter;        /* CG iterations per solve (0 = 1000) */
+  int precision;       /* STERN_FP64 */
+  int guess;           /* STERN_GUESS_ZERO */
+  int mem_kind;        /* STERN_MEM_HOST or STERN_MEM_DEVICE for dv_r / dn_r */
+  int band_begin;      /* solve bands [band_begin, band_end); band_end <= 0 means n_occ.
+                          P_c always uses every occupied band; dn is the partial sum. */
+  int band_end;
+  int max_batch;       /* solves held in flight at once (0 = choose from free memory) */
+  int check_every;     /* iterations between convergence checks (0 = 4) */
+  /* optional per-solve outputs for a list of (band, perturbation) pairs:
+     sample_pairs[2k] = v, sample_pairs[2k+1] = i; sample_x receives
+     n_sample x n_pw complex solutions in canonical order (host memory). */
+  int n_sample;
+  const int* sample_pairs;
+  double* sample_x;
+} stern_opts;
+
+typedef struct {
+  int n_solves;        /* (band, perturbation) pairs solved */
+  int n_converged;     /* pairs with FP64 true relative residual <= tol */
+  int n_fallback;      /* pairs restarted from their true residual */
+  long long total_iters;
+  int max_iters;
+  double wall_s;       /* wall time of the call */
+  double max_true_resid;
+  int* iters;          /* optional caller array [n_solves] (pair order: i major, v minor) */
+  double* resid;       /* optional caller array [n_solves] */
+} stern_stats;
+
+/* Host only, no GPU needed: basis size, FFT grid and (if miller != NULL) the
+ * [n_pw][3] Miller triples in canonical order. */
+int stern_basis_info(const stern_cell* cell, int* n_pw, int* fft_n, int32_t* miller);
+
+/* Builds the basis, V_loc on the grid and the projectors on the GPU.
+ * Returns STERN_ERR_UNSUPPORTED for grids other than 2^a 3^b in [8, 128]. */
+int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_system** out);
+
+int stern_query(const stern_system* sys, int* n_pw, int* fft_n, double* omega);
+
+/* Occupied states: psi [n_occ][n_pw] complex in canonical order (orthonormal),
+ * eps [n_occ] Ha. Both host (mem_kind = STERN_MEM_HOST) or device pointers. */
+int stern_set_occupied(stern_system* sys, int n_occ, const double* psi, const double* eps, int mem_kind);
+
+/* dn_r[i] = chi0 dv_r[i] for i < n_pert, summed over bands [band_begin, band_end).
+ * dv_r, dn_r: [n_pert][N][N][N] real, host or device per opts->mem_kind.
+ * Returns STERN_OK, STERN_WARN_NOT_CONVERGED, or an error. stats may be NULL. */
+int stern_apply_chi0(stern_system* sys, int n_pert, const double* dv_r, double* dn_r,
+                     const stern_opts* opts, stern_stats* stats);
+
+/* out = (H - shift_k) c_k for n_vec coefficient rows (canonical order), host or
+ * device memory; shift may be NULL (zero). Exposes the H apply of the solver. */
+int stern_apply_h(stern_system* sys, int n_vec, const double* c, const double* shift, double* out, int mem_kind);
+
+/* out = P_c c for n_vec rows (canonical order). Requires set_occupied. */
+int stern_apply_pc(stern_system* sys, int n_vec, const double* c, double* out, int mem_kind);
+
+/* NULL-safe. */
+void stern_free(stern_system* sys);
+
+const char* stern_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,248 @@
+// Per-solve vector kernels of the projected PCG: one workgroup per solve,
+// FP64 scalars and FP64 dot products with a fixed reduction order (so runs are
+// bitwise reproducible), Teter-Payne-Allan diagonal preconditioner
+//   K(G) = (27 + 18y + 12y^2 + 8y^3) / (27 + 18y + 12y^2 + 8y^3 + 16y^4), y = (|G|^2/2) / T_v
+// (Phys. Rev. B 40, 12255 (1989)) evaluated on the fly.
+#include "kernels.hpp"
+
+namespace stern {
+
+namespace {
+
+constexpr int kCgThreads = 256;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kCgThreads / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ double teter(double g2h, double invT) {
+  const double y = g2h * invT;
+  const double num = 27.0 + y * (18.0 + y * (12.0 + 8.0 * y));
+  const double y2 = y * y;
+  return num / (num + 16.0 * y2 * y2);
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  const double iT = S.invT[s];
+  double bb = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k];
+    bb += b.re * b.re + b.im * b.im;
+    S.x[o + k] = zmk(0.0, 0.0);
+    S.r[o + k] = b;
+    S.z[o + k] = zscale(b, teter(S.g2h[k], iT));
+  }
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    S.bb[s] = bb;
+    S.iters[s] = 0;
+    S.flag[s] = (bb > 0.0) ? 0 : 2;
+    S.tres[s] = 0.0;
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg_init2(CgState S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  double rz = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 r = S.r[o + k], z = S.z[o + k];
+    rz += r.re * z.re + r.im * z.im;
+    S.p[o + k] = z;
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0) S.rz[s] = rz;
+}
+
+// alpha = <r,z> / <p,q>; x += alpha p; r -= alpha q; z = K r; flag on ||r|| <= tol ||b||
+__global__ __launch_bounds__(kCgThreads) void k_cg_alpha(CgState S, const int* __restrict__ act, double tol2) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double pq = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 p = S.p[o + k], q = S.q[o + k];
+    pq += p.re * q.re + p.im * q.im;
+  }
+  pq = block_sum(pq, sh);
+  const double alpha = (pq > 0.0) ? S.rz[s] / pq : 0.0;
+  const double iT = S.invT[s];
+  double rr = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 p = S.p[o + k], q = S.q[o + k];
+    Z64 x = S.x[o + k], r = S.r[o + k];
+    x = zmk(x.re + alpha * p.re, x.im + alpha * p.im);
+    r = zmk(r.re - alpha * q.re, r.im - alpha * q.im);
+    S.x[o + k] = x;
+    S.r[o + k] = r;
+    rr += r.re * r.re + r.im * r.im;
+    S.z[o + k] = zscale(r, teter(S.g2h[k], iT));
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    S.rr[s] = rr;
+    S.iters[s] += 1;
+    if (rr <= tol2 * S.bb[s] || !(pq > 0.0)) S.flag[s] = 1;
+  }
+}
+
+// beta = <r,z>_new / <r,z>_old; p = z + beta p
+__global__ __launch_bounds__(kCgThreads) void k_cg_beta(CgState S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double rz = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 r = S.r[o + k], z = S.z[o + k];
+    rz += r.re * z.re + r.im * z.im;
+  }
+  rz = block_sum(rz, sh);
+  const double beta = rz / S.rz[s];
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 z = S.z[o + k], p = S.p[o + k];
+    S.p[o + k] = zmk(z.re + beta * p.re, z.im + beta * p.im);
+  }
+  if (threadIdx.x == 0) S.rz[s] = rz;
+}
+
+__global__ void k_copy_rows(const Z64* __restrict__ src, Z64* __restrict__ dst, int ld, const int* __restrict__ act) {
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * ld;
+  for (int k = threadIdx.x; k < ld; k += blockDim.x) dst[o + k] = src[o + k];
+}
+
+// q holds A x for solves with flag 1: accept (flag 2) or restart from r = b - A x (flag 3)
+__global__ __launch_bounds__(kCgThreads) void k_true_resid(CgState S, const int* __restrict__ act, double tol) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 1) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double tt = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k], q = S.q[o + k];
+    const double re = b.re - q.re, im = b.im - q.im;
+    tt += re * re + im * im;
+  }
+  tt = block_sum(tt, sh);
+  const double bb = S.bb[s];
+  const bool ok = tt <= tol * tol * bb;
+  if (!ok) {
+    const double iT = S.invT[s];
+    for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+      const Z64 b = S.b[o + k], q = S.q[o + k];
+      const Z64 r = zmk(b.re - q.re, b.im - q.im);
+      S.r[o + k] = r;
+      S.z[o + k] = zscale(r, teter(S.g2h[k], iT));
+    }
+  }
+  if (threadIdx.x == 0) {
+    S.tres[s] = sqrt(tt / bb);
+    S.flag[s] = ok ? 2 : 3;
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg_restart(CgState S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 3) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double rz = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 r = S.r[o + k], z = S.z[o + k];
+    rz += r.re * z.re + r.im * z.im;
+    S.p[o + k] = z;
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0) {
+    S.rz[s] = rz;
+    S.flag[s] = 0;
+  }
+}
+
+__global__ void k_permute(const Z64* __restrict__ in, int ld_in, Z64* __restrict__ out, int ld_out,
+                          const int* __restrict__ perm, int npw, int scatter) {
+  const int v = blockIdx.y;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= npw) return;
+  if (scatter)
+    out[(size_t)v * ld_out + perm[k]] = in[(size_t)v * ld_in + k];
+  else
+    out[(size_t)v * ld_out + k] = in[(size_t)v * ld_in + perm[k]];
+}
+
+__global__ void k_fill_zero(Z64* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = zmk(0.0, 0.0);
+}
+
+__global__ void k_set_flag(int* __restrict__ flag, const int* __restrict__ list, int n, int value) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) flag[list[i]] = value;
+}
+
+__global__ void k_ri(const double* __restrict__ in, Z64* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = zmk(in[2 * i], in[2 * i + 1]);
+}
+
+}  // namespace
+
+void launch_cg_init(const CgState& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg_init<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg_init2<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_cg_alpha(const CgState& s, const int* act, int n, double tol2, hipStream_t st) {
+  if (n > 0) k_cg_alpha<<<n, kCgThreads, 0, st>>>(s, act, tol2);
+}
+void launch_cg_beta(const CgState& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg_beta<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_copy_rows(const Z64* src, Z64* dst, int ld, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_copy_rows<<<n, 256, 0, st>>>(src, dst, ld, act);
+}
+void launch_true_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st) {
+  if (n > 0) k_true_resid<<<n, kCgThreads, 0, st>>>(s, act, tol);
+}
+void launch_cg_restart(const CgState& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg_restart<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_permute(const Z64* in, int ld_in, Z64* out, int ld_out, const int* perm, int npw, int nvec, bool scatter,
+                    hipStream_t st) {
+  if (nvec <= 0 || npw <= 0) return;
+  dim3 grid((npw + 255) / 256, nvec);
+  k_permute<<<grid, 256, 0, st>>>(in, ld_in, out, ld_out, perm, npw, scatter ? 1 : 0);
+}
+void launch_fill_zero(Z64* p, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_fill_zero<<<(unsigned)blocks, 256, 0, st>>>(p, n);
+}
+void launch_set_flag(int* flag, const int* list, int n, int value, hipStream_t st) {
+  if (n > 0) k_set_flag<<<(n + 255) / 256, 256, 0, st>>>(flag, list, n, value);
+}
+void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_ri<<<(unsigned)blocks, 256, 0, st>>>(in, out, n);
+}
+
+}  // namespace stern

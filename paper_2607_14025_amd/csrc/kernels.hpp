@@ -1,0 +1,89 @@
+// Host-side launchers of the gfx950 kernels (defined in fft.hip, gemm.hip, cg.hip).
+#pragma once
+#include "common.hpp"
+
+namespace stern {
+
+// Geometry of the pruned 3-D FFT of one system.
+// Sphere coefficients are stored per vector in "column order": the plane waves
+// grouped by x-pencil column (n_y, n_z), n_x ascending inside a column, padded
+// to npw_pad. Pencil data after the x pass is [vec][ix][ncol_pad].
+struct FftGeom {
+  int N;
+  int npw;
+  int npw_pad;
+  int ncol;
+  int ncol_pad;
+  int nza;                  // number of active n_z lines of the yz plane
+  const int* col_start;     // [ncol_pad] first sphere index of the column
+  const int* col_len;       // [ncol_pad] number of n_x values (0 for padding)
+  const int* col_xmin;      // [ncol_pad] smallest n_x of the column
+  const int* col_pos;       // [ncol] iy * N + iz of the column in a yz plane
+  const int* zl;            // [nza] iz of the active lines
+  const double* g2h;        // [npw_pad] |G|^2 / 2 in column order (0 for padding)
+  const Z64* tw64;          // [N] exp(-2 pi i m / N)
+  const Z32* tw32;
+};
+
+constexpr int kColBlock = 16;  // columns per workgroup in the x-pencil passes
+
+bool fft_size_supported(int N);
+size_t plane_lds_bytes(int N, int elem_bytes);
+
+// x pass, inverse: sphere coefficients of vectors vidx[b] (b < nvec) -> pencils.
+void launch_xinv(const FftGeom& g, const Z64* sph, const int* vidx, int nvec, Z64* pen, hipStream_t st);
+// x pass, forward + output mode:
+//   mode 0: out = pencil transform
+//   mode 1: out = pencil transform + (|G|^2/2 - eps[vec]) * pin        (H apply without KB)
+//   mode 2: out = scale * pencil transform
+void launch_xfwd(const FftGeom& g, const Z64* pen, const int* vidx, int nvec, Z64* out, int mode,
+                 const Z64* pin, const double* eps, double scale, hipStream_t st);
+// yz planes of the H apply: inverse, multiply by v_r (pre-scaled by 1/N^3), forward; in place.
+void launch_plane_vloc(const FftGeom& g, Z64* pen, const int* vidx, int nvec, const double* v_r, hipStream_t st);
+// yz planes of the right-hand side: pencils[s] = forward planes of psi_r[band[s]] * dv[pert[s]].
+void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
+                      int nvec, Z64* pen, hipStream_t st);
+// yz planes, inverse to a full real-space grid: out[vec] = [N][N][N] complex.
+void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out, hipStream_t st);
+// dn[pert_out[p]] = scale * Re sum_{b < nb} conj(psi_r[band0 + b]) * x_r[p * nb + b], from pencils.
+void launch_plane_dn(const FftGeom& g, const Z64* pen, const Z64* psi_r, int band0, int nb, int npert,
+                     const int* pert_out, double scale, double* dn, hipStream_t st);
+
+// C[n][m] = sum_k conj(A[m][k]) X[xidx[n]][k]; partial sums per K split.
+// A: [M_pad][K] (M_pad multiple of 64), X rows of length ldx, K multiple of 8.
+void launch_zgemm_reduce(const Z64* A, int M_pad, const Z64* X, int ldx, const int* xidx, int ncols, int K,
+                         Z64* cpart, int nsplit, hipStream_t st);
+// C[n][m] = scale * sum_s cpart[s][n][m]
+void launch_sum_parts(const Z64* cpart, int nsplit, int ncols, int M_pad, double scale, Z64* C, hipStream_t st);
+// Y[yidx[n]][k] += sum_m A[m][k] C[n][m], k < K (multiple of 64).
+void launch_zgemm_expand(const Z64* A, int M_pad, const Z64* C, Z64* Y, int ldy, const int* yidx, int ncols, int K,
+                         hipStream_t st);
+int choose_nsplit(int M_pad, int ncols, int K);
+
+// ---- CG vector kernels; one workgroup per solve s = act[b] ----
+struct CgState {
+  Z64 *x, *r, *p, *q, *z, *b;  // [nbatch][npw_pad]
+  double *bb, *rz, *rr;        // [nbatch]
+  int* flag;                   // 0 active, 1 recurrence-converged, 2 done (true residual accepted)
+  int* iters;
+  double* tres;                // true relative residual
+  const double* eps;           // [nbatch] eps of the band of each solve
+  const double* invT;          // [nbatch] 1 / T_v of the band of each solve
+  const double* g2h;           // [npw_pad]
+  int npw_pad;
+};
+void launch_cg_init(const CgState& s, const int* act, int n, hipStream_t st);
+void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st);
+void launch_cg_alpha(const CgState& s, const int* act, int n, double tol2, hipStream_t st);
+void launch_cg_beta(const CgState& s, const int* act, int n, hipStream_t st);
+void launch_copy_rows(const Z64* src, Z64* dst, int ld, const int* act, int n, hipStream_t st);
+void launch_true_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st);
+void launch_cg_restart(const CgState& s, const int* act, int n, hipStream_t st);
+// permutations between canonical and column order: out[v][perm[k]] = in[v][k] (scatter) or gather
+void launch_permute(const Z64* in, int ld_in, Z64* out, int ld_out, const int* perm, int npw, int nvec, bool scatter,
+                    hipStream_t st);
+void launch_fill_zero(Z64* p, size_t n, hipStream_t st);
+void launch_set_flag(int* flag, const int* list, int n, int value, hipStream_t st);
+void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st);
+
+}  // namespace stern

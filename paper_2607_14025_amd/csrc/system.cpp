@@ -1,0 +1,664 @@
+// C ABI of the Sternheimer chi0 library: system setup, occupied states, the
+// batched projected-PCG driver and the density response.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/stern.h"
+#include "basis.hpp"
+#include "kernels.hpp"
+
+using namespace stern;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPOK(expr)                                                                                    \
+  do {                                                                                                 \
+    hipError_t e_ = (expr);                                                                            \
+    if (e_ != hipSuccess) return fail(e_ == hipErrorOutOfMemory ? STERN_ERR_OOM : STERN_ERR_HIP,       \
+                                      "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, \
+                                      __LINE__);                                                       \
+  } while (0)
+
+#define CHECKED(expr)         \
+  do {                        \
+    int rc_ = (expr);         \
+    if (rc_ < 0) return rc_;  \
+  } while (0)
+
+// A device allocation that only grows.
+struct DBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  int ensure(size_t bytes) {
+    if (bytes <= n) return 0;
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+    if (bytes == 0) return 0;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      return fail(STERN_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    n = bytes;
+    return 0;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  template <class T>
+  T* as() const {
+    return reinterpret_cast<T*>(p);
+  }
+};
+
+int upload(DBuf& d, const void* src, size_t bytes, hipStream_t st) {
+  CHECKED(d.ensure(bytes));
+  if (bytes) HIPOK(hipMemcpyAsync(d.p, src, bytes, hipMemcpyHostToDevice, st));
+  return 0;
+}
+
+}  // namespace
+
+struct stern_system {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  CellParams cell;
+  HostBasis hb;
+  int n_atoms = 0, natoms_pad = 0;
+  // static device data
+  DBuf col_start, col_len, col_xmin, col_pos, zl, g2h, tw64, v_r, kb, perm;
+  // occupied states
+  int n_occ = 0, nocc_pad = 0;
+  bool have_occ = false;
+  std::vector<double> eps, invT;
+  DBuf psi, psi_r;
+  // workspace
+  DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
+      sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
+  int ws_solves = 0;
+
+  FftGeom geom() const {
+    FftGeom g;
+    g.N = hb.N;
+    g.npw = hb.npw;
+    g.npw_pad = hb.npw_pad;
+    g.ncol = hb.ncol;
+    g.ncol_pad = hb.ncol_pad;
+    g.nza = hb.nza;
+    g.col_start = col_start.as<int>();
+    g.col_len = col_len.as<int>();
+    g.col_xmin = col_xmin.as<int>();
+    g.col_pos = col_pos.as<int>();
+    g.zl = zl.as<int>();
+    g.g2h = g2h.as<double>();
+    g.tw64 = tw64.as<Z64>();
+    g.tw32 = nullptr;
+    return g;
+  }
+
+  void release_all() {
+    DBuf* all[] = {&col_start, &col_len,  &col_xmin, &col_pos, &zl,       &g2h,     &tw64,     &v_r,      &kb,
+                   &perm,      &psi,      &psi_r,    &wx,      &wr,       &wp,      &wq,       &wz,       &wb,
+                   &pen,       &cpart,    &cmat,     &sv_eps,  &sv_invT,  &sv_band, &sv_pert,  &sv_bb,    &sv_rz,
+                   &sv_rr,     &sv_flag,  &sv_iters, &sv_tres, &list_act, &list_f,  &pert_out, &dv_dev,   &dn_dev,
+                   &tmp_in,    &tmp_out};
+    for (DBuf* d : all) d->release();
+  }
+};
+
+namespace {
+
+// ---- operator pieces on solve rows `list` (device ints) of batch buffers ----
+
+// Y <- P_c Y on rows list[0..n)
+int apply_pc_rows(stern_system* S, Z64* Y, const int* list, int n) {
+  if (n <= 0) return 0;
+  const int K = S->hb.npw_pad;
+  const int ns = choose_nsplit(S->nocc_pad, n, K);
+  launch_zgemm_reduce(S->psi.as<Z64>(), S->nocc_pad, Y, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
+  launch_sum_parts(S->cpart.as<Z64>(), ns, n, S->nocc_pad, -1.0, S->cmat.as<Z64>(), S->stream);
+  launch_zgemm_expand(S->psi.as<Z64>(), S->nocc_pad, S->cmat.as<Z64>(), Y, K, list, n, K, S->stream);
+  return 0;
+}
+
+// out = (H - eps_s) in on rows list (without projection); eps per row index
+int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int n, const double* eps_rows) {
+  if (n <= 0) return 0;
+  const FftGeom g = S->geom();
+  const int K = S->hb.npw_pad;
+  launch_xinv(g, in, list, n, S->pen.as<Z64>(), S->stream);
+  launch_plane_vloc(g, S->pen.as<Z64>(), list, n, S->v_r.as<double>(), S->stream);
+  launch_xfwd(g, S->pen.as<Z64>(), list, n, out, 1, in, eps_rows, 0.0, S->stream);
+  if (S->n_atoms > 0) {
+    const int ns = choose_nsplit(S->natoms_pad, n, K);
+    launch_zgemm_reduce(S->kb.as<Z64>(), S->natoms_pad, in, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
+    launch_sum_parts(S->cpart.as<Z64>(), ns, n, S->natoms_pad, S->cell.D, S->cmat.as<Z64>(), S->stream);
+    launch_zgemm_expand(S->kb.as<Z64>(), S->natoms_pad, S->cmat.as<Z64>(), out, K, list, n, K, S->stream);
+  }
+  return 0;
+}
+
+size_t cpart_capacity(int M_pad, int nmax, int K) {
+  size_t best = 0;
+  for (int n = 1; n <= nmax; ++n) {
+    const size_t c = (size_t)choose_nsplit(M_pad, n, K) * n;
+    if (c > best) best = c;
+  }
+  return best * M_pad;
+}
+
+// workspace for `ns` rows held at once
+int ensure_workspace(stern_system* S, int ns) {
+  const size_t K = S->hb.npw_pad;
+  const size_t vec = (size_t)ns * K * sizeof(Z64);
+  for (DBuf* d : {&S->wx, &S->wr, &S->wp, &S->wq, &S->wz, &S->wb}) CHECKED(d->ensure(vec));
+  CHECKED(S->pen.ensure((size_t)ns * S->hb.N * S->hb.ncol_pad * sizeof(Z64)));
+  const int mp = std::max(S->nocc_pad, S->natoms_pad);
+  CHECKED(S->cpart.ensure(std::max(cpart_capacity(std::max(S->nocc_pad, 64), ns, (int)K),
+                                   cpart_capacity(S->natoms_pad, ns, (int)K)) * sizeof(Z64)));
+  CHECKED(S->cmat.ensure((size_t)ns * mp * sizeof(Z64)));
+  for (DBuf* d : {&S->sv_eps, &S->sv_invT, &S->sv_bb, &S->sv_rz, &S->sv_rr, &S->sv_tres})
+    CHECKED(d->ensure((size_t)ns * sizeof(double)));
+  for (DBuf* d : {&S->sv_band, &S->sv_pert, &S->sv_flag, &S->sv_iters, &S->list_act, &S->list_f})
+    CHECKED(d->ensure((size_t)ns * sizeof(int)));
+  // padding entries of every vector stay zero: clear once when (re)allocated
+  if (S->ws_solves < ns) {
+    for (DBuf* d : {&S->wx, &S->wr, &S->wp, &S->wq, &S->wz, &S->wb})
+      launch_fill_zero(d->as<Z64>(), (size_t)ns * K, S->stream);
+    S->ws_solves = ns;
+  }
+  return 0;
+}
+
+CgState cg_state(stern_system* S) {
+  CgState c;
+  c.x = S->wx.as<Z64>();
+  c.r = S->wr.as<Z64>();
+  c.p = S->wp.as<Z64>();
+  c.q = S->wq.as<Z64>();
+  c.z = S->wz.as<Z64>();
+  c.b = S->wb.as<Z64>();
+  c.bb = S->sv_bb.as<double>();
+  c.rz = S->sv_rz.as<double>();
+  c.rr = S->sv_rr.as<double>();
+  c.flag = S->sv_flag.as<int>();
+  c.iters = S->sv_iters.as<int>();
+  c.tres = S->sv_tres.as<double>();
+  c.eps = S->sv_eps.as<double>();
+  c.invT = S->sv_invT.as<double>();
+  c.g2h = S->g2h.as<double>();
+  c.npw_pad = S->hb.npw_pad;
+  return c;
+}
+
+// q = A x for rows in list with the FP64 projected operator, then the true-residual test
+int true_residual(stern_system* S, const CgState& cs, const int* list, int n, double tol) {
+  launch_copy_rows(cs.x, cs.z, S->hb.npw_pad, list, n, S->stream);
+  CHECKED(apply_pc_rows(S, cs.z, list, n));
+  CHECKED(apply_h_rows(S, cs.z, cs.q, list, n, cs.eps));
+  CHECKED(apply_pc_rows(S, cs.q, list, n));
+  launch_true_resid(cs, list, n, tol, S->stream);
+  return 0;
+}
+
+int launch_check() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(STERN_ERR_HIP, "kernel launch failed: %s", hipGetErrorString(e));
+  return 0;
+}
+
+struct Scope {
+  int dev_prev = -1;
+  explicit Scope(int dev) {
+    (void)hipGetDevice(&dev_prev);
+    (void)hipSetDevice(dev);
+  }
+  ~Scope() {
+    if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
+  }
+};
+
+}  // namespace
+
+// ============================================================== C ABI ======
+
+extern "C" {
+
+const char* stern_last_error(void) { return g_err.c_str(); }
+
+static int cell_from_abi(const stern_cell* c, CellParams& p) {
+  if (!c) return fail(STERN_ERR_INVALID_ARG, "cell is NULL");
+  if (c->n_atoms < 0 || (c->n_atoms > 0 && !c->pos)) return fail(STERN_ERR_INVALID_ARG, "bad atoms");
+  if (!(c->L > 0) || !(c->ecut_ry > 0)) return fail(STERN_ERR_INVALID_ARG, "L and ecut_ry must be > 0");
+  if (c->fft_n < 0) return fail(STERN_ERR_INVALID_ARG, "fft_n must be >= 0");
+  p.L = c->L;
+  p.ecut = c->ecut_ry;
+  p.pos.assign(c->pos, c->pos + 3 * (size_t)c->n_atoms);
+  p.amp = c->vloc_amp;
+  p.sigma = c->vloc_sigma;
+  p.D = c->kb_D;
+  p.width = c->kb_width;
+  p.fft_n = c->fft_n;
+  if (!(p.sigma > 0) || !(p.width > 0)) return fail(STERN_ERR_INVALID_ARG, "vloc_sigma and kb_width must be > 0");
+  return 0;
+}
+
+int stern_basis_info(const stern_cell* cell, int* n_pw, int* fft_n, int32_t* miller) {
+  CellParams p;
+  CHECKED(cell_from_abi(cell, p));
+  HostBasis hb;
+  std::string e = build_basis(p, hb);
+  if (!e.empty()) return fail(STERN_ERR_INVALID_ARG, "%s", e.c_str());
+  if (n_pw) *n_pw = hb.npw;
+  if (fft_n) *fft_n = hb.N;
+  if (miller) std::memcpy(miller, hb.miller.data(), hb.miller.size() * sizeof(int32_t));
+  return STERN_OK;
+}
+
+int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_system** out) {
+  if (!out) return fail(STERN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  CellParams p;
+  CHECKED(cell_from_abi(cell, p));
+  stern_system* S = new stern_system();
+  S->device = rt ? rt->device : 0;
+  S->stream = rt ? (hipStream_t)rt->stream : nullptr;
+  S->cell = p;
+  std::string e = build_basis(p, S->hb);
+  if (!e.empty()) {
+    delete S;
+    return fail(STERN_ERR_INVALID_ARG, "%s", e.c_str());
+  }
+  const HostBasis& hb = S->hb;
+  if (!fft_size_supported(hb.N)) {
+    delete S;
+    return fail(STERN_ERR_UNSUPPORTED, "FFT grid %d is not a supported 2^a 3^b size", hb.N);
+  }
+  Scope sc(S->device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) {
+    delete S;
+    return fail(STERN_ERR_HIP, "hipGetDeviceProperties failed");
+  }
+  const size_t lds = plane_lds_bytes(hb.N, sizeof(Z64));
+  if (lds > prop.sharedMemPerBlock && lds > (size_t)prop.maxSharedMemoryPerMultiProcessor) {
+    delete S;
+    return fail(STERN_ERR_UNSUPPORTED, "FP64 plane of grid %d needs %zu bytes of LDS", hb.N, lds);
+  }
+  S->n_atoms = (int)(p.pos.size() / 3);
+  S->natoms_pad = std::max(64, (S->n_atoms + 63) / 64 * 64);
+  auto run = [&]() -> int {
+    hipStream_t st = S->stream;
+    CHECKED(upload(S->col_start, hb.col_start.data(), hb.col_start.size() * sizeof(int), st));
+    CHECKED(upload(S->col_len, hb.col_len.data(), hb.col_len.size() * sizeof(int), st));
+    CHECKED(upload(S->col_xmin, hb.col_xmin.data(), hb.col_xmin.size() * sizeof(int), st));
+    CHECKED(upload(S->col_pos, hb.col_pos.data(), hb.col_pos.size() * sizeof(int), st));
+    CHECKED(upload(S->zl, hb.zl.data(), hb.zl.size() * sizeof(int), st));
+    CHECKED(upload(S->g2h, hb.g2h.data(), hb.g2h.size() * sizeof(double), st));
+    CHECKED(upload(S->perm, hb.perm.data(), hb.perm.size() * sizeof(int), st));
+    std::vector<Z64> tw(hb.N);
+    for (int m = 0; m < hb.N; ++m) {
+      const double a = 6.283185307179586476925286766559 * m / hb.N;
+      tw[m] = zmk(std::cos(a), -std::sin(a));
+    }
+    CHECKED(upload(S->tw64, tw.data(), tw.size() * sizeof(Z64), st));
+    const double n3 = (double)hb.N * hb.N * hb.N;
+    std::vector<double> v = vloc_grid(p, hb, 1.0 / n3);
+    CHECKED(upload(S->v_r, v.data(), v.size() * sizeof(double), st));
+    std::vector<std::complex<double>> B = kb_projectors(p, hb, S->natoms_pad);
+    CHECKED(upload(S->kb, B.data(), B.size() * sizeof(Z64), st));
+    HIPOK(hipStreamSynchronize(st));
+    return 0;
+  };
+  int rc = run();
+  if (rc < 0) {
+    S->release_all();
+    delete S;
+    return rc;
+  }
+  *out = S;
+  return STERN_OK;
+}
+
+int stern_query(const stern_system* S, int* n_pw, int* fft_n, double* omega) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (n_pw) *n_pw = S->hb.npw;
+  if (fft_n) *fft_n = S->hb.N;
+  if (omega) *omega = S->hb.omega;
+  return STERN_OK;
+}
+
+int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const double* eps, int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (n_occ <= 0 || !psi || !eps) return fail(STERN_ERR_INVALID_ARG, "need n_occ > 0, psi and eps");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  Scope sc(S->device);
+  const HostBasis& hb = S->hb;
+  hipStream_t st = S->stream;
+  const int npw = hb.npw, K = hb.npw_pad, N = hb.N;
+  std::vector<double> h_psi, h_eps(n_occ);
+  const double* hp = psi;
+  if (mem_kind == STERN_MEM_DEVICE) {
+    h_psi.resize((size_t)n_occ * npw * 2);
+    HIPOK(hipMemcpy(h_psi.data(), psi, h_psi.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPOK(hipMemcpy(h_eps.data(), eps, n_occ * sizeof(double), hipMemcpyDeviceToHost));
+    hp = h_psi.data();
+  } else {
+    std::memcpy(h_eps.data(), eps, n_occ * sizeof(double));
+  }
+  // kinetic energy per band, T_v = sum_G |G|^2/2 |c|^2, floored at (2 pi / L)^2 / 2
+  S->eps = h_eps;
+  S->invT.assign(n_occ, 0.0);
+  const double floor_t = 0.5 * hb.b * hb.b;
+  for (int v = 0; v < n_occ; ++v) {
+    double t = 0.0;
+    for (int k = 0; k < npw; ++k) {
+      const double re = hp[2 * ((size_t)v * npw + k)], im = hp[2 * ((size_t)v * npw + k) + 1];
+      t += hb.g2h[hb.perm[k]] * (re * re + im * im);
+    }
+    S->invT[v] = 1.0 / std::max(t, floor_t);
+  }
+  S->n_occ = n_occ;
+  S->nocc_pad = std::max(64, (n_occ + 63) / 64 * 64);
+  CHECKED(S->psi.ensure((size_t)S->nocc_pad * K * sizeof(Z64)));
+  launch_fill_zero(S->psi.as<Z64>(), (size_t)S->nocc_pad * K, st);
+  CHECKED(S->tmp_in.ensure((size_t)n_occ * npw * sizeof(Z64)));
+  HIPOK(hipMemcpyAsync(S->tmp_in.p, hp, (size_t)n_occ * npw * sizeof(Z64), hipMemcpyHostToDevice, st));
+  launch_permute(S->tmp_in.as<Z64>(), npw, S->psi.as<Z64>(), K, S->perm.as<int>(), npw, n_occ, true, st);
+  // psi_v(r) on the grid (unnormalised sum_G c_G e^{iG.r}) for the RHS and dn
+  CHECKED(S->psi_r.ensure((size_t)n_occ * N * N * N * sizeof(Z64)));
+  CHECKED(S->pen.ensure((size_t)n_occ * N * hb.ncol_pad * sizeof(Z64)));
+  const FftGeom g = S->geom();
+  launch_xinv(g, S->psi.as<Z64>(), nullptr, n_occ, S->pen.as<Z64>(), st);
+  launch_plane_full_inv(g, S->pen.as<Z64>(), n_occ, S->psi_r.as<Z64>(), st);
+  CHECKED(launch_check());
+  HIPOK(hipStreamSynchronize(st));
+  S->have_occ = true;
+  return STERN_OK;
+}
+
+static int rows_in(stern_system* S, int n_vec, const double* c, int mem_kind, DBuf& dst) {
+  const int npw = S->hb.npw, K = S->hb.npw_pad;
+  CHECKED(dst.ensure((size_t)n_vec * K * sizeof(Z64)));
+  launch_fill_zero(dst.as<Z64>(), (size_t)n_vec * K, S->stream);
+  CHECKED(S->tmp_out.ensure((size_t)n_vec * npw * sizeof(Z64)));
+  HIPOK(hipMemcpyAsync(S->tmp_out.p, c, (size_t)n_vec * npw * sizeof(Z64),
+                       mem_kind == STERN_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, S->stream));
+  launch_permute(S->tmp_out.as<Z64>(), npw, dst.as<Z64>(), K, S->perm.as<int>(), npw, n_vec, true, S->stream);
+  return 0;
+}
+
+static int rows_out(stern_system* S, int n_vec, const Z64* src, const int* rows_host, double* out, int mem_kind) {
+  const int npw = S->hb.npw, K = S->hb.npw_pad;
+  CHECKED(S->tmp_out.ensure((size_t)n_vec * npw * sizeof(Z64)));
+  for (int v = 0; v < n_vec; ++v) {
+    const int row = rows_host ? rows_host[v] : v;
+    launch_permute(src + (size_t)row * K, K, S->tmp_out.as<Z64>() + (size_t)v * npw, npw, S->perm.as<int>(), npw, 1,
+                   false, S->stream);
+  }
+  HIPOK(hipMemcpyAsync(out, S->tmp_out.p, (size_t)n_vec * npw * sizeof(Z64),
+                       mem_kind == STERN_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, S->stream));
+  HIPOK(hipStreamSynchronize(S->stream));
+  return 0;
+}
+
+int stern_apply_h(stern_system* S, int n_vec, const double* c, const double* shift, double* out, int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (n_vec <= 0) return STERN_OK;
+  if (!c || !out) return fail(STERN_ERR_INVALID_ARG, "NULL array");
+  Scope sc(S->device);
+  CHECKED(ensure_workspace(S, std::max(n_vec, S->ws_solves)));
+  CHECKED(rows_in(S, n_vec, c, mem_kind, S->wp));
+  std::vector<double> sh(n_vec, 0.0);
+  if (shift) {
+    if (mem_kind == STERN_MEM_DEVICE)
+      HIPOK(hipMemcpy(sh.data(), shift, n_vec * sizeof(double), hipMemcpyDeviceToHost));
+    else
+      std::memcpy(sh.data(), shift, n_vec * sizeof(double));
+  }
+  HIPOK(hipMemcpyAsync(S->sv_eps.p, sh.data(), n_vec * sizeof(double), hipMemcpyHostToDevice, S->stream));
+  CHECKED(apply_h_rows(S, S->wp.as<Z64>(), S->wq.as<Z64>(), nullptr, n_vec, S->sv_eps.as<double>()));
+  CHECKED(launch_check());
+  return rows_out(S, n_vec, S->wq.as<Z64>(), nullptr, out, mem_kind);
+}
+
+int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
+  if (n_vec <= 0) return STERN_OK;
+  if (!c || !out) return fail(STERN_ERR_INVALID_ARG, "NULL array");
+  Scope sc(S->device);
+  CHECKED(ensure_workspace(S, std::max(n_vec, S->ws_solves)));
+  CHECKED(rows_in(S, n_vec, c, mem_kind, S->wp));
+  CHECKED(apply_pc_rows(S, S->wp.as<Z64>(), nullptr, n_vec));
+  CHECKED(launch_check());
+  return rows_out(S, n_vec, S->wp.as<Z64>(), nullptr, out, mem_kind);
+}
+
+int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn_r, const stern_opts* opts,
+                     stern_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
+  if (!opts) return fail(STERN_ERR_INVALID_ARG, "opts is NULL");
+  if (n_pert <= 0 || !dv_r || !dn_r) return fail(STERN_ERR_INVALID_ARG, "need n_pert > 0, dv_r and dn_r");
+  if (opts->precision != STERN_FP64) return fail(STERN_ERR_UNSUPPORTED, "only STERN_FP64 is available");
+  if (opts->guess != STERN_GUESS_ZERO) return fail(STERN_ERR_UNSUPPORTED, "only STERN_GUESS_ZERO is available");
+  if (opts->mem_kind != STERN_MEM_HOST && opts->mem_kind != STERN_MEM_DEVICE)
+    return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  if (!(opts->tol > 0)) return fail(STERN_ERR_INVALID_ARG, "tol must be > 0");
+  const int v0 = opts->band_begin;
+  const int v1 = opts->band_end > 0 ? opts->band_end : S->n_occ;
+  if (v0 < 0 || v1 > S->n_occ || v0 >= v1) return fail(STERN_ERR_INVALID_ARG, "bad band range [%d, %d)", v0, v1);
+  if (opts->n_sample < 0 || (opts->n_sample > 0 && (!opts->sample_pairs || !opts->sample_x)))
+    return fail(STERN_ERR_INVALID_ARG, "bad sample request");
+  for (int k = 0; k < opts->n_sample; ++k) {
+    const int v = opts->sample_pairs[2 * k], i = opts->sample_pairs[2 * k + 1];
+    if (v < v0 || v >= v1 || i < 0 || i >= n_pert) return fail(STERN_ERR_INVALID_ARG, "sample pair %d out of range", k);
+  }
+  Scope sc(S->device);
+  hipStream_t st = S->stream;
+  const HostBasis& hb = S->hb;
+  const int N = hb.N, K = hb.npw_pad;
+  const size_t n3 = (size_t)N * N * N;
+  const int nb = v1 - v0;
+  const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
+  const int check_every = opts->check_every > 0 ? opts->check_every : 4;
+  const double tol = opts->tol;
+
+  // perturbations per batch
+  int per = opts->max_batch > 0 ? std::max(1, opts->max_batch / nb) : 0;
+  if (per == 0) {
+    size_t free_b = 0, total_b = 0;
+    HIPOK(hipMemGetInfo(&free_b, &total_b));
+    const size_t have = (size_t)S->ws_solves >= (size_t)nb ? S->wx.n * 6 + S->pen.n : 0;
+    const size_t per_solve = (size_t)K * sizeof(Z64) * 6 + (size_t)N * hb.ncol_pad * sizeof(Z64) +
+                             (size_t)(2 * std::max(S->nocc_pad, 64)) * sizeof(Z64) * 2 + 64;
+    const size_t budget = (size_t)(0.6 * (double)(free_b + have));
+    per = (int)std::max<size_t>(1, budget / (per_solve * nb));
+  }
+  per = std::min(per, n_pert);
+  const int max_ns = per * nb;
+  CHECKED(ensure_workspace(S, max_ns));
+  CHECKED(S->pert_out.ensure((size_t)n_pert * sizeof(int)));
+  {
+    std::vector<int> po(n_pert);
+    for (int i = 0; i < n_pert; ++i) po[i] = i;
+    HIPOK(hipMemcpyAsync(S->pert_out.p, po.data(), n_pert * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPOK(hipStreamSynchronize(st));  // po is released at the end of this block
+  }
+  const double* dv_dev = dv_r;
+  double* dn_dev = dn_r;
+  if (opts->mem_kind == STERN_MEM_HOST) {
+    CHECKED(S->dv_dev.ensure((size_t)n_pert * n3 * sizeof(double)));
+    CHECKED(S->dn_dev.ensure((size_t)n_pert * n3 * sizeof(double)));
+    HIPOK(hipMemcpyAsync(S->dv_dev.p, dv_r, (size_t)n_pert * n3 * sizeof(double), hipMemcpyHostToDevice, st));
+    dv_dev = S->dv_dev.as<double>();
+    dn_dev = S->dn_dev.as<double>();
+  }
+  const CgState cs = cg_state(S);
+  const FftGeom g = S->geom();
+  std::vector<int> all_iters, all_flag;
+  std::vector<double> all_tres;
+  all_iters.reserve((size_t)n_pert * nb);
+  long long tot_iters = 0;
+  int n_restart = 0;
+
+  std::vector<int> h_flag(max_ns), h_band(max_ns), h_pert(max_ns), act, flist;
+  std::vector<double> h_eps(max_ns), h_invT(max_ns);
+  for (int i0 = 0; i0 < n_pert; i0 += per) {
+    const int i1 = std::min(n_pert, i0 + per);
+    const int ns = (i1 - i0) * nb;
+    for (int s = 0; s < ns; ++s) {
+      h_band[s] = v0 + s % nb;
+      h_pert[s] = i0 + s / nb;
+      h_eps[s] = S->eps[h_band[s]];
+      h_invT[s] = S->invT[h_band[s]];
+    }
+    HIPOK(hipMemcpyAsync(S->sv_band.p, h_band.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPOK(hipMemcpyAsync(S->sv_pert.p, h_pert.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+    HIPOK(hipMemcpyAsync(S->sv_eps.p, h_eps.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPOK(hipMemcpyAsync(S->sv_invT.p, h_invT.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
+    // b = -P_c [dV psi_v]
+    launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, S->sv_band.as<int>(), S->sv_pert.as<int>(), ns,
+                     S->pen.as<Z64>(), st);
+    launch_xfwd(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
+    CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
+    launch_cg_init(cs, nullptr, ns, st);
+    CHECKED(apply_pc_rows(S, cs.z, nullptr, ns));
+    launch_cg_init2(cs, nullptr, ns, st);
+    CHECKED(launch_check());
+    HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    act.clear();
+    for (int s = 0; s < ns; ++s)
+      if (h_flag[s] == 0) act.push_back(s);
+    int it = 0;
+    while (!act.empty()) {
+      const int na = (int)act.size();
+      HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+      const int* L = S->list_act.as<int>();
+      const int nsteps = std::min(check_every, max_iter - it);
+      for (int k = 0; k < nsteps; ++k) {
+        CHECKED(apply_h_rows(S, cs.p, cs.q, L, na, cs.eps));
+        CHECKED(apply_pc_rows(S, cs.q, L, na));
+        launch_cg_alpha(cs, L, na, tol * tol, st);
+        CHECKED(apply_pc_rows(S, cs.z, L, na));
+        launch_cg_beta(cs, L, na, st);
+      }
+      it += nsteps;
+      CHECKED(launch_check());
+      HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      const bool last = it >= max_iter;
+      flist.clear();
+      for (int s : act)
+        if (h_flag[s] == 1 || last) flist.push_back(s);
+      if (!flist.empty()) {
+        const int nf = (int)flist.size();
+        HIPOK(hipMemcpyAsync(S->list_f.p, flist.data(), nf * sizeof(int), hipMemcpyHostToDevice, st));
+        const int* F = S->list_f.as<int>();
+        if (last) launch_set_flag(cs.flag, F, nf, 1, st);  // final check on everything still running
+        CHECKED(true_residual(S, cs, F, nf, tol));
+        if (!last) {
+          CHECKED(apply_pc_rows(S, cs.z, F, nf));
+          launch_cg_restart(cs, F, nf, st);
+        }
+        CHECKED(launch_check());
+        HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+        if (!last)
+          for (int s : flist)
+            if (h_flag[s] == 0) ++n_restart;
+      }
+      if (last) break;
+      std::vector<int> nxt;
+      for (int s : act)
+        if (h_flag[s] != 2) nxt.push_back(s);
+      act.swap(nxt);
+    }
+    // dn_i = 4/Omega Re sum_v conj(psi_v(r)) x_{v,i}(r)
+    launch_xinv(g, cs.x, nullptr, ns, S->pen.as<Z64>(), st);
+    launch_plane_dn(g, S->pen.as<Z64>(), S->psi_r.as<Z64>(), v0, nb, i1 - i0, S->pert_out.as<int>() + i0,
+                    4.0 / hb.omega, dn_dev, st);
+    CHECKED(launch_check());
+    // per-solve statistics
+    std::vector<int> hi(ns);
+    std::vector<double> ht(ns);
+    HIPOK(hipMemcpyAsync(hi.data(), cs.iters, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipMemcpyAsync(ht.data(), cs.tres, ns * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    for (int s = 0; s < ns; ++s) {
+      all_iters.push_back(hi[s]);
+      all_tres.push_back(ht[s]);
+      all_flag.push_back(h_flag[s]);
+      tot_iters += hi[s];
+    }
+    // sampled solution vectors
+    for (int k = 0; k < opts->n_sample; ++k) {
+      const int v = opts->sample_pairs[2 * k], i = opts->sample_pairs[2 * k + 1];
+      if (i < i0 || i >= i1) continue;
+      const int row = (i - i0) * nb + (v - v0);
+      CHECKED(rows_out(S, 1, cs.x, &row, opts->sample_x + 2 * (size_t)k * hb.npw, STERN_MEM_HOST));
+    }
+  }
+  if (opts->mem_kind == STERN_MEM_HOST)
+    HIPOK(hipMemcpyAsync(dn_r, dn_dev, (size_t)n_pert * n3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  const int nsol = (int)all_iters.size();
+  int nconv = 0, mx = 0;
+  double mres = 0.0;
+  for (int s = 0; s < nsol; ++s) {
+    if (all_flag[s] == 2) ++nconv;
+    mx = std::max(mx, all_iters[s]);
+    mres = std::max(mres, all_tres[s]);
+  }
+  if (stats) {
+    stats->n_solves = nsol;
+    stats->n_converged = nconv;
+    stats->n_fallback = n_restart;
+    stats->total_iters = tot_iters;
+    stats->max_iters = mx;
+    stats->max_true_resid = mres;
+    if (stats->iters) std::memcpy(stats->iters, all_iters.data(), nsol * sizeof(int));
+    if (stats->resid) std::memcpy(stats->resid, all_tres.data(), nsol * sizeof(double));
+    stats->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return nconv == nsol ? STERN_OK : STERN_WARN_NOT_CONVERGED;
+}
+
+void stern_free(stern_system* S) {
+  if (!S) return;
+  {
+    Scope sc(S->device);
+    if (S->stream) (void)hipStreamSynchronize(S->stream);
+    else (void)hipDeviceSynchronize();
+    S->release_all();
+  }
+  delete S;
+}
+
+}  // extern "C"

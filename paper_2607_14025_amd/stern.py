@@ -1,0 +1,226 @@
+"""ctypes binding of libstern.so (argument marshalling only; every step runs in the HIP library).
+
+Arrays may be numpy (host) or torch CUDA tensors (device, passed by pointer on
+torch's current stream). The library is required: importing works without it,
+but every call raises if libstern.so is missing or fails to load.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libstern.so")
+
+STERN_OK = 0
+STERN_WARN_NOT_CONVERGED = 1
+STERN_FP64 = 0
+STERN_MIXED = 1
+STERN_GUESS_ZERO = 0
+STERN_MEM_HOST = 0
+STERN_MEM_DEVICE = 1
+
+EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
+            "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
+
+
+class SternError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"stern error {code}: {msg}")
+        self.code = code
+
+
+class Cell(C.Structure):
+    _fields_ = [("L", C.c_double), ("ecut_ry", C.c_double), ("n_atoms", C.c_int), ("pos", C.POINTER(C.c_double)),
+                ("vloc_amp", C.c_double), ("vloc_sigma", C.c_double), ("kb_D", C.c_double),
+                ("kb_width", C.c_double), ("fft_n", C.c_int)]
+
+
+class Runtime(C.Structure):
+    _fields_ = [("device", C.c_int), ("stream", C.c_void_p)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
+                ("mem_kind", C.c_int), ("band_begin", C.c_int), ("band_end", C.c_int), ("max_batch", C.c_int),
+                ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
+                ("sample_x", C.POINTER(C.c_double))]
+
+
+class Stats(C.Structure):
+    _fields_ = [("n_solves", C.c_int), ("n_converged", C.c_int), ("n_fallback", C.c_int),
+                ("total_iters", C.c_longlong), ("max_iters", C.c_int), ("wall_s", C.c_double),
+                ("max_true_resid", C.c_double), ("iters", C.POINTER(C.c_int)), ("resid", C.POINTER(C.c_double))]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2607_14025_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        L.stern_basis_info.argtypes = [P(Cell), P(C.c_int), P(C.c_int), P(C.c_int32)]
+        L.stern_init_system.argtypes = [P(Cell), P(Runtime), P(C.c_void_p)]
+        L.stern_query.argtypes = [C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_double)]
+        L.stern_set_occupied.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        L.stern_apply_chi0.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, P(Opts), P(Stats)]
+        L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
+        L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        L.stern_free.argtypes = [C.c_void_p]
+        L.stern_free.restype = None
+        L.stern_last_error.restype = C.c_char_p
+        for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied",
+                     "stern_apply_chi0", "stern_apply_h", "stern_apply_pc"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc < 0:
+        raise SternError(rc, lib().stern_last_error().decode())
+    return rc
+
+
+def _cell(L, ecut, pos, vloc_amp, vloc_sigma, kb_D, kb_width, fft_n):
+    pos = np.ascontiguousarray(np.asarray(pos, dtype=np.float64).reshape(-1, 3))
+    c = Cell(float(L), float(ecut), len(pos), pos.ctypes.data_as(C.POINTER(C.c_double)), float(vloc_amp),
+             float(vloc_sigma), float(kb_D), float(kb_width), int(fft_n))
+    return c, pos
+
+
+def basis_info(L, ecut, fft_n=0):
+    """(n_pw, N, miller [n_pw, 3] int32) of the library's canonical order; host only."""
+    c, _keep = _cell(L, ecut, np.zeros((0, 3)), -2.0, 1.0, 1.0, 1.0, fft_n)
+    npw, n = C.c_int(), C.c_int()
+    _check(lib().stern_basis_info(C.byref(c), C.byref(npw), C.byref(n), None))
+    mil = np.zeros((npw.value, 3), dtype=np.int32)
+    _check(lib().stern_basis_info(C.byref(c), None, None, mil.ctypes.data_as(C.POINTER(C.c_int32))))
+    return npw.value, n.value, mil
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, want_complex):
+    """(pointer, mem_kind, keepalive) for a numpy array or a CUDA torch tensor."""
+    if _is_torch(a):
+        if not a.is_cuda or not a.is_contiguous():
+            raise ValueError("torch tensors must be contiguous CUDA tensors")
+        return C.c_void_p(a.data_ptr()), STERN_MEM_DEVICE, a
+    dt = np.complex128 if want_complex else np.float64
+    arr = np.ascontiguousarray(a, dtype=dt)
+    return C.c_void_p(arr.ctypes.data), STERN_MEM_HOST, arr
+
+
+def _torch_stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class System:
+    """One cell on one GPU (stern_init_system ... stern_free)."""
+
+    def __init__(self, L, ecut, pos, vloc_amp=-2.0, vloc_sigma=1.0, kb_D=1.0, kb_width=1.0, fft_n=0, device=0,
+                 stream=None):
+        c, self._pos = _cell(L, ecut, pos, vloc_amp, vloc_sigma, kb_D, kb_width, fft_n)
+        rt = Runtime(int(device), stream if stream is not None else _torch_stream())
+        h = C.c_void_p()
+        _check(lib().stern_init_system(C.byref(c), C.byref(rt), C.byref(h)))
+        self._h = h
+        npw, n, om = C.c_int(), C.c_int(), C.c_double()
+        _check(lib().stern_query(h, C.byref(npw), C.byref(n), C.byref(om)))
+        self.n_pw, self.fft_n, self.omega = npw.value, n.value, om.value
+        self.n_occ = 0
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stern_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_occupied(self, psi, eps):
+        """psi [n_occ, n_pw] complex (canonical order), eps [n_occ]; numpy or CUDA tensors."""
+        n_occ = psi.shape[0]
+        pp, mk, k1 = _ptr(psi, True)
+        ep, mk2, k2 = _ptr(eps, False)
+        if mk != mk2:
+            raise ValueError("psi and eps must both be host or both device arrays")
+        _check(lib().stern_set_occupied(self._h, n_occ, pp, ep, mk))
+        self.n_occ = n_occ
+
+    def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
+                   samples=None, precision=STERN_FP64):
+        """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
+
+        samples: optional list of (band, pert) pairs whose solution vectors are returned."""
+        n_pert = dv_r.shape[0]
+        dp, mk, k1 = _ptr(dv_r, False)
+        if dn_out is None:
+            if mk == STERN_MEM_DEVICE:
+                import torch
+                dn_out = torch.empty_like(dv_r)
+            else:
+                dn_out = np.empty(dv_r.shape, dtype=np.float64)
+        op, mk2, k2 = _ptr(dn_out, False)
+        if mk != mk2:
+            raise ValueError("dv and dn must both be host or both device arrays")
+        o = Opts()
+        o.tol = float(tol)
+        o.max_iter = int(max_iter)
+        o.precision = int(precision)
+        o.guess = STERN_GUESS_ZERO
+        o.mem_kind = mk
+        o.band_begin, o.band_end = (0, 0) if band_range is None else (int(band_range[0]), int(band_range[1]))
+        o.max_batch = int(max_batch)
+        o.check_every = int(check_every)
+        keep = []
+        sx = None
+        if samples:
+            sp = np.ascontiguousarray(np.asarray(samples, dtype=np.int32).reshape(-1, 2))
+            sx = np.zeros((len(sp), self.n_pw), dtype=np.complex128)
+            keep += [sp, sx]
+            o.n_sample = len(sp)
+            o.sample_pairs = sp.ctypes.data_as(C.POINTER(C.c_int))
+            o.sample_x = sx.ctypes.data_as(C.POINTER(C.c_double))
+        nb = (self.n_occ if band_range is None else band_range[1] - band_range[0])
+        n_sol = max(n_pert * nb, 0)
+        iters = np.zeros(n_sol, dtype=np.int32)
+        resid = np.zeros(n_sol, dtype=np.float64)
+        st = Stats()
+        st.iters = iters.ctypes.data_as(C.POINTER(C.c_int))
+        st.resid = resid.ctypes.data_as(C.POINTER(C.c_double))
+        rc = _check(lib().stern_apply_chi0(self._h, n_pert, dp, op, C.byref(o), C.byref(st)))
+        info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
+                    total_iters=st.total_iters, max_iters=st.max_iters, wall_s=st.wall_s,
+                    max_true_resid=st.max_true_resid, iters=iters, resid=resid, samples=sx)
+        return dn_out, info
+
+    def apply_h(self, c, shift=None):
+        c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.complex128)
+        out = np.empty_like(c)
+        sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
+        _check(lib().stern_apply_h(self._h, c.shape[0], C.c_void_p(c.ctypes.data),
+                                   None if sh is None else C.c_void_p(sh.ctypes.data), C.c_void_p(out.ctypes.data),
+                                   STERN_MEM_HOST))
+        return out
+
+    def apply_pc(self, c):
+        c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.complex128)
+        out = np.empty_like(c)
+        _check(lib().stern_apply_pc(self._h, c.shape[0], C.c_void_p(c.ctypes.data), C.c_void_p(out.ctypes.data),
+                                    STERN_MEM_HOST))
+        return out
