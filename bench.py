@@ -1,0 +1,159 @@
+"""Benchmark: converged Sternheimer solves per second of one chi0 apply on one GPU.
+
+A step is one stern_apply_chi0 call on the mid cell (L = 20 bohr, 64 atoms,
+25 Ry: 16,879 plane waves, 72^3 grid, 128 occupied bands x 64 band-limited
+fields = 8,192 Sternheimer solves, FP64 true residual <= 1e-8), inputs already
+resident in HBM. Prints one JSON line with the throughput, the roofline of the
+dominant kernel (per-launch HIP events on the library's stream) and the CPU
+oracle timed on a bounded sample of the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {"plane_h": "fft.hip", "xinv": "fft.hip", "xfwd": "fft.hip", "rhs_plane": "fft.hip",
+                  "dn_plane": "fft.hip", "pc_reduce": "gemm.hip", "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip",
+                  "kb_expand": "gemm.hip", "sum_parts": "gemm.hip", "cg": "cg.hip"}
+
+
+def source_hash(kernel: str) -> str:
+    f = KERNEL_SOURCES.get(kernel)
+    if f is None:
+        return ""
+    with open(os.path.join(ROOT, "paper_2607_14025_amd", "csrc", f), "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()[:12]
+
+
+def measured_traffic(kernel: str):
+    """Per-launch HBM bytes of `kernel` from committed rocprofv3 counters, if the kernel source is unchanged."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    t = json.load(open(TRAFFIC_FILE)).get(kernel)
+    if not t or t.get("source_sha1") != source_hash(kernel):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(wl, n_bands: int, tol: float):
+    """The oracle on `n_bands` solves (bands 0.. of field 0): RHS, PCG and dn."""
+    from oracle import OracleCell, apply_chi0
+    spec = wl["spec"]
+    cell = OracleCell(spec.L, spec.ecut, wl["pos"])
+    psi = cell.take(wl["psi"], wl["miller"])
+    t0 = time.perf_counter()
+    out = apply_chi0(cell, psi, wl["eps"], wl["dv"][:1], tol=tol, bands=range(n_bands), perts=[0])
+    dt = time.perf_counter() - t0
+    return dict(value=n_bands / dt, unit="solves/s", cores=len(os.sched_getaffinity(0)), kind="oracle",
+                sample=f"{n_bands} (band, field) pairs of the same cell (bands 0-{n_bands - 1} of field 0): "
+                       f"RHS + projected Teter-PCG to true residual {tol:g} + dn, numpy/scipy FP64, "
+                       f"{dt:.1f} s, mean {out['iters'].mean():.1f} CG iterations")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--cpu-bands", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the chi0 apply of one cell runs on one MI355X); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2607_14025_amd import System
+    from synth.cells import MID
+    from synth.inputs import load_workload
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    print("bench: loading mid cell inputs", file=sys.stderr, flush=True)
+    wl = load_workload(MID)
+    spec = wl["spec"]
+    s = System(spec.L, spec.ecut, wl["pos"], spec.vloc_amp, spec.vloc_sigma, spec.kb_D, spec.kb_width, device=0)
+    psi = torch.from_numpy(np.ascontiguousarray(wl["psi"])).to(dev)
+    eps = torch.from_numpy(wl["eps"]).to(dev)
+    s.set_occupied(psi, eps)
+    dv = torch.from_numpy(wl["dv"]).to(dev)
+    dn = torch.empty_like(dv)
+    n_pert = dv.shape[0]
+    n_solves = n_pert * s.n_occ
+
+    for w in range(args.warmup):
+        _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn)
+        print(f"bench: warmup {w}: {info['n_converged']}/{info['n_solves']} converged in {info['wall_s']:.2f} s",
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    conv = 0
+    kern = {}
+    iters = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True)
+        conv += info["n_converged"]
+        iters.append(info["total_iters"] / max(1, info["n_solves"]))
+        for name, v in info["kernels"].items():
+            a = kern.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0, flops=0.0))
+            for f in a:
+                a[f] += v[f]
+        print(f"bench: step {k}: {info['n_converged']}/{info['n_solves']} converged, {info['wall_s']:.3f} s, "
+              f"max true resid {info['max_true_resid']:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    value = conv / dt
+
+    dom = max(kern, key=lambda n: kern[n]["ms"])
+    d = kern[dom]
+    per_launch_s = d["ms"] / d["launches"] / 1e3
+    traffic = measured_traffic(dom)
+    if d["flops"] > 0:
+        achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
+        roof = dict(bound="mfma", achieved=achieved, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s",
+                    frac=achieved / FP64_MFMA_PEAK_TFS, traffic=traffic, kernel=dom)
+    else:
+        achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=traffic, kernel=dom)
+    roof["launches"] = d["launches"]
+    roof["ms_per_launch"] = d["ms"] / d["launches"]
+    total_ms = sum(v["ms"] for v in kern.values())
+    breakdown = {n: dict(share=round(v["ms"] / total_ms, 4), ms_per_launch=round(v["ms"] / v["launches"], 4),
+                         GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
+                         TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["flops"] > 0 else None)
+                 for n, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(wl, args.cpu_bands, args.tol)
+
+    line = dict(metric="converged Sternheimer solves/s at resid<=1e-8", value=value, unit="solves/s", n_gpus=1,
+                steps=args.steps, warmup=args.warmup, ms_per_step=dt / args.steps * 1e3, higher_is_better=True,
+                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
+                config=dict(workload=spec.name, L_bohr=spec.L, ecut_ry=spec.ecut, atoms=spec.n_atoms, n_pw=s.n_pw,
+                            grid=s.fft_n, n_occ=s.n_occ, n_pert=n_pert, solves_per_step=n_solves, tol=args.tol,
+                            path="plain FP64 projected Teter-PCG", mean_cg_iters=float(np.mean(iters))),
+                roofline=roof, cpu_baseline=cpu, kernels=breakdown)
+    s.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

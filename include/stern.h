@@ -101,7 +101,25 @@ typedef struct {
   int n_sample;
   const int* sample_pairs;
   double* sample_x;
+  /* nonzero: time every kernel launch with HIP events on the library's stream
+     and report per-class totals in stern_stats (adds one event pair per launch) */
+  int profile;
 } stern_opts;
+
+/* kernel classes of the per-launch profile */
+#define STERN_K_XINV 0        /* x pencils, inverse (sphere -> pencils) */
+#define STERN_K_PLANE_H 1     /* yz planes of the H apply (inverse, x V_loc, forward) */
+#define STERN_K_XFWD 2        /* x pencils, forward (pencils -> sphere, + kinetic - eps) */
+#define STERN_K_PC_REDUCE 3   /* C = Psi^H Y partial sums (MFMA) */
+#define STERN_K_PC_EXPAND 4   /* Y -= Psi C (MFMA) */
+#define STERN_K_KB_REDUCE 5   /* P = B^H p (MFMA) */
+#define STERN_K_KB_EXPAND 6   /* w += B D P (MFMA) */
+#define STERN_K_SUM_PARTS 7   /* split-K partial sums */
+#define STERN_K_CG 8          /* fused CG vector updates and FP64 dots */
+#define STERN_K_RHS 9         /* yz planes of dV psi_v (right-hand side) */
+#define STERN_K_DN 10         /* yz planes of the density response accumulation */
+#define STERN_K_OTHER 11
+#define STERN_NKERNEL 12
 
 typedef struct {
   int n_solves;        /* (band, perturbation) pairs solved */
@@ -113,6 +131,13 @@ typedef struct {
   double max_true_resid;
   int* iters;          /* optional caller array [n_solves] (pair order: i major, v minor) */
   double* resid;       /* optional caller array [n_solves] */
+  /* filled when opts->profile != 0, per STERN_K_* class: launches, summed
+     event time (ms), and the algorithmic HBM bytes / real flops of those
+     launches (the minimum the operation must move or compute) */
+  long long kernel_launches[STERN_NKERNEL];
+  double kernel_ms[STERN_NKERNEL];
+  double kernel_bytes[STERN_NKERNEL];
+  double kernel_flops[STERN_NKERNEL];
 } stern_stats;
 
 /* Host only, no GPU needed: basis size, FFT grid and (if miller != NULL) the

@@ -99,6 +99,17 @@ struct stern_system {
       sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
   int ws_solves = 0;
 
+  // per-launch event profile (opts->profile)
+  struct Rec {
+    int cls;
+    int ev;
+    double bytes, flops;
+  };
+  bool prof_on = false;
+  std::vector<hipEvent_t> events;
+  std::vector<Rec> recs;
+  size_t ev_used = 0;
+
   FftGeom geom() const {
     FftGeom g;
     g.N = hb.N;
@@ -125,10 +136,34 @@ struct stern_system {
                    &sv_rr,     &sv_flag,  &sv_iters, &sv_tres, &list_act, &list_f,  &pert_out, &dv_dev,   &dn_dev,
                    &tmp_in,    &tmp_out};
     for (DBuf* d : all) d->release();
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    events.clear();
   }
 };
 
 namespace {
+
+// Launches `launch` on the system stream; with profiling on, brackets it with
+// an event pair and records the algorithmic bytes and flops of the launch.
+template <class F>
+int timed(stern_system* S, int cls, double bytes, double flops, F&& launch) {
+  if (!S->prof_on) {
+    launch();
+    return 0;
+  }
+  while (S->events.size() < S->ev_used + 2) {
+    hipEvent_t e;
+    HIPOK(hipEventCreate(&e));
+    S->events.push_back(e);
+  }
+  const int ev = (int)S->ev_used;
+  S->ev_used += 2;
+  HIPOK(hipEventRecord(S->events[ev], S->stream));
+  launch();
+  HIPOK(hipEventRecord(S->events[ev + 1], S->stream));
+  S->recs.push_back({cls, ev, bytes, flops});
+  return 0;
+}
 
 // ---- operator pieces on solve rows `list` (device ints) of batch buffers ----
 
@@ -136,10 +171,17 @@ namespace {
 int apply_pc_rows(stern_system* S, Z64* Y, const int* list, int n) {
   if (n <= 0) return 0;
   const int K = S->hb.npw_pad;
+  const double npw = S->hb.npw, m = S->n_occ, zb = sizeof(Z64);
   const int ns = choose_nsplit(S->nocc_pad, n, K);
-  launch_zgemm_reduce(S->psi.as<Z64>(), S->nocc_pad, Y, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
-  launch_sum_parts(S->cpart.as<Z64>(), ns, n, S->nocc_pad, -1.0, S->cmat.as<Z64>(), S->stream);
-  launch_zgemm_expand(S->psi.as<Z64>(), S->nocc_pad, S->cmat.as<Z64>(), Y, K, list, n, K, S->stream);
+  CHECKED(timed(S, STERN_K_PC_REDUCE, zb * npw * (n + m), 8.0 * m * npw * n, [&] {
+    launch_zgemm_reduce(S->psi.as<Z64>(), S->nocc_pad, Y, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_SUM_PARTS, zb * m * n * (ns + 1), 0.0, [&] {
+    launch_sum_parts(S->cpart.as<Z64>(), ns, n, S->nocc_pad, -1.0, S->cmat.as<Z64>(), S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_PC_EXPAND, zb * npw * (2.0 * n + m), 8.0 * m * npw * n, [&] {
+    launch_zgemm_expand(S->psi.as<Z64>(), S->nocc_pad, S->cmat.as<Z64>(), Y, K, list, n, K, S->stream);
+  }));
   return 0;
 }
 
@@ -148,14 +190,25 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
   if (n <= 0) return 0;
   const FftGeom g = S->geom();
   const int K = S->hb.npw_pad;
-  launch_xinv(g, in, list, n, S->pen.as<Z64>(), S->stream);
-  launch_plane_vloc(g, S->pen.as<Z64>(), list, n, S->v_r.as<double>(), S->stream);
-  launch_xfwd(g, S->pen.as<Z64>(), list, n, out, 1, in, eps_rows, 0.0, S->stream);
+  const double zb = sizeof(Z64), npw = S->hb.npw, N = S->hb.N, pen = N * S->hb.ncol * zb;
+  CHECKED(timed(S, STERN_K_XINV, n * (npw * zb + pen), 0.0,
+                [&] { launch_xinv(g, in, list, n, S->pen.as<Z64>(), S->stream); }));
+  CHECKED(timed(S, STERN_K_PLANE_H, n * 2.0 * pen + N * N * N * sizeof(double), 0.0,
+                [&] { launch_plane_vloc(g, S->pen.as<Z64>(), list, n, S->v_r.as<double>(), S->stream); }));
+  CHECKED(timed(S, STERN_K_XFWD, n * (pen + 2.0 * npw * zb), 0.0,
+                [&] { launch_xfwd(g, S->pen.as<Z64>(), list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
   if (S->n_atoms > 0) {
+    const double na = S->n_atoms;
     const int ns = choose_nsplit(S->natoms_pad, n, K);
-    launch_zgemm_reduce(S->kb.as<Z64>(), S->natoms_pad, in, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
-    launch_sum_parts(S->cpart.as<Z64>(), ns, n, S->natoms_pad, S->cell.D, S->cmat.as<Z64>(), S->stream);
-    launch_zgemm_expand(S->kb.as<Z64>(), S->natoms_pad, S->cmat.as<Z64>(), out, K, list, n, K, S->stream);
+    CHECKED(timed(S, STERN_K_KB_REDUCE, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
+      launch_zgemm_reduce(S->kb.as<Z64>(), S->natoms_pad, in, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
+    }));
+    CHECKED(timed(S, STERN_K_SUM_PARTS, zb * na * n * (ns + 1), 0.0, [&] {
+      launch_sum_parts(S->cpart.as<Z64>(), ns, n, S->natoms_pad, S->cell.D, S->cmat.as<Z64>(), S->stream);
+    }));
+    CHECKED(timed(S, STERN_K_KB_EXPAND, zb * npw * (2.0 * n + na), 8.0 * na * npw * n, [&] {
+      launch_zgemm_expand(S->kb.as<Z64>(), S->natoms_pad, S->cmat.as<Z64>(), out, K, list, n, K, S->stream);
+    }));
   }
   return 0;
 }
@@ -487,6 +540,10 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
   const int check_every = opts->check_every > 0 ? opts->check_every : 4;
   const double tol = opts->tol;
+  const double vecb = (double)hb.npw * sizeof(Z64);  // bytes of one coefficient vector
+  S->prof_on = opts->profile != 0;
+  S->recs.clear();
+  S->ev_used = 0;
 
   // perturbations per batch
   int per = opts->max_batch > 0 ? std::max(1, opts->max_batch / nb) : 0;
@@ -542,9 +599,13 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
     HIPOK(hipMemcpyAsync(S->sv_eps.p, h_eps.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
     HIPOK(hipMemcpyAsync(S->sv_invT.p, h_invT.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
     // b = -P_c [dV psi_v]
-    launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, S->sv_band.as<int>(), S->sv_pert.as<int>(), ns,
-                     S->pen.as<Z64>(), st);
-    launch_xfwd(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
+    CHECKED(timed(S, STERN_K_RHS, ns * ((double)n3 * 24.0 + (double)N * hb.ncol * 16.0), 0.0, [&] {
+      launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, S->sv_band.as<int>(), S->sv_pert.as<int>(), ns,
+                       S->pen.as<Z64>(), st);
+    }));
+    CHECKED(timed(S, STERN_K_XFWD, ns * ((double)N * hb.ncol * 16.0 + vecb), 0.0, [&] {
+      launch_xfwd(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
+    }));
     CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
     launch_cg_init(cs, nullptr, ns, st);
     CHECKED(apply_pc_rows(S, cs.z, nullptr, ns));
@@ -564,9 +625,9 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
       for (int k = 0; k < nsteps; ++k) {
         CHECKED(apply_h_rows(S, cs.p, cs.q, L, na, cs.eps));
         CHECKED(apply_pc_rows(S, cs.q, L, na));
-        launch_cg_alpha(cs, L, na, tol * tol, st);
+        CHECKED(timed(S, STERN_K_CG, vecb * na * 7.0, 0.0, [&] { launch_cg_alpha(cs, L, na, tol * tol, st); }));
         CHECKED(apply_pc_rows(S, cs.z, L, na));
-        launch_cg_beta(cs, L, na, st);
+        CHECKED(timed(S, STERN_K_CG, vecb * na * 4.0, 0.0, [&] { launch_cg_beta(cs, L, na, st); }));
       }
       it += nsteps;
       CHECKED(launch_check());
@@ -600,9 +661,14 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
       act.swap(nxt);
     }
     // dn_i = 4/Omega Re sum_v conj(psi_v(r)) x_{v,i}(r)
-    launch_xinv(g, cs.x, nullptr, ns, S->pen.as<Z64>(), st);
-    launch_plane_dn(g, S->pen.as<Z64>(), S->psi_r.as<Z64>(), v0, nb, i1 - i0, S->pert_out.as<int>() + i0,
-                    4.0 / hb.omega, dn_dev, st);
+    CHECKED(timed(S, STERN_K_XINV, ns * (vecb + (double)N * hb.ncol * 16.0), 0.0,
+                  [&] { launch_xinv(g, cs.x, nullptr, ns, S->pen.as<Z64>(), st); }));
+    CHECKED(timed(S, STERN_K_DN,
+                  ns * (double)N * hb.ncol * 16.0 + (double)(i1 - i0) * nb * n3 * 16.0 + (double)(i1 - i0) * n3 * 8.0,
+                  0.0, [&] {
+                    launch_plane_dn(g, S->pen.as<Z64>(), S->psi_r.as<Z64>(), v0, nb, i1 - i0,
+                                    S->pert_out.as<int>() + i0, 4.0 / hb.omega, dn_dev, st);
+                  }));
     CHECKED(launch_check());
     // per-solve statistics
     std::vector<int> hi(ns);
@@ -628,6 +694,22 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   if (opts->mem_kind == STERN_MEM_HOST)
     HIPOK(hipMemcpyAsync(dn_r, dn_dev, (size_t)n_pert * n3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
+  if (stats) {
+    for (int k = 0; k < STERN_NKERNEL; ++k) {
+      stats->kernel_launches[k] = 0;
+      stats->kernel_ms[k] = stats->kernel_bytes[k] = stats->kernel_flops[k] = 0.0;
+    }
+    for (const auto& r : S->recs) {
+      float ms = 0.f;
+      HIPOK(hipEventElapsedTime(&ms, S->events[r.ev], S->events[r.ev + 1]));
+      stats->kernel_launches[r.cls] += 1;
+      stats->kernel_ms[r.cls] += ms;
+      stats->kernel_bytes[r.cls] += r.bytes;
+      stats->kernel_flops[r.cls] += r.flops;
+    }
+  }
+  S->prof_on = false;
+  S->recs.clear();
   const int nsol = (int)all_iters.size();
   int nconv = 0, mx = 0;
   double mres = 0.0;
