@@ -25,7 +25,7 @@ def _lib_or_skip():
 
 def test_library_exports_every_declared_symbol():
     L = _lib_or_skip()
-    decl = set(re.findall(r"\b(stern_[a-z0-9_]+)\s*\(", open(HEADER).read()))
+    decl = set(re.findall(r"^(?:int|void|const char\*)\s+(stern_[a-z0-9_]+)\s*\(", open(HEADER).read(), re.M))
     assert decl, "no declarations parsed"
     assert decl == set(stern.EXPORTED)
     for name in decl:
