@@ -87,6 +87,18 @@ std::string build_basis(const CellParams& c, HostBasis& hb) {
   for (int nz = -nm; nz <= nm; ++nz) hb.zl.push_back(imod(nz, N));
   std::sort(hb.zl.begin(), hb.zl.end());
   hb.nza = (int)hb.zl.size();
+  hb.zact_lo = nm;
+  hb.zact_hi = N - nm;
+  hb.ycol.assign((size_t)hb.nza * N, -1);
+  for (int f = 0; f < hb.nza; ++f) {
+    const int iz = hb.zl[f];
+    const int nz = (2 * iz < N) ? iz : iz - N;
+    for (int iy = 0; iy < N; ++iy) {
+      const int ny = (2 * iy < N) ? iy : iy - N;
+      if (ny < -nm || ny > nm) continue;
+      hb.ycol[(size_t)iy * hb.nza + f] = colid[(ny + nm) * (2 * nm + 1) + (nz + nm)];
+    }
+  }
 
   hb.perm.resize(hb.npw);
   hb.g2h.assign(hb.npw_pad, 0.0);

@@ -25,6 +25,8 @@ struct HostBasis {
   std::vector<int> col_start, col_len, col_xmin;  // [ncol_pad]
   std::vector<int> col_pos;      // [ncol]
   std::vector<int> zl;           // [nza]
+  std::vector<int> ycol;         // [N][nza] column of (iy, zl[f]) or -1
+  int zact_lo = 0, zact_hi = 0;  // active z lines: iz <= zact_lo or iz >= zact_hi
   std::vector<double> g2h;       // [npw_pad], column order
 };
 

@@ -1,8 +1,19 @@
 // Pruned 3-D FFT kernels of the H apply, the right-hand side and the density
-// response, FP64. A vector on the plane-wave sphere goes through
-//   x pass:  per x-pencil column (n_y, n_z) of the sphere, length-N DFT along x
-//   yz pass: per plane ix, 2-D DFT over the columns' (iy, iz) positions
-// so only the sphere's columns are ever read from or written to HBM.
+// response. A vector on the plane-wave sphere goes through
+//   x pass:  per x-pencil column (n_y, n_z) of the sphere, a length-N DFT along x
+//   yz pass: per plane ix, a 2-D DFT over the columns' (iy, iz) positions
+// so HBM only ever holds the sphere and its columns, never the N^3 box.
+//
+// Every length-N transform is two Stockham stages N = R1 * R2 done in
+// registers with one LDS exchange between them. The first stage of a pass
+// gathers straight from global memory and the last scatters straight to it.
+// In the yz pass of the H apply the inverse transform along z ends with the
+// radix-R2 stage over the elements {j + r R1}; the forward transform is run
+// with the reversed plan (R2 first), whose first stage consumes exactly those
+// elements, so inverse stage 2, the V_loc multiply and forward stage 1 happen
+// in registers without an LDS round trip.
+#include <algorithm>
+
 #include "fft_dev.hpp"
 #include "kernels.hpp"
 
@@ -10,246 +21,520 @@ namespace stern {
 
 namespace {
 
-template <int N>
-constexpr int plane_threads() {
-  return N >= 48 ? 512 : 256;
+// threads of a yz-plane workgroup: enough for one item per thread in the row
+// stages, capped so that the FP64 kernels keep 2 waves per SIMD (256 VGPRs)
+template <int N, class T = double>
+constexpr int plane_nt() {
+  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  constexpr int m = N * (R1 > R2 ? R1 : R2);
+  constexpr int r = (m + 63) / 64 * 64;
+  constexpr int cap = sizeof(T) == 8 ? 512 : 768;
+  return r < 256 ? 256 : (r > cap ? cap : r);
 }
-constexpr int kXThreads = 128;
+constexpr int kXThreads = 256;
+
+template <class T>
+__device__ __forceinline__ const Z<T>* twtab(const FftGeom& g);
+template <>
+__device__ __forceinline__ const Z64* twtab<double>(const FftGeom& g) { return g.tw64; }
+template <>
+__device__ __forceinline__ const Z32* twtab<float>(const FftGeom& g) { return g.tw32; }
+
+// One radix-R Stockham stage of length-N transforms over F lines. Item (f, j)
+// with j < N/R loads v[r] = ld(f, j, r), applies exp(DIR 2 pi i r j / N) when
+// TWID, transforms and stores st(f, j, r, v[r]). LINE_FAST orders items with
+// the line index fastest. SYNC puts a barrier between all loads and all
+// stores (for stages that read and write different LDS positions).
+template <int N, int R, int DIR, bool TWID, bool SYNC, bool LINE_FAST, int NT, int MAXF, class T, class Ld,
+          class St>
+__device__ __forceinline__ void stage(int F, Ld ld, St st, const Z<T>* __restrict__ tw) {
+  constexpr int J = N / R;
+  const int tid = threadIdx.x;
+  // item -> (line f, index j)
+  auto line_of = [F](int it) { return LINE_FAST ? it % F : it / J; };
+  auto idx_of = [F](int it) { return LINE_FAST ? it / F : it % J; };
+  if constexpr (SYNC) {
+    constexpr int MAXIT = (MAXF * J + NT - 1) / NT;
+    Z<T> v[MAXIT][R];
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+      const int it = tid + k * NT;
+      if (it < F * J) {
+        const int f = line_of(it), j = idx_of(it);
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k][r] = ld(f, j, r);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+      const int it = tid + k * NT;
+      if (it < F * J) {
+        const int f = line_of(it), j = idx_of(it);
+        if constexpr (TWID) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) v[k][r] = v[k][r] * twid<DIR>(tw, r * j);
+        }
+        dft<R, DIR>(v[k]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) st(f, j, r, v[k][r]);
+      }
+    }
+  } else {
+    for (int it = tid; it < F * J; it += NT) {
+      const int f = line_of(it), j = idx_of(it);
+      Z<T> v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = ld(f, j, r);
+      if constexpr (TWID) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = v[r] * twid<DIR>(tw, r * j);
+      }
+      dft<R, DIR>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) st(f, j, r, v[r]);
+    }
+  }
+}
 
 // ---------------------------------------------------------------- x pass ----
-template <int N>
-__global__ __launch_bounds__(kXThreads) void k_xinv(const Z64* __restrict__ sph, const int* __restrict__ vidx,
-                                                    Z64* __restrict__ pen, FftGeom g) {
+// inverse: sphere coefficients -> pencils [vec][ix][ncol_pad]
+template <int N, class T>
+__global__ __launch_bounds__(kXThreads) void k_xinv(const Z<T>* __restrict__ sph, const int* __restrict__ vidx,
+                                                    Z<T>* __restrict__ pen, FftGeom g) {
   constexpr int CB = kColBlock, LDX = N + 1;
-  __shared__ Z64 P[CB * LDX];
+  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  __shared__ Z<T> P[CB * LDX];
+  const Z<T>* tw = twtab<T>(g);
   const int c0 = blockIdx.x * CB;
   const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
-  for (int i = threadIdx.x; i < CB * LDX; i += kXThreads) P[i] = zmk(0.0, 0.0);
+  const Z<T>* src = sph + (size_t)vec * g.npw_pad;
+  const int* __restrict__ cstart = g.col_start;
+  const int* __restrict__ clen = g.col_len;
+  const int* __restrict__ cxmin = g.col_xmin;
+  stage<N, R1, +1, false, false, true, kXThreads, CB>(
+      CB,
+      [&](int cc, int j, int r) {
+        const int x = j + r * R2;
+        const int nx = (2 * x < N) ? x : x - N;
+        const int t = nx - cxmin[c0 + cc];
+        Z<T> v = zmk(T(0), T(0));
+        if (t >= 0 && t < clen[c0 + cc]) v = src[cstart[c0 + cc] + t];
+        return v;
+      },
+      [&](int cc, int j, int r, Z<T> v) { P[cc * LDX + j * R1 + r] = v; }, tw);
   __syncthreads();
-  const Z64* src = sph + (size_t)vec * g.npw_pad;
-  for (int i = threadIdx.x; i < CB * N; i += kXThreads) {
-    const int cc = i / N, t = i - cc * N;
-    const int c = c0 + cc;
-    if (t < g.col_len[c]) {
-      int nx = g.col_xmin[c] + t;
-      nx += (nx < 0) ? N : 0;
-      P[cc * LDX + nx] = src[g.col_start[c] + t];
-    }
-  }
-  __syncthreads();
-  fft_lines<N, +1, kXThreads, CB>(P, CB, 1, [](int f) { return f * LDX; }, NoPost{}, g.tw64);
-  Z64* dst = pen + (size_t)vec * N * g.ncol_pad + c0;
-  for (int i = threadIdx.x; i < CB * N; i += kXThreads) {
-    const int ix = i / CB, cc = i - ix * CB;
-    dst[(size_t)ix * g.ncol_pad + cc] = P[cc * LDX + ix];
-  }
+  Z<T>* dst = pen + (size_t)vec * N * g.ncol_pad + c0;
+  const int ld = g.ncol_pad;
+  stage<N, R2, +1, true, false, true, kXThreads, CB>(
+      CB, [&](int cc, int j, int r) { return P[cc * LDX + j + r * R1]; },
+      [&](int cc, int j, int r, Z<T> v) { dst[(size_t)(j + r * R1) * ld + cc] = v; }, tw);
 }
 
-template <int N, int MODE>
-__global__ __launch_bounds__(kXThreads) void k_xfwd(const Z64* __restrict__ pen, const int* __restrict__ vidx,
-                                                    Z64* __restrict__ out, const Z64* __restrict__ pin,
+// forward: pencils -> sphere; MODE 0 plain, 1 adds (|G|^2/2 - eps) pin, 2 scales
+template <int N, class T, int MODE>
+__global__ __launch_bounds__(kXThreads) void k_xfwd(const Z<T>* __restrict__ pen, const int* __restrict__ vidx,
+                                                    Z<T>* __restrict__ out, const Z<T>* __restrict__ pin,
                                                     const double* __restrict__ eps, double scale, FftGeom g) {
   constexpr int CB = kColBlock, LDX = N + 1;
-  __shared__ Z64 P[CB * LDX];
+  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  __shared__ Z<T> P[CB * LDX];
+  const Z<T>* tw = twtab<T>(g);
   const int c0 = blockIdx.x * CB;
   const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
-  const Z64* src = pen + (size_t)vec * N * g.ncol_pad + c0;
-  for (int i = threadIdx.x; i < CB * N; i += kXThreads) {
-    const int ix = i / CB, cc = i - ix * CB;
-    P[cc * LDX + ix] = src[(size_t)ix * g.ncol_pad + cc];
-  }
+  const Z<T>* src = pen + (size_t)vec * N * g.ncol_pad + c0;
+  const int ld = g.ncol_pad;
+  stage<N, R1, -1, false, false, true, kXThreads, CB>(
+      CB, [&](int cc, int j, int r) { return src[(size_t)(j + r * R2) * ld + cc]; },
+      [&](int cc, int j, int r, Z<T> v) { P[cc * LDX + j * R1 + r] = v; }, tw);
   __syncthreads();
-  fft_lines<N, -1, kXThreads, CB>(P, CB, 1, [](int f) { return f * LDX; }, NoPost{}, g.tw64);
-  Z64* dst = out + (size_t)vec * g.npw_pad;
-  const Z64* pv = (MODE == 1) ? pin + (size_t)vec * g.npw_pad : nullptr;
-  const double e = (MODE == 1) ? eps[vec] : 0.0;
-  for (int i = threadIdx.x; i < CB * N; i += kXThreads) {
-    const int cc = i / N, t = i - cc * N;
-    const int c = c0 + cc;
-    if (t < g.col_len[c]) {
-      int nx = g.col_xmin[c] + t;
-      nx += (nx < 0) ? N : 0;
-      const int gi = g.col_start[c] + t;
-      Z64 v = P[cc * LDX + nx];
-      if (MODE == 1) {
-        const double d = g.g2h[gi] - e;
-        const Z64 pp = pv[gi];
-        v = zmk(v.re + d * pp.re, v.im + d * pp.im);
-      } else if (MODE == 2) {
-        v = zscale(v, scale);
-      }
-      dst[gi] = v;
-    }
-  }
+  Z<T>* dst = out + (size_t)vec * g.npw_pad;
+  const Z<T>* pv = (MODE == 1) ? pin + (size_t)vec * g.npw_pad : nullptr;
+  const T e = (MODE == 1) ? T(eps[vec]) : T(0);
+  const T sc = T(scale);
+  const int* __restrict__ cstart = g.col_start;
+  const int* __restrict__ clen = g.col_len;
+  const int* __restrict__ cxmin = g.col_xmin;
+  const double* __restrict__ g2h = g.g2h;
+  stage<N, R2, -1, true, false, true, kXThreads, CB>(
+      CB, [&](int cc, int j, int r) { return P[cc * LDX + j + r * R1]; },
+      [&](int cc, int j, int r, Z<T> v) {
+        const int x = j + r * R1;
+        const int nx = (2 * x < N) ? x : x - N;
+        const int t = nx - cxmin[c0 + cc];
+        if (t >= 0 && t < clen[c0 + cc]) {
+          const int gi = cstart[c0 + cc] + t;
+          if (MODE == 1) {
+            const T d = T(g2h[gi]) - e;
+            const Z<T> pp = pv[gi];
+            v = zmk(v.re + d * pp.re, v.im + d * pp.im);
+          } else if (MODE == 2) {
+            v = zscale(v, sc);
+          }
+          dst[gi] = v;
+        }
+      },
+      tw);
 }
 
 // --------------------------------------------------------------- yz pass ----
-template <int N>
-__device__ __forceinline__ void plane_scatter(Z64* P, const Z64* __restrict__ src, const FftGeom& g, int NT) {
-  constexpr int LD = N + 1;
-  for (int c = threadIdx.x; c < g.ncol; c += NT) {
-    const int p = g.col_pos[c];
-    const int iy = p / N, iz = p - iy * N;
-    P[iy * LD + iz] = src[c];
-  }
+// Shared pieces. The plane is P[iy * LD + iz]; the active z lines are the
+// grid columns iz holding sphere data (iz <= zlo or iz >= zhi); yc[iy * nza + f]
+// is the pencil column of (iy, zl[f]) or -1 outside the sphere's disk, laid out
+// [iy][f] so that lanes walking the lines read consecutive entries.
+template <int N, class T>
+struct PlaneCtx {
+  static constexpr int LD = N + 1;
+  static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  static constexpr int NT = plane_nt<N, T>();
+  Z<T>* P;
+  const int* __restrict__ zl;
+  const int* __restrict__ yc;
+  int nza, zlo, zhi;
+  const Z<T>* tw;
+  __device__ bool zact(int z) const { return z <= zlo || z >= zhi; }
+};
+
+// The twiddle table is copied behind the plane in LDS (N entries); the copy is
+// ordered before its first use by the barrier that follows the first stage.
+template <int N, class T>
+__device__ __forceinline__ const Z<T>* plane_twiddles(unsigned char* smem, const FftGeom& g) {
+  Z<T>* t = reinterpret_cast<Z<T>*>(smem) + N * PlaneCtx<N, T>::LD;
+  const Z<T>* src = twtab<T>(g);
+  for (int i = threadIdx.x; i < N; i += blockDim.x) t[i] = src[i];
+  return t;
 }
 
-template <int N>
-__device__ __forceinline__ void plane_zero(Z64* P, int NT) {
-  constexpr int LD = N + 1;
-  for (int i = threadIdx.x; i < N * LD; i += NT) P[i] = zmk(0.0, 0.0);
+// pencils of one plane -> inverse DFT along y on the active z lines (in LDS)
+template <int N, class T>
+__device__ __forceinline__ void y_inverse_from_pencils(const PlaneCtx<N, T>& c, const Z<T>* __restrict__ tp) {
+  constexpr int LD = PlaneCtx<N, T>::LD, R1 = PlaneCtx<N, T>::R1, R2 = PlaneCtx<N, T>::R2, NT = PlaneCtx<N, T>::NT;
+  Z<T>* P = c.P;
+  const int* zl = c.zl;
+  const int* yc = c.yc;
+  const Z<T> zero = zmk(T(0), T(0));
+  stage<N, R1, +1, false, false, true, NT, N / 2 + 1>(
+      c.nza,
+      [&](int f, int j, int r) {
+        const int col = yc[(j + r * R2) * c.nza + f];
+        Z<T> v = zero;
+        if (col >= 0) v = tp[col];
+        return v;
+      },
+      [&](int f, int j, int r, Z<T> v) { P[(j * R1 + r) * LD + zl[f]] = v; }, c.tw);
+  __syncthreads();
+  stage<N, R2, +1, true, false, true, NT, N / 2 + 1>(
+      c.nza, [&](int f, int j, int r) { return P[(j + r * R1) * LD + zl[f]]; },
+      [&](int f, int j, int r, Z<T> v) { P[(j + r * R1) * LD + zl[f]] = v; }, c.tw);
+  __syncthreads();
 }
 
-template <int N>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_vloc(Z64* __restrict__ pen, const int* __restrict__ vidx,
-                                                                  const double* __restrict__ v_r, FftGeom g) {
-  constexpr int NT = plane_threads<N>(), LD = N + 1;
+// forward DFT along y on the active z lines (in LDS) -> pencils of one plane
+template <int N, class T>
+__device__ __forceinline__ void y_forward_to_pencils(const PlaneCtx<N, T>& c, Z<T>* __restrict__ tp) {
+  constexpr int LD = PlaneCtx<N, T>::LD, R1 = PlaneCtx<N, T>::R1, R2 = PlaneCtx<N, T>::R2, NT = PlaneCtx<N, T>::NT;
+  Z<T>* P = c.P;
+  const int* zl = c.zl;
+  const int* yc = c.yc;
+  stage<N, R1, -1, false, true, true, NT, N / 2 + 1>(
+      c.nza, [&](int f, int j, int r) { return P[(j + r * R2) * LD + zl[f]]; },
+      [&](int f, int j, int r, Z<T> v) { P[(j * R1 + r) * LD + zl[f]] = v; }, c.tw);
+  __syncthreads();
+  stage<N, R2, -1, true, false, true, NT, N / 2 + 1>(
+      c.nza, [&](int f, int j, int r) { return P[(j + r * R1) * LD + zl[f]]; },
+      [&](int f, int j, int r, Z<T> v) {
+        const int col = yc[(j + r * R1) * c.nza + f];
+        if (col >= 0) tp[col] = v;
+      },
+      c.tw);
+}
+
+// inverse stage 1 along z on every row (inputs outside the active lines are zero)
+template <int N, class T>
+__device__ __forceinline__ void z_inverse_stage1(const PlaneCtx<N, T>& c) {
+  constexpr int LD = PlaneCtx<N, T>::LD, R1 = PlaneCtx<N, T>::R1, R2 = PlaneCtx<N, T>::R2, NT = PlaneCtx<N, T>::NT;
+  Z<T>* P = c.P;
+  const Z<T> zero = zmk(T(0), T(0));
+  stage<N, R1, +1, false, true, false, NT, N>(
+      N,
+      [&](int y, int j, int r) {
+        const int z = j + r * R2;
+        return c.zact(z) ? P[y * LD + z] : zero;
+      },
+      [&](int y, int j, int r, Z<T> v) { P[y * LD + j * R1 + r] = v; }, c.tw);
+  __syncthreads();
+}
+
+// LDS of the H-apply plane kernel: the plane, the twiddles and (when it fits
+// in 160 KiB) the V_loc plane.
+template <int N, class T>
+constexpr size_t vloc_lds_bytes(bool with_v) {
+  return ((size_t)N * (N + 1) + N) * sizeof(Z<T>) + (with_v ? (size_t)N * (N + 1) * sizeof(T) : 0);
+}
+template <int N, class T>
+constexpr bool vloc_v_in_lds() {
+  return vloc_lds_bytes<N, T>(true) <= 160 * 1024;
+}
+
+// H apply, in place on the pencils of vectors vidx[b] (b < nvec): for each
+// plane, inverse y, inverse z, x V_loc, forward z, forward y.
+//
+// Persistent and software-pipelined: workgroup w walks the (plane, vector)
+// pairs q = w, w + gridDim.x, ... in plane-major order and, while the row
+// stages of pair q run, already has the pencil loads of pair q + gridDim.x in
+// flight in registers; V_loc(ix, :, :) is re-staged in LDS only when the plane
+// changes. Row stages take the row index as the fast lane index, so LDS
+// accesses stride by N + 1 elements and avoid bank conflicts.
+template <int N, class T>
+__global__ __launch_bounds__((plane_nt<N, T>())) void k_plane_vloc(Z<T>* __restrict__ pen, const int* __restrict__ vidx,
+                                                             int nvec, const T* __restrict__ v_r, FftGeom g) {
+  using C = PlaneCtx<N, T>;
+  constexpr int LD = C::LD, R1 = C::R1, R2 = C::R2, NT = C::NT;
+  constexpr bool VL = vloc_v_in_lds<N, T>();
+  constexpr int MAXA = ((N / 2 + 1) * R2 + NT - 1) / NT;  // first-stage items per thread (nza <= N/2 + 1)
   extern __shared__ unsigned char smem_raw[];
-  Z64* P = reinterpret_cast<Z64*>(smem_raw);
-  const int ix = blockIdx.x;
-  const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
-  Z64* tp = pen + ((size_t)vec * N + ix) * g.ncol_pad;
-  plane_zero<N>(P, NT);
-  __syncthreads();
-  plane_scatter<N>(P, tp, g, NT);
-  __syncthreads();
-  const int* zl = g.zl;
-  auto zline = [zl](int f) { return zl[f]; };
-  auto row = [](int f) { return f * LD; };
-  fft_lines<N, +1, NT, N>(P, g.nza, LD, zline, NoPost{}, g.tw64);
-  const double* vp = v_r + (size_t)ix * N * N;
-  fft_lines<N, +1, NT, N>(
-      P, N, 1, row, [vp](int f, int n, int, int, Z64 v) { return zscale(v, vp[f * N + n]); }, g.tw64);
-  fft_lines<N, -1, NT, N>(P, N, 1, row, NoPost{}, g.tw64);
-  fft_lines<N, -1, NT, N>(P, g.nza, LD, zline, NoPost{}, g.tw64);
-  for (int c = threadIdx.x; c < g.ncol; c += NT) {
-    const int p = g.col_pos[c];
-    const int iy = p / N, iz = p - iy * N;
-    tp[c] = P[iy * LD + iz];
-  }
-}
-
-template <int N>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_rhs(const Z64* __restrict__ psi_r,
-                                                                 const double* __restrict__ dv,
-                                                                 const int* __restrict__ band,
-                                                                 const int* __restrict__ pert,
-                                                                 Z64* __restrict__ pen, FftGeom g) {
-  constexpr int NT = plane_threads<N>(), LD = N + 1;
-  extern __shared__ unsigned char smem_raw[];
-  Z64* P = reinterpret_cast<Z64*>(smem_raw);
-  const int ix = blockIdx.x;
-  const int s = blockIdx.y;
-  const Z64* ps = psi_r + ((size_t)band[s] * N + ix) * N * N;
-  const double* dp = dv + ((size_t)pert[s] * N + ix) * N * N;
-  for (int i = threadIdx.x; i < N * N; i += NT) {
-    const int iy = i / N, iz = i - iy * N;
-    P[iy * LD + iz] = zscale(ps[i], dp[i]);
-  }
-  __syncthreads();
-  auto row = [](int f) { return f * LD; };
-  const int* zl = g.zl;
-  fft_lines<N, -1, NT, N>(P, N, 1, row, NoPost{}, g.tw64);
-  fft_lines<N, -1, NT, N>(P, g.nza, LD, [zl](int f) { return zl[f]; }, NoPost{}, g.tw64);
-  Z64* tp = pen + ((size_t)s * N + ix) * g.ncol_pad;
-  for (int c = threadIdx.x; c < g.ncol; c += NT) {
-    const int p = g.col_pos[c];
-    const int iy = p / N, iz = p - iy * N;
-    tp[c] = P[iy * LD + iz];
-  }
-}
-
-template <int N>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_full_inv(const Z64* __restrict__ pen,
-                                                                      Z64* __restrict__ out, FftGeom g) {
-  constexpr int NT = plane_threads<N>(), LD = N + 1;
-  extern __shared__ unsigned char smem_raw[];
-  Z64* P = reinterpret_cast<Z64*>(smem_raw);
-  const int ix = blockIdx.x;
-  const int vec = blockIdx.y;
-  plane_zero<N>(P, NT);
-  __syncthreads();
-  plane_scatter<N>(P, pen + ((size_t)vec * N + ix) * g.ncol_pad, g, NT);
-  __syncthreads();
-  const int* zl = g.zl;
-  fft_lines<N, +1, NT, N>(P, g.nza, LD, [zl](int f) { return zl[f]; }, NoPost{}, g.tw64);
-  fft_lines<N, +1, NT, N>(P, N, 1, [](int f) { return f * LD; }, NoPost{}, g.tw64);
-  Z64* op = out + ((size_t)vec * N + ix) * N * N;
-  for (int i = threadIdx.x; i < N * N; i += NT) {
-    const int iy = i / N, iz = i - iy * N;
-    op[i] = P[iy * LD + iz];
-  }
-}
-
-// One workgroup per (plane ix, perturbation p): accumulates the nb bands of the
-// perturbation in band order, each thread keeping the grid points it owns in
-// the last FFT stage in registers.
-template <int N>
-__global__ __launch_bounds__(plane_threads<N>()) void k_plane_dn(const Z64* __restrict__ pen,
-                                                                const Z64* __restrict__ psi_r, int band0, int nb,
-                                                                const int* __restrict__ pert_out, double scale,
-                                                                double* __restrict__ dn, FftGeom g) {
-  constexpr int NT = plane_threads<N>(), LD = N + 1;
-  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
-  constexpr int NSLOT = (R2 == 1) ? (N + NT - 1) / NT : (N * R1 + NT - 1) / NT;
-  constexpr int NR = (R2 == 1) ? R1 : R2;
-  extern __shared__ unsigned char smem_raw[];
-  Z64* P = reinterpret_cast<Z64*>(smem_raw);
-  const int ix = blockIdx.x;
-  const int pl = blockIdx.y;
-  double acc[NSLOT][NR];
+  C c{reinterpret_cast<Z<T>*>(smem_raw), g.zl, g.ycol, g.nza, g.zact_lo, g.zact_hi, plane_twiddles<N, T>(smem_raw, g)};
+  Z<T>* P = c.P;
+  T* VS = reinterpret_cast<T*>(smem_raw + ((size_t)N * LD + N) * sizeof(Z<T>));
+  const int tid = threadIdx.x;
+  const int nza = c.nza;
+  const long total = (long)N * nvec;
+  const Z<T> zero = zmk(T(0), T(0));
+  Z<T> pre[MAXA][R1];
+  auto prefetch = [&](long q) {
+    const int ix = (int)(q / nvec), b = (int)(q - (long)ix * nvec);
+    const int vec = vidx ? vidx[b] : b;
+    const Z<T>* tp = pen + ((size_t)vec * N + ix) * g.ncol_pad;
 #pragma unroll
-  for (int a = 0; a < NSLOT; ++a)
+    for (int k = 0; k < MAXA; ++k) {
+      const int it = tid + k * NT;
+      const int f = it % nza, j = it / nza;
 #pragma unroll
-    for (int b = 0; b < NR; ++b) acc[a][b] = 0.0;
-  const int* zl = g.zl;
-  for (int bb = 0; bb < nb; ++bb) {
-    const int s = pl * nb + bb;
-    plane_zero<N>(P, NT);
+      for (int r = 0; r < R1; ++r) {
+        const int cl = (it < nza * R2) ? c.yc[(j + r * R2) * nza + f] : -1;
+        Z<T> v = zero;
+        if (cl >= 0) v = tp[cl];
+        pre[k][r] = v;
+      }
+    }
+  };
+  long q = blockIdx.x;
+  if (q < total) prefetch(q);
+  int cur_ix = -1;
+  for (; q < total; q += gridDim.x) {
+    const int ix = (int)(q / nvec), b = (int)(q - (long)ix * nvec);
+    const int vec = vidx ? vidx[b] : b;
+    Z<T>* tp = pen + ((size_t)vec * N + ix) * g.ncol_pad;
+    const T* __restrict__ vg = v_r + (size_t)ix * N * N;
+    if (VL && ix != cur_ix) {
+      for (int i = tid; i < N * N; i += NT) VS[(i / N) * LD + i % N] = vg[i];
+    }
+    cur_ix = ix;
+    // y inverse, stage 1 from the prefetched pencils
+#pragma unroll
+    for (int k = 0; k < MAXA; ++k) {
+      const int it = tid + k * NT;
+      if (it < nza * R2) {
+        const int f = it % nza, j = it / nza;
+        dft<R1, +1>(pre[k]);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) P[(j * R1 + r) * LD + c.zl[f]] = pre[k][r];
+      }
+    }
     __syncthreads();
-    plane_scatter<N>(P, pen + ((size_t)s * N + ix) * g.ncol_pad, g, NT);
+    stage<N, R2, +1, true, false, true, NT, N / 2 + 1>(
+        nza, [&](int f, int j, int r) { return P[(j + r * R1) * LD + c.zl[f]]; },
+        [&](int f, int j, int r, Z<T> v) { P[(j + r * R1) * LD + c.zl[f]] = v; }, c.tw);
     __syncthreads();
-    fft_lines<N, +1, NT, N>(P, g.nza, LD, [zl](int f) { return zl[f]; }, NoPost{}, g.tw64);
-    const Z64* ps = psi_r + ((size_t)(band0 + bb) * N + ix) * N * N;
-    fft_lines<N, +1, NT, N>(
-        P, N, 1, [](int f) { return f * LD; },
-        [&acc, ps](int f, int n, int slot, int r, Z64 v) {
-          const Z64 w = ps[f * N + n];
-          acc[slot][r] += w.re * v.re + w.im * v.im;
+    if (q + gridDim.x < total) prefetch(q + gridDim.x);  // in flight during the row stages
+    // z inverse stage 1 (inputs off the active lines are zero)
+    stage<N, R1, +1, false, true, true, NT, N>(
+        N,
+        [&](int y, int j, int r) {
+          const int z = j + r * R2;
+          Z<T> v = zero;
+          if (c.zact(z)) v = P[y * LD + z];
           return v;
         },
-        g.tw64);
+        [&](int y, int j, int r, Z<T> v) { P[y * LD + j * R1 + r] = v; }, c.tw);
+    __syncthreads();
+    // z inverse stage 2 (radix R2), x V, z forward stage 1 of the (R2, R1) plan: in registers
+    {
+      constexpr int J = R1;
+      constexpr int MAXIT = (N * J + NT - 1) / NT;
+      Z<T> v[MAXIT][R2];
+#pragma unroll
+      for (int k = 0; k < MAXIT; ++k) {
+        const int it = tid + k * NT;
+        if (it < N * J) {
+          const int y = it % N, j = it / N;
+#pragma unroll
+          for (int r = 0; r < R2; ++r) v[k][r] = P[y * LD + j + r * R1];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < MAXIT; ++k) {
+        const int it = tid + k * NT;
+        if (it < N * J) {
+          const int y = it % N, j = it / N;
+#pragma unroll
+          for (int r = 1; r < R2; ++r) v[k][r] = v[k][r] * twid<+1>(c.tw, r * j);
+          dft<R2, +1>(v[k]);
+#pragma unroll
+          for (int r = 0; r < R2; ++r) {
+            const int z = j + r * R1;
+            const T w = VL ? VS[y * LD + z] : vg[y * N + z];
+            v[k][r] = zscale(v[k][r], w);
+          }
+          dft<R2, -1>(v[k]);
+#pragma unroll
+          for (int r = 0; r < R2; ++r) P[y * LD + j * R2 + r] = v[k][r];
+        }
+      }
+    }
+    __syncthreads();
+    // z forward stage 2 of the (R2, R1) plan: radix R1 over {j + r R2}; keep active z only
+    stage<N, R1, -1, true, false, true, NT, N>(
+        N, [&](int y, int j, int r) { return P[y * LD + j + r * R2]; },
+        [&](int y, int j, int r, Z<T> v) {
+          const int z = j + r * R2;
+          if (c.zact(z)) P[y * LD + z] = v;
+        },
+        c.tw);
+    __syncthreads();
+    y_forward_to_pencils<N, T>(c, tp);
+    __syncthreads();  // the next pair overwrites P (and possibly V)
   }
-  double* dp = dn + ((size_t)pert_out[pl] * N + ix) * N * N;
+}
+
+// right-hand side: pencils[s] of plane ix = forward yz DFT of psi_r[band[s]] * dv[pert[s]]
+template <int N>
+__global__ __launch_bounds__(plane_nt<N>()) void k_plane_rhs(const Z64* __restrict__ psi_r,
+                                                            const double* __restrict__ dv,
+                                                            const int* __restrict__ band,
+                                                            const int* __restrict__ pert, Z64* __restrict__ pen,
+                                                            FftGeom g) {
+  using C = PlaneCtx<N, double>;
+  constexpr int LD = C::LD, R1 = C::R1, R2 = C::R2, NT = C::NT;
+  extern __shared__ unsigned char smem_raw[];
+  C c{reinterpret_cast<Z64*>(smem_raw), g.zl, g.ycol, g.nza, g.zact_lo, g.zact_hi,
+      plane_twiddles<N, double>(smem_raw, g)};
+  Z64* P = c.P;
+  const int ix = blockIdx.x;
+  const int s = blockIdx.y;
+  const Z64* __restrict__ ps = psi_r + ((size_t)band[s] * N + ix) * N * N;
+  const double* __restrict__ dp = dv + ((size_t)pert[s] * N + ix) * N * N;
+  stage<N, R1, -1, false, false, false, NT, N>(
+      N,
+      [&](int y, int j, int r) {
+        const int o = y * N + j + r * R2;
+        return zscale(ps[o], dp[o]);
+      },
+      [&](int y, int j, int r, Z64 v) { P[y * LD + j * R1 + r] = v; }, c.tw);
+  __syncthreads();
+  stage<N, R2, -1, true, false, false, NT, N>(
+      N, [&](int y, int j, int r) { return P[y * LD + j + r * R1]; },
+      [&](int y, int j, int r, Z64 v) {
+        const int z = j + r * R1;
+        if (c.zact(z)) P[y * LD + z] = v;
+      },
+      c.tw);
+  __syncthreads();
+  y_forward_to_pencils<N, double>(c, pen + ((size_t)s * N + ix) * g.ncol_pad);
+}
+
+// inverse yz DFT of the pencils of vector `vec` to the full plane out[vec][ix][iy][iz]
+template <int N>
+__global__ __launch_bounds__(plane_nt<N>()) void k_plane_full_inv(const Z64* __restrict__ pen, Z64* __restrict__ out,
+                                                                 FftGeom g) {
+  using C = PlaneCtx<N, double>;
+  constexpr int LD = C::LD, R1 = C::R1, R2 = C::R2, NT = C::NT;
+  extern __shared__ unsigned char smem_raw[];
+  C c{reinterpret_cast<Z64*>(smem_raw), g.zl, g.ycol, g.nza, g.zact_lo, g.zact_hi,
+      plane_twiddles<N, double>(smem_raw, g)};
+  Z64* P = c.P;
+  const int ix = blockIdx.x;
+  const int vec = blockIdx.y;
+  y_inverse_from_pencils<N, double>(c, pen + ((size_t)vec * N + ix) * g.ncol_pad);
+  z_inverse_stage1<N, double>(c);
+  Z64* __restrict__ op = out + ((size_t)vec * N + ix) * N * N;
+  stage<N, R2, +1, true, false, false, NT, N>(
+      N, [&](int y, int j, int r) { return P[y * LD + j + r * R1]; },
+      [&](int y, int j, int r, Z64 v) { op[y * N + j + r * R1] = v; }, c.tw);
+}
+
+// One workgroup per (plane ix, perturbation p): for the nb bands of p in band
+// order, inverse yz DFT of the solution pencils and accumulation of
+// Re conj(psi_v(r)) x(r) in registers (each thread owns the grid points of its
+// last-stage items, the same ones for every band).
+template <int N>
+__global__ __launch_bounds__(plane_nt<N>()) void k_plane_dn(const Z64* __restrict__ pen,
+                                                           const Z64* __restrict__ psi_r, int band0, int nb,
+                                                           const int* __restrict__ pert_out, double scale,
+                                                           double* __restrict__ dn, FftGeom g) {
+  using C = PlaneCtx<N, double>;
+  constexpr int LD = C::LD, R1 = C::R1, R2 = C::R2, NT = C::NT;
+  constexpr int J = R1;
+  constexpr int MAXIT = (N * J + NT - 1) / NT;
+  extern __shared__ unsigned char smem_raw[];
+  C c{reinterpret_cast<Z64*>(smem_raw), g.zl, g.ycol, g.nza, g.zact_lo, g.zact_hi,
+      plane_twiddles<N, double>(smem_raw, g)};
+  Z64* P = c.P;
+  const int ix = blockIdx.x;
+  const int pl = blockIdx.y;
   const int tid = threadIdx.x;
+  double acc[MAXIT][R2];
 #pragma unroll
-  for (int k = 0; k < NSLOT; ++k) {
-    if constexpr (R2 == 1) {
-      const int f = tid + k * NT;
-      if (f < N) {
+  for (int k = 0; k < MAXIT; ++k)
 #pragma unroll
-        for (int r = 0; r < R1; ++r) dp[f * N + r] = scale * acc[k][r];
-      }
-    } else {
+    for (int r = 0; r < R2; ++r) acc[k][r] = 0.0;
+  for (int bb = 0; bb < nb; ++bb) {
+    const int s = pl * nb + bb;
+    y_inverse_from_pencils<N, double>(c, pen + ((size_t)s * N + ix) * g.ncol_pad);
+    z_inverse_stage1<N, double>(c);
+    const Z64* __restrict__ ps = psi_r + ((size_t)(band0 + bb) * N + ix) * N * N;
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
       const int it = tid + k * NT;
-      if (it < N * R1) {
-        const int f = it / R1, j = it - f * R1;
+      if (it < N * J) {
+        const int y = it / J, j = it - y * J;
+        Z64 v[R2];
 #pragma unroll
-        for (int r = 0; r < R2; ++r) dp[f * N + j + r * R1] = scale * acc[k][r];
+        for (int r = 0; r < R2; ++r) v[r] = P[y * LD + j + r * R1];
+#pragma unroll
+        for (int r = 1; r < R2; ++r) v[r] = v[r] * twid<+1>(c.tw, r * j);
+        dft<R2, +1>(v);
+#pragma unroll
+        for (int r = 0; r < R2; ++r) {
+          const Z64 w = ps[y * N + j + r * R1];
+          acc[k][r] += w.re * v[r].re + w.im * v[r].im;
+        }
       }
+    }
+    __syncthreads();  // P is rewritten by the next band
+  }
+  double* __restrict__ dp = dn + ((size_t)pert_out[pl] * N + ix) * N * N;
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    const int it = tid + k * NT;
+    if (it < N * J) {
+      const int y = it / J, j = it - y * J;
+#pragma unroll
+      for (int r = 0; r < R2; ++r) dp[y * N + j + r * R1] = scale * acc[k][r];
     }
   }
 }
 
 // Raise the dynamic LDS limit of a plane kernel once per instantiation.
 void set_lds(const void* kernel, size_t bytes) {
-  static const void* done[64];
+  static const void* done[128];
   static int ndone = 0;
   if (bytes <= 64 * 1024) return;
   for (int i = 0; i < ndone; ++i)
     if (done[i] == kernel) return;
   (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (ndone < 64) done[ndone++] = kernel;
+  if (ndone < 128) done[ndone++] = kernel;
 }
 
 }  // namespace
@@ -264,10 +549,10 @@ bool fft_size_supported(int N) {
   }
 }
 
-size_t plane_lds_bytes(int N, int elem_bytes) { return (size_t)N * (N + 1) * elem_bytes; }
+size_t plane_lds_bytes(int N, int elem_bytes) { return ((size_t)N * (N + 1) + N) * elem_bytes; }
 
-#define STERN_DISPATCH_N(N_, CALL)                  \
-  switch (N_) {                                     \
+#define STERN_DISPATCH_N(N_, CALL)                     \
+  switch (N_) {                                        \
     case 8: { constexpr int NN = 8; CALL; } break;     \
     case 9: { constexpr int NN = 9; CALL; } break;     \
     case 12: { constexpr int NN = 12; CALL; } break;   \
@@ -285,35 +570,50 @@ size_t plane_lds_bytes(int N, int elem_bytes) { return (size_t)N * (N + 1) * ele
     case 96: { constexpr int NN = 96; CALL; } break;   \
     case 108: { constexpr int NN = 108; CALL; } break; \
     case 128: { constexpr int NN = 128; CALL; } break; \
-    default: break;                                 \
+    default: break;                                    \
   }
 
-void launch_xinv(const FftGeom& g, const Z64* sph, const int* vidx, int nvec, Z64* pen, hipStream_t st) {
+template <class T>
+void launch_xinv(const FftGeom& g, const Z<T>* sph, const int* vidx, int nvec, Z<T>* pen, hipStream_t st) {
   if (nvec <= 0) return;
   dim3 grid(g.ncol_pad / kColBlock, nvec);
-  STERN_DISPATCH_N(g.N, (k_xinv<NN><<<grid, kXThreads, 0, st>>>(sph, vidx, pen, g)));
+  STERN_DISPATCH_N(g.N, (k_xinv<NN, T><<<grid, kXThreads, 0, st>>>(sph, vidx, pen, g)));
 }
+template void launch_xinv<double>(const FftGeom&, const Z64*, const int*, int, Z64*, hipStream_t);
+template void launch_xinv<float>(const FftGeom&, const Z32*, const int*, int, Z32*, hipStream_t);
 
-void launch_xfwd(const FftGeom& g, const Z64* pen, const int* vidx, int nvec, Z64* out, int mode, const Z64* pin,
+template <class T>
+void launch_xfwd(const FftGeom& g, const Z<T>* pen, const int* vidx, int nvec, Z<T>* out, int mode, const Z<T>* pin,
                  const double* eps, double scale, hipStream_t st) {
   if (nvec <= 0) return;
   dim3 grid(g.ncol_pad / kColBlock, nvec);
   if (mode == 0) {
-    STERN_DISPATCH_N(g.N, (k_xfwd<NN, 0><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
+    STERN_DISPATCH_N(g.N, (k_xfwd<NN, T, 0><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
   } else if (mode == 1) {
-    STERN_DISPATCH_N(g.N, (k_xfwd<NN, 1><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
+    STERN_DISPATCH_N(g.N, (k_xfwd<NN, T, 1><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
   } else {
-    STERN_DISPATCH_N(g.N, (k_xfwd<NN, 2><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
+    STERN_DISPATCH_N(g.N, (k_xfwd<NN, T, 2><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
   }
 }
+template void launch_xfwd<double>(const FftGeom&, const Z64*, const int*, int, Z64*, int, const Z64*, const double*,
+                                  double, hipStream_t);
+template void launch_xfwd<float>(const FftGeom&, const Z32*, const int*, int, Z32*, int, const Z32*, const double*,
+                                 double, hipStream_t);
 
-void launch_plane_vloc(const FftGeom& g, Z64* pen, const int* vidx, int nvec, const double* v_r, hipStream_t st) {
+template <class T>
+void launch_plane_vloc(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* v_r, hipStream_t st) {
   if (nvec <= 0) return;
-  const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
-  dim3 grid(g.N, nvec);
-  STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_vloc<NN>, lds),
-                         k_plane_vloc<NN><<<grid, plane_threads<NN>(), lds, st>>>(pen, vidx, v_r, g)));
+  STERN_DISPATCH_N(g.N, ({
+                     const size_t lds = vloc_lds_bytes<NN, T>(vloc_v_in_lds<NN, T>());
+                     set_lds((const void*)k_plane_vloc<NN, T>, lds);
+                     const int per_cu = lds > 80 * 1024 ? 1 : (lds > 53 * 1024 ? 2 : 3);
+                     const long pairs = (long)NN * nvec;
+                     const int grid = (int)std::min<long>(pairs, (long)g.n_cu * per_cu);
+                     k_plane_vloc<NN, T><<<grid, plane_nt<NN, T>(), lds, st>>>(pen, vidx, nvec, v_r, g);
+                   }));
 }
+template void launch_plane_vloc<double>(const FftGeom&, Z64*, const int*, int, const double*, hipStream_t);
+template void launch_plane_vloc<float>(const FftGeom&, Z32*, const int*, int, const float*, hipStream_t);
 
 void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
                       int nvec, Z64* pen, hipStream_t st) {
@@ -321,7 +621,7 @@ void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, cons
   const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
   dim3 grid(g.N, nvec);
   STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_rhs<NN>, lds),
-                         k_plane_rhs<NN><<<grid, plane_threads<NN>(), lds, st>>>(psi_r, dv, band, pert, pen, g)));
+                         k_plane_rhs<NN><<<grid, plane_nt<NN>(), lds, st>>>(psi_r, dv, band, pert, pen, g)));
 }
 
 void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out, hipStream_t st) {
@@ -329,7 +629,7 @@ void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out,
   const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
   dim3 grid(g.N, nvec);
   STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_full_inv<NN>, lds),
-                         k_plane_full_inv<NN><<<grid, plane_threads<NN>(), lds, st>>>(pen, out, g)));
+                         k_plane_full_inv<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, out, g)));
 }
 
 void launch_plane_dn(const FftGeom& g, const Z64* pen, const Z64* psi_r, int band0, int nb, int npert,
@@ -338,8 +638,8 @@ void launch_plane_dn(const FftGeom& g, const Z64* pen, const Z64* psi_r, int ban
   const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
   dim3 grid(g.N, npert);
   STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_dn<NN>, lds),
-                         k_plane_dn<NN><<<grid, plane_threads<NN>(), lds, st>>>(pen, psi_r, band0, nb, pert_out,
-                                                                               scale, dn, g)));
+                         k_plane_dn<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, psi_r, band0, nb, pert_out, scale,
+                                                                          dn, g)));
 }
 
 }  // namespace stern

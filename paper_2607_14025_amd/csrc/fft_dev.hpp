@@ -22,7 +22,7 @@ STERN_PLAN(24, 8, 3)
 STERN_PLAN(27, 9, 3)
 STERN_PLAN(32, 8, 4)
 STERN_PLAN(36, 9, 4)
-STERN_PLAN(48, 16, 3)
+STERN_PLAN(48, 8, 6)
 STERN_PLAN(54, 9, 6)
 STERN_PLAN(64, 8, 8)
 STERN_PLAN(72, 9, 8)

@@ -20,6 +20,9 @@ struct FftGeom {
   const int* col_xmin;      // [ncol_pad] smallest n_x of the column
   const int* col_pos;       // [ncol] iy * N + iz of the column in a yz plane
   const int* zl;            // [nza] iz of the active lines
+  const int* ycol;          // [N][nza] pencil column of (iy, zl[f]), -1 outside the sphere's disk
+  int zact_lo, zact_hi;     // active lines are iz <= zact_lo or iz >= zact_hi
+  int n_cu;                 // compute units of the device (persistent launches)
   const double* g2h;        // [npw_pad] |G|^2 / 2 in column order (0 for padding)
   const Z64* tw64;          // [N] exp(-2 pi i m / N)
   const Z32* tw32;
@@ -31,15 +34,18 @@ bool fft_size_supported(int N);
 size_t plane_lds_bytes(int N, int elem_bytes);
 
 // x pass, inverse: sphere coefficients of vectors vidx[b] (b < nvec) -> pencils.
-void launch_xinv(const FftGeom& g, const Z64* sph, const int* vidx, int nvec, Z64* pen, hipStream_t st);
+template <class T>
+void launch_xinv(const FftGeom& g, const Z<T>* sph, const int* vidx, int nvec, Z<T>* pen, hipStream_t st);
 // x pass, forward + output mode:
 //   mode 0: out = pencil transform
 //   mode 1: out = pencil transform + (|G|^2/2 - eps[vec]) * pin        (H apply without KB)
 //   mode 2: out = scale * pencil transform
-void launch_xfwd(const FftGeom& g, const Z64* pen, const int* vidx, int nvec, Z64* out, int mode,
-                 const Z64* pin, const double* eps, double scale, hipStream_t st);
+template <class T>
+void launch_xfwd(const FftGeom& g, const Z<T>* pen, const int* vidx, int nvec, Z<T>* out, int mode,
+                 const Z<T>* pin, const double* eps, double scale, hipStream_t st);
 // yz planes of the H apply: inverse, multiply by v_r (pre-scaled by 1/N^3), forward; in place.
-void launch_plane_vloc(const FftGeom& g, Z64* pen, const int* vidx, int nvec, const double* v_r, hipStream_t st);
+template <class T>
+void launch_plane_vloc(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* v_r, hipStream_t st);
 // yz planes of the right-hand side: pencils[s] = forward planes of psi_r[band[s]] * dv[pert[s]].
 void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
                       int nvec, Z64* pen, hipStream_t st);

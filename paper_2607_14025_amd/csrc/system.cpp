@@ -83,12 +83,13 @@ int upload(DBuf& d, const void* src, size_t bytes, hipStream_t st) {
 
 struct stern_system {
   int device = 0;
+  int n_cu = 256;
   hipStream_t stream = nullptr;
   CellParams cell;
   HostBasis hb;
   int n_atoms = 0, natoms_pad = 0;
   // static device data
-  DBuf col_start, col_len, col_xmin, col_pos, zl, g2h, tw64, v_r, kb, perm;
+  DBuf col_start, col_len, col_xmin, col_pos, zl, ycol, g2h, tw64, tw32, v_r, v_r32, kb, perm;
   // occupied states
   int n_occ = 0, nocc_pad = 0;
   bool have_occ = false;
@@ -123,14 +124,18 @@ struct stern_system {
     g.col_xmin = col_xmin.as<int>();
     g.col_pos = col_pos.as<int>();
     g.zl = zl.as<int>();
+    g.ycol = ycol.as<int>();
+    g.zact_lo = hb.zact_lo;
+    g.zact_hi = hb.zact_hi;
+    g.n_cu = n_cu;
     g.g2h = g2h.as<double>();
     g.tw64 = tw64.as<Z64>();
-    g.tw32 = nullptr;
+    g.tw32 = tw32.as<Z32>();
     return g;
   }
 
   void release_all() {
-    DBuf* all[] = {&col_start, &col_len,  &col_xmin, &col_pos, &zl,       &g2h,     &tw64,     &v_r,      &kb,
+    DBuf* all[] = {&ycol, &tw32, &v_r32, &col_start, &col_len,  &col_xmin, &col_pos, &zl,       &g2h,     &tw64,     &v_r,      &kb,
                    &perm,      &psi,      &psi_r,    &wx,      &wr,       &wp,      &wq,       &wz,       &wb,
                    &pen,       &cpart,    &cmat,     &sv_eps,  &sv_invT,  &sv_band, &sv_pert,  &sv_bb,    &sv_rz,
                    &sv_rr,     &sv_flag,  &sv_iters, &sv_tres, &list_act, &list_f,  &pert_out, &dv_dev,   &dn_dev,
@@ -360,6 +365,7 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     delete S;
     return fail(STERN_ERR_UNSUPPORTED, "FP64 plane of grid %d needs %zu bytes of LDS", hb.N, lds);
   }
+  S->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   S->n_atoms = (int)(p.pos.size() / 3);
   S->natoms_pad = std::max(64, (S->n_atoms + 63) / 64 * 64);
   auto run = [&]() -> int {
@@ -369,6 +375,7 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     CHECKED(upload(S->col_xmin, hb.col_xmin.data(), hb.col_xmin.size() * sizeof(int), st));
     CHECKED(upload(S->col_pos, hb.col_pos.data(), hb.col_pos.size() * sizeof(int), st));
     CHECKED(upload(S->zl, hb.zl.data(), hb.zl.size() * sizeof(int), st));
+    CHECKED(upload(S->ycol, hb.ycol.data(), hb.ycol.size() * sizeof(int), st));
     CHECKED(upload(S->g2h, hb.g2h.data(), hb.g2h.size() * sizeof(double), st));
     CHECKED(upload(S->perm, hb.perm.data(), hb.perm.size() * sizeof(int), st));
     std::vector<Z64> tw(hb.N);
@@ -377,9 +384,14 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
       tw[m] = zmk(std::cos(a), -std::sin(a));
     }
     CHECKED(upload(S->tw64, tw.data(), tw.size() * sizeof(Z64), st));
+    std::vector<Z32> tw32(hb.N);
+    for (int m = 0; m < hb.N; ++m) tw32[m] = zmk((float)tw[m].re, (float)tw[m].im);
+    CHECKED(upload(S->tw32, tw32.data(), tw32.size() * sizeof(Z32), st));
     const double n3 = (double)hb.N * hb.N * hb.N;
     std::vector<double> v = vloc_grid(p, hb, 1.0 / n3);
     CHECKED(upload(S->v_r, v.data(), v.size() * sizeof(double), st));
+    std::vector<float> v32(v.begin(), v.end());
+    CHECKED(upload(S->v_r32, v32.data(), v32.size() * sizeof(float), st));
     std::vector<std::complex<double>> B = kb_projectors(p, hb, S->natoms_pad);
     CHECKED(upload(S->kb, B.data(), B.size() * sizeof(Z64), st));
     HIPOK(hipStreamSynchronize(st));
@@ -604,7 +616,7 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
                        S->pen.as<Z64>(), st);
     }));
     CHECKED(timed(S, STERN_K_XFWD, ns * ((double)N * hb.ncol * 16.0 + vecb), 0.0, [&] {
-      launch_xfwd(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
+      launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
     }));
     CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
     launch_cg_init(cs, nullptr, ns, st);
