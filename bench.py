@@ -23,6 +23,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
+BF16_MFMA_PEAK_TFS = 2500.0  # MI355X dense BF16 matrix
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {"plane_h": "fft.hip", "xinv": "fft.hip", "xfwd": "fft.hip", "rhs_plane": "fft.hip",
                   "dn_plane": "fft.hip", "pc_reduce": "gemm.hip", "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip",
@@ -70,6 +71,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-bands", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the chi0 apply of one cell runs on one MI355X); "
@@ -78,7 +80,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2607_14025_amd import System
+    from paper_2607_14025_amd import System, STERN_FP64, STERN_MIXED
     from synth.cells import MID
     from synth.inputs import load_workload
 
@@ -96,37 +98,59 @@ def main():
     n_pert = dv.shape[0]
     n_solves = n_pert * s.n_occ
 
-    for w in range(args.warmup):
-        _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn)
-        print(f"bench: warmup {w}: {info['n_converged']}/{info['n_solves']} converged in {info['wall_s']:.2f} s",
-              file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    conv = 0
-    kern = {}
-    iters = []
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True)
-        conv += info["n_converged"]
-        iters.append(info["total_iters"] / max(1, info["n_solves"]))
-        for name, v in info["kernels"].items():
-            a = kern.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0, flops=0.0))
-            for f in a:
-                a[f] += v[f]
-        print(f"bench: step {k}: {info['n_converged']}/{info['n_solves']} converged, {info['wall_s']:.3f} s, "
-              f"max true resid {info['max_true_resid']:.2e}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    value = conv / dt
+    def run(precision, steps, warmup, label):
+        for w in range(warmup):
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision)
+            print(f"bench: {label} warmup {w}: {info['n_converged']}/{info['n_solves']} converged in "
+                  f"{info['wall_s']:.2f} s", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        conv = 0
+        kern = {}
+        iters = []
+        fallback = 0
+        t0 = time.perf_counter()
+        for k in range(steps):
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, precision=precision)
+            conv += info["n_converged"]
+            fallback += info["n_fallback"]
+            iters.append(info["total_iters"] / max(1, info["n_solves"]))
+            for name, v in info["kernels"].items():
+                a = kern.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0, flops=0.0))
+                for f in a:
+                    a[f] += v[f]
+            print(f"bench: {label} step {k}: {info['n_converged']}/{info['n_solves']} converged, "
+                  f"{info['wall_s']:.3f} s, max true resid {info['max_true_resid']:.2e}, "
+                  f"fallback {info['n_fallback']}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        return dict(value=conv / dt, dt=dt, kern=kern, iters=float(np.mean(iters)), fallback=fallback)
+
+    plain = run(STERN_FP64, args.steps, args.warmup, "fp64")
+    head = plain
+    mixed = None
+    if args.precision == "mixed":
+        mixed = run(STERN_MIXED, args.steps, args.warmup, "mixed")
+        torch.cuda.synchronize()
+        ref = torch.empty_like(dv)
+        s.apply_chi0(dv, tol=args.tol, dn_out=ref, precision=STERN_FP64)
+        s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=STERN_MIXED)
+        torch.cuda.synchronize()
+        err = ((dn - ref).reshape(n_pert, -1).norm(dim=1) / ref.reshape(n_pert, -1).norm(dim=1)).max().item()
+        mixed["dn_rel_err_vs_fp64"] = err
+        head = mixed
+    value = head["value"]
+    dt = head["dt"]
+    kern = head["kern"]
 
     dom = max(kern, key=lambda n: kern[n]["ms"])
     d = kern[dom]
     per_launch_s = d["ms"] / d["launches"] / 1e3
     traffic = measured_traffic(dom)
     if d["flops"] > 0:
+        peak = BF16_MFMA_PEAK_TFS if dom == "gemm_bf16" else FP64_MFMA_PEAK_TFS
         achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=FP64_MFMA_PEAK_TFS, unit="TFLOP/s",
-                    frac=achieved / FP64_MFMA_PEAK_TFS, traffic=traffic, kernel=dom)
+        roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    traffic=traffic, kernel=dom)
     else:
         achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
@@ -144,12 +168,21 @@ def main():
         print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
         cpu = cpu_baseline(wl, args.cpu_bands, args.tol)
 
+    cfg = dict(workload=spec.name, L_bohr=spec.L, ecut_ry=spec.ecut, atoms=spec.n_atoms, n_pw=s.n_pw,
+               grid=s.fft_n, n_occ=s.n_occ, n_pert=n_pert, solves_per_step=n_solves, tol=args.tol,
+               plain_fp64=dict(solves_per_s=plain["value"], mean_cg_iters=plain["iters"]))
+    if mixed is not None:
+        cfg.update(path="FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction (fallback: FP64 PCG)",
+                   mixed=dict(solves_per_s=mixed["value"], mean_inner_iters=mixed["iters"],
+                              fallback_solves=mixed["fallback"], dn_rel_err_vs_fp64=mixed["dn_rel_err_vs_fp64"]),
+                   speedup_vs_plain_fp64=mixed["value"] / plain["value"])
+        dtype = "f32+bf16/f64"
+    else:
+        cfg.update(path="plain FP64 projected Teter-PCG")
+        dtype = "f64"
     line = dict(metric="converged Sternheimer solves/s at resid<=1e-8", value=value, unit="solves/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=dt / args.steps * 1e3, higher_is_better=True,
-                scaling="weak", vs_baseline=None, dtype="f64", data="synthetic",
-                config=dict(workload=spec.name, L_bohr=spec.L, ecut_ry=spec.ecut, atoms=spec.n_atoms, n_pw=s.n_pw,
-                            grid=s.fft_n, n_occ=s.n_occ, n_pert=n_pert, solves_per_step=n_solves, tol=args.tol,
-                            path="plain FP64 projected Teter-PCG", mean_cg_iters=float(np.mean(iters))),
+                scaling="weak", vs_baseline=None, dtype=dtype, data="synthetic", config=cfg,
                 roofline=roof, cpu_baseline=cpu, kernels=breakdown)
     s.close()
     print(json.dumps(line), flush=True)

@@ -50,7 +50,8 @@ extern "C" {
 #define STERN_ERR_HIP (-4)
 #define STERN_ERR_UNSUPPORTED (-6)    /* e.g. FFT size not of the form 2^a 3^b <= 128 */
 
-/* precision of the inner solver */
+/* precision of the solver: plain FP64 PCG, or FP32 FFTs + split-BF16 MFMA
+   GEMMs inside an FP64 defect-correction loop (FP64 scalars, FP64 true residual) */
 #define STERN_FP64 0
 #define STERN_MIXED 1
 
@@ -104,6 +105,11 @@ typedef struct {
   /* nonzero: time every kernel launch with HIP events on the library's stream
      and report per-class totals in stern_stats (adds one event pair per launch) */
   int profile;
+  /* STERN_MIXED only: relative tolerance of each FP32/BF16 inner solve (0 = 1e-4)
+     and the number of FP64 defect-correction steps before the solves still above
+     tol fall back to FP64 PCG from zero (0 = 8) */
+  double inner_tol;
+  int max_outer;
 } stern_opts;
 
 /* kernel classes of the per-launch profile */
@@ -119,12 +125,17 @@ typedef struct {
 #define STERN_K_RHS 9         /* yz planes of dV psi_v (right-hand side) */
 #define STERN_K_DN 10         /* yz planes of the density response accumulation */
 #define STERN_K_OTHER 11
-#define STERN_NKERNEL 12
+#define STERN_K_PLANE_H32 12  /* FP32 yz planes of the mixed inner H apply */
+#define STERN_K_X32 13        /* FP32 x pencils (both directions) */
+#define STERN_K_GEMM_BF16 14  /* split-BF16 MFMA GEMMs (KB and P_c) */
+#define STERN_K_CG32 15       /* FP32 CG updates with FP64 dots */
+#define STERN_NKERNEL 16
 
 typedef struct {
   int n_solves;        /* (band, perturbation) pairs solved */
   int n_converged;     /* pairs with FP64 true relative residual <= tol */
-  int n_fallback;      /* pairs restarted from their true residual */
+  int n_fallback;      /* mixed: pairs re-solved by FP64 PCG from zero after max_outer steps */
+  int n_restarts;      /* PCG restarts from the FP64 true residual */
   long long total_iters;
   int max_iters;
   double wall_s;       /* wall time of the call */

@@ -47,9 +47,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __
   bb = block_sum(bb, sh);
   if (threadIdx.x == 0) {
     S.bb[s] = bb;
-    S.iters[s] = 0;
     S.flag[s] = (bb > 0.0) ? 0 : 2;
-    S.tres[s] = 0.0;
   }
 }
 
@@ -200,6 +198,156 @@ __global__ void k_ri(const double* __restrict__ in, Z64* __restrict__ out, size_
     out[i] = zmk(in[2 * i], in[2 * i + 1]);
 }
 
+// ---------------------------------------------------------------- mixed ----
+// FP32 inner CG of the defect correction: vectors in FP32, dots accumulated
+// and scalars kept in FP64.
+
+// ri = fp32(r64); d = 0; z = K ri; rr0 = ||ri||^2; inner flag 0 (2 if rr0 == 0)
+__global__ __launch_bounds__(kCgThreads) void k_cg32_init(Cg32State S, const Z64* __restrict__ r64,
+                                                          const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  const double iT = S.invT[s];
+  double rr = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 v = r64[o + k];
+    const Z32 r = zmk((float)v.re, (float)v.im);
+    rr += (double)r.re * r.re + (double)r.im * r.im;
+    S.r[o + k] = r;
+    S.d[o + k] = zmk(0.f, 0.f);
+    const float t = (float)teter(S.g2h[k], iT);
+    S.z[o + k] = zmk(r.re * t, r.im * t);
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    S.rr0[s] = rr;
+    S.flag[s] = rr > 0.0 ? 0 : 2;
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg32_init2(Cg32State S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  double rz = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z32 r = S.r[o + k], z = S.z[o + k];
+    rz += (double)r.re * z.re + (double)r.im * z.im;
+    S.p[o + k] = z;
+  }
+  rz = block_sum(rz, sh);
+  if (threadIdx.x == 0) S.rz[s] = rz;
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const int* __restrict__ act, double tol2) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double pq = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z32 p = S.p[o + k], q = S.q[o + k];
+    pq += (double)p.re * q.re + (double)p.im * q.im;
+  }
+  pq = block_sum(pq, sh);
+  const float alpha = (float)((pq > 0.0) ? S.rz[s] / pq : 0.0);
+  const double iT = S.invT[s];
+  double rr = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z32 p = S.p[o + k], q = S.q[o + k];
+    Z32 d = S.d[o + k], r = S.r[o + k];
+    d = zmk(d.re + alpha * p.re, d.im + alpha * p.im);
+    r = zmk(r.re - alpha * q.re, r.im - alpha * q.im);
+    S.d[o + k] = d;
+    S.r[o + k] = r;
+    rr += (double)r.re * r.re + (double)r.im * r.im;
+    const float t = (float)teter(S.g2h[k], iT);
+    S.z[o + k] = zmk(r.re * t, r.im * t);
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    S.iters[s] += 1;
+    if (rr <= tol2 * S.rr0[s] || !(pq > 0.0)) S.flag[s] = 1;
+  }
+}
+
+__global__ __launch_bounds__(kCgThreads) void k_cg32_beta(Cg32State S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double rz = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z32 r = S.r[o + k], z = S.z[o + k];
+    rz += (double)r.re * z.re + (double)r.im * z.im;
+  }
+  rz = block_sum(rz, sh);
+  const float beta = (float)(rz / S.rz[s]);
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z32 z = S.z[o + k], p = S.p[o + k];
+    S.p[o + k] = zmk(z.re + beta * p.re, z.im + beta * p.im);
+  }
+  if (threadIdx.x == 0) S.rz[s] = rz;
+}
+
+// x64 += d32
+__global__ void k_add_d(Z64* __restrict__ x, const Z32* __restrict__ d, int ld, const int* __restrict__ act) {
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * ld;
+  for (int k = threadIdx.x; k < ld; k += blockDim.x) {
+    const Z64 a = x[o + k];
+    const Z32 b = d[o + k];
+    x[o + k] = zmk(a.re + (double)b.re, a.im + (double)b.im);
+  }
+}
+
+// r = b - q (FP64 true residual of the outer loop); accept when ||r|| <= tol ||b||
+__global__ __launch_bounds__(kCgThreads) void k_outer_resid(CgState S, const int* __restrict__ act, double tol) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  double tt = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k], q = S.q[o + k];
+    const Z64 r = zmk(b.re - q.re, b.im - q.im);
+    S.r[o + k] = r;
+    tt += r.re * r.re + r.im * r.im;
+  }
+  tt = block_sum(tt, sh);
+  if (threadIdx.x == 0) {
+    const double bb = S.bb[s];
+    S.tres[s] = bb > 0.0 ? sqrt(tt / bb) : 0.0;
+    S.flag[s] = (tt <= tol * tol * bb) ? 2 : 0;
+  }
+}
+
+// x = 0, r = b, bb = ||b||^2 (outer loop start); flag 2 when b = 0
+__global__ __launch_bounds__(kCgThreads) void k_outer_init(CgState S, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  double bb = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k];
+    bb += b.re * b.re + b.im * b.im;
+    S.x[o + k] = zmk(0.0, 0.0);
+    S.r[o + k] = b;
+  }
+  bb = block_sum(bb, sh);
+  if (threadIdx.x == 0) {
+    S.bb[s] = bb;
+    S.iters[s] = 0;
+    S.tres[s] = bb > 0.0 ? 1.0 : 0.0;
+    S.flag[s] = bb > 0.0 ? 0 : 2;
+  }
+}
+
+__global__ void k_fill_zero32(Z32* __restrict__ p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = zmk(0.f, 0.f);
+}
+
 }  // namespace
 
 void launch_cg_init(const CgState& s, const int* act, int n, hipStream_t st) {
@@ -245,4 +393,34 @@ void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st) 
   k_ri<<<(unsigned)blocks, 256, 0, st>>>(in, out, n);
 }
 
+}  // namespace stern
+
+namespace stern {
+void launch_cg32_init(const Cg32State& s, const Z64* r64, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg32_init<<<n, kCgThreads, 0, st>>>(s, r64, act);
+}
+void launch_cg32_init2(const Cg32State& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg32_init2<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st) {
+  if (n > 0) k_cg32_alpha<<<n, kCgThreads, 0, st>>>(s, act, tol2);
+}
+void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cg32_beta<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_add_d(Z64* x, const Z32* d, int ld, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_add_d<<<n, 256, 0, st>>>(x, d, ld, act);
+}
+void launch_outer_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st) {
+  if (n > 0) k_outer_resid<<<n, kCgThreads, 0, st>>>(s, act, tol);
+}
+void launch_outer_init(const CgState& s, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_outer_init<<<n, kCgThreads, 0, st>>>(s, act);
+}
+void launch_fill_zero32(Z32* p, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  size_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  k_fill_zero32<<<(unsigned)blocks, 256, 0, st>>>(p, n);
+}
 }  // namespace stern

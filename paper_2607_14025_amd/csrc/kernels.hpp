@@ -92,4 +92,34 @@ void launch_fill_zero(Z64* p, size_t n, hipStream_t st);
 void launch_set_flag(int* flag, const int* list, int n, int value, hipStream_t st);
 void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st);
 
+// ---- mixed precision (FP32 vectors, BF16 MFMA GEMMs, FP64 scalars) ----
+struct Cg32State {
+  Z32 *d, *r, *p, *q, *z;      // [nbatch][npw_pad]
+  double *rz, *rr0;            // [nbatch]
+  int* flag;                   // inner: 0 active, 1 reached the inner tolerance, 2 nothing to do
+  int* iters;
+  const double* invT;
+  const double* g2h;
+  int npw_pad;
+};
+void launch_cg32_init(const Cg32State& s, const Z64* r64, const int* act, int n, hipStream_t st);
+void launch_cg32_init2(const Cg32State& s, const int* act, int n, hipStream_t st);
+void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st);
+void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st);
+void launch_add_d(Z64* x, const Z32* d, int ld, const int* act, int n, hipStream_t st);
+void launch_outer_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st);
+void launch_outer_init(const CgState& s, const int* act, int n, hipStream_t st);
+void launch_fill_zero32(Z32* p, size_t n, hipStream_t st);
+
+int choose_nsplit_bf16(int M_pad, int ncols, int K);
+// hi/lo BF16 split of complex rows A [M][K] into [M][2K] and transposed [K][2M] layouts
+void launch_split_bf16(const Z64* A, int M, int K, __bf16* hi, __bf16* lo, __bf16* thi, __bf16* tlo, hipStream_t st);
+// C[n][m] partial = sum_k conj(A[m][k]) X[xidx[n]][k] (BF16 split operands, FP32 accumulation)
+void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,
+                        int ncols, int K, Z32* cpart, int nsplit, hipStream_t st);
+void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, Z32* C, hipStream_t st);
+// Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A
+void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const Z32* C, Z32* Y, int ldy,
+                        const int* yidx, int ncols, int K, hipStream_t st);
+
 }  // namespace stern

@@ -95,10 +95,13 @@ struct stern_system {
   bool have_occ = false;
   std::vector<double> eps, invT;
   DBuf psi, psi_r;
+  // split BF16 copies of Psi and of the KB rows (row and transposed layouts)
+  DBuf psi_hi, psi_lo, psiT_hi, psiT_lo, kb_hi, kb_lo, kbT_hi, kbT_lo;
   // workspace
   DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
       sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
-  int ws_solves = 0;
+  DBuf m_d, m_r, m_p, m_q, m_z, m_rz, m_rr0, m_flag;  // mixed inner solve
+  int ws_solves = 0, ws32_solves = 0;
 
   // per-launch event profile (opts->profile)
   struct Rec {
@@ -139,7 +142,9 @@ struct stern_system {
                    &perm,      &psi,      &psi_r,    &wx,      &wr,       &wp,      &wq,       &wz,       &wb,
                    &pen,       &cpart,    &cmat,     &sv_eps,  &sv_invT,  &sv_band, &sv_pert,  &sv_bb,    &sv_rz,
                    &sv_rr,     &sv_flag,  &sv_iters, &sv_tres, &list_act, &list_f,  &pert_out, &dv_dev,   &dn_dev,
-                   &tmp_in,    &tmp_out};
+                   &tmp_in,    &tmp_out,  &psi_hi,  &psi_lo,   &psiT_hi, &psiT_lo,  &kb_hi,    &kb_lo,
+                   &kbT_hi,    &kbT_lo,   &m_d,     &m_r,      &m_p,     &m_q,      &m_z,      &m_rz,
+                   &m_rr0,     &m_flag};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -218,6 +223,61 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
   return 0;
 }
 
+// ---- mixed-precision operator pieces (FP32 vectors, split-BF16 GEMMs) ----
+
+// Y <- P_c Y (FP32 rows, BF16 MFMA)
+int apply_pc32_rows(stern_system* S, Z32* Y, const int* list, int n) {
+  if (n <= 0) return 0;
+  const int K = S->hb.npw_pad;
+  const double npw = S->hb.npw, m = S->n_occ;
+  const int ns = choose_nsplit_bf16(S->nocc_pad, n, K);
+  Z32* cp = S->cpart.as<Z32>();
+  Z32* cm = S->cmat.as<Z32>();
+  CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (n + m), 8.0 * m * npw * n, [&] {
+    launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, Y, K, list, n, K, cp, ns,
+                       S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_SUM_PARTS, 8.0 * m * n * (ns + 1), 0.0,
+                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, -1.f, cm, S->stream); }));
+  CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (2.0 * n + m), 8.0 * m * npw * n, [&] {
+    launch_expand_bf16(S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), S->nocc_pad, cm, Y, K, list, n, K,
+                       S->stream);
+  }));
+  return 0;
+}
+
+// out = (H - eps_s) in for FP32 rows: FP32 FFTs, BF16 KB projectors
+int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, int n, const double* eps_rows) {
+  if (n <= 0) return 0;
+  const FftGeom g = S->geom();
+  const int K = S->hb.npw_pad;
+  const double zb = sizeof(Z32), npw = S->hb.npw, N = S->hb.N, pen = N * S->hb.ncol * zb;
+  Z32* pen32 = S->pen.as<Z32>();
+  CHECKED(timed(S, STERN_K_X32, n * (npw * zb + pen), 0.0,
+                [&] { launch_xinv<float>(g, in, list, n, pen32, S->stream); }));
+  CHECKED(timed(S, STERN_K_PLANE_H32, n * 2.0 * pen + N * N * N * sizeof(float), 0.0,
+                [&] { launch_plane_vloc<float>(g, pen32, list, n, S->v_r32.as<float>(), S->stream); }));
+  CHECKED(timed(S, STERN_K_X32, n * (pen + 2.0 * npw * zb), 0.0,
+                [&] { launch_xfwd<float>(g, pen32, list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
+  if (S->n_atoms > 0) {
+    const double na = S->n_atoms;
+    const int ns = choose_nsplit_bf16(S->natoms_pad, n, K);
+    Z32* cp = S->cpart.as<Z32>();
+    Z32* cm = S->cmat.as<Z32>();
+    CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
+      launch_reduce_bf16(S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(), S->natoms_pad, in, K, list, n, K, cp, ns,
+                         S->stream);
+    }));
+    CHECKED(timed(S, STERN_K_SUM_PARTS, zb * na * n * (ns + 1), 0.0,
+                  [&] { launch_sum_parts32(cp, ns, n, S->natoms_pad, (float)S->cell.D, cm, S->stream); }));
+    CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (2.0 * n + na), 8.0 * na * npw * n, [&] {
+      launch_expand_bf16(S->kbT_hi.as<__bf16>(), S->kbT_lo.as<__bf16>(), S->natoms_pad, cm, out, K, list, n, K,
+                         S->stream);
+    }));
+  }
+  return 0;
+}
+
 size_t cpart_capacity(int M_pad, int nmax, int K) {
   size_t best = 0;
   for (int n = 1; n <= nmax; ++n) {
@@ -248,6 +308,36 @@ int ensure_workspace(stern_system* S, int ns) {
     S->ws_solves = ns;
   }
   return 0;
+}
+
+int ensure_workspace32(stern_system* S, int ns) {
+  const size_t K = S->hb.npw_pad;
+  for (DBuf* d : {&S->m_d, &S->m_r, &S->m_p, &S->m_q, &S->m_z}) CHECKED(d->ensure((size_t)ns * K * sizeof(Z32)));
+  for (DBuf* d : {&S->m_rz, &S->m_rr0}) CHECKED(d->ensure((size_t)ns * sizeof(double)));
+  CHECKED(S->m_flag.ensure((size_t)ns * sizeof(int)));
+  if (S->ws32_solves < ns) {
+    for (DBuf* d : {&S->m_d, &S->m_r, &S->m_p, &S->m_q, &S->m_z})
+      launch_fill_zero32(d->as<Z32>(), (size_t)ns * K, S->stream);
+    S->ws32_solves = ns;
+  }
+  return 0;
+}
+
+Cg32State cg32_state(stern_system* S, int* iters) {
+  Cg32State c;
+  c.d = S->m_d.as<Z32>();
+  c.r = S->m_r.as<Z32>();
+  c.p = S->m_p.as<Z32>();
+  c.q = S->m_q.as<Z32>();
+  c.z = S->m_z.as<Z32>();
+  c.rz = S->m_rz.as<double>();
+  c.rr0 = S->m_rr0.as<double>();
+  c.flag = S->m_flag.as<int>();
+  c.iters = iters;
+  c.invT = S->sv_invT.as<double>();
+  c.g2h = S->g2h.as<double>();
+  c.npw_pad = S->hb.npw_pad;
+  return c;
 }
 
 CgState cg_state(stern_system* S) {
@@ -297,6 +387,149 @@ struct Scope {
     if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
   }
 };
+
+
+// Plain FP64 projected PCG from zero on the solves in `list` (batch row indices).
+int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, int max_iter,
+              int check_every, int& n_restart, double vecb) {
+  hipStream_t st = S->stream;
+  const int ns_all = S->ws_solves;
+  std::vector<int> h_flag(ns_all), act, flist;
+  if (list.empty()) return 0;
+  const int n0 = (int)list.size();
+  HIPOK(hipMemcpyAsync(S->list_act.p, list.data(), n0 * sizeof(int), hipMemcpyHostToDevice, st));
+  {
+    const int* L = S->list_act.as<int>();
+    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 4.0, 0.0, [&] { launch_cg_init(cs, L, n0, st); }));
+    CHECKED(apply_pc_rows(S, cs.z, L, n0));
+    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 3.0, 0.0, [&] { launch_cg_init2(cs, L, n0, st); }));
+  }
+  CHECKED(launch_check());
+  HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  for (int s : list)
+    if (h_flag[s] == 0) act.push_back(s);
+  int it = 0;
+  while (!act.empty()) {
+    const int na = (int)act.size();
+    HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    const int* L = S->list_act.as<int>();
+    const int nsteps = std::min(check_every, max_iter - it);
+    for (int k = 0; k < nsteps; ++k) {
+      CHECKED(apply_h_rows(S, cs.p, cs.q, L, na, cs.eps));
+      CHECKED(apply_pc_rows(S, cs.q, L, na));
+      CHECKED(timed(S, STERN_K_CG, vecb * na * 7.0, 0.0, [&] { launch_cg_alpha(cs, L, na, tol * tol, st); }));
+      CHECKED(apply_pc_rows(S, cs.z, L, na));
+      CHECKED(timed(S, STERN_K_CG, vecb * na * 4.0, 0.0, [&] { launch_cg_beta(cs, L, na, st); }));
+    }
+    it += nsteps;
+    CHECKED(launch_check());
+    HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    const bool last = it >= max_iter;
+    flist.clear();
+    for (int s : act)
+      if (h_flag[s] == 1 || last) flist.push_back(s);
+    if (!flist.empty()) {
+      const int nf = (int)flist.size();
+      HIPOK(hipMemcpyAsync(S->list_f.p, flist.data(), nf * sizeof(int), hipMemcpyHostToDevice, st));
+      const int* F = S->list_f.as<int>();
+      if (last) launch_set_flag(cs.flag, F, nf, 1, st);  // final check on everything still running
+      CHECKED(true_residual(S, cs, F, nf, tol));
+      if (!last) {
+        CHECKED(apply_pc_rows(S, cs.z, F, nf));
+        launch_cg_restart(cs, F, nf, st);
+      }
+      CHECKED(launch_check());
+      HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      if (!last)
+        for (int s : flist)
+          if (h_flag[s] == 0) ++n_restart;
+    }
+    if (last) break;
+    std::vector<int> nxt;
+    for (int s : act)
+      if (h_flag[s] != 2) nxt.push_back(s);
+    act.swap(nxt);
+  }
+  return 0;
+}
+
+// Mixed precision: FP64 defect correction around FP32/BF16 inner PCG solves.
+//   repeat: solve A d = r to inner_tol with FP32 FFTs and split-BF16 MFMA GEMMs
+//           (FP64 dots and scalars); x += d; x = P_c x (FP64); r = b - A x (FP64)
+//   until ||r|| <= tol ||b||; solves still above tol after max_outer steps are
+//   re-solved by FP64 PCG from zero.
+int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, double inner_tol,
+              int max_outer, int max_iter, int check_every, int& n_restart, int& n_fallback, double vecb) {
+  hipStream_t st = S->stream;
+  const int ns_all = S->ws_solves;
+  const int K = S->hb.npw_pad;
+  const double vec32 = vecb / 2;
+  const Cg32State c32 = cg32_state(S, cs.iters);
+  std::vector<int> h_flag(ns_all), h_iflag(ns_all), act, iact;
+  HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  for (int s : list)
+    if (h_flag[s] == 0) act.push_back(s);
+  const int max_inner = std::max(1, max_iter);
+  for (int outer = 0; outer < max_outer && !act.empty(); ++outer) {
+    const int na = (int)act.size();
+    HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    const int* L = S->list_act.as<int>();
+    CHECKED(timed(S, STERN_K_CG32, na * (vecb + 3.0 * vec32), 0.0, [&] { launch_cg32_init(c32, cs.r, L, na, st); }));
+    CHECKED(apply_pc32_rows(S, c32.z, L, na));
+    CHECKED(timed(S, STERN_K_CG32, na * 3.0 * vec32, 0.0, [&] { launch_cg32_init2(c32, L, na, st); }));
+    CHECKED(launch_check());
+    HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    iact.clear();
+    for (int s : act)
+      if (h_iflag[s] == 0) iact.push_back(s);
+    int it = 0;
+    while (!iact.empty() && it < max_inner) {
+      const int ni = (int)iact.size();
+      HIPOK(hipMemcpyAsync(S->list_f.p, iact.data(), ni * sizeof(int), hipMemcpyHostToDevice, st));
+      const int* F = S->list_f.as<int>();
+      const int nsteps = std::min(check_every, max_inner - it);
+      for (int k = 0; k < nsteps; ++k) {
+        CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
+        CHECKED(apply_pc32_rows(S, c32.q, F, ni));
+        CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 7.0, 0.0,
+                      [&] { launch_cg32_alpha(c32, F, ni, inner_tol * inner_tol, st); }));
+        CHECKED(apply_pc32_rows(S, c32.z, F, ni));
+        CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 4.0, 0.0, [&] { launch_cg32_beta(c32, F, ni, st); }));
+      }
+      it += nsteps;
+      CHECKED(launch_check());
+      HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      std::vector<int> nxt;
+      for (int s : iact)
+        if (h_iflag[s] == 0) nxt.push_back(s);
+      iact.swap(nxt);
+    }
+    // FP64 update, re-orthogonalisation and true residual
+    CHECKED(timed(S, STERN_K_CG, na * (2.0 * vecb + vec32), 0.0, [&] { launch_add_d(cs.x, c32.d, K, L, na, st); }));
+    CHECKED(apply_pc_rows(S, cs.x, L, na));
+    CHECKED(apply_h_rows(S, cs.x, cs.q, L, na, cs.eps));
+    CHECKED(apply_pc_rows(S, cs.q, L, na));
+    CHECKED(timed(S, STERN_K_CG, na * 3.0 * vecb, 0.0, [&] { launch_outer_resid(cs, L, na, tol, st); }));
+    CHECKED(launch_check());
+    HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    std::vector<int> nxt;
+    for (int s : act)
+      if (h_flag[s] != 2) nxt.push_back(s);
+    act.swap(nxt);
+  }
+  if (!act.empty()) {
+    n_fallback += (int)act.size();
+    CHECKED(run_pcg64(S, cs, act, tol, max_iter, check_every, n_restart, vecb));
+  }
+  return 0;
+}
 
 }  // namespace
 
@@ -394,6 +627,10 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     CHECKED(upload(S->v_r32, v32.data(), v32.size() * sizeof(float), st));
     std::vector<std::complex<double>> B = kb_projectors(p, hb, S->natoms_pad);
     CHECKED(upload(S->kb, B.data(), B.size() * sizeof(Z64), st));
+    const size_t kbn = (size_t)S->natoms_pad * hb.npw_pad * 2 * sizeof(__bf16);
+    for (DBuf* d : {&S->kb_hi, &S->kb_lo, &S->kbT_hi, &S->kbT_lo}) CHECKED(d->ensure(kbn));
+    launch_split_bf16(S->kb.as<Z64>(), S->natoms_pad, hb.npw_pad, S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(),
+                      S->kbT_hi.as<__bf16>(), S->kbT_lo.as<__bf16>(), st);
     HIPOK(hipStreamSynchronize(st));
     return 0;
   };
@@ -452,6 +689,10 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   CHECKED(S->tmp_in.ensure((size_t)n_occ * npw * sizeof(Z64)));
   HIPOK(hipMemcpyAsync(S->tmp_in.p, hp, (size_t)n_occ * npw * sizeof(Z64), hipMemcpyHostToDevice, st));
   launch_permute(S->tmp_in.as<Z64>(), npw, S->psi.as<Z64>(), K, S->perm.as<int>(), npw, n_occ, true, st);
+  const size_t psn = (size_t)S->nocc_pad * K * 2 * sizeof(__bf16);
+  for (DBuf* d : {&S->psi_hi, &S->psi_lo, &S->psiT_hi, &S->psiT_lo}) CHECKED(d->ensure(psn));
+  launch_split_bf16(S->psi.as<Z64>(), S->nocc_pad, K, S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(),
+                    S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), st);
   // psi_v(r) on the grid (unnormalised sum_G c_G e^{iG.r}) for the RHS and dn
   CHECKED(S->psi_r.ensure((size_t)n_occ * N * N * N * sizeof(Z64)));
   CHECKED(S->pen.ensure((size_t)n_occ * N * hb.ncol_pad * sizeof(Z64)));
@@ -529,7 +770,9 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
   if (!opts) return fail(STERN_ERR_INVALID_ARG, "opts is NULL");
   if (n_pert <= 0 || !dv_r || !dn_r) return fail(STERN_ERR_INVALID_ARG, "need n_pert > 0, dv_r and dn_r");
-  if (opts->precision != STERN_FP64) return fail(STERN_ERR_UNSUPPORTED, "only STERN_FP64 is available");
+  if (opts->precision != STERN_FP64 && opts->precision != STERN_MIXED)
+    return fail(STERN_ERR_INVALID_ARG, "precision must be STERN_FP64 or STERN_MIXED");
+  if (opts->inner_tol < 0 || opts->max_outer < 0) return fail(STERN_ERR_INVALID_ARG, "bad inner_tol / max_outer");
   if (opts->guess != STERN_GUESS_ZERO) return fail(STERN_ERR_UNSUPPORTED, "only STERN_GUESS_ZERO is available");
   if (opts->mem_kind != STERN_MEM_HOST && opts->mem_kind != STERN_MEM_DEVICE)
     return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
@@ -552,6 +795,8 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
   const int check_every = opts->check_every > 0 ? opts->check_every : 4;
   const double tol = opts->tol;
+  const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
+  const int max_outer = opts->max_outer > 0 ? opts->max_outer : 8;
   const double vecb = (double)hb.npw * sizeof(Z64);  // bytes of one coefficient vector
   S->prof_on = opts->profile != 0;
   S->recs.clear();
@@ -571,6 +816,7 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   per = std::min(per, n_pert);
   const int max_ns = per * nb;
   CHECKED(ensure_workspace(S, max_ns));
+  if (opts->precision == STERN_MIXED) CHECKED(ensure_workspace32(S, max_ns));
   CHECKED(S->pert_out.ensure((size_t)n_pert * sizeof(int)));
   {
     std::vector<int> po(n_pert);
@@ -593,9 +839,9 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   std::vector<double> all_tres;
   all_iters.reserve((size_t)n_pert * nb);
   long long tot_iters = 0;
-  int n_restart = 0;
+  int n_restart = 0, n_fallback = 0;
 
-  std::vector<int> h_flag(max_ns), h_band(max_ns), h_pert(max_ns), act, flist;
+  std::vector<int> h_flag(max_ns), h_band(max_ns), h_pert(max_ns);
   std::vector<double> h_eps(max_ns), h_invT(max_ns);
   for (int i0 = 0; i0 < n_pert; i0 += per) {
     const int i1 = std::min(n_pert, i0 + per);
@@ -619,58 +865,13 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
       launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
     }));
     CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
-    launch_cg_init(cs, nullptr, ns, st);
-    CHECKED(apply_pc_rows(S, cs.z, nullptr, ns));
-    launch_cg_init2(cs, nullptr, ns, st);
-    CHECKED(launch_check());
-    HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPOK(hipStreamSynchronize(st));
-    act.clear();
-    for (int s = 0; s < ns; ++s)
-      if (h_flag[s] == 0) act.push_back(s);
-    int it = 0;
-    while (!act.empty()) {
-      const int na = (int)act.size();
-      HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
-      const int* L = S->list_act.as<int>();
-      const int nsteps = std::min(check_every, max_iter - it);
-      for (int k = 0; k < nsteps; ++k) {
-        CHECKED(apply_h_rows(S, cs.p, cs.q, L, na, cs.eps));
-        CHECKED(apply_pc_rows(S, cs.q, L, na));
-        CHECKED(timed(S, STERN_K_CG, vecb * na * 7.0, 0.0, [&] { launch_cg_alpha(cs, L, na, tol * tol, st); }));
-        CHECKED(apply_pc_rows(S, cs.z, L, na));
-        CHECKED(timed(S, STERN_K_CG, vecb * na * 4.0, 0.0, [&] { launch_cg_beta(cs, L, na, st); }));
-      }
-      it += nsteps;
-      CHECKED(launch_check());
-      HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
-      HIPOK(hipStreamSynchronize(st));
-      const bool last = it >= max_iter;
-      flist.clear();
-      for (int s : act)
-        if (h_flag[s] == 1 || last) flist.push_back(s);
-      if (!flist.empty()) {
-        const int nf = (int)flist.size();
-        HIPOK(hipMemcpyAsync(S->list_f.p, flist.data(), nf * sizeof(int), hipMemcpyHostToDevice, st));
-        const int* F = S->list_f.as<int>();
-        if (last) launch_set_flag(cs.flag, F, nf, 1, st);  // final check on everything still running
-        CHECKED(true_residual(S, cs, F, nf, tol));
-        if (!last) {
-          CHECKED(apply_pc_rows(S, cs.z, F, nf));
-          launch_cg_restart(cs, F, nf, st);
-        }
-        CHECKED(launch_check());
-        HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
-        HIPOK(hipStreamSynchronize(st));
-        if (!last)
-          for (int s : flist)
-            if (h_flag[s] == 0) ++n_restart;
-      }
-      if (last) break;
-      std::vector<int> nxt;
-      for (int s : act)
-        if (h_flag[s] != 2) nxt.push_back(s);
-      act.swap(nxt);
+    launch_outer_init(cs, nullptr, ns, st);  // x = 0, r = b, ||b||, counters
+    std::vector<int> all(ns);
+    for (int s = 0; s < ns; ++s) all[s] = s;
+    if (opts->precision == STERN_MIXED) {
+      CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb));
+    } else {
+      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb));
     }
     // dn_i = 4/Omega Re sum_v conj(psi_v(r)) x_{v,i}(r)
     CHECKED(timed(S, STERN_K_XINV, ns * (vecb + (double)N * hb.ncol * 16.0), 0.0,
@@ -733,7 +934,8 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   if (stats) {
     stats->n_solves = nsol;
     stats->n_converged = nconv;
-    stats->n_fallback = n_restart;
+    stats->n_fallback = n_fallback;
+    stats->n_restarts = n_restart;
     stats->total_iters = tot_iters;
     stats->max_iters = mx;
     stats->max_true_resid = mres;

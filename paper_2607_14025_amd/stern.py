@@ -46,16 +46,17 @@ class Opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
                 ("mem_kind", C.c_int), ("band_begin", C.c_int), ("band_end", C.c_int), ("max_batch", C.c_int),
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
-                ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int)]
+                ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
+                ("max_outer", C.c_int)]
 
 
-NKERNEL = 12
+NKERNEL = 16
 KERNEL_NAMES = ["xinv", "plane_h", "xfwd", "pc_reduce", "pc_expand", "kb_reduce", "kb_expand", "sum_parts", "cg",
-                "rhs_plane", "dn_plane", "other"]
+                "rhs_plane", "dn_plane", "other", "plane_h32", "x32", "gemm_bf16", "cg32"]
 
 
 class Stats(C.Structure):
-    _fields_ = [("n_solves", C.c_int), ("n_converged", C.c_int), ("n_fallback", C.c_int),
+    _fields_ = [("n_solves", C.c_int), ("n_converged", C.c_int), ("n_fallback", C.c_int), ("n_restarts", C.c_int),
                 ("total_iters", C.c_longlong), ("max_iters", C.c_int), ("wall_s", C.c_double),
                 ("max_true_resid", C.c_double), ("iters", C.POINTER(C.c_int)), ("resid", C.POINTER(C.c_double)),
                 ("kernel_launches", C.c_longlong * NKERNEL), ("kernel_ms", C.c_double * NKERNEL),
@@ -170,7 +171,7 @@ class System:
         self.n_occ = n_occ
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
-                   samples=None, precision=STERN_FP64, profile=False):
+                   samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned."""
@@ -195,6 +196,8 @@ class System:
         o.max_batch = int(max_batch)
         o.check_every = int(check_every)
         o.profile = 1 if profile else 0
+        o.inner_tol = float(inner_tol)
+        o.max_outer = int(max_outer)
         keep = []
         sx = None
         if samples:
@@ -213,6 +216,7 @@ class System:
         st.resid = resid.ctypes.data_as(C.POINTER(C.c_double))
         rc = _check(lib().stern_apply_chi0(self._h, n_pert, dp, op, C.byref(o), C.byref(st)))
         info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
+                    n_restarts=st.n_restarts,
                     total_iters=st.total_iters, max_iters=st.max_iters, wall_s=st.wall_s,
                     max_true_resid=st.max_true_resid, iters=iters, resid=resid, samples=sx)
         if profile:

@@ -85,3 +85,20 @@ def test_band_split_partials_sum_to_full(mid):
     b, _ = s.apply_chi0(dv, tol=1e-10, band_range=(50, 128))
     torch.cuda.synchronize()
     assert rel_l2((a + b).cpu().numpy(), full.cpu().numpy()).max() < 1e-8
+
+
+def test_mixed_precision_full_size(mid):
+    """The mixed path on the bench workload: every solve accepted at 1e-8 by the FP64 true residual,
+    dn within 1e-6 of the plain FP64 path, sampled solutions satisfy the oracle's equation."""
+    from paper_2607_14025_amd import STERN_MIXED
+    cell, psi, wl = mid["cell"], mid["psi"], mid["wl"]
+    dn, info = mid["s"].apply_chi0(mid["dv_t"], tol=1e-8, precision=STERN_MIXED, samples=PAIRS)
+    assert info["n_converged"] == 8192 and info["max_true_resid"] <= 1e-8
+    assert rel_l2(dn.cpu().numpy(), mid["dn"]).max() < 1e-6
+    x = cell.take(info["samples"], wl["miller"])
+    bands = [v for v, _ in PAIRS]
+    b = rhs(cell, psi, wl["dv"], bands, [i for _, i in PAIRS])
+    px = project(psi, x)
+    ax = project(psi, cell.h_apply(px) - wl["eps"][bands][:, None] * px)
+    res = np.linalg.norm(b - ax, axis=1) / np.linalg.norm(b, axis=1)
+    assert res.max() <= 1.05e-8, res

@@ -125,3 +125,28 @@ def test_error_paths(tiny_system, torch_cuda):
     _, info = s.apply_chi0(t["dv"][:1], tol=1e-12, max_iter=2)
     assert info["rc"] == 1 and info["n_converged"] < info["n_solves"]
     s.close()
+
+
+def test_chi0_tiny_mixed_precision(tiny_gpu):
+    """FP32 FFTs + split-BF16 MFMA GEMMs inside FP64 defect correction: dn within 1e-6 of the oracle,
+    every solve accepted by the FP64 true residual."""
+    from paper_2607_14025_amd import STERN_MIXED
+    t = tiny_gpu
+    pairs = [(0, 0), (15, 7)]
+    dn, info = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED, samples=pairs)
+    assert info["n_converged"] == 128 and info["max_true_resid"] <= 1e-10
+    assert rel_l2(dn, t["ref"]["dn"]).max() < 1e-6
+    for k, pr in enumerate(pairs):
+        ref = t["ref"]["x"][t["ref"]["pairs"].index(pr)]
+        assert np.linalg.norm(info["samples"][k] - ref) / np.linalg.norm(ref) < 1e-7
+
+
+def test_mixed_fallback_path(tiny_gpu):
+    """With one defect-correction step and a loose inner tolerance the unconverged solves
+    are re-solved by FP64 PCG from zero and still meet the tolerance."""
+    from paper_2607_14025_amd import STERN_MIXED
+    t = tiny_gpu
+    dn, info = t["sys"].apply_chi0(t["dv"][:2], tol=1e-10, precision=STERN_MIXED, max_outer=1, inner_tol=1e-2)
+    assert info["n_fallback"] > 0
+    assert info["n_converged"] == 32
+    assert rel_l2(dn, t["ref"]["dn"][:2]).max() < 1e-6
