@@ -110,6 +110,10 @@ typedef struct {
      tol fall back to FP64 PCG from zero (0 = 8) */
   double inner_tol;
   int max_outer;
+  /* nonzero: capture one CG iteration (all its launches) into a hipGraph after
+     every active-set compaction and replay it check_every times (ignored when
+     profile != 0) */
+  int use_graph;
 } stern_opts;
 
 /* kernel classes of the per-launch profile */
@@ -170,6 +174,18 @@ int stern_set_occupied(stern_system* sys, int n_occ, const double* psi, const do
  * Returns STERN_OK, STERN_WARN_NOT_CONVERGED, or an error. stats may be NULL. */
 int stern_apply_chi0(stern_system* sys, int n_pert, const double* dv_r, double* dn_r,
                      const stern_opts* opts, stern_stats* stats);
+
+/* Batched apply over n_sys independent cells of uneven size (e.g. different L,
+ * atom counts, bands and grids): dn_r[k] = chi0_k dv_r[k] for each system k,
+ * with n_pert[k] fields. The systems are spread over concurrent HIP streams
+ * (one per worker thread, default priority), each system keeping its own
+ * workspace and per-solve convergence masks; opts applies to every system.
+ * Every system must have had set_occupied; no system may appear twice.
+ * stats (may be NULL) accumulates over all systems (iters/resid arrays are
+ * ignored). Returns the first error, else STERN_WARN_NOT_CONVERGED if any
+ * solve missed tol, else STERN_OK. Synchronous: all work is complete on return. */
+int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert, const double* const* dv_r,
+                          double* const* dn_r, const stern_opts* opts, stern_stats* stats);
 
 /* out = (H - shift_k) c_k for n_vec coefficient rows (canonical order), host or
  * device memory; shift may be NULL (zero). Exposes the H apply of the solver. */

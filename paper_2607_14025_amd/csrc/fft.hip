@@ -13,6 +13,7 @@
 // elements, so inverse stage 2, the V_loc multiply and forward stage 1 happen
 // in registers without an LDS round trip.
 #include <algorithm>
+#include <mutex>
 
 #include "fft_dev.hpp"
 #include "kernels.hpp"
@@ -526,15 +527,18 @@ __global__ __launch_bounds__(plane_nt<N>()) void k_plane_dn(const Z64* __restric
   }
 }
 
-// Raise the dynamic LDS limit of a plane kernel once per instantiation.
+// Raise the dynamic LDS limit of a plane kernel once per instantiation
+// (thread-safe: several host threads may launch concurrently).
 void set_lds(const void* kernel, size_t bytes) {
-  static const void* done[128];
+  static std::mutex mu;
+  static const void* done[256];
   static int ndone = 0;
   if (bytes <= 64 * 1024) return;
+  std::lock_guard<std::mutex> lock(mu);
   for (int i = 0; i < ndone; ++i)
     if (done[i] == kernel) return;
   (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (ndone < 128) done[ndone++] = kernel;
+  if (ndone < 256) done[ndone++] = kernel;
 }
 
 }  // namespace

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/stern.h"
@@ -85,6 +86,7 @@ struct stern_system {
   int device = 0;
   int n_cu = 256;
   hipStream_t stream = nullptr;
+  hipStream_t own_stream = nullptr;  // non-blocking stream for graph capture (created on demand)
   CellParams cell;
   HostBasis hb;
   int n_atoms = 0, natoms_pad = 0;
@@ -148,6 +150,8 @@ struct stern_system {
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+    own_stream = nullptr;
   }
 };
 
@@ -389,9 +393,40 @@ struct Scope {
 };
 
 
+// Runs `body` (one CG iteration's launches on the system stream) `steps` times:
+// eagerly, or captured once into a hipGraph and replayed.
+template <class F>
+int run_steps(stern_system* S, int steps, bool graph, F&& body) {
+  if (steps <= 0) return 0;
+  if (!graph || S->prof_on) {
+    for (int k = 0; k < steps; ++k) CHECKED(body());
+    return 0;
+  }
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  HIPOK(hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal));
+  const int rc = body();
+  hipError_t e = hipStreamEndCapture(S->stream, &g);
+  if (rc < 0) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(STERN_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return fail(STERN_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  for (int k = 0; k < steps && e == hipSuccess; ++k) e = hipGraphLaunch(ex, S->stream);
+  (void)hipGraphExecDestroy(ex);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return fail(STERN_ERR_HIP, "hipGraphLaunch: %s", hipGetErrorString(e));
+  return 0;
+}
+
 // Plain FP64 projected PCG from zero on the solves in `list` (batch row indices).
 int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, int max_iter,
-              int check_every, int& n_restart, double vecb) {
+              int check_every, int& n_restart, double vecb, bool use_graph) {
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   std::vector<int> h_flag(ns_all), act, flist;
@@ -415,13 +450,14 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
     HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
     const int* L = S->list_act.as<int>();
     const int nsteps = std::min(check_every, max_iter - it);
-    for (int k = 0; k < nsteps; ++k) {
+    CHECKED(run_steps(S, nsteps, use_graph && it > 0, [&]() -> int {
       CHECKED(apply_h_rows(S, cs.p, cs.q, L, na, cs.eps));
       CHECKED(apply_pc_rows(S, cs.q, L, na));
       CHECKED(timed(S, STERN_K_CG, vecb * na * 7.0, 0.0, [&] { launch_cg_alpha(cs, L, na, tol * tol, st); }));
       CHECKED(apply_pc_rows(S, cs.z, L, na));
       CHECKED(timed(S, STERN_K_CG, vecb * na * 4.0, 0.0, [&] { launch_cg_beta(cs, L, na, st); }));
-    }
+      return 0;
+    }));
     it += nsteps;
     CHECKED(launch_check());
     HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -462,7 +498,8 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
 //   until ||r|| <= tol ||b||; solves still above tol after max_outer steps are
 //   re-solved by FP64 PCG from zero.
 int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, double inner_tol,
-              int max_outer, int max_iter, int check_every, int& n_restart, int& n_fallback, double vecb) {
+              int max_outer, int max_iter, int check_every, int& n_restart, int& n_fallback, double vecb,
+              bool use_graph) {
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   const int K = S->hb.npw_pad;
@@ -493,14 +530,15 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       HIPOK(hipMemcpyAsync(S->list_f.p, iact.data(), ni * sizeof(int), hipMemcpyHostToDevice, st));
       const int* F = S->list_f.as<int>();
       const int nsteps = std::min(check_every, max_inner - it);
-      for (int k = 0; k < nsteps; ++k) {
+      CHECKED(run_steps(S, nsteps, use_graph && (it > 0 || outer > 0), [&]() -> int {
         CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
         CHECKED(apply_pc32_rows(S, c32.q, F, ni));
         CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 7.0, 0.0,
                       [&] { launch_cg32_alpha(c32, F, ni, inner_tol * inner_tol, st); }));
         CHECKED(apply_pc32_rows(S, c32.z, F, ni));
         CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 4.0, 0.0, [&] { launch_cg32_beta(c32, F, ni, st); }));
-      }
+        return 0;
+      }));
       it += nsteps;
       CHECKED(launch_check());
       HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -526,7 +564,7 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
   }
   if (!act.empty()) {
     n_fallback += (int)act.size();
-    CHECKED(run_pcg64(S, cs, act, tol, max_iter, check_every, n_restart, vecb));
+    CHECKED(run_pcg64(S, cs, act, tol, max_iter, check_every, n_restart, vecb, use_graph));
   }
   return 0;
 }
@@ -763,8 +801,26 @@ int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int
   return rows_out(S, n_vec, S->wp.as<Z64>(), nullptr, out, mem_kind);
 }
 
+static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, double* dn_r, const stern_opts* opts,
+                           stern_stats* stats);
+
 int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn_r, const stern_opts* opts,
                      stern_stats* stats) {
+  if (!S || !opts || !opts->use_graph || opts->profile) return apply_chi0_impl(S, n_pert, dv_r, dn_r, opts, stats);
+  // stream capture is not allowed on the legacy default stream: run on the system's own stream
+  Scope sc(S->device);
+  if (!S->own_stream) HIPOK(hipStreamCreateWithFlags(&S->own_stream, hipStreamNonBlocking));
+  HIPOK(hipStreamSynchronize(S->stream));
+  hipStream_t caller = S->stream;
+  S->stream = S->own_stream;
+  const int rc = apply_chi0_impl(S, n_pert, dv_r, dn_r, opts, stats);
+  (void)hipStreamSynchronize(S->stream);
+  S->stream = caller;
+  return rc;
+}
+
+static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, double* dn_r, const stern_opts* opts,
+                           stern_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
@@ -797,6 +853,7 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
   const double tol = opts->tol;
   const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
   const int max_outer = opts->max_outer > 0 ? opts->max_outer : 8;
+  const bool use_graph = opts->use_graph != 0;
   const double vecb = (double)hb.npw * sizeof(Z64);  // bytes of one coefficient vector
   S->prof_on = opts->profile != 0;
   S->recs.clear();
@@ -869,9 +926,10 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
     std::vector<int> all(ns);
     for (int s = 0; s < ns; ++s) all[s] = s;
     if (opts->precision == STERN_MIXED) {
-      CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb));
+      CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
+                        use_graph));
     } else {
-      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb));
+      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph));
     }
     // dn_i = 4/Omega Re sum_v conj(psi_v(r)) x_{v,i}(r)
     CHECKED(timed(S, STERN_K_XINV, ns * (vecb + (double)N * hb.ncol * 16.0), 0.0,
@@ -944,6 +1002,84 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
     stats->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return nconv == nsol ? STERN_OK : STERN_WARN_NOT_CONVERGED;
+}
+
+int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert, const double* const* dv_r,
+                          double* const* dn_r, const stern_opts* opts, stern_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (n_sys <= 0 || !sys || !n_pert || !dv_r || !dn_r || !opts)
+    return fail(STERN_ERR_INVALID_ARG, "need n_sys > 0 and non-NULL arrays");
+  for (int k = 0; k < n_sys; ++k) {
+    if (!sys[k]) return fail(STERN_ERR_INVALID_ARG, "system %d is NULL", k);
+    if (!sys[k]->have_occ) return fail(STERN_ERR_STATE, "system %d has no occupied states", k);
+    for (int j = 0; j < k; ++j)
+      if (sys[j] == sys[k]) return fail(STERN_ERR_INVALID_ARG, "system %d appears twice", k);
+  }
+  const int workers = std::min(n_sys, 8);
+  std::vector<hipStream_t> streams(workers, nullptr);
+  std::vector<hipStream_t> saved(n_sys);
+  for (int k = 0; k < n_sys; ++k) {  // inputs were produced on the systems' own streams
+    Scope sc(sys[k]->device);
+    HIPOK(hipStreamSynchronize(sys[k]->stream));
+    saved[k] = sys[k]->stream;
+  }
+  for (int w = 0; w < workers; ++w) {
+    Scope sc(sys[w]->device);
+    HIPOK(hipStreamCreateWithFlags(&streams[w], hipStreamNonBlocking));
+  }
+  std::vector<int> rc(n_sys, 0);
+  std::vector<stern_stats> st(n_sys);
+  std::vector<std::string> err(n_sys);
+  std::vector<std::thread> pool;
+  for (int w = 0; w < workers; ++w) {
+    pool.emplace_back([&, w]() {
+      for (int k = w; k < n_sys; k += workers) {
+        stern_system* S = sys[k];
+        S->stream = streams[w];
+        std::memset(&st[k], 0, sizeof(stern_stats));
+        rc[k] = stern_apply_chi0(S, n_pert[k], dv_r[k], dn_r[k], opts, stats ? &st[k] : nullptr);
+        if (rc[k] < 0) err[k] = g_err;
+        S->stream = saved[k];
+      }
+    });
+  }
+  for (auto& t : pool) t.join();
+  for (int w = 0; w < workers; ++w) {
+    Scope sc(sys[w]->device);
+    (void)hipStreamDestroy(streams[w]);
+  }
+  int out = STERN_OK;
+  for (int k = 0; k < n_sys; ++k) {
+    if (rc[k] < 0) {
+      g_err = "system " + std::to_string(k) + ": " + err[k];
+      return rc[k];
+    }
+    if (rc[k] == STERN_WARN_NOT_CONVERGED) out = STERN_WARN_NOT_CONVERGED;
+  }
+  if (stats) {
+    stern_stats a;
+    std::memset(&a, 0, sizeof a);
+    for (int k = 0; k < n_sys; ++k) {
+      a.n_solves += st[k].n_solves;
+      a.n_converged += st[k].n_converged;
+      a.n_fallback += st[k].n_fallback;
+      a.n_restarts += st[k].n_restarts;
+      a.total_iters += st[k].total_iters;
+      a.max_iters = std::max(a.max_iters, st[k].max_iters);
+      a.max_true_resid = std::max(a.max_true_resid, st[k].max_true_resid);
+      for (int c = 0; c < STERN_NKERNEL; ++c) {
+        a.kernel_launches[c] += st[k].kernel_launches[c];
+        a.kernel_ms[c] += st[k].kernel_ms[c];
+        a.kernel_bytes[c] += st[k].kernel_bytes[c];
+        a.kernel_flops[c] += st[k].kernel_flops[c];
+      }
+    }
+    a.iters = stats->iters;
+    a.resid = stats->resid;
+    a.wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    *stats = a;
+  }
+  return out;
 }
 
 void stern_free(stern_system* S) {

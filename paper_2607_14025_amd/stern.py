@@ -23,7 +23,7 @@ STERN_MEM_HOST = 0
 STERN_MEM_DEVICE = 1
 
 EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
-            "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
+            "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
 
 
 class SternError(RuntimeError):
@@ -47,7 +47,7 @@ class Opts(C.Structure):
                 ("mem_kind", C.c_int), ("band_begin", C.c_int), ("band_end", C.c_int), ("max_batch", C.c_int),
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
                 ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int)]
+                ("max_outer", C.c_int), ("use_graph", C.c_int)]
 
 
 NKERNEL = 16
@@ -79,13 +79,15 @@ def lib():
         L.stern_query.argtypes = [C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_double)]
         L.stern_set_occupied.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_chi0.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, P(Opts), P(Stats)]
+        L.stern_apply_chi0_many.argtypes = [C.c_int, P(C.c_void_p), P(C.c_int), P(C.c_void_p), P(C.c_void_p),
+                                            P(Opts), P(Stats)]
         L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_free.argtypes = [C.c_void_p]
         L.stern_free.restype = None
         L.stern_last_error.restype = C.c_char_p
         for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied",
-                     "stern_apply_chi0", "stern_apply_h", "stern_apply_pc"):
+                     "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -134,6 +136,60 @@ def _torch_stream():
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
+def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
+              inner_tol=0.0, max_outer=0, use_graph=False):
+    o = Opts()
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.precision = int(precision)
+    o.guess = STERN_GUESS_ZERO
+    o.mem_kind = mem_kind
+    o.band_begin, o.band_end = (0, 0) if band_range is None else (int(band_range[0]), int(band_range[1]))
+    o.max_batch = int(max_batch)
+    o.check_every = int(check_every)
+    o.profile = 1 if profile else 0
+    o.inner_tol = float(inner_tol)
+    o.max_outer = int(max_outer)
+    o.use_graph = 1 if use_graph else 0
+    return o
+
+
+def _kernels(st):
+    return {KERNEL_NAMES[k]: dict(launches=int(st.kernel_launches[k]), ms=float(st.kernel_ms[k]),
+                                  bytes=float(st.kernel_bytes[k]), flops=float(st.kernel_flops[k]))
+            for k in range(NKERNEL) if st.kernel_launches[k] > 0}
+
+
+def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, max_iter=0, check_every=0,
+                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False):
+    """Batched apply over independent systems (stern_apply_chi0_many); returns (list of dn, info)."""
+    n = len(systems)
+    ptrs = [_ptr(d, False) for d in dvs]
+    mk = ptrs[0][1]
+    if any(p[1] != mk for p in ptrs):
+        raise ValueError("all fields must be host arrays or all CUDA tensors")
+    if dn_outs is None:
+        if mk == STERN_MEM_DEVICE:
+            import torch
+            dn_outs = [torch.empty_like(d) for d in dvs]
+        else:
+            dn_outs = [np.empty(d.shape, dtype=np.float64) for d in dvs]
+    outs = [_ptr(d, False) for d in dn_outs]
+    hs = (C.c_void_p * n)(*[s._h for s in systems])
+    npert = (C.c_int * n)(*[d.shape[0] for d in dvs])
+    dvp = (C.c_void_p * n)(*[p[0] for p in ptrs])
+    dnp = (C.c_void_p * n)(*[p[0] for p in outs])
+    o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph)
+    st = Stats()
+    rc = _check(lib().stern_apply_chi0_many(n, hs, npert, dvp, dnp, C.byref(o), C.byref(st)))
+    info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
+                n_restarts=st.n_restarts, total_iters=st.total_iters, max_iters=st.max_iters, wall_s=st.wall_s,
+                max_true_resid=st.max_true_resid)
+    if profile:
+        info["kernels"] = _kernels(st)
+    return dn_outs, info
+
+
 class System:
     """One cell on one GPU (stern_init_system ... stern_free)."""
 
@@ -171,7 +227,7 @@ class System:
         self.n_occ = n_occ
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
-                   samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0):
+                   samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned."""
@@ -186,18 +242,8 @@ class System:
         op, mk2, k2 = _ptr(dn_out, False)
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
-        o = Opts()
-        o.tol = float(tol)
-        o.max_iter = int(max_iter)
-        o.precision = int(precision)
-        o.guess = STERN_GUESS_ZERO
-        o.mem_kind = mk
-        o.band_begin, o.band_end = (0, 0) if band_range is None else (int(band_range[0]), int(band_range[1]))
-        o.max_batch = int(max_batch)
-        o.check_every = int(check_every)
-        o.profile = 1 if profile else 0
-        o.inner_tol = float(inner_tol)
-        o.max_outer = int(max_outer)
+        o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
+                      use_graph)
         keep = []
         sx = None
         if samples:
@@ -220,9 +266,7 @@ class System:
                     total_iters=st.total_iters, max_iters=st.max_iters, wall_s=st.wall_s,
                     max_true_resid=st.max_true_resid, iters=iters, resid=resid, samples=sx)
         if profile:
-            info["kernels"] = {KERNEL_NAMES[k]: dict(launches=int(st.kernel_launches[k]), ms=float(st.kernel_ms[k]),
-                                                     bytes=float(st.kernel_bytes[k]), flops=float(st.kernel_flops[k]))
-                               for k in range(NKERNEL) if st.kernel_launches[k] > 0}
+            info["kernels"] = _kernels(st)
         return dn_out, info
 
     def apply_h(self, c, shift=None):

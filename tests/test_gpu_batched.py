@@ -1,0 +1,69 @@
+"""Batched uneven cells (stern_apply_chi0_many) and hipGraph-replayed iterations."""
+import numpy as np
+import pytest
+
+from oracle import OracleCell, apply_chi0
+from oracle.sternheimer import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def cells():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2607_14025_amd import System
+    from synth.cells import batched_specs, random_dv
+    from synth.inputs import load_ground_state
+    specs = sorted(batched_specs(), key=lambda s: s.L)[:3]   # the three smallest uneven cells
+    out = []
+    for sp in specs:
+        gs = load_ground_state(sp)
+        s = System(sp.L, sp.ecut, gs["pos"], sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width)
+        s.set_occupied(gs["psi"], gs["eps"])
+        _, _, dv = random_dv(gs["spec"], n_pert=4, N=gs["N"])
+        out.append(dict(s=s, gs=gs, dv=dv))
+    yield out
+    for c in out:
+        c["s"].close()
+
+
+def test_cells_are_uneven(cells):
+    grids = {c["s"].fft_n for c in cells}
+    bands = {c["s"].n_occ for c in cells}
+    assert len(bands) > 1 and all(n in (32, 36, 48, 54) for n in grids)
+
+
+def test_many_equals_single_calls_and_oracle(cells):
+    from paper_2607_14025_amd import apply_chi0_many
+    dns, info = apply_chi0_many([c["s"] for c in cells], [c["dv"] for c in cells], tol=1e-10)
+    assert info["n_converged"] == info["n_solves"] == sum(4 * c["s"].n_occ for c in cells)
+    for c, dn in zip(cells, dns):
+        single, _ = c["s"].apply_chi0(c["dv"], tol=1e-10)
+        assert np.array_equal(single, dn)
+    c = cells[0]
+    sp, gs = c["gs"]["spec"], c["gs"]
+    cell = OracleCell(sp.L, sp.ecut, gs["pos"])
+    ref = apply_chi0(cell, cell.take(gs["psi"], gs["miller"]), gs["eps"], c["dv"], tol=1e-12)
+    assert rel_l2(dns[0], ref["dn"]).max() < 1e-9
+
+
+def test_graph_replay_equals_eager(cells):
+    from paper_2607_14025_amd import STERN_MIXED
+    c = cells[1]
+    eager, i1 = c["s"].apply_chi0(c["dv"], tol=1e-10, check_every=3)
+    graph, i2 = c["s"].apply_chi0(c["dv"], tol=1e-10, check_every=3, use_graph=True)
+    assert np.array_equal(eager, graph) and i1["total_iters"] == i2["total_iters"]
+    e32, _ = c["s"].apply_chi0(c["dv"], tol=1e-10, precision=STERN_MIXED)
+    g32, _ = c["s"].apply_chi0(c["dv"], tol=1e-10, precision=STERN_MIXED, use_graph=True)
+    assert np.array_equal(e32, g32)
+
+
+def test_many_mixed_precision(cells):
+    from paper_2607_14025_amd import apply_chi0_many, STERN_MIXED
+    ref, _ = apply_chi0_many([c["s"] for c in cells], [c["dv"] for c in cells], tol=1e-10)
+    dns, info = apply_chi0_many([c["s"] for c in cells], [c["dv"] for c in cells], tol=1e-10,
+                                precision=STERN_MIXED, use_graph=True)
+    assert info["n_converged"] == info["n_solves"]
+    for a, b in zip(dns, ref):
+        assert rel_l2(a, b).max() < 1e-6
