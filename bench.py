@@ -3,11 +3,15 @@
 A step is one stern_apply_chi0 call on the mid cell (L = 20 bohr, 64 atoms,
 25 Ry: 16,879 plane waves, 72^3 grid, 128 occupied bands x 64 band-limited
 fields = 8,192 Sternheimer solves, FP64 true residual <= 1e-8), inputs already
-resident in HBM. Prints one JSON line with the throughput, the roofline of the
-dominant kernel (per-launch HIP events on the library's stream) and the CPU
-oracle timed on a bounded sample of the same workload.
+resident in HBM. The headline path is the learned guess and preconditioner
+(trained beforehand, untimed, on two other seeded cells of the same model and
+size) with mixed-precision defect correction; the plain FP64 path is timed
+on the same cell as the baseline. Prints one JSON line with the throughput,
+the roofline of the dominant kernel (per-launch HIP events on the library's
+stream) and the CPU oracle timed on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--path learned-mixed|mixed|fp64]
 """
 from __future__ import annotations
 
@@ -71,7 +75,8 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--cpu-bands", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--path", choices=["learned-mixed", "mixed", "fp64"], default="learned-mixed")
+    ap.add_argument("--train-solves", type=int, default=8192)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the chi0 apply of one cell runs on one MI355X); "
@@ -80,7 +85,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2607_14025_amd import System, STERN_FP64, STERN_MIXED
+    from paper_2607_14025_amd import Model, System, STERN_FP64, STERN_MIXED
     from synth.cells import MID
     from synth.inputs import load_workload
 
@@ -89,18 +94,41 @@ def main():
     print("bench: loading mid cell inputs", file=sys.stderr, flush=True)
     wl = load_workload(MID)
     spec = wl["spec"]
-    s = System(spec.L, spec.ecut, wl["pos"], spec.vloc_amp, spec.vloc_sigma, spec.kb_D, spec.kb_width, device=0)
-    psi = torch.from_numpy(np.ascontiguousarray(wl["psi"])).to(dev)
-    eps = torch.from_numpy(wl["eps"]).to(dev)
-    s.set_occupied(psi, eps)
+
+    def make_system(w):
+        sp = w["spec"]
+        sy = System(sp.L, sp.ecut, w["pos"], sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width, device=0)
+        sy.set_occupied(torch.from_numpy(np.ascontiguousarray(w["psi"])).to(dev), torch.from_numpy(w["eps"]).to(dev))
+        return sy
+
+    s = make_system(wl)
     dv = torch.from_numpy(wl["dv"]).to(dev)
     dn = torch.empty_like(dv)
     n_pert = dv.shape[0]
     n_solves = n_pert * s.n_occ
 
-    def run(precision, steps, warmup, label):
+    model = None
+    train = None
+    if args.path == "learned-mixed":
+        print("bench: training the learned guess and preconditioner on two other mid cells", file=sys.stderr,
+              flush=True)
+        tr_sys, tr_dv = [], []
+        for sid in (1, 2):
+            w = load_workload(MID.with_system(sid))
+            tr_sys.append(make_system(w))
+            tr_dv.append(torch.from_numpy(w["dv"]).to(dev))
+        model = Model(seed=0, device=0)
+        train = model.train(tr_sys, tr_dv, epochs=4, batch=16, lr=1e-3, max_solves=args.train_solves, tol=1e-10,
+                            seed=1, prec_epochs=4)
+        for t in tr_sys:
+            t.close()
+        del tr_dv
+        torch.cuda.synchronize()
+        print(f"bench: training done: {train}", file=sys.stderr, flush=True)
+
+    def run(precision, steps, warmup, label, mdl=None):
         for w in range(warmup):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision)
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl)
             print(f"bench: {label} warmup {w}: {info['n_converged']}/{info['n_solves']} converged in "
                   f"{info['wall_s']:.2f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -110,7 +138,7 @@ def main():
         fallback = 0
         t0 = time.perf_counter()
         for k in range(steps):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, precision=precision)
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, precision=precision, model=mdl)
             conv += info["n_converged"]
             fallback += info["n_fallback"]
             iters.append(info["total_iters"] / max(1, info["n_solves"]))
@@ -123,21 +151,27 @@ def main():
                   f"fallback {info['n_fallback']}", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        return dict(value=conv / dt, dt=dt, kern=kern, iters=float(np.mean(iters)), fallback=fallback)
+        r = dict(value=conv / dt, dt=dt, kern=kern, iters=float(np.mean(iters)), fallback=fallback)
+        if label != "fp64":  # dn against the plain FP64 path at the same tolerance
+            s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl)
+            torch.cuda.synchronize()
+            r["dn_rel_err_vs_fp64"] = ((dn - ref).reshape(n_pert, -1).norm(dim=1)
+                                       / ref.reshape(n_pert, -1).norm(dim=1)).max().item()
+        return r
 
+    ref = torch.empty_like(dv)
+    s.apply_chi0(dv, tol=args.tol, dn_out=ref, precision=STERN_FP64)
+    torch.cuda.synchronize()
     plain = run(STERN_FP64, args.steps, args.warmup, "fp64")
     head = plain
-    mixed = None
-    if args.precision == "mixed":
+    mixed = learned = learned_fp64 = None
+    if args.path in ("mixed", "learned-mixed"):
         mixed = run(STERN_MIXED, args.steps, args.warmup, "mixed")
-        torch.cuda.synchronize()
-        ref = torch.empty_like(dv)
-        s.apply_chi0(dv, tol=args.tol, dn_out=ref, precision=STERN_FP64)
-        s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=STERN_MIXED)
-        torch.cuda.synchronize()
-        err = ((dn - ref).reshape(n_pert, -1).norm(dim=1) / ref.reshape(n_pert, -1).norm(dim=1)).max().item()
-        mixed["dn_rel_err_vs_fp64"] = err
         head = mixed
+    if args.path == "learned-mixed":
+        learned_fp64 = run(STERN_FP64, args.steps, args.warmup, "learned-fp64", model)
+        learned = run(STERN_MIXED, args.steps, args.warmup, "learned-mixed", model)
+        head = learned
     value = head["value"]
     dt = head["dt"]
     kern = head["kern"]
@@ -177,14 +211,27 @@ def main():
                               fallback_solves=mixed["fallback"], dn_rel_err_vs_fp64=mixed["dn_rel_err_vs_fp64"]),
                    speedup_vs_plain_fp64=mixed["value"] / plain["value"])
         dtype = "f32+bf16/f64"
-    else:
+    if learned is not None:
+        cfg.update(path="learned guess + learned diagonal preconditioner (BF16 MFMA conv net on the coarse grid), "
+                        "FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction; Teter FP64 PCG fallback",
+                   learned_fp64=dict(solves_per_s=learned_fp64["value"], mean_cg_iters=learned_fp64["iters"],
+                                     fallback_solves=learned_fp64["fallback"],
+                                     dn_rel_err_vs_fp64=learned_fp64["dn_rel_err_vs_fp64"]),
+                   learned_mixed=dict(solves_per_s=learned["value"], mean_inner_iters=learned["iters"],
+                                      fallback_solves=learned["fallback"],
+                                      dn_rel_err_vs_fp64=learned["dn_rel_err_vs_fp64"]),
+                   training=dict(cells="two other seeded mid cells (same L, Ecut, atom count)", **train),
+                   speedup_vs_plain_fp64=learned["value"] / plain["value"])
+    if mixed is None:
         cfg.update(path="plain FP64 projected Teter-PCG")
         dtype = "f64"
-    line = dict(metric="converged Sternheimer solves/s at resid<=1e-8", value=value, unit="solves/s", n_gpus=1,
+    line = dict(metric="converged Sternheimer solves/s at resid≤1e-8 (learned+mixed vs plain FP64)", value=value, unit="solves/s", n_gpus=1,
                 steps=args.steps, warmup=args.warmup, ms_per_step=dt / args.steps * 1e3, higher_is_better=True,
                 scaling="weak", vs_baseline=None, dtype=dtype, data="synthetic", config=cfg,
                 roofline=roof, cpu_baseline=cpu, kernels=breakdown)
     s.close()
+    if model is not None:
+        model.close()
     print(json.dumps(line), flush=True)
 
 

@@ -55,8 +55,9 @@ extern "C" {
 #define STERN_FP64 0
 #define STERN_MIXED 1
 
-/* initial guess */
+/* initial guess: zero, or the learned guess of a trained stern_model */
 #define STERN_GUESS_ZERO 0
+#define STERN_GUESS_LEARNED 1
 
 /* where pointer arguments live */
 #define STERN_MEM_HOST 0
@@ -88,8 +89,8 @@ typedef struct {
 typedef struct {
   double tol;          /* relative FP64 true residual ||b - A x|| / ||b|| to accept */
   int max_iter;        /* CG iterations per solve (0 = 1000) */
-  int precision;       /* STERN_FP64 */
-  int guess;           /* STERN_GUESS_ZERO */
+  int precision;       /* STERN_FP64 or STERN_MIXED */
+  int guess;           /* STERN_GUESS_ZERO or STERN_GUESS_LEARNED (needs model) */
   int mem_kind;        /* STERN_MEM_HOST or STERN_MEM_DEVICE for dv_r / dn_r */
   int band_begin;      /* solve bands [band_begin, band_end); band_end <= 0 means n_occ.
                           P_c always uses every occupied band; dn is the partial sum. */
@@ -114,6 +115,8 @@ typedef struct {
      every active-set compaction and replay it check_every times (ignored when
      profile != 0) */
   int use_graph;
+  /* trained stern_model for STERN_GUESS_LEARNED (not owned) */
+  const struct stern_model* model;
 } stern_opts;
 
 /* kernel classes of the per-launch profile */
@@ -133,13 +136,16 @@ typedef struct {
 #define STERN_K_X32 13        /* FP32 x pencils (both directions) */
 #define STERN_K_GEMM_BF16 14  /* split-BF16 MFMA GEMMs (KB and P_c) */
 #define STERN_K_CG32 15       /* FP32 CG updates with FP64 dots */
-#define STERN_NKERNEL 16
+#define STERN_K_NET 16        /* learned guess and K: coarse-grid transforms, BF16 MFMA convolutions, head */
+#define STERN_NKERNEL 17
 
 typedef struct {
   int n_solves;        /* (band, perturbation) pairs solved */
   int n_converged;     /* pairs with FP64 true relative residual <= tol */
-  int n_fallback;      /* mixed: pairs re-solved by FP64 PCG from zero after max_outer steps */
+  int n_fallback;      /* pairs re-solved by Teter FP64 PCG from zero: mixed, after max_outer steps;
+                          learned guess, after missing tol with the learned start and K */
   int n_restarts;      /* PCG restarts from the FP64 true residual */
+  int n_guess_rejected;/* learned guesses rejected (non-finite, or residual >= ||b||): started from zero */
   long long total_iters;
   int max_iters;
   double wall_s;       /* wall time of the call */
@@ -186,6 +192,69 @@ int stern_apply_chi0(stern_system* sys, int n_pert, const double* dv_r, double* 
  * solve missed tol, else STERN_OK. Synchronous: all work is complete on return. */
 int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert, const double* const* dv_r,
                           double* const* dn_r, const stern_opts* opts, stern_stats* stats);
+
+/* ---- learned initial guess and diagonal preconditioner ----
+ * A small 3-D convolutional net (3 periodic 3x3x3 layers, 16 channels, ReLU,
+ * BF16 weights, FP32 accumulation) on the coarse (N/2)^3 grid, which holds the
+ * wave-function sphere exactly. Input channels per (v, i): psi_v(r), the
+ * right-hand side b_{v,i}(r) / ||b|| (the sphere part of -P_c dV_i psi_v) and
+ * eps_v; output: x0(r) / ||b||, mapped back to the sphere and projected by
+ * P_c. A linear head on the grid-averaged second hidden layer (plus eps_v and
+ * T_v) gives 8 knot values z_k on u = log2(|G|^2 / 2 T_v) in [-6, 8]; the
+ * solve's diagonal preconditioner is K(G) = Teter(G) softplus(z(u)) / ln 2,
+ * positive, equal to Teter when the head is zero.
+ * The net is fitted to the solutions the plain FP64 path produces (relative L2
+ * of x0); then the head to the error left after the guess, minimising
+ * ||P_c (K o r0) - e0||^2 / ||e0||^2 with r0 = b - A x0 and e0 = x* - x0.
+ * The FP64 true residual still judges every solve: a guess that is non-finite
+ * or whose residual is not below ||b|| is dropped (the solve starts from zero),
+ * and a solve that misses tol with the learned start and K is re-solved by
+ * Teter-preconditioned FP64 PCG from zero (counted in n_fallback).
+ * Needs an even grid N with N/2 >= 2 nmax + 1 (STERN_ERR_UNSUPPORTED otherwise). */
+typedef struct stern_model stern_model;
+
+typedef struct {
+  int epochs;          /* passes over the training solves for the net (0 = 4) */
+  int batch;           /* solves per Adam step (0 = 16) */
+  double lr;           /* Adam learning rate of the net (0 = 1e-3) */
+  int max_solves;      /* cap on training solves, drawn at random (0 = 4096) */
+  double tol;          /* tolerance of the FP64 solves that make the targets (0 = 1e-8) */
+  unsigned long long seed;
+  int prec_epochs;     /* passes for the preconditioner head (0 = 4, < 0 = keep Teter) */
+  double prec_lr;      /* its Adam learning rate (0 = 1e-2) */
+  int prec_max_solves; /* cap on its training solves (0 = 1024) */
+} stern_train_opts;
+
+typedef struct {
+  int n_samples;       /* training solves used for the net */
+  int steps;           /* Adam steps */
+  double loss_first;   /* root mean relative squared L2 error of x0 over the first epoch */
+  double loss_last;    /* ... over the last epoch */
+  int prec_samples;    /* training solves used for the preconditioner head */
+  double prec_loss_first; /* mean ||P_c (K o r0) - e0||^2 / ||e0||^2, first epoch (head at zero = Teter) */
+  double prec_loss_last;  /* ... last epoch */
+  double wall_s;
+} stern_train_stats;
+
+/* New model with seeded random weights (the output layer starts near zero, the
+ * preconditioner head at zero). */
+int stern_model_create(int device, unsigned long long seed, stern_model** out);
+/* Trains on n_sys systems (same coarse grid, each with set_occupied): solves
+ * their fields dv_r[k] ([n_pert[k]][N][N][N], host or device per mem_kind) with
+ * the plain FP64 path, fits the net to the solutions, then solves them again
+ * from the trained guess and fits the preconditioner head. Uses the systems'
+ * workspaces and streams; synchronous. */
+int stern_model_train(stern_model* m, int n_sys, stern_system* const* sys, const int* n_pert,
+                      const double* const* dv_r, int mem_kind, const stern_train_opts* opts,
+                      stern_train_stats* stats);
+/* Number of float parameters: per conv layer l = 0..2, weights [16 out][27
+ * neighbours (dx, dy, dz in -1..1, dz fastest)][16 in] then 16 biases; then the
+ * head, weights [8 knots][18 features] and 8 biases. Copy them out / in (host
+ * memory, n floats); set_weights enables the head when any of it is nonzero. */
+int stern_model_num_params(void);
+int stern_model_get_weights(const stern_model* m, float* w, int n);
+int stern_model_set_weights(stern_model* m, const float* w, int n);
+void stern_model_free(stern_model* m);
 
 /* out = (H - shift_k) c_k for n_vec coefficient rows (canonical order), host or
  * device memory; shift may be NULL (zero). Exposes the H apply of the solver. */

@@ -32,7 +32,7 @@ int default_fft_n(double L, double ecut) {
   return n;
 }
 
-std::string build_basis(const CellParams& c, HostBasis& hb) {
+std::string build_basis(const CellParams& c, HostBasis& hb, bool sphere_only) {
   if (!(c.L > 0) || !(c.ecut > 0)) return "L and ecut must be positive";
   hb = HostBasis();
   hb.L = c.L;
@@ -43,7 +43,7 @@ std::string build_basis(const CellParams& c, HostBasis& hb) {
   const double r2 = c.ecut * c.L * c.L / (kTwoPi * kTwoPi);
   const int nm = isqrt_floor(r2);
   const int N = hb.N;
-  if (N < 2 * (2 * nm) + 1) return "fft_n too small for the 4 ecut sphere";
+  if (N < (sphere_only ? 2 * nm + 1 : 2 * (2 * nm) + 1)) return "fft_n too small for the 4 ecut sphere";
 
   // canonical order: |n|^2, then n_x, n_y, n_z
   std::vector<std::tuple<int, int, int, int>> pts;

@@ -33,7 +33,9 @@ struct HostBasis {
 // Smallest 2^a 3^b >= 2 (floor(2 sqrt(ecut) L / 2 pi) + 1) + 1.
 int default_fft_n(double L, double ecut);
 // Fills everything but needs no GPU. Returns an empty string or an error message.
-std::string build_basis(const CellParams& c, HostBasis& hb);
+// sphere_only: the grid only has to hold the wave-function sphere (N >= 2 nmax + 1),
+// not the products of two wave functions (N >= 4 nmax + 1).
+std::string build_basis(const CellParams& c, HostBasis& hb, bool sphere_only = false);
 // V(r) on the grid, [ix][iy][iz], from V(q) on |q|^2 <= 4 ecut, multiplied by `scale`.
 std::vector<double> vloc_grid(const CellParams& c, const HostBasis& hb, double scale);
 // beta_a(G) rows [n_rows][npw_pad] in column order (rows >= n_atoms are zero).

@@ -31,7 +31,15 @@ __device__ __forceinline__ double teter(double g2h, double invT) {
   return num / (num + 16.0 * y2 * y2);
 }
 
-__global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __restrict__ act) {
+// diagonal preconditioner of solve s at coefficient k: the learned K when given, else Teter
+template <class St>
+__device__ __forceinline__ double precond(const St& S, int s, int k, double iT) {
+  return S.kprec ? (double)S.kprec[(size_t)s * S.npw_pad + k] : teter(S.g2h[k], iT);
+}
+
+// keep == 0: x = 0, r = b. keep != 0: x and r = b - A x are given (a guess).
+// z = K r; ||b||^2; flag 0 (2 when b = 0).
+__global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __restrict__ act, int keep) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   const size_t o = (size_t)s * S.npw_pad;
@@ -40,14 +48,49 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
     const Z64 b = S.b[o + k];
     bb += b.re * b.re + b.im * b.im;
-    S.x[o + k] = zmk(0.0, 0.0);
-    S.r[o + k] = b;
-    S.z[o + k] = zscale(b, teter(S.g2h[k], iT));
+    Z64 r = b;
+    if (keep) {
+      r = S.r[o + k];
+    } else {
+      S.x[o + k] = zmk(0.0, 0.0);
+      S.r[o + k] = b;
+    }
+    S.z[o + k] = zscale(r, precond(S, s, k, iT));
   }
   bb = block_sum(bb, sh);
   if (threadIdx.x == 0) {
     S.bb[s] = bb;
     S.flag[s] = (bb > 0.0) ? 0 : 2;
+  }
+}
+
+// q = A x for a guess x: r = b - q; keep the guess only when ||r|| is finite
+// and below ||b||, else x = 0, r = b. rejected[s] = 1 when dropped.
+__global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int* __restrict__ act,
+                                                            int* __restrict__ rejected) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  const size_t o = (size_t)s * S.npw_pad;
+  double rr = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k], q = S.q[o + k];
+    const double re = b.re - q.re, im = b.im - q.im;
+    rr += re * re + im * im;
+  }
+  rr = block_sum(rr, sh);
+  const bool ok = (rr == rr) && rr < S.bb[s];  // false for NaN
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k], q = S.q[o + k];
+    if (ok) {
+      S.r[o + k] = zmk(b.re - q.re, b.im - q.im);
+    } else {
+      S.r[o + k] = b;
+      S.x[o + k] = zmk(0.0, 0.0);
+    }
+  }
+  if (threadIdx.x == 0) {
+    rejected[s] = ok ? 0 : 1;
+    S.tres[s] = ok ? sqrt(rr / S.bb[s]) : 1.0;
   }
 }
 
@@ -88,7 +131,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_alpha(CgState S, const int* _
     S.x[o + k] = x;
     S.r[o + k] = r;
     rr += r.re * r.re + r.im * r.im;
-    S.z[o + k] = zscale(r, teter(S.g2h[k], iT));
+    S.z[o + k] = zscale(r, precond(S, s, k, iT));
   }
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
@@ -145,7 +188,7 @@ __global__ __launch_bounds__(kCgThreads) void k_true_resid(CgState S, const int*
       const Z64 b = S.b[o + k], q = S.q[o + k];
       const Z64 r = zmk(b.re - q.re, b.im - q.im);
       S.r[o + k] = r;
-      S.z[o + k] = zscale(r, teter(S.g2h[k], iT));
+      S.z[o + k] = zscale(r, precond(S, s, k, iT));
     }
   }
   if (threadIdx.x == 0) {
@@ -216,7 +259,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_init(Cg32State S, const Z64
     rr += (double)r.re * r.re + (double)r.im * r.im;
     S.r[o + k] = r;
     S.d[o + k] = zmk(0.f, 0.f);
-    const float t = (float)teter(S.g2h[k], iT);
+    const float t = (float)precond(S, s, k, iT);
     S.z[o + k] = zmk(r.re * t, r.im * t);
   }
   rr = block_sum(rr, sh);
@@ -262,7 +305,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const in
     S.d[o + k] = d;
     S.r[o + k] = r;
     rr += (double)r.re * r.re + (double)r.im * r.im;
-    const float t = (float)teter(S.g2h[k], iT);
+    const float t = (float)precond(S, s, k, iT);
     S.z[o + k] = zmk(r.re * t, r.im * t);
   }
   rr = block_sum(rr, sh);
@@ -350,8 +393,11 @@ __global__ void k_fill_zero32(Z32* __restrict__ p, size_t n) {
 
 }  // namespace
 
-void launch_cg_init(const CgState& s, const int* act, int n, hipStream_t st) {
-  if (n > 0) k_cg_init<<<n, kCgThreads, 0, st>>>(s, act);
+void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st) {
+  if (n > 0) k_cg_init<<<n, kCgThreads, 0, st>>>(s, act, keep ? 1 : 0);
+}
+void launch_guess_resid(const CgState& s, const int* act, int n, int* rejected, hipStream_t st) {
+  if (n > 0) k_guess_resid<<<n, kCgThreads, 0, st>>>(s, act, rejected);
 }
 void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg_init2<<<n, kCgThreads, 0, st>>>(s, act);

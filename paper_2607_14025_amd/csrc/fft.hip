@@ -176,6 +176,9 @@ __global__ __launch_bounds__(kXThreads) void k_xfwd(const Z<T>* __restrict__ pen
         }
       },
       tw);
+  // the row padding [npw, npw_pad) is kept at zero: the GEMMs reduce over it
+  if (blockIdx.x == 0)
+    for (int k = g.npw + threadIdx.x; k < g.npw_pad; k += kXThreads) dst[k] = zmk(T(0), T(0));
 }
 
 // --------------------------------------------------------------- yz pass ----
@@ -465,6 +468,34 @@ __global__ __launch_bounds__(plane_nt<N>()) void k_plane_full_inv(const Z64* __r
       [&](int y, int j, int r, Z64 v) { op[y * N + j + r * R1] = v; }, c.tw);
 }
 
+// forward yz DFT of full planes in[vec][ix][iy][iz] -> pencils of vector `vec`
+template <int N>
+__global__ __launch_bounds__(plane_nt<N>()) void k_plane_full_fwd(const Z64* __restrict__ in, Z64* __restrict__ pen,
+                                                                 FftGeom g) {
+  using C = PlaneCtx<N, double>;
+  constexpr int LD = C::LD, R1 = C::R1, R2 = C::R2, NT = C::NT;
+  extern __shared__ unsigned char smem_raw[];
+  C c{reinterpret_cast<Z64*>(smem_raw), g.zl, g.ycol, g.nza, g.zact_lo, g.zact_hi,
+      plane_twiddles<N, double>(smem_raw, g)};
+  Z64* P = c.P;
+  const int ix = blockIdx.x;
+  const int vec = blockIdx.y;
+  const Z64* __restrict__ ip = in + ((size_t)vec * N + ix) * N * N;
+  stage<N, R1, -1, false, false, false, NT, N>(
+      N, [&](int y, int j, int r) { return ip[y * N + j + r * R2]; },
+      [&](int y, int j, int r, Z64 v) { P[y * LD + j * R1 + r] = v; }, c.tw);
+  __syncthreads();
+  stage<N, R2, -1, true, false, false, NT, N>(
+      N, [&](int y, int j, int r) { return P[y * LD + j + r * R1]; },
+      [&](int y, int j, int r, Z64 v) {
+        const int z = j + r * R1;
+        if (c.zact(z)) P[y * LD + z] = v;
+      },
+      c.tw);
+  __syncthreads();
+  y_forward_to_pencils<N, double>(c, pen + ((size_t)vec * N + ix) * g.ncol_pad);
+}
+
 // One workgroup per (plane ix, perturbation p): for the nb bands of p in band
 // order, inverse yz DFT of the solution pencils and accumulation of
 // Re conj(psi_v(r)) x(r) in registers (each thread owns the grid points of its
@@ -634,6 +665,14 @@ void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out,
   dim3 grid(g.N, nvec);
   STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_full_inv<NN>, lds),
                          k_plane_full_inv<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, out, g)));
+}
+
+void launch_plane_full_fwd(const FftGeom& g, const Z64* in, int nvec, Z64* pen, hipStream_t st) {
+  if (nvec <= 0) return;
+  const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
+  dim3 grid(g.N, nvec);
+  STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_full_fwd<NN>, lds),
+                         k_plane_full_fwd<NN><<<grid, plane_nt<NN>(), lds, st>>>(in, pen, g)));
 }
 
 void launch_plane_dn(const FftGeom& g, const Z64* pen, const Z64* psi_r, int band0, int nb, int npert,

@@ -76,9 +76,11 @@ struct CgState {
   const double* eps;           // [nbatch] eps of the band of each solve
   const double* invT;          // [nbatch] 1 / T_v of the band of each solve
   const double* g2h;           // [npw_pad]
+  const float* kprec;          // [nbatch][npw_pad] learned diagonal preconditioner, or null for Teter
   int npw_pad;
 };
-void launch_cg_init(const CgState& s, const int* act, int n, hipStream_t st);
+void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st);
+void launch_guess_resid(const CgState& s, const int* act, int n, int* rejected, hipStream_t st);
 void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st);
 void launch_cg_alpha(const CgState& s, const int* act, int n, double tol2, hipStream_t st);
 void launch_cg_beta(const CgState& s, const int* act, int n, hipStream_t st);
@@ -92,6 +94,45 @@ void launch_fill_zero(Z64* p, size_t n, hipStream_t st);
 void launch_set_flag(int* flag, const int* list, int n, int value, hipStream_t st);
 void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st);
 
+// ---- learned initial guess (coarse-grid 3-D conv net, learn.hip) ----
+constexpr int kNetChannels = 16;
+constexpr int kNetLayers = 3;
+constexpr int kNetLayerParams = kNetChannels * 27 * kNetChannels + kNetChannels;  // weights + bias
+int net_ldp(int Nc);  // per-solve point stride of the activations (multiple of 16)
+// preconditioner head: knots of the scale on u = log2(|G|^2 / 2T_v), features, parameters
+constexpr int kPrecKnots = 8;
+constexpr double kPrecU0 = -6.0;
+constexpr double kPrecDu = 2.0;
+constexpr int kPrecIn = kNetChannels + 2;
+constexpr int kPrecParams = kPrecKnots * kPrecIn + kPrecKnots;
+void launch_pool(const __bf16* act, const double* eps, const double* invT, float* f, int Nc, int nsolve,
+                 hipStream_t st);
+void launch_prec_coef(const float* head, const float* f, float* coef, int n, hipStream_t st);
+void launch_prec_build(const float* coef, const float* f, const double* g2h, float* K, int npw_pad, int n,
+                       hipStream_t st);
+void launch_prec_apply(const float* K, const Z64* R0, const int* idx, Z64* out, int npw_pad, int n, hipStream_t st);
+void launch_prec_grad(const Z64* P, const Z64* R0, const Z64* E0, const int* idx, const float* coef, const float* f,
+                      const double* g2h, int npw, int npw_pad, float* gc, float* loss, int n, hipStream_t st);
+void launch_head_grad(const float* gc, const float* f, int n, float* grad, hipStream_t st);
+void launch_gather_rows(Z64* dst, const Z64* src, const int* rows, int ld, int n, bool sub, hipStream_t st);
+void launch_gather_f32(float* dst, const float* src, const int* rows, int ld, int n, hipStream_t st);
+void launch_conv3(const __bf16* in, const __bf16* W, const float* bias, void* out, int Nc, int nsolve, int act,
+                  bool out_f32, hipStream_t st);
+void launch_conv3_wgrad(const __bf16* in, const float* gout, float* part, float* grad, int Nc, int nsolve,
+                        int nslice, hipStream_t st);
+void launch_relu_bwd(float* g, const __bf16* act, size_t n, hipStream_t st);
+void launch_f32_to_bf16(const float* a, __bf16* b, size_t n, hipStream_t st);
+void launch_flip_weights(const float* W, __bf16* Wt, hipStream_t st);
+void launch_loss(const float* out, const float* tgt, float* gout, float* loss, int Nc, int nsolve, hipStream_t st);
+void launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, int step, float scale,
+                 hipStream_t st);
+void launch_pack_input(const Z64* psi_c, const Z64* b_c, const int* band, const double* eps, const double* bnorm2,
+                       __bf16* out, int Nc, int nsolve, hipStream_t st);
+void launch_pack_target(const Z64* x_c, const double* bnorm2, float* tgt, int Nc, int nsolve, hipStream_t st);
+void launch_unpack_output(const float* out, const double* bnorm2, Z64* x_c, int Nc, int nsolve, hipStream_t st);
+// yz planes, forward: full complex planes in[vec][ix][iy][iz] -> pencils (for the coarse grid)
+void launch_plane_full_fwd(const FftGeom& g, const Z64* in, int nvec, Z64* pen, hipStream_t st);
+
 // ---- mixed precision (FP32 vectors, BF16 MFMA GEMMs, FP64 scalars) ----
 struct Cg32State {
   Z32 *d, *r, *p, *q, *z;      // [nbatch][npw_pad]
@@ -100,6 +141,7 @@ struct Cg32State {
   int* iters;
   const double* invT;
   const double* g2h;
+  const float* kprec;  // as in CgState
   int npw_pad;
 };
 void launch_cg32_init(const Cg32State& s, const Z64* r64, const int* act, int n, hipStream_t st);

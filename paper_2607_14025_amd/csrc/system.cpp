@@ -7,6 +7,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <numeric>
+#include <random>
 #include <string>
 #include <thread>
 #include <vector>
@@ -103,6 +105,11 @@ struct stern_system {
   DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
       sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
   DBuf m_d, m_r, m_p, m_q, m_z, m_rz, m_rr0, m_flag;  // mixed inner solve
+  // coarse (N/2)^3 grid of the learned guess, when it holds the sphere
+  bool have_coarse = false;
+  HostBasis hbc;
+  DBuf c_col_start, c_col_len, c_col_xmin, c_col_pos, c_zl, c_ycol, c_tw64, psi_c, c_pen, c_field, net_a0, net_a1,
+      net_a2, net_out, g_rej, net_feat, net_coef, kprec;
   int ws_solves = 0, ws32_solves = 0;
 
   // per-launch event profile (opts->profile)
@@ -139,6 +146,29 @@ struct stern_system {
     return g;
   }
 
+  FftGeom geom_c() const {
+    FftGeom g;
+    g.N = hbc.N;
+    g.npw = hbc.npw;
+    g.npw_pad = hbc.npw_pad;
+    g.ncol = hbc.ncol;
+    g.ncol_pad = hbc.ncol_pad;
+    g.nza = hbc.nza;
+    g.col_start = c_col_start.as<int>();
+    g.col_len = c_col_len.as<int>();
+    g.col_xmin = c_col_xmin.as<int>();
+    g.col_pos = c_col_pos.as<int>();
+    g.zl = c_zl.as<int>();
+    g.ycol = c_ycol.as<int>();
+    g.zact_lo = hbc.zact_lo;
+    g.zact_hi = hbc.zact_hi;
+    g.n_cu = n_cu;
+    g.g2h = g2h.as<double>();
+    g.tw64 = c_tw64.as<Z64>();
+    g.tw32 = nullptr;
+    return g;
+  }
+
   void release_all() {
     DBuf* all[] = {&ycol, &tw32, &v_r32, &col_start, &col_len,  &col_xmin, &col_pos, &zl,       &g2h,     &tw64,     &v_r,      &kb,
                    &perm,      &psi,      &psi_r,    &wx,      &wr,       &wp,      &wq,       &wz,       &wb,
@@ -146,12 +176,37 @@ struct stern_system {
                    &sv_rr,     &sv_flag,  &sv_iters, &sv_tres, &list_act, &list_f,  &pert_out, &dv_dev,   &dn_dev,
                    &tmp_in,    &tmp_out,  &psi_hi,  &psi_lo,   &psiT_hi, &psiT_lo,  &kb_hi,    &kb_lo,
                    &kbT_hi,    &kbT_lo,   &m_d,     &m_r,      &m_p,     &m_q,      &m_z,      &m_rz,
-                   &m_rr0,     &m_flag};
+                   &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
+                   &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
+                   &g_rej,     &net_feat, &net_coef, &kprec};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
     if (own_stream) (void)hipStreamDestroy(own_stream);
     own_stream = nullptr;
+  }
+};
+
+// Weights of the learned-guess net: per layer [co][27][ci] floats then 16 biases.
+struct stern_model {
+  int device = 0;
+  DBuf w, m, v, grad, part, wbf, wtf;
+  int step = 0;
+  bool trained = false;
+  bool prec_trained = false;  // the preconditioner head has been fitted (else Teter is used)
+  int prec_step = 0;
+  DBuf a0, a1, a2, out, tgt, g3, g2, gbf, loss, din, dtgt;  // training workspace
+  DBuf r0set, e0set, fset, fb, coef, gc, kb, idx;          // preconditioner-head training
+  static constexpr int LP = kNetLayerParams;
+  static constexpr int WN = kNetChannels * 27 * kNetChannels;
+  static constexpr int HEAD = kNetLayers * LP;  // offset of the preconditioner head
+  const __bf16* wb(int l) const { return wbf.as<__bf16>() + (size_t)l * WN; }
+  const float* bias(int l) const { return w.as<float>() + (size_t)l * LP + WN; }
+  const float* head() const { return w.as<float>() + HEAD; }
+  void release_all() {
+    DBuf* all[] = {&w, &m, &v, &grad, &part, &wbf, &wtf, &a0, &a1, &a2, &out, &tgt, &g3, &g2, &gbf, &loss, &din,
+                   &dtgt, &r0set, &e0set, &fset, &fb, &coef, &gc, &kb, &idx};
+    for (DBuf* d : all) d->release();
   }
 };
 
@@ -340,6 +395,7 @@ Cg32State cg32_state(stern_system* S, int* iters) {
   c.iters = iters;
   c.invT = S->sv_invT.as<double>();
   c.g2h = S->g2h.as<double>();
+  c.kprec = nullptr;
   c.npw_pad = S->hb.npw_pad;
   return c;
 }
@@ -361,6 +417,7 @@ CgState cg_state(stern_system* S) {
   c.eps = S->sv_eps.as<double>();
   c.invT = S->sv_invT.as<double>();
   c.g2h = S->g2h.as<double>();
+  c.kprec = nullptr;
   c.npw_pad = S->hb.npw_pad;
   return c;
 }
@@ -392,6 +449,126 @@ struct Scope {
   }
 };
 
+
+// ---- learned initial guess ----
+
+size_t net_bytes_per_solve(const stern_system* S) {
+  const int Nc = S->hbc.N;
+  const size_t ldp = (size_t)net_ldp(Nc);
+  return (size_t)Nc * S->hbc.ncol_pad * sizeof(Z64) + (size_t)Nc * Nc * Nc * sizeof(Z64) +
+         3 * ldp * kNetChannels * sizeof(__bf16) + ldp * kNetChannels * sizeof(float);
+}
+
+// coarse-grid fields of rows [s0, s0 + c) of `rows` (sphere vectors): c_field = inverse yz of pencils
+int coarse_fields(stern_system* S, const Z64* rows, int s0, int c) {
+  const FftGeom gc = S->geom_c();
+  launch_xinv(gc, rows + (size_t)s0 * S->hb.npw_pad, nullptr, c, S->c_pen.as<Z64>(), S->stream);
+  launch_plane_full_inv(gc, S->c_pen.as<Z64>(), c, S->c_field.as<Z64>(), S->stream);
+  return 0;
+}
+
+// net input of rows [s0, s0 + c) into a0 (needs b and ||b||^2 of the rows)
+int net_input(stern_system* S, const CgState& cs, int s0, int c, __bf16* a0) {
+  CHECKED(coarse_fields(S, cs.b, s0, c));
+  launch_pack_input(S->psi_c.as<Z64>(), S->c_field.as<Z64>(), S->sv_band.as<int>() + s0, cs.eps + s0, cs.bb + s0, a0,
+                    S->hbc.N, c, S->stream);
+  return 0;
+}
+
+void net_forward(const stern_model* M, const __bf16* a0, __bf16* a1, __bf16* a2, float* out, int Nc, int c,
+                 hipStream_t st) {
+  launch_conv3(a0, M->wb(0), M->bias(0), a1, Nc, c, 1, false, st);
+  launch_conv3(a1, M->wb(1), M->bias(1), a2, Nc, c, 1, false, st);
+  launch_conv3(a2, M->wb(2), M->bias(2), out, Nc, c, 0, true, st);
+}
+
+// x = P_c (net output mapped to the sphere) for all ns rows; then r = b - A x in FP64,
+// dropping guesses whose residual is non-finite or not below ||b||.
+int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, int& n_rej) {
+  hipStream_t st = S->stream;
+  const FftGeom gc = S->geom_c();
+  const int Nc = gc.N, K = S->hb.npw_pad;
+  const size_t ldp = (size_t)net_ldp(Nc), nc3 = (size_t)Nc * Nc * Nc;
+  const int chunk = std::min(ns, 1024);
+  CHECKED(S->c_pen.ensure((size_t)chunk * Nc * gc.ncol_pad * sizeof(Z64)));
+  CHECKED(S->c_field.ensure((size_t)chunk * nc3 * sizeof(Z64)));
+  for (DBuf* d : {&S->net_a0, &S->net_a1, &S->net_a2})
+    CHECKED(d->ensure((size_t)chunk * ldp * kNetChannels * sizeof(__bf16)));
+  CHECKED(S->net_out.ensure((size_t)chunk * ldp * kNetChannels * sizeof(float)));
+  CHECKED(S->g_rej.ensure((size_t)S->ws_solves * sizeof(int)));
+  CHECKED(S->net_feat.ensure((size_t)S->ws_solves * kPrecIn * sizeof(float)));
+  const double flops = 3.0 * 2.0 * kNetChannels * 27 * kNetChannels * (double)nc3;
+  for (int s0 = 0; s0 < ns; s0 += chunk) {
+    const int c = std::min(chunk, ns - s0);
+    CHECKED(timed(S, STERN_K_NET, c * (double)(nc3 * 16 * 4 + ldp * 16 * 14), c * flops, [&] {
+      (void)net_input(S, cs, s0, c, S->net_a0.as<__bf16>());
+      net_forward(M, S->net_a0.as<__bf16>(), S->net_a1.as<__bf16>(), S->net_a2.as<__bf16>(),
+                  S->net_out.as<float>(), Nc, c, st);
+      launch_pool(S->net_a2.as<__bf16>(), cs.eps + s0, cs.invT + s0, S->net_feat.as<float>() + (size_t)s0 * kPrecIn,
+                  Nc, c, st);
+      launch_unpack_output(S->net_out.as<float>(), cs.bb + s0, S->c_field.as<Z64>(), Nc, c, st);
+      launch_plane_full_fwd(gc, S->c_field.as<Z64>(), c, S->c_pen.as<Z64>(), st);
+      launch_xfwd<double>(gc, S->c_pen.as<Z64>(), nullptr, c, cs.x + (size_t)s0 * K, 2, nullptr, nullptr,
+                          1.0 / (double)nc3, st);
+    }));
+  }
+  // learned diagonal preconditioner of every solve
+  cs.kprec = nullptr;
+  if (M->prec_trained) {
+    CHECKED(S->net_coef.ensure((size_t)S->ws_solves * kPrecKnots * sizeof(float)));
+    CHECKED(S->kprec.ensure((size_t)S->ws_solves * K * sizeof(float)));
+    CHECKED(timed(S, STERN_K_NET, ns * (double)K * 12.0, 0.0, [&] {
+      launch_prec_coef(M->head(), S->net_feat.as<float>(), S->net_coef.as<float>(), ns, st);
+      launch_prec_build(S->net_coef.as<float>(), S->net_feat.as<float>(), cs.g2h, S->kprec.as<float>(), K, ns, st);
+    }));
+    cs.kprec = S->kprec.as<float>();
+  }
+  CHECKED(apply_pc_rows(S, cs.x, nullptr, ns));
+  CHECKED(apply_h_rows(S, cs.x, cs.q, nullptr, ns, cs.eps));
+  CHECKED(apply_pc_rows(S, cs.q, nullptr, ns));
+  launch_guess_resid(cs, nullptr, ns, S->g_rej.as<int>(), st);
+  CHECKED(launch_check());
+  std::vector<int> rej(ns);
+  HIPOK(hipMemcpyAsync(rej.data(), S->g_rej.p, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  for (int v : rej) n_rej += v;
+  return 0;
+}
+
+// Per-solve arrays, right-hand sides b = -P_c [dV psi_v] and x = 0, r = b for the
+// solves of perturbations [i0, i1) x bands [v0, v0 + nb) (row s = (i - i0) nb + v - v0).
+int setup_batch(stern_system* S, int i0, int i1, int v0, int nb, const double* dv_dev, double vecb) {
+  hipStream_t st = S->stream;
+  const HostBasis& hb = S->hb;
+  const int N = hb.N;
+  const size_t n3 = (size_t)N * N * N;
+  const int ns = (i1 - i0) * nb;
+  std::vector<int> h_band(ns), h_pert(ns);
+  std::vector<double> h_eps(ns), h_invT(ns);
+  for (int s = 0; s < ns; ++s) {
+    h_band[s] = v0 + s % nb;
+    h_pert[s] = i0 + s / nb;
+    h_eps[s] = S->eps[h_band[s]];
+    h_invT[s] = S->invT[h_band[s]];
+  }
+  HIPOK(hipMemcpyAsync(S->sv_band.p, h_band.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPOK(hipMemcpyAsync(S->sv_pert.p, h_pert.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
+  HIPOK(hipMemcpyAsync(S->sv_eps.p, h_eps.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPOK(hipMemcpyAsync(S->sv_invT.p, h_invT.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
+  const CgState cs = cg_state(S);
+  const FftGeom g = S->geom();
+  CHECKED(timed(S, STERN_K_RHS, ns * ((double)n3 * 24.0 + (double)N * hb.ncol * 16.0), 0.0, [&] {
+    launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, S->sv_band.as<int>(), S->sv_pert.as<int>(), ns,
+                     S->pen.as<Z64>(), st);
+  }));
+  CHECKED(timed(S, STERN_K_XFWD, ns * ((double)N * hb.ncol * 16.0 + vecb), 0.0, [&] {
+    launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
+  }));
+  CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
+  launch_outer_init(cs, nullptr, ns, st);  // x = 0, r = b, ||b||, counters
+  HIPOK(hipStreamSynchronize(st));         // the host arrays above are released on return
+  return 0;
+}
 
 // Runs `body` (one CG iteration's launches on the system stream) `steps` times:
 // eagerly, or captured once into a hipGraph and replayed.
@@ -426,7 +603,7 @@ int run_steps(stern_system* S, int steps, bool graph, F&& body) {
 
 // Plain FP64 projected PCG from zero on the solves in `list` (batch row indices).
 int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, int max_iter,
-              int check_every, int& n_restart, double vecb, bool use_graph) {
+              int check_every, int& n_restart, double vecb, bool use_graph, bool keep_x = false) {
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   std::vector<int> h_flag(ns_all), act, flist;
@@ -435,7 +612,7 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
   HIPOK(hipMemcpyAsync(S->list_act.p, list.data(), n0 * sizeof(int), hipMemcpyHostToDevice, st));
   {
     const int* L = S->list_act.as<int>();
-    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 4.0, 0.0, [&] { launch_cg_init(cs, L, n0, st); }));
+    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 4.0, 0.0, [&] { launch_cg_init(cs, L, n0, keep_x, st); }));
     CHECKED(apply_pc_rows(S, cs.z, L, n0));
     CHECKED(timed(S, STERN_K_CG, vecb * n0 * 3.0, 0.0, [&] { launch_cg_init2(cs, L, n0, st); }));
   }
@@ -504,7 +681,8 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
   const int ns_all = S->ws_solves;
   const int K = S->hb.npw_pad;
   const double vec32 = vecb / 2;
-  const Cg32State c32 = cg32_state(S, cs.iters);
+  Cg32State c32 = cg32_state(S, cs.iters);
+  c32.kprec = cs.kprec;
   std::vector<int> h_flag(ns_all), h_iflag(ns_all), act, iact;
   HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
@@ -562,9 +740,11 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       if (h_flag[s] != 2) nxt.push_back(s);
     act.swap(nxt);
   }
-  if (!act.empty()) {
+  if (!act.empty()) {  // Teter-preconditioned FP64 PCG from zero
     n_fallback += (int)act.size();
-    CHECKED(run_pcg64(S, cs, act, tol, max_iter, check_every, n_restart, vecb, use_graph));
+    CgState teter = cs;
+    teter.kprec = nullptr;
+    CHECKED(run_pcg64(S, teter, act, tol, max_iter, check_every, n_restart, vecb, use_graph));
   }
   return 0;
 }
@@ -669,6 +849,27 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     for (DBuf* d : {&S->kb_hi, &S->kb_lo, &S->kbT_hi, &S->kbT_lo}) CHECKED(d->ensure(kbn));
     launch_split_bf16(S->kb.as<Z64>(), S->natoms_pad, hb.npw_pad, S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(),
                       S->kbT_hi.as<__bf16>(), S->kbT_lo.as<__bf16>(), st);
+    // coarse grid of the learned guess
+    if (hb.N % 2 == 0 && fft_size_supported(hb.N / 2)) {
+      CellParams pc = p;
+      pc.fft_n = hb.N / 2;
+      if (build_basis(pc, S->hbc, true).empty() && S->hbc.npw == hb.npw) {
+        const HostBasis& c = S->hbc;
+        CHECKED(upload(S->c_col_start, c.col_start.data(), c.col_start.size() * sizeof(int), st));
+        CHECKED(upload(S->c_col_len, c.col_len.data(), c.col_len.size() * sizeof(int), st));
+        CHECKED(upload(S->c_col_xmin, c.col_xmin.data(), c.col_xmin.size() * sizeof(int), st));
+        CHECKED(upload(S->c_col_pos, c.col_pos.data(), c.col_pos.size() * sizeof(int), st));
+        CHECKED(upload(S->c_zl, c.zl.data(), c.zl.size() * sizeof(int), st));
+        CHECKED(upload(S->c_ycol, c.ycol.data(), c.ycol.size() * sizeof(int), st));
+        std::vector<Z64> twc(c.N);
+        for (int m = 0; m < c.N; ++m) {
+          const double a = 6.283185307179586476925286766559 * m / c.N;
+          twc[m] = zmk(std::cos(a), -std::sin(a));
+        }
+        CHECKED(upload(S->c_tw64, twc.data(), twc.size() * sizeof(Z64), st));
+        S->have_coarse = true;
+      }
+    }
     HIPOK(hipStreamSynchronize(st));
     return 0;
   };
@@ -737,6 +938,13 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   const FftGeom g = S->geom();
   launch_xinv(g, S->psi.as<Z64>(), nullptr, n_occ, S->pen.as<Z64>(), st);
   launch_plane_full_inv(g, S->pen.as<Z64>(), n_occ, S->psi_r.as<Z64>(), st);
+  if (S->have_coarse) {  // psi_v(r) on the coarse grid, input of the learned guess
+    const FftGeom gc = S->geom_c();
+    const size_t nc3 = (size_t)gc.N * gc.N * gc.N;
+    CHECKED(S->psi_c.ensure((size_t)n_occ * nc3 * sizeof(Z64)));
+    launch_xinv(gc, S->psi.as<Z64>(), nullptr, n_occ, S->pen.as<Z64>(), st);
+    launch_plane_full_inv(gc, S->pen.as<Z64>(), n_occ, S->psi_c.as<Z64>(), st);
+  }
   CHECKED(launch_check());
   HIPOK(hipStreamSynchronize(st));
   S->have_occ = true;
@@ -829,7 +1037,13 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->precision != STERN_FP64 && opts->precision != STERN_MIXED)
     return fail(STERN_ERR_INVALID_ARG, "precision must be STERN_FP64 or STERN_MIXED");
   if (opts->inner_tol < 0 || opts->max_outer < 0) return fail(STERN_ERR_INVALID_ARG, "bad inner_tol / max_outer");
-  if (opts->guess != STERN_GUESS_ZERO) return fail(STERN_ERR_UNSUPPORTED, "only STERN_GUESS_ZERO is available");
+  if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED)
+    return fail(STERN_ERR_INVALID_ARG, "guess must be STERN_GUESS_ZERO or STERN_GUESS_LEARNED");
+  if (opts->guess == STERN_GUESS_LEARNED) {
+    if (!opts->model) return fail(STERN_ERR_INVALID_ARG, "STERN_GUESS_LEARNED needs a model");
+    if (!S->have_coarse) return fail(STERN_ERR_UNSUPPORTED, "grid %d has no coarse grid for the learned guess", S->hb.N);
+    if (opts->model->device != S->device) return fail(STERN_ERR_INVALID_ARG, "model and system on different devices");
+  }
   if (opts->mem_kind != STERN_MEM_HOST && opts->mem_kind != STERN_MEM_DEVICE)
     return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
   if (!(opts->tol > 0)) return fail(STERN_ERR_INVALID_ARG, "tol must be > 0");
@@ -890,46 +1104,41 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     dv_dev = S->dv_dev.as<double>();
     dn_dev = S->dn_dev.as<double>();
   }
-  const CgState cs = cg_state(S);
+  CgState cs = cg_state(S);
   const FftGeom g = S->geom();
   std::vector<int> all_iters, all_flag;
   std::vector<double> all_tres;
   all_iters.reserve((size_t)n_pert * nb);
   long long tot_iters = 0;
-  int n_restart = 0, n_fallback = 0;
+  int n_restart = 0, n_fallback = 0, n_rejected = 0;
 
-  std::vector<int> h_flag(max_ns), h_band(max_ns), h_pert(max_ns);
-  std::vector<double> h_eps(max_ns), h_invT(max_ns);
+  std::vector<int> h_flag(max_ns);
   for (int i0 = 0; i0 < n_pert; i0 += per) {
     const int i1 = std::min(n_pert, i0 + per);
     const int ns = (i1 - i0) * nb;
-    for (int s = 0; s < ns; ++s) {
-      h_band[s] = v0 + s % nb;
-      h_pert[s] = i0 + s / nb;
-      h_eps[s] = S->eps[h_band[s]];
-      h_invT[s] = S->invT[h_band[s]];
-    }
-    HIPOK(hipMemcpyAsync(S->sv_band.p, h_band.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPOK(hipMemcpyAsync(S->sv_pert.p, h_pert.data(), ns * sizeof(int), hipMemcpyHostToDevice, st));
-    HIPOK(hipMemcpyAsync(S->sv_eps.p, h_eps.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPOK(hipMemcpyAsync(S->sv_invT.p, h_invT.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
-    // b = -P_c [dV psi_v]
-    CHECKED(timed(S, STERN_K_RHS, ns * ((double)n3 * 24.0 + (double)N * hb.ncol * 16.0), 0.0, [&] {
-      launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, S->sv_band.as<int>(), S->sv_pert.as<int>(), ns,
-                       S->pen.as<Z64>(), st);
-    }));
-    CHECKED(timed(S, STERN_K_XFWD, ns * ((double)N * hb.ncol * 16.0 + vecb), 0.0, [&] {
-      launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
-    }));
-    CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
-    launch_outer_init(cs, nullptr, ns, st);  // x = 0, r = b, ||b||, counters
+    CHECKED(setup_batch(S, i0, i1, v0, nb, dv_dev, vecb));
+    const bool guess = opts->guess == STERN_GUESS_LEARNED;
+    if (guess) CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected));
     std::vector<int> all(ns);
     for (int s = 0; s < ns; ++s) all[s] = s;
     if (opts->precision == STERN_MIXED) {
       CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
                         use_graph));
     } else {
-      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph));
+      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph, guess));
+      if (guess) {  // solves the learned start did not bring below tol: Teter-PCG from zero
+        HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+        std::vector<int> rest;
+        for (int s = 0; s < ns; ++s)
+          if (h_flag[s] != 2) rest.push_back(s);
+        if (!rest.empty()) {
+          n_fallback += (int)rest.size();
+          CgState teter = cs;
+          teter.kprec = nullptr;
+          CHECKED(run_pcg64(S, teter, rest, tol, max_iter, check_every, n_restart, vecb, use_graph));
+        }
+      }
     }
     // dn_i = 4/Omega Re sum_v conj(psi_v(r)) x_{v,i}(r)
     CHECKED(timed(S, STERN_K_XINV, ns * (vecb + (double)N * hb.ncol * 16.0), 0.0,
@@ -994,6 +1203,7 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     stats->n_converged = nconv;
     stats->n_fallback = n_fallback;
     stats->n_restarts = n_restart;
+    stats->n_guess_rejected = n_rejected;
     stats->total_iters = tot_iters;
     stats->max_iters = mx;
     stats->max_true_resid = mres;
@@ -1064,6 +1274,7 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
       a.n_converged += st[k].n_converged;
       a.n_fallback += st[k].n_fallback;
       a.n_restarts += st[k].n_restarts;
+      a.n_guess_rejected += st[k].n_guess_rejected;
       a.total_iters += st[k].total_iters;
       a.max_iters = std::max(a.max_iters, st[k].max_iters);
       a.max_true_resid = std::max(a.max_true_resid, st[k].max_true_resid);
@@ -1080,6 +1291,401 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
     *stats = a;
   }
   return out;
+}
+
+// ---------------------------------------------------------- learned model ----
+
+int stern_model_num_params(void) { return kNetLayers * kNetLayerParams + kPrecParams; }
+
+static int model_refresh_bf16(stern_model* M, hipStream_t st) {
+  for (int l = 0; l < kNetLayers; ++l)
+    launch_f32_to_bf16(M->w.as<float>() + (size_t)l * stern_model::LP, M->wbf.as<__bf16>() + (size_t)l * stern_model::WN,
+                       stern_model::WN, st);
+  return launch_check();
+}
+
+int stern_model_create(int device, unsigned long long seed, stern_model** out) {
+  if (!out) return fail(STERN_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  Scope sc(device);
+  stern_model* M = new stern_model();
+  M->device = device;
+  const int np = stern_model_num_params();
+  auto run = [&]() -> int {
+    CHECKED(M->w.ensure(np * sizeof(float)));
+    CHECKED(M->m.ensure(np * sizeof(float)));
+    CHECKED(M->v.ensure(np * sizeof(float)));
+    CHECKED(M->grad.ensure(np * sizeof(float)));
+    CHECKED(M->wbf.ensure((size_t)kNetLayers * stern_model::WN * sizeof(__bf16)));
+    CHECKED(M->wtf.ensure((size_t)stern_model::WN * sizeof(__bf16)));
+    // He-normal weights for the ReLU layers (fan-in 27 x 5 input channels for the
+    // first layer, 27 x 16 after), a small output layer, zero biases
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<float> nd(0.f, 1.f);
+    std::vector<float> w(np, 0.f), z(np, 0.f);
+    for (int l = 0; l < kNetLayers; ++l) {
+      const float sd = l == 0 ? std::sqrt(2.f / (27.f * 5.f)) : (l == 1 ? std::sqrt(2.f / (27.f * 16.f)) : 1e-3f);
+      for (int co = 0; co < kNetChannels; ++co)
+        for (int n = 0; n < 27; ++n)
+          for (int ci = 0; ci < kNetChannels; ++ci) {
+            const bool live = (l == 0 ? ci < 5 : true) && (l == 2 ? co < 2 : true);
+            w[(size_t)l * stern_model::LP + ((size_t)co * 27 + n) * kNetChannels + ci] = live ? sd * nd(rng) : 0.f;
+          }
+    }
+    HIPOK(hipMemcpy(M->w.p, w.data(), np * sizeof(float), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(M->m.p, z.data(), np * sizeof(float), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(M->v.p, z.data(), np * sizeof(float), hipMemcpyHostToDevice));
+    CHECKED(model_refresh_bf16(M, nullptr));
+    HIPOK(hipDeviceSynchronize());
+    return 0;
+  };
+  const int rc = run();
+  if (rc < 0) {
+    M->release_all();
+    delete M;
+    return rc;
+  }
+  *out = M;
+  return STERN_OK;
+}
+
+int stern_model_get_weights(const stern_model* M, float* w, int n) {
+  if (!M || !w || n != stern_model_num_params()) return fail(STERN_ERR_INVALID_ARG, "bad model or size");
+  Scope sc(M->device);
+  HIPOK(hipMemcpy(w, M->w.p, n * sizeof(float), hipMemcpyDeviceToHost));
+  return n;
+}
+
+int stern_model_set_weights(stern_model* M, const float* w, int n) {
+  if (!M || !w || n != stern_model_num_params()) return fail(STERN_ERR_INVALID_ARG, "bad model or size");
+  Scope sc(M->device);
+  HIPOK(hipMemcpy(M->w.p, w, n * sizeof(float), hipMemcpyHostToDevice));
+  CHECKED(model_refresh_bf16(M, nullptr));
+  HIPOK(hipDeviceSynchronize());
+  M->trained = true;
+  M->prec_trained = false;
+  for (int k = stern_model::HEAD; k < n; ++k) M->prec_trained = M->prec_trained || w[k] != 0.f;
+  return n;
+}
+
+void stern_model_free(stern_model* M) {
+  if (!M) return;
+  {
+    Scope sc(M->device);
+    (void)hipDeviceSynchronize();
+    M->release_all();
+  }
+  delete M;
+}
+
+int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const int* n_pert, const double* const* dv_r,
+                      int mem_kind, const stern_train_opts* o, stern_train_stats* tstats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!M || n_sys <= 0 || !sys || !n_pert || !dv_r) return fail(STERN_ERR_INVALID_ARG, "bad arguments");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  const int epochs = (o && o->epochs > 0) ? o->epochs : 4;
+  const int B = (o && o->batch > 0) ? o->batch : 16;
+  const float lr = (float)((o && o->lr > 0) ? o->lr : 1e-3);
+  const int max_solves = (o && o->max_solves > 0) ? o->max_solves : 4096;
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  std::mt19937_64 rng(o ? o->seed : 0);
+  int Nc = -1;
+  long long total = 0;
+  for (int k = 0; k < n_sys; ++k) {
+    if (!sys[k] || !sys[k]->have_occ) return fail(STERN_ERR_STATE, "system %d is not ready", k);
+    if (!sys[k]->have_coarse) return fail(STERN_ERR_UNSUPPORTED, "system %d has no coarse grid", k);
+    if (sys[k]->device != M->device) return fail(STERN_ERR_INVALID_ARG, "system %d on another device", k);
+    if (Nc < 0) Nc = sys[k]->hbc.N;
+    if (sys[k]->hbc.N != Nc) return fail(STERN_ERR_INVALID_ARG, "training systems need the same coarse grid");
+    if (n_pert[k] <= 0 || !dv_r[k]) return fail(STERN_ERR_INVALID_ARG, "system %d has no fields", k);
+    total += (long long)n_pert[k] * sys[k]->n_occ;
+  }
+  for (int k = 0; k < n_sys; ++k) {  // no event profile during training
+    sys[k]->prof_on = false;
+    sys[k]->recs.clear();
+    sys[k]->ev_used = 0;
+  }
+  Scope sc(M->device);
+  const size_t ldp = (size_t)net_ldp(Nc), C = kNetChannels;
+  const int nsamp_max = (int)std::min<long long>(total, max_solves);
+  // which solves (global index) become training samples
+  std::vector<long long> pick(total);
+  std::iota(pick.begin(), pick.end(), 0LL);
+  std::shuffle(pick.begin(), pick.end(), rng);
+  std::vector<char> chosen(total, 0);
+  for (int k = 0; k < nsamp_max; ++k) chosen[pick[k]] = 1;
+  CHECKED(M->din.ensure((size_t)nsamp_max * ldp * C * sizeof(__bf16)));
+  CHECKED(M->dtgt.ensure((size_t)nsamp_max * ldp * 2 * sizeof(float)));
+  int nsamp = 0;
+  long long base = 0;
+  // ---- dataset: plain FP64 solutions of every system ----
+  for (int k = 0; k < n_sys; ++k) {
+    stern_system* S = sys[k];
+    hipStream_t st = S->stream;
+    const HostBasis& hb = S->hb;
+    const size_t n3 = (size_t)hb.N * hb.N * hb.N;
+    const int nb = S->n_occ;
+    const double* dv_dev = dv_r[k];
+    if (mem_kind == STERN_MEM_HOST) {
+      CHECKED(S->dv_dev.ensure((size_t)n_pert[k] * n3 * sizeof(double)));
+      HIPOK(hipMemcpyAsync(S->dv_dev.p, dv_r[k], (size_t)n_pert[k] * n3 * sizeof(double), hipMemcpyHostToDevice, st));
+      dv_dev = S->dv_dev.as<double>();
+    }
+    size_t free_b = 0, total_b = 0;
+    HIPOK(hipMemGetInfo(&free_b, &total_b));
+    const size_t per_solve = (size_t)hb.npw_pad * sizeof(Z64) * 6 + (size_t)hb.N * hb.ncol_pad * sizeof(Z64) +
+                             net_bytes_per_solve(S) + 1024;
+    int per = (int)std::max<size_t>(1, (size_t)(0.4 * (double)free_b) / (per_solve * nb));
+    per = std::min(per, n_pert[k]);
+    CHECKED(ensure_workspace(S, per * nb));
+    const CgState cs = cg_state(S);
+    const double vecb = (double)hb.npw * sizeof(Z64);
+    int n_restart = 0;
+    const int chunk = std::min(per * nb, 512);
+    CHECKED(S->c_pen.ensure((size_t)chunk * Nc * S->hbc.ncol_pad * sizeof(Z64)));
+    CHECKED(S->c_field.ensure((size_t)chunk * Nc * Nc * Nc * sizeof(Z64)));
+    CHECKED(S->net_a0.ensure((size_t)chunk * ldp * C * sizeof(__bf16)));
+    CHECKED(S->net_out.ensure((size_t)chunk * ldp * C * sizeof(float)));
+    for (int i0 = 0; i0 < n_pert[k]; i0 += per) {
+      const int i1 = std::min(n_pert[k], i0 + per);
+      const int ns = (i1 - i0) * nb;
+      CHECKED(setup_batch(S, i0, i1, 0, nb, dv_dev, vecb));
+      std::vector<int> all(ns);
+      std::iota(all.begin(), all.end(), 0);
+      CHECKED(run_pcg64(S, cs, all, tol, 1000, 4, n_restart, vecb, false));
+      for (int s0 = 0; s0 < ns; s0 += chunk) {
+        const int c = std::min(chunk, ns - s0);
+        CHECKED(net_input(S, cs, s0, c, S->net_a0.as<__bf16>()));
+        CHECKED(coarse_fields(S, cs.x, s0, c));
+        launch_pack_target(S->c_field.as<Z64>(), cs.bb + s0, S->net_out.as<float>(), Nc, c, st);
+        for (int t = 0; t < c; ++t) {
+          if (!chosen[base + (long long)i0 * nb + s0 + t]) continue;
+          HIPOK(hipMemcpyAsync(M->din.as<__bf16>() + (size_t)nsamp * ldp * C,
+                               S->net_a0.as<__bf16>() + (size_t)t * ldp * C, ldp * C * sizeof(__bf16),
+                               hipMemcpyDeviceToDevice, st));
+          HIPOK(hipMemcpyAsync(M->dtgt.as<float>() + (size_t)nsamp * ldp * 2,
+                               S->net_out.as<float>() + (size_t)t * ldp * 2, ldp * 2 * sizeof(float),
+                               hipMemcpyDeviceToDevice, st));
+          ++nsamp;
+        }
+      }
+      CHECKED(launch_check());
+      HIPOK(hipStreamSynchronize(st));
+    }
+    base += (long long)n_pert[k] * nb;
+  }
+  // ---- training: Adam on mini-batches of B solves ----
+  hipStream_t st = sys[0]->stream;
+  CHECKED(M->a0.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  CHECKED(M->a1.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  CHECKED(M->a2.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  CHECKED(M->gbf.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  for (DBuf* d : {&M->out, &M->g3, &M->g2}) CHECKED(d->ensure((size_t)B * ldp * C * sizeof(float)));
+  CHECKED(M->tgt.ensure((size_t)B * ldp * 2 * sizeof(float)));
+  CHECKED(M->loss.ensure((size_t)B * sizeof(float)));
+  CHECKED(M->part.ensure((size_t)B * (stern_model::LP) * sizeof(float)));
+  const int np_layer = stern_model::LP;
+  std::vector<int> order(nsamp);
+  std::iota(order.begin(), order.end(), 0);
+  std::vector<float> hl(B);
+  double first = 0.0, last = 0.0;
+  int steps = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    std::shuffle(order.begin(), order.end(), rng);
+    double ep_loss = 0.0;
+    int ep_n = 0;
+    for (int b0 = 0; b0 + B <= std::max(nsamp, B) && b0 < nsamp; b0 += B) {
+      const int nb_ = std::min(B, nsamp - b0);
+      for (int t = 0; t < nb_; ++t) {
+        const int id = order[b0 + t];
+        HIPOK(hipMemcpyAsync(M->a0.as<__bf16>() + (size_t)t * ldp * C, M->din.as<__bf16>() + (size_t)id * ldp * C,
+                             ldp * C * sizeof(__bf16), hipMemcpyDeviceToDevice, st));
+        HIPOK(hipMemcpyAsync(M->tgt.as<float>() + (size_t)t * ldp * 2, M->dtgt.as<float>() + (size_t)id * ldp * 2,
+                             ldp * 2 * sizeof(float), hipMemcpyDeviceToDevice, st));
+      }
+      net_forward(M, M->a0.as<__bf16>(), M->a1.as<__bf16>(), M->a2.as<__bf16>(), M->out.as<float>(), Nc, nb_, st);
+      launch_loss(M->out.as<float>(), M->tgt.as<float>(), M->g3.as<float>(), M->loss.as<float>(), Nc, nb_, st);
+      const size_t nact = (size_t)nb_ * ldp * C;
+      float* gw = M->grad.as<float>();
+      // layer 3 (index 2)
+      launch_conv3_wgrad(M->a2.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw + 2 * np_layer, Nc, nb_, nb_,
+                         st);
+      launch_flip_weights(M->w.as<float>() + 2 * np_layer, M->wtf.as<__bf16>(), st);
+      launch_f32_to_bf16(M->g3.as<float>(), M->gbf.as<__bf16>(), nact, st);
+      launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g2.as<float>(), Nc, nb_, 0, true, st);
+      launch_relu_bwd(M->g2.as<float>(), M->a2.as<__bf16>(), nact, st);
+      // layer 2 (index 1)
+      launch_conv3_wgrad(M->a1.as<__bf16>(), M->g2.as<float>(), M->part.as<float>(), gw + 1 * np_layer, Nc, nb_, nb_,
+                         st);
+      launch_flip_weights(M->w.as<float>() + 1 * np_layer, M->wtf.as<__bf16>(), st);
+      launch_f32_to_bf16(M->g2.as<float>(), M->gbf.as<__bf16>(), nact, st);
+      launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g3.as<float>(), Nc, nb_, 0, true, st);
+      launch_relu_bwd(M->g3.as<float>(), M->a1.as<__bf16>(), nact, st);
+      // layer 1 (index 0)
+      launch_conv3_wgrad(M->a0.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw, Nc, nb_, nb_, st);
+      ++M->step;
+      launch_adam(M->w.as<float>(), M->m.as<float>(), M->v.as<float>(), gw, stern_model_num_params(), lr, M->step,
+                  1.f / (float)nb_, st);
+      CHECKED(model_refresh_bf16(M, st));
+      HIPOK(hipMemcpyAsync(hl.data(), M->loss.p, nb_ * sizeof(float), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      for (int t = 0; t < nb_; ++t) ep_loss += hl[t];
+      ep_n += nb_;
+      ++steps;
+    }
+    const double mean = ep_n ? ep_loss / ep_n : 0.0;
+    if (ep == 0) first = mean;
+    last = mean;
+  }
+  M->trained = true;
+  // ---- preconditioner head: r0, e0 and features from the trained guess ----
+  const int prec_epochs = (o && o->prec_epochs != 0) ? o->prec_epochs : 4;
+  const float prec_lr = (float)((o && o->prec_lr > 0) ? o->prec_lr : 1e-2);
+  const int prec_cap = (o && o->prec_max_solves > 0) ? o->prec_max_solves : 1024;
+  int nprec = 0;
+  double pfirst = 0.0, plast = 0.0;
+  if (prec_epochs > 0) {
+    M->prec_trained = false;
+    // per system: its sample rows in the shared r0 / e0 / feature sets
+    std::vector<int> sys_begin(n_sys + 1, 0);
+    std::vector<size_t> sys_off(n_sys + 1, 0);  // element offset of system k's rows (stride npw_pad of k)
+    std::vector<std::vector<char>> pick2(n_sys);
+    long long gbase = 0;
+    int ld_max = 0;
+    for (int k = 0; k < n_sys; ++k) ld_max = std::max(ld_max, sys[k]->hb.npw_pad);
+    {
+      std::vector<long long> ids(total);
+      std::iota(ids.begin(), ids.end(), 0LL);
+      std::shuffle(ids.begin(), ids.end(), rng);
+      std::vector<char> ch(total, 0);
+      for (long long k = 0; k < std::min<long long>(total, prec_cap); ++k) ch[ids[k]] = 1;
+      for (int k = 0; k < n_sys; ++k) {
+        const long long n = (long long)n_pert[k] * sys[k]->n_occ;
+        pick2[k].assign(ch.begin() + gbase, ch.begin() + gbase + n);
+        gbase += n;
+      }
+    }
+    const int ncap = (int)std::min<long long>(total, prec_cap);
+    CHECKED(M->r0set.ensure((size_t)ncap * ld_max * sizeof(Z64)));
+    CHECKED(M->e0set.ensure((size_t)ncap * ld_max * sizeof(Z64)));
+    CHECKED(M->fset.ensure((size_t)ncap * kPrecIn * sizeof(float)));
+    for (int k = 0; k < n_sys; ++k) {
+      stern_system* S = sys[k];
+      hipStream_t st2 = S->stream;
+      const HostBasis& hb = S->hb;
+      const int nb = S->n_occ, K = hb.npw_pad;
+      const size_t n3 = (size_t)hb.N * hb.N * hb.N;
+      const double* dv_dev = mem_kind == STERN_MEM_HOST ? S->dv_dev.as<double>() : dv_r[k];
+      if (mem_kind == STERN_MEM_HOST) {  // the dataset pass above may have used another system's upload
+        CHECKED(S->dv_dev.ensure((size_t)n_pert[k] * n3 * sizeof(double)));
+        HIPOK(hipMemcpyAsync(S->dv_dev.p, dv_r[k], (size_t)n_pert[k] * n3 * sizeof(double), hipMemcpyHostToDevice,
+                             st2));
+        dv_dev = S->dv_dev.as<double>();
+      }
+      const double vecb = (double)hb.npw * sizeof(Z64);
+      const int per = std::max(1, std::min(n_pert[k], S->ws_solves / nb));
+      CgState cs = cg_state(S);
+      sys_begin[k] = nprec;
+      if (k > 0) sys_off[k] = sys_off[k - 1] + (size_t)(sys_begin[k] - sys_begin[k - 1]) * sys[k - 1]->hb.npw_pad;
+      int n_restart = 0, n_rej = 0;
+      for (int i0 = 0; i0 < n_pert[k]; i0 += per) {
+        const int i1 = std::min(n_pert[k], i0 + per);
+        const int ns = (i1 - i0) * nb;
+        std::vector<int> rows, slots;
+        for (int s = 0; s < ns; ++s)
+          if (pick2[k][(size_t)i0 * nb + s]) {
+            rows.push_back(s);
+            slots.push_back(nprec + (int)rows.size() - 1);
+          }
+        if (rows.empty()) continue;
+        CHECKED(setup_batch(S, i0, i1, 0, nb, dv_dev, vecb));
+        CHECKED(learned_guess(S, M, cs, ns, n_rej));  // x0, r0 and features; K is still Teter here
+        const int nr = (int)rows.size();
+        CHECKED(M->idx.ensure((size_t)nr * sizeof(int)));
+        HIPOK(hipMemcpyAsync(M->idx.p, rows.data(), nr * sizeof(int), hipMemcpyHostToDevice, st2));
+        const size_t off = sys_off[k] + (size_t)(nprec - sys_begin[k]) * K;
+        Z64* R0 = M->r0set.as<Z64>() + off;
+        Z64* E0 = M->e0set.as<Z64>() + off;
+        launch_gather_rows(R0, cs.r, M->idx.as<int>(), K, nr, false, st2);
+        launch_gather_rows(E0, cs.x, M->idx.as<int>(), K, nr, false, st2);
+        launch_gather_f32(M->fset.as<float>() + (size_t)nprec * kPrecIn, S->net_feat.as<float>(), M->idx.as<int>(),
+                          kPrecIn, nr, st2);
+        std::vector<int> all(ns);
+        std::iota(all.begin(), all.end(), 0);
+        CHECKED(run_pcg64(S, cs, all, tol, 1000, 4, n_restart, vecb, false, true));
+        launch_gather_rows(E0, cs.x, M->idx.as<int>(), K, nr, true, st2);  // e0 = x* - x0
+        CHECKED(launch_check());
+        HIPOK(hipStreamSynchronize(st2));
+        nprec += nr;
+      }
+    }
+    sys_begin[n_sys] = nprec;
+    // Adam on the head, mini-batches within one system (they share its P_c)
+    const int Bp = B;
+    CHECKED(M->fb.ensure((size_t)Bp * kPrecIn * sizeof(float)));
+    CHECKED(M->coef.ensure((size_t)Bp * kPrecKnots * sizeof(float)));
+    CHECKED(M->gc.ensure((size_t)Bp * kPrecKnots * sizeof(float)));
+    CHECKED(M->kb.ensure((size_t)Bp * ld_max * sizeof(float)));
+    CHECKED(M->idx.ensure((size_t)2 * Bp * sizeof(int)));
+    std::vector<std::pair<int, int>> batches;  // (system, first sample)
+    for (int k = 0; k < n_sys; ++k) {
+      CHECKED(ensure_workspace(sys[k], std::max(sys[k]->ws_solves, Bp)));
+      for (int j = sys_begin[k]; j < sys_begin[k + 1]; j += Bp) batches.push_back({k, j});
+    }
+    std::vector<float> hl(Bp);
+    std::vector<int> hidx(2 * Bp);
+    for (int ep = 0; ep < prec_epochs && nprec > 0; ++ep) {
+      std::shuffle(batches.begin(), batches.end(), rng);
+      double ep_loss = 0.0;
+      int ep_n = 0;
+      for (const auto& bt : batches) {
+        stern_system* S = sys[bt.first];
+        hipStream_t st2 = S->stream;
+        const int K = S->hb.npw_pad;
+        const int nbt = std::min(Bp, sys_begin[bt.first + 1] - bt.second);
+        for (int t = 0; t < nbt; ++t) {
+          hidx[t] = bt.second - sys_begin[bt.first] + t;  // row within the system's block
+          hidx[Bp + t] = bt.second + t;                   // global sample (features)
+        }
+        HIPOK(hipMemcpyAsync(M->idx.p, hidx.data(), 2 * Bp * sizeof(int), hipMemcpyHostToDevice, st2));
+        const CgState cs = cg_state(S);
+        const Z64* R0 = M->r0set.as<Z64>() + sys_off[bt.first];
+        const Z64* E0 = M->e0set.as<Z64>() + sys_off[bt.first];
+        launch_gather_f32(M->fb.as<float>(), M->fset.as<float>(), M->idx.as<int>() + Bp, kPrecIn, nbt, st2);
+        launch_prec_coef(M->head(), M->fb.as<float>(), M->coef.as<float>(), nbt, st2);
+        launch_prec_build(M->coef.as<float>(), M->fb.as<float>(), cs.g2h, M->kb.as<float>(), K, nbt, st2);
+        launch_prec_apply(M->kb.as<float>(), R0, M->idx.as<int>(), cs.z, K, nbt, st2);
+        CHECKED(apply_pc_rows(S, cs.z, nullptr, nbt));
+        launch_prec_grad(cs.z, R0, E0, M->idx.as<int>(), M->coef.as<float>(), M->fb.as<float>(), cs.g2h, S->hb.npw, K,
+                         M->gc.as<float>(), M->loss.as<float>(), nbt, st2);
+        launch_head_grad(M->gc.as<float>(), M->fb.as<float>(), nbt, M->grad.as<float>() + stern_model::HEAD, st2);
+        ++M->prec_step;
+        launch_adam(M->w.as<float>() + stern_model::HEAD, M->m.as<float>() + stern_model::HEAD,
+                    M->v.as<float>() + stern_model::HEAD, M->grad.as<float>() + stern_model::HEAD, kPrecParams,
+                    prec_lr, M->prec_step, 1.f / (float)nbt, st2);
+        CHECKED(launch_check());
+        HIPOK(hipMemcpyAsync(hl.data(), M->loss.p, nbt * sizeof(float), hipMemcpyDeviceToHost, st2));
+        HIPOK(hipStreamSynchronize(st2));
+        for (int t = 0; t < nbt; ++t) ep_loss += hl[t];
+        ep_n += nbt;
+      }
+      const double mean = ep_n ? ep_loss / ep_n : 0.0;
+      if (ep == 0) pfirst = mean;
+      plast = mean;
+    }
+    M->prec_trained = nprec > 0;
+  }
+  if (tstats) {
+    tstats->n_samples = nsamp;
+    tstats->steps = steps;
+    tstats->loss_first = std::sqrt(first);
+    tstats->loss_last = std::sqrt(last);
+    tstats->prec_samples = nprec;
+    tstats->prec_loss_first = pfirst;
+    tstats->prec_loss_last = plast;
+    tstats->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return STERN_OK;
 }
 
 void stern_free(stern_system* S) {

@@ -19,11 +19,14 @@ STERN_WARN_NOT_CONVERGED = 1
 STERN_FP64 = 0
 STERN_MIXED = 1
 STERN_GUESS_ZERO = 0
+STERN_GUESS_LEARNED = 1
 STERN_MEM_HOST = 0
 STERN_MEM_DEVICE = 1
 
 EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
-            "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
+            "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
+            "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_apply_h",
+            "stern_apply_pc", "stern_free", "stern_last_error"]
 
 
 class SternError(RuntimeError):
@@ -47,20 +50,32 @@ class Opts(C.Structure):
                 ("mem_kind", C.c_int), ("band_begin", C.c_int), ("band_end", C.c_int), ("max_batch", C.c_int),
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
                 ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int), ("use_graph", C.c_int)]
+                ("max_outer", C.c_int), ("use_graph", C.c_int), ("model", C.c_void_p)]
 
 
-NKERNEL = 16
+NKERNEL = 17
 KERNEL_NAMES = ["xinv", "plane_h", "xfwd", "pc_reduce", "pc_expand", "kb_reduce", "kb_expand", "sum_parts", "cg",
-                "rhs_plane", "dn_plane", "other", "plane_h32", "x32", "gemm_bf16", "cg32"]
+                "rhs_plane", "dn_plane", "other", "plane_h32", "x32", "gemm_bf16", "cg32", "net"]
 
 
 class Stats(C.Structure):
     _fields_ = [("n_solves", C.c_int), ("n_converged", C.c_int), ("n_fallback", C.c_int), ("n_restarts", C.c_int),
-                ("total_iters", C.c_longlong), ("max_iters", C.c_int), ("wall_s", C.c_double),
+                ("n_guess_rejected", C.c_int), ("total_iters", C.c_longlong), ("max_iters", C.c_int), ("wall_s", C.c_double),
                 ("max_true_resid", C.c_double), ("iters", C.POINTER(C.c_int)), ("resid", C.POINTER(C.c_double)),
                 ("kernel_launches", C.c_longlong * NKERNEL), ("kernel_ms", C.c_double * NKERNEL),
                 ("kernel_bytes", C.c_double * NKERNEL), ("kernel_flops", C.c_double * NKERNEL)]
+
+
+class TrainOpts(C.Structure):
+    _fields_ = [("epochs", C.c_int), ("batch", C.c_int), ("lr", C.c_double), ("max_solves", C.c_int),
+                ("tol", C.c_double), ("seed", C.c_ulonglong), ("prec_epochs", C.c_int), ("prec_lr", C.c_double),
+                ("prec_max_solves", C.c_int)]
+
+
+class TrainStats(C.Structure):
+    _fields_ = [("n_samples", C.c_int), ("steps", C.c_int), ("loss_first", C.c_double), ("loss_last", C.c_double),
+                ("prec_samples", C.c_int), ("prec_loss_first", C.c_double), ("prec_loss_last", C.c_double),
+                ("wall_s", C.c_double)]
 
 
 _lib = None
@@ -81,13 +96,23 @@ def lib():
         L.stern_apply_chi0.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, P(Opts), P(Stats)]
         L.stern_apply_chi0_many.argtypes = [C.c_int, P(C.c_void_p), P(C.c_int), P(C.c_void_p), P(C.c_void_p),
                                             P(Opts), P(Stats)]
+        L.stern_model_create.argtypes = [C.c_int, C.c_ulonglong, P(C.c_void_p)]
+        L.stern_model_train.argtypes = [C.c_void_p, C.c_int, P(C.c_void_p), P(C.c_int), P(C.c_void_p), C.c_int,
+                                        P(TrainOpts), P(TrainStats)]
+        L.stern_model_num_params.argtypes = []
+        L.stern_model_get_weights.argtypes = [C.c_void_p, P(C.c_float), C.c_int]
+        L.stern_model_set_weights.argtypes = [C.c_void_p, P(C.c_float), C.c_int]
+        L.stern_model_free.argtypes = [C.c_void_p]
+        L.stern_model_free.restype = None
         L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_free.argtypes = [C.c_void_p]
         L.stern_free.restype = None
         L.stern_last_error.restype = C.c_char_p
         for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied",
-                     "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc"):
+                     "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc",
+                     "stern_model_create", "stern_model_train", "stern_model_num_params", "stern_model_get_weights",
+                     "stern_model_set_weights"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -137,12 +162,13 @@ def _torch_stream():
 
 
 def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
-              inner_tol=0.0, max_outer=0, use_graph=False):
+              inner_tol=0.0, max_outer=0, use_graph=False, model=None):
     o = Opts()
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
-    o.guess = STERN_GUESS_ZERO
+    o.guess = STERN_GUESS_ZERO if model is None else STERN_GUESS_LEARNED
+    o.model = None if model is None else model._h
     o.mem_kind = mem_kind
     o.band_begin, o.band_end = (0, 0) if band_range is None else (int(band_range[0]), int(band_range[1]))
     o.max_batch = int(max_batch)
@@ -161,7 +187,7 @@ def _kernels(st):
 
 
 def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, max_iter=0, check_every=0,
-                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False):
+                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None):
     """Batched apply over independent systems (stern_apply_chi0_many); returns (list of dn, info)."""
     n = len(systems)
     ptrs = [_ptr(d, False) for d in dvs]
@@ -179,12 +205,12 @@ def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, 
     npert = (C.c_int * n)(*[d.shape[0] for d in dvs])
     dvp = (C.c_void_p * n)(*[p[0] for p in ptrs])
     dnp = (C.c_void_p * n)(*[p[0] for p in outs])
-    o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph)
+    o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph, model)
     st = Stats()
     rc = _check(lib().stern_apply_chi0_many(n, hs, npert, dvp, dnp, C.byref(o), C.byref(st)))
     info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
-                n_restarts=st.n_restarts, total_iters=st.total_iters, max_iters=st.max_iters, wall_s=st.wall_s,
-                max_true_resid=st.max_true_resid)
+                n_restarts=st.n_restarts, n_guess_rejected=st.n_guess_rejected, total_iters=st.total_iters,
+                max_iters=st.max_iters, wall_s=st.wall_s, max_true_resid=st.max_true_resid)
     if profile:
         info["kernels"] = _kernels(st)
     return dn_outs, info
@@ -227,10 +253,12 @@ class System:
         self.n_occ = n_occ
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
-                   samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False):
+                   samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False,
+                   model=None):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
-        samples: optional list of (band, pert) pairs whose solution vectors are returned."""
+        samples: optional list of (band, pert) pairs whose solution vectors are returned.
+        model: a trained Model for the learned guess and preconditioner (None: zero guess, Teter)."""
         n_pert = dv_r.shape[0]
         dp, mk, k1 = _ptr(dv_r, False)
         if dn_out is None:
@@ -243,7 +271,7 @@ class System:
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
         o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
-                      use_graph)
+                      use_graph, model)
         keep = []
         sx = None
         if samples:
@@ -262,7 +290,7 @@ class System:
         st.resid = resid.ctypes.data_as(C.POINTER(C.c_double))
         rc = _check(lib().stern_apply_chi0(self._h, n_pert, dp, op, C.byref(o), C.byref(st)))
         info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
-                    n_restarts=st.n_restarts,
+                    n_restarts=st.n_restarts, n_guess_rejected=st.n_guess_rejected,
                     total_iters=st.total_iters, max_iters=st.max_iters, wall_s=st.wall_s,
                     max_true_resid=st.max_true_resid, iters=iters, resid=resid, samples=sx)
         if profile:
@@ -284,3 +312,55 @@ class System:
         _check(lib().stern_apply_pc(self._h, c.shape[0], C.c_void_p(c.ctypes.data), C.c_void_p(out.ctypes.data),
                                     STERN_MEM_HOST))
         return out
+
+
+class Model:
+    """Learned initial guess and diagonal preconditioner (stern_model_*)."""
+
+    def __init__(self, seed=0, device=0):
+        h = C.c_void_p()
+        _check(lib().stern_model_create(int(device), int(seed), C.byref(h)))
+        self._h = h
+
+    @staticmethod
+    def num_params():
+        return int(lib().stern_model_num_params())
+
+    def train(self, systems, dvs, epochs=0, batch=0, lr=0.0, max_solves=0, tol=0.0, seed=0, prec_epochs=0,
+              prec_lr=0.0, prec_max_solves=0):
+        """Fits the net to plain-FP64 solutions of each system's fields, then the preconditioner head."""
+        n = len(systems)
+        ptrs = [_ptr(d, False) for d in dvs]
+        mk = ptrs[0][1]
+        if any(p[1] != mk for p in ptrs):
+            raise ValueError("all fields must be host arrays or all CUDA tensors")
+        hs = (C.c_void_p * n)(*[s._h for s in systems])
+        npert = (C.c_int * n)(*[d.shape[0] for d in dvs])
+        dvp = (C.c_void_p * n)(*[p[0] for p in ptrs])
+        o = TrainOpts(int(epochs), int(batch), float(lr), int(max_solves), float(tol), int(seed), int(prec_epochs),
+                      float(prec_lr), int(prec_max_solves))
+        st = TrainStats()
+        _check(lib().stern_model_train(self._h, n, hs, npert, dvp, mk, C.byref(o), C.byref(st)))
+        return dict(n_samples=st.n_samples, steps=st.steps, loss_first=st.loss_first, loss_last=st.loss_last,
+                    prec_samples=st.prec_samples, prec_loss_first=st.prec_loss_first,
+                    prec_loss_last=st.prec_loss_last, wall_s=st.wall_s)
+
+    def get_weights(self):
+        w = np.zeros(self.num_params(), dtype=np.float32)
+        _check(lib().stern_model_get_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), len(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        _check(lib().stern_model_set_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), len(w)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stern_model_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
