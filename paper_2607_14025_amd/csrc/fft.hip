@@ -412,6 +412,204 @@ __global__ __launch_bounds__((plane_nt<N, T>())) void k_plane_vloc(Z<T>* __restr
   }
 }
 
+// ---- H apply, compact variant: active z lines in LDS, wave-local transforms ----
+//
+// Per (plane ix, vector) pair only the nza active z lines of the plane are
+// kept in LDS, as Q[f][y] (line f of the sphere's z range, all N values of y).
+// Each wave owns a contiguous set of those lines for the y transforms, which
+// run in place in Q, and a contiguous block of rows y for the z transforms,
+// which go through a per-wave scratch of ZR rows x N. Lines and rows never
+// cross waves inside a pass, so the stages of a pass need only wave-level
+// ordering; a pair needs two workgroup barriers (after the inverse y pass and
+// after the z pass). The z transform of a row is inverse stage 1 (radix R1),
+// then inverse stage 2 (radix R2), x V_loc and the first stage of the
+// reversed forward plan (radix R2) in registers, then forward stage 2 (radix
+// R1), keeping the active z only. V_loc is read from a [x][z][y] copy so that
+// lanes walking consecutive rows read consecutive addresses.
+template <int N, class T, int W, int ZR>
+struct PlaneWCfg {
+  static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  static constexpr int RM = R1 > R2 ? R1 : R2;
+  static constexpr int QLD = N + 1;
+  static constexpr int NT = 64 * W;
+  static constexpr int MAXZ = (ZR * RM + 63) / 64;         // items per lane in a z stage
+};
+
+template <int N, class T, int W, int ZR>
+constexpr size_t planew_lds_bytes(int nza) {
+  return ((size_t)nza * (N + 1) + N + (size_t)W * N * ZR) * sizeof(Z<T>);
+}
+
+// orders the LDS accesses of one wave: stores above, loads below
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int N, class T, int W, int ZR>
+__global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, const int* __restrict__ vidx, int nvec,
+                                                     const T* __restrict__ vt, FftGeom g) {
+  using C = PlaneWCfg<N, T, W, ZR>;
+  constexpr int R1 = C::R1, R2 = C::R2, QLD = C::QLD, MAXZ = C::MAXZ;
+  extern __shared__ unsigned char smem_raw[];
+  const int nza = g.nza, nm = g.zact_lo;
+  Z<T>* Q = reinterpret_cast<Z<T>*>(smem_raw);
+  Z<T>* tw = Q + (size_t)nza * QLD;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  Z<T>* Sw = tw + N + (size_t)wave * N * ZR;
+  {
+    const Z<T>* src = twtab<T>(g);
+    for (int i = tid; i < N; i += C::NT) tw[i] = src[i];
+  }
+  __syncthreads();
+  const Z<T> zero = zmk(T(0), T(0));
+  auto act = [nm](int i) { return i <= nm || i >= N - nm; };             // active y or z index
+  auto fz = [nm](int z) { return z <= nm ? z : z - N + 2 * nm + 1; };     // active z -> line
+  // this wave's y lines [f0, f0 + nl) and z-pass rows [y0w, y0w + nr)
+  const int lpw = (nza + W - 1) / W;
+  const int f0 = min(nza, wave * lpw), nl = min(nza, f0 + lpw) - f0;
+  constexpr int RPW = (N + W - 1) / W;
+  const int y0w = min(N, wave * RPW), nr = min(N, y0w + RPW) - y0w;
+  const int* __restrict__ yc = g.ycol;
+  const long total = (long)N * nvec;
+  for (long q = blockIdx.x; q < total; q += gridDim.x) {
+    const int ix = (int)(q / nvec), b = (int)(q - (long)ix * nvec);
+    const int vec = vidx ? vidx[b] : b;
+    Z<T>* tp = pen + ((size_t)vec * N + ix) * g.ncol_pad;
+    const T* __restrict__ vx = vt + (size_t)ix * N * N;
+    // ---- inverse y on this wave's lines, in place in Q ----
+    for (int it = lane; it < nl * R2; it += 64) {
+      const int j = it % R2, f = f0 + it / R2;
+      Z<T> v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int y = j + r * R2;
+        v[r] = zero;
+        if (act(y)) {
+          const int col = yc[y * nza + f];
+          if (col >= 0) v[r] = tp[col];
+        }
+      }
+      dft<R1, +1>(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) Q[f * QLD + j * R1 + r] = v[r];
+    }
+    wave_sync();
+    for (int it = lane; it < nl * R1; it += 64) {
+      const int j = it % R1, f = f0 + it / R1;
+      Z<T> v[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[r] = Q[f * QLD + j + r * R1];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) v[r] = v[r] * twid<+1>(tw, r * j);
+      dft<R2, +1>(v);
+#pragma unroll
+      for (int r = 0; r < R2; ++r) Q[f * QLD + j + r * R1] = v[r];
+    }
+    __syncthreads();
+    // ---- z transforms of this wave's rows, ZR at a time ----
+    for (int m0 = 0; m0 < nr; m0 += ZR) {
+      const int nz = min(ZR, nr - m0), y0 = y0w + m0;
+      // inverse stage 1 (radix R1) from the active z of Q
+      for (int it = lane; it < nz * R2; it += 64) {
+        const int l = it % nz, j = it / nz;
+        Z<T> v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int z = j + r * R2;
+          v[r] = zero;
+          if (act(z)) v[r] = Q[fz(z) * QLD + y0 + l];
+        }
+        dft<R1, +1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) Sw[(j * R1 + r) * ZR + l] = v[r];
+      }
+      wave_sync();
+      // inverse stage 2 (radix R2), x V, forward stage 1 of the reversed plan (radix R2)
+      {
+        Z<T> v[MAXZ][R2];
+#pragma unroll
+        for (int k = 0; k < MAXZ; ++k) {
+          const int it = lane + 64 * k;
+          if (it < nz * R1) {
+            const int l = it % nz, j = it / nz;
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[k][r] = Sw[(j + r * R1) * ZR + l];
+          }
+        }
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < MAXZ; ++k) {
+          const int it = lane + 64 * k;
+          if (it < nz * R1) {
+            const int l = it % nz, j = it / nz;
+#pragma unroll
+            for (int r = 1; r < R2; ++r) v[k][r] = v[k][r] * twid<+1>(tw, r * j);
+            dft<R2, +1>(v[k]);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) v[k][r] = zscale(v[k][r], vx[(size_t)(j + r * R1) * N + y0 + l]);
+            dft<R2, -1>(v[k]);
+#pragma unroll
+            for (int r = 0; r < R2; ++r) Sw[(j * R2 + r) * ZR + l] = v[k][r];
+          }
+        }
+      }
+      wave_sync();
+      // forward stage 2 (radix R1), active z back into Q
+      for (int it = lane; it < nz * R2; it += 64) {
+        const int l = it % nz, j = it / nz;
+        Z<T> v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = Sw[(j + r * R2) * ZR + l];
+#pragma unroll
+        for (int r = 1; r < R1; ++r) v[r] = v[r] * twid<-1>(tw, r * j);
+        dft<R1, -1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+          const int z = j + r * R2;
+          if (act(z)) Q[fz(z) * QLD + y0 + l] = v[r];
+        }
+      }
+      wave_sync();
+    }
+    __syncthreads();
+    // ---- forward y on this wave's lines, out to the pencils ----
+    // Decimation in frequency, in place in Q: with y = j + R2 r and k = R1 k2 + k1,
+    // stage A takes the radix-R1 DFT over r of each j and scales output k1 by
+    // w^(j k1); stage B takes the radix-R2 DFT over j of each k1 (a contiguous
+    // group) and yields k = R1 k2 + k1.
+    for (int it = lane; it < nl * R2; it += 64) {
+      const int j = it % R2, f = f0 + it / R2;
+      Z<T> v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[r] = Q[f * QLD + j + r * R2];
+      dft<R1, -1>(v);
+#pragma unroll
+      for (int k1 = 1; k1 < R1; ++k1) v[k1] = v[k1] * twid<-1>(tw, j * k1);
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) Q[f * QLD + j + k1 * R2] = v[k1];
+    }
+    wave_sync();
+    for (int it = lane; it < nl * R1; it += 64) {
+      const int k1 = it % R1, f = f0 + it / R1;
+      Z<T> v[R2];
+#pragma unroll
+      for (int jj = 0; jj < R2; ++jj) v[jj] = Q[f * QLD + k1 * R2 + jj];
+      dft<R2, -1>(v);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int y = k2 * R1 + k1;
+        if (act(y)) {
+          const int col = yc[y * nza + f];
+          if (col >= 0) tp[col] = v[k2];
+        }
+      }
+    }
+    wave_sync();  // the next pair's inverse y rewrites this wave's lines of Q
+  }
+}
+
 // right-hand side: pencils[s] of plane ix = forward yz DFT of psi_r[band[s]] * dv[pert[s]]
 template <int N>
 __global__ __launch_bounds__(plane_nt<N>()) void k_plane_rhs(const Z64* __restrict__ psi_r,
@@ -648,6 +846,56 @@ void launch_plane_vloc(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, c
                    }));
 }
 template void launch_plane_vloc<double>(const FftGeom&, Z64*, const int*, int, const double*, hipStream_t);
+namespace {
+// resident workgroups per CU of a kernel at a block size and dynamic LDS size (cached)
+int blocks_per_cu(const void* kernel, int nt, size_t lds) {
+  static std::mutex mu;
+  struct E {
+    const void* k;
+    int nt;
+    size_t lds;
+    int n;
+  };
+  static E cache[256];
+  static int nc = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  for (int i = 0; i < nc; ++i)
+    if (cache[i].k == kernel && cache[i].nt == nt && cache[i].lds == lds) return cache[i].n;
+  if (lds > 64 * 1024) (void)hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, nt, lds) != hipSuccess || n < 1) n = 1;
+  if (nc < 256) cache[nc++] = E{kernel, nt, lds, n};
+  return n;
+}
+}  // namespace
+
+template <class T>
+void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, hipStream_t st) {
+  if (nvec <= 0) return;
+  STERN_DISPATCH_N(g.N, ({
+                     constexpr int W = 4;
+                     constexpr int RM = PlaneWCfg<NN, T, W, 1>::RM;
+                     constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
+                     const size_t lds = planew_lds_bytes<NN, T, W, ZR>(g.nza);
+                     const void* kp = (const void*)k_plane_hw<NN, T, W, ZR>;
+                     const int per_cu = blocks_per_cu(kp, 64 * W, lds);
+                     const long pairs = (long)NN * nvec;
+                     const int grid = (int)std::min<long>(pairs, (long)g.n_cu * per_cu);
+                     k_plane_hw<NN, T, W, ZR><<<grid, 64 * W, lds, st>>>(pen, vidx, nvec, vt, g);
+                   }));
+}
+size_t plane_hw_lds(int N, int nza, bool fp64) {
+  size_t r = 0;
+  STERN_DISPATCH_N(N, ({
+                     constexpr int RM = PlaneWCfg<NN, double, 4, 1>::RM;
+                     constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
+                     r = fp64 ? planew_lds_bytes<NN, double, 4, ZR>(nza) : planew_lds_bytes<NN, float, 4, ZR>(nza);
+                   }));
+  return r;
+}
+template void launch_plane_hw<double>(const FftGeom&, Z64*, const int*, int, const double*, hipStream_t);
+template void launch_plane_hw<float>(const FftGeom&, Z32*, const int*, int, const float*, hipStream_t);
+
 template void launch_plane_vloc<float>(const FftGeom&, Z32*, const int*, int, const float*, hipStream_t);
 
 void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,

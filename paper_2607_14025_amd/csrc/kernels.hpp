@@ -46,6 +46,10 @@ void launch_xfwd(const FftGeom& g, const Z<T>* pen, const int* vidx, int nvec, Z
 // yz planes of the H apply: inverse, multiply by v_r (pre-scaled by 1/N^3), forward; in place.
 template <class T>
 void launch_plane_vloc(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* v_r, hipStream_t st);
+// same operation, compact-LDS wave-local kernel; vt = V_loc as [x][z][y]
+template <class T>
+void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, hipStream_t st);
+size_t plane_hw_lds(int N, int nza, bool fp64);  // its LDS bytes per workgroup
 // yz planes of the right-hand side: pencils[s] = forward planes of psi_r[band[s]] * dv[pert[s]].
 void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
                       int nvec, Z64* pen, hipStream_t st);

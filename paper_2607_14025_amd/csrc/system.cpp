@@ -93,7 +93,10 @@ struct stern_system {
   HostBasis hb;
   int n_atoms = 0, natoms_pad = 0;
   // static device data
-  DBuf col_start, col_len, col_xmin, col_pos, zl, ycol, g2h, tw64, tw32, v_r, v_r32, kb, perm;
+  DBuf col_start, col_len, col_xmin, col_pos, zl, ycol, g2h, tw64, tw32, v_r, v_r32, v_t, v_t32, kb, perm;
+  // yz-plane kernel of the H apply per precision: 0 full-plane, 1 compact wave-local
+  int plane_var64 = 1, plane_var32 = 1;
+  size_t lds_max = 160 * 1024;
   // occupied states
   int n_occ = 0, nocc_pad = 0;
   bool have_occ = false;
@@ -178,7 +181,7 @@ struct stern_system {
                    &kbT_hi,    &kbT_lo,   &m_d,     &m_r,      &m_p,     &m_q,      &m_z,      &m_rz,
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
-                   &g_rej,     &net_feat, &net_coef, &kprec};
+                   &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -263,7 +266,12 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
   CHECKED(timed(S, STERN_K_XINV, n * (npw * zb + pen), 0.0,
                 [&] { launch_xinv(g, in, list, n, S->pen.as<Z64>(), S->stream); }));
   CHECKED(timed(S, STERN_K_PLANE_H, n * 2.0 * pen + N * N * N * sizeof(double), 0.0,
-                [&] { launch_plane_vloc(g, S->pen.as<Z64>(), list, n, S->v_r.as<double>(), S->stream); }));
+                [&] {
+                  if (S->plane_var64 == 1)
+                    launch_plane_hw<double>(g, S->pen.as<Z64>(), list, n, S->v_t.as<double>(), S->stream);
+                  else
+                    launch_plane_vloc(g, S->pen.as<Z64>(), list, n, S->v_r.as<double>(), S->stream);
+                }));
   CHECKED(timed(S, STERN_K_XFWD, n * (pen + 2.0 * npw * zb), 0.0,
                 [&] { launch_xfwd(g, S->pen.as<Z64>(), list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
   if (S->n_atoms > 0) {
@@ -315,7 +323,12 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
   CHECKED(timed(S, STERN_K_X32, n * (npw * zb + pen), 0.0,
                 [&] { launch_xinv<float>(g, in, list, n, pen32, S->stream); }));
   CHECKED(timed(S, STERN_K_PLANE_H32, n * 2.0 * pen + N * N * N * sizeof(float), 0.0,
-                [&] { launch_plane_vloc<float>(g, pen32, list, n, S->v_r32.as<float>(), S->stream); }));
+                [&] {
+                  if (S->plane_var32 == 1)
+                    launch_plane_hw<float>(g, pen32, list, n, S->v_t32.as<float>(), S->stream);
+                  else
+                    launch_plane_vloc<float>(g, pen32, list, n, S->v_r32.as<float>(), S->stream);
+                }));
   CHECKED(timed(S, STERN_K_X32, n * (pen + 2.0 * npw * zb), 0.0,
                 [&] { launch_xfwd<float>(g, pen32, list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
   if (S->n_atoms > 0) {
@@ -816,6 +829,12 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     delete S;
     return fail(STERN_ERR_UNSUPPORTED, "FP64 plane of grid %d needs %zu bytes of LDS", hb.N, lds);
   }
+  {  // yz-plane kernel of the H apply: the compact one when its LDS fits
+    const size_t lds_max = std::max((size_t)prop.sharedMemPerBlock, (size_t)prop.maxSharedMemoryPerMultiProcessor);
+    S->plane_var64 = plane_hw_lds(hb.N, hb.nza, true) <= lds_max ? 1 : 0;
+    S->plane_var32 = plane_hw_lds(hb.N, hb.nza, false) <= lds_max ? 1 : 0;
+    S->lds_max = lds_max;
+  }
   S->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
   S->n_atoms = (int)(p.pos.size() / 3);
   S->natoms_pad = std::max(64, (S->n_atoms + 63) / 64 * 64);
@@ -843,6 +862,20 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     CHECKED(upload(S->v_r, v.data(), v.size() * sizeof(double), st));
     std::vector<float> v32(v.begin(), v.end());
     CHECKED(upload(S->v_r32, v32.data(), v32.size() * sizeof(float), st));
+    {  // [x][z][y] copies for the compact plane kernel
+      const size_t Nn = hb.N;
+      std::vector<double> vt(v.size());
+      std::vector<float> vt32(v.size());
+      for (size_t x = 0; x < Nn; ++x)
+        for (size_t y = 0; y < Nn; ++y)
+          for (size_t z = 0; z < Nn; ++z) {
+            vt[(x * Nn + z) * Nn + y] = v[(x * Nn + y) * Nn + z];
+            vt32[(x * Nn + z) * Nn + y] = (float)v[(x * Nn + y) * Nn + z];
+          }
+      CHECKED(upload(S->v_t, vt.data(), vt.size() * sizeof(double), st));
+      CHECKED(upload(S->v_t32, vt32.data(), vt32.size() * sizeof(float), st));
+      HIPOK(hipStreamSynchronize(st));  // vt, vt32 are released at the end of this block
+    }
     std::vector<std::complex<double>> B = kb_projectors(p, hb, S->natoms_pad);
     CHECKED(upload(S->kb, B.data(), B.size() * sizeof(Z64), st));
     const size_t kbn = (size_t)S->natoms_pad * hb.npw_pad * 2 * sizeof(__bf16);
