@@ -33,97 +33,164 @@ __device__ __forceinline__ void split8(const float (&v)[8], bf16x8& hi, bf16x8& 
   }
 }
 
-constexpr int kThreads = 256;  // 4 waves in a 2 x 2 arrangement of 32 x 32 tiles
+constexpr int kThreads = 256;  // 4 waves
+constexpr int kBf16TargetGroups = 512;  // workgroups a split-K reduce aims for
 
-// C[n][m] partial over this split's K range = sum_k conj(A[m][k]) X[xidx[n]][k]
-// A: hi/lo [M_pad][2 K] bf16 interleaved; X: [rows][ldx] complex float
-__global__ __launch_bounds__(kThreads) void k_reduce_bf16(const __bf16* __restrict__ Ahi,
-                                                          const __bf16* __restrict__ Alo, int M_pad,
-                                                          const Z32* __restrict__ X, int ldx,
-                                                          const int* __restrict__ xidx, int ncols, int K,
-                                                          int kchunk, Z32* __restrict__ cpart) {
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// (-a_im, a_re) for each complex (a_re, a_im) of an interleaved bf16x8: rotate
+// every dword by 16 bits and flip the sign of the new low half
+__device__ __forceinline__ bf16x8 rot_neg(bf16x8 a) {
+  u32x4 d = __builtin_bit_cast(u32x4, a);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) d[e] = __builtin_amdgcn_alignbit(d[e], d[e], 16) ^ 0x8000u;
+  return __builtin_bit_cast(bf16x8, d);
+}
+
+// 4 complex floats (interleaved re, im) -> bf16 hi and lo
+__device__ __forceinline__ void split_z4(const Z32 (&v)[4], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const __bf16 hr = (__bf16)v[t].re, hm = (__bf16)v[t].im;
+    hi[2 * t] = hr;
+    hi[2 * t + 1] = hm;
+    lo[2 * t] = (__bf16)(v[t].re - (float)hr);
+    lo[2 * t + 1] = (__bf16)(v[t].im - (float)hm);
+  }
+}
+
+constexpr int kWM = 128;     // reduce: rows of A per workgroup (4 row groups of 32)
+constexpr int kWN = 128;     // reduce: columns per workgroup (2 column groups of 64)
+constexpr int kET = 256;     // expand: rows k per workgroup (4 groups of 64)
+constexpr int kEN = 128;     // expand: columns per workgroup (2 groups of 64)
+constexpr int kThreads8 = 512;
+
+// C[n][m] partial over this split's K range = sum_k conj(A[m][k]) X[xidx[n]][k].
+// 8 waves: wave (wm, wn) owns rows [32 wm, 32 wm + 32) and columns
+// [64 wn, 64 wn + 64) of the 128 x 128 tile. The 128 x 16 slice of X of a K
+// step is split into bf16 hi/lo once and staged in LDS (double-buffered);
+// A's fragments of the next step are loaded while this step's MFMAs run.
+// Re C = A . X and Im C = A' . X along the interleaved reduction index, with
+// A' = (-a_im, a_re) formed from A in registers.
+__global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __restrict__ Ahi,
+                                                            const __bf16* __restrict__ Alo, int M_pad,
+                                                            const Z32* __restrict__ X, int ldx,
+                                                            const int* __restrict__ xidx, int ncols, int K,
+                                                            int kchunk, Z32* __restrict__ cpart) {
+  __shared__ bf16x8 xs[2][2][kWN * 4];  // [buffer][hi, lo][column * 4 + group of 4 complex]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
-  const int m0 = blockIdx.x * 64 + (wave & 1) * 32;
-  const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  const int split = blockIdx.z;
+  const int wm = wave & 3, wn = wave >> 2;
+  const int n0 = blockIdx.x * kWN;
+  const int split = blockIdx.y;
+  const int m0 = blockIdx.z * kWM + wm * 32;
+  const bool live = m0 < M_pad;
   const int kb = split * kchunk;
   const int ke = min(K, kb + kchunk);
+  // staging: thread -> (column tn, group tq of 4 complex)
+  const int tn = threadIdx.x >> 2, tq = threadIdx.x & 3;
+  const int ncol = n0 + tn;
+  const bool xval = ncol < ncols;
+  const Z32* xrow = X + (size_t)(xval ? (xidx ? xidx[ncol] : ncol) : 0) * ldx;
   const __bf16* ah[2];
   const __bf16* al[2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi) {
-    const size_t row = (size_t)(m0 + 16 * bi + l16) * 2 * K;
+    const size_t row = (size_t)(live ? m0 + 16 * bi + l16 : 0) * 2 * K;
     ah[bi] = Ahi + row;
     al[bi] = Alo + row;
   }
-  const Z32* xr[2];
-  bool xv[2];
-#pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
-    const int n = n0 + 16 * bj + l16;
-    xv[bj] = n < ncols;
-    xr[bj] = X + (size_t)(xv[bj] ? (xidx ? xidx[n] : n) : 0) * ldx;
-  }
-  f32x4 cre[2][2], cim[2][2];
+  f32x4 cre[2][4], cim[2][4];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      cre[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
-      cim[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < 4; ++nb) {
+      cre[bi][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
+      cim[bi][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int kc = kb; kc < ke; kc += 16) {
-    const int k = kc + 4 * g;  // this lane group's 4 complex k
-    bf16x8 a_hi[2], a_lo[2];
+  Z32 xv[4];
+  auto load_x = [&](int kc) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      xv[t] = zmk(0.f, 0.f);
+      if (xval) xv[t] = xrow[kc + 4 * tq + t];
+    }
+  };
+  auto put_x = [&](int buf) {
+    bf16x8 hi, lo;
+    split_z4(xv, hi, lo);
+    xs[buf][0][tn * 4 + tq] = hi;
+    xs[buf][1][tn * 4 + tq] = lo;
+  };
+  bf16x8 a_hi[2], a_lo[2];
+  auto load_a = [&](int kc) {
+    const int k = kc + 4 * g;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
       a_hi[bi] = *reinterpret_cast<const bf16x8*>(ah[bi] + 2 * k);
       a_lo[bi] = *reinterpret_cast<const bf16x8*>(al[bi] + 2 * k);
     }
-    bf16x8 xr_hi[2], xr_lo[2], xi_hi[2], xi_lo[2];
-#pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      float re8[8], im8[8];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        Z32 v = zmk(0.f, 0.f);
-        if (xv[bj]) v = xr[bj][k + t];
-        re8[2 * t] = v.re;
-        re8[2 * t + 1] = v.im;
-        im8[2 * t] = v.im;
-        im8[2 * t + 1] = -v.re;
-      }
-      split8(re8, xr_hi[bj], xr_lo[bj]);
-      split8(im8, xi_hi[bj], xi_lo[bj]);
-    }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        cre[bi][bj] = mfma(a_hi[bi], xr_hi[bj], cre[bi][bj]);
-        cre[bi][bj] = mfma(a_hi[bi], xr_lo[bj], cre[bi][bj]);
-        cre[bi][bj] = mfma(a_lo[bi], xr_hi[bj], cre[bi][bj]);
-        cim[bi][bj] = mfma(a_hi[bi], xi_hi[bj], cim[bi][bj]);
-        cim[bi][bj] = mfma(a_hi[bi], xi_lo[bj], cim[bi][bj]);
-        cim[bi][bj] = mfma(a_lo[bi], xi_hi[bj], cim[bi][bj]);
-      }
+  };
+  if (kb < ke) {
+    load_x(kb);
+    put_x(0);
+    if (live) load_a(kb);
   }
-  // D[i][j]: column j = lane % 16, row i = 4 (lane / 16) + r
+  __syncthreads();
+  int buf = 0;
+  for (int kc = kb; kc < ke; kc += 16) {
+    const bool more = kc + 16 < ke;
+    if (more) load_x(kc + 16);  // in flight during the MFMAs
+    if (live) {
+      bf16x8 c_hi[2], c_lo[2], b_hi[2], b_lo[2];
 #pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
-    const int n = n0 + 16 * bj + l16;
+      for (int bi = 0; bi < 2; ++bi) {
+        c_hi[bi] = a_hi[bi];
+        c_lo[bi] = a_lo[bi];
+        b_hi[bi] = rot_neg(c_hi[bi]);
+        b_lo[bi] = rot_neg(c_lo[bi]);
+      }
+      if (more) load_a(kc + 16);
+#pragma unroll
+      for (int nb = 0; nb < 4; ++nb) {
+        const int col = wn * 64 + nb * 16 + l16;
+        const bf16x8 x_hi = xs[buf][0][col * 4 + g];
+        const bf16x8 x_lo = xs[buf][1][col * 4 + g];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+          cre[bi][nb] = mfma(c_hi[bi], x_hi, cre[bi][nb]);
+          cre[bi][nb] = mfma(c_hi[bi], x_lo, cre[bi][nb]);
+          cre[bi][nb] = mfma(c_lo[bi], x_hi, cre[bi][nb]);
+          cim[bi][nb] = mfma(b_hi[bi], x_hi, cim[bi][nb]);
+          cim[bi][nb] = mfma(b_hi[bi], x_lo, cim[bi][nb]);
+          cim[bi][nb] = mfma(b_lo[bi], x_hi, cim[bi][nb]);
+        }
+      }
+    }
+    if (more) put_x(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+  if (!live) return;
+  // D[i][j]: column j = lane % 16 (vector), row i = 4 (lane / 16) + r
+#pragma unroll
+  for (int nb = 0; nb < 4; ++nb) {
+    const int n = n0 + wn * 64 + nb * 16 + l16;
     if (n >= ncols) continue;
     Z32* dst = cpart + ((size_t)split * ncols + n) * M_pad;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dst[m0 + 16 * bi + 4 * g + r] = zmk(cre[bi][bj][r], cim[bi][bj][r]);
+      for (int r = 0; r < 4; ++r) dst[m0 + 16 * bi + 4 * g + r] = zmk(cre[bi][nb][r], cim[bi][nb][r]);
   }
 }
 
-__global__ void k_sum_parts32(const Z32* __restrict__ cpart, int nsplit, int total, float scale, Z32* __restrict__ C) {
+// C = scale * sum of the split partials, as bf16 hi and lo of (c_re, c_im):
+// Cs[0], Cs[1], each [ncols][2 M_pad] interleaved along m.
+__global__ void k_sum_split(const Z32* __restrict__ cpart, int nsplit, int ncols, int M_pad, float scale,
+                            __bf16* __restrict__ Cs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = ncols * M_pad;
   if (i >= total) return;
   float re = 0.f, im = 0.f;
   for (int s = 0; s < nsplit; ++s) {
@@ -131,82 +198,110 @@ __global__ void k_sum_parts32(const Z32* __restrict__ cpart, int nsplit, int tot
     re += v.re;
     im += v.im;
   }
-  C[i] = zmk(scale * re, scale * im);
+  re *= scale;
+  im *= scale;
+  const size_t plane = (size_t)total * 2;
+  const __bf16 rh = (__bf16)re, ih = (__bf16)im;
+  Cs[2 * (size_t)i] = rh;
+  Cs[2 * (size_t)i + 1] = ih;
+  Cs[plane + 2 * (size_t)i] = (__bf16)(re - (float)rh);
+  Cs[plane + 2 * (size_t)i + 1] = (__bf16)(im - (float)ih);
 }
 
-// Y[yidx[n]][k] += sum_m A[m][k] C[n][m]; AT: hi/lo [K][2 M_pad] bf16 interleaved along m
-__global__ __launch_bounds__(kThreads) void k_expand_bf16(const __bf16* __restrict__ ATh,
-                                                          const __bf16* __restrict__ ATl, int M_pad, int K,
-                                                          const Z32* __restrict__ C, Z32* __restrict__ Y, int ldy,
-                                                          const int* __restrict__ yidx, int ncols) {
+// (c_re, -c_im) and (c_im, c_re) of an interleaved bf16x8 of (c_re, c_im)
+__device__ __forceinline__ bf16x8 conj_b(bf16x8 c) {
+  u32x4 d = __builtin_bit_cast(u32x4, c);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) d[e] ^= 0x80000000u;
+  return __builtin_bit_cast(bf16x8, d);
+}
+__device__ __forceinline__ bf16x8 swap_b(bf16x8 c) {
+  u32x4 d = __builtin_bit_cast(u32x4, c);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) d[e] = __builtin_amdgcn_alignbit(d[e], d[e], 16);
+  return __builtin_bit_cast(bf16x8, d);
+}
+
+// Y[yidx[n]][k] += sum_m A[m][k] C[n][m], A given transposed (AT [K][2 M_pad]
+// hi/lo) and C as k_sum_split writes it. 8 waves: wave (wk, wn) owns rows
+// [64 wk, 64 wk + 64) and columns [64 wn, 64 wn + 64) of the 256 x 128 tile.
+// Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
+__global__ __launch_bounds__(kThreads8) void k_expand_bf16s(const __bf16* __restrict__ ATh,
+                                                            const __bf16* __restrict__ ATl, int M_pad, int K,
+                                                            const __bf16* __restrict__ Cs, Z32* __restrict__ Y,
+                                                            int ldy, const int* __restrict__ yidx, int ncols) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
-  const int k0 = blockIdx.x * 64 + (wave & 1) * 32;
-  const int n0 = blockIdx.y * 64 + (wave >> 1) * 32;
-  int nn[2];
-  bool nv[2];
+  const int wk = wave & 3, wn = wave >> 2;
+  const int k0 = blockIdx.x * kET + wk * 64;
+  if (k0 >= K) return;  // K is a multiple of 64; no barrier below
+  const int n0 = blockIdx.y * kEN + wn * 64;
+  const size_t plane = (size_t)ncols * M_pad * 2;
+  int nn[4];
+  bool nv[4];
 #pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
+  for (int bj = 0; bj < 4; ++bj) {
     nn[bj] = n0 + 16 * bj + l16;
     nv[bj] = nn[bj] < ncols;
   }
-  f32x4 dre[2][2], dim_[2][2];
+  f32x4 dre[4][4], dim_[4][4];
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int bi = 0; bi < 4; ++bi)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
+    for (int bj = 0; bj < 4; ++bj) {
       dre[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
       dim_[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
+  const bf16x8 zero8 = bf16x8{};
   for (int mc = 0; mc < M_pad; mc += 16) {
     const int m = mc + 4 * g;  // this lane group's 4 complex m
-    bf16x8 a_hi[2], a_lo[2];
+    bf16x8 a_hi[4], a_lo[4];
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
+    for (int bi = 0; bi < 4; ++bi) {
       const size_t row = (size_t)(k0 + 16 * bi + l16) * 2 * M_pad + 2 * m;
       a_hi[bi] = *reinterpret_cast<const bf16x8*>(ATh + row);
       a_lo[bi] = *reinterpret_cast<const bf16x8*>(ATl + row);
     }
-    bf16x8 cr_hi[2], cr_lo[2], ci_hi[2], ci_lo[2];
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj) {
-      float re8[8], im8[8];
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        Z32 c = zmk(0.f, 0.f);
-        if (nv[bj]) c = C[(size_t)nn[bj] * M_pad + m + t];
-        re8[2 * t] = c.re;
-        re8[2 * t + 1] = -c.im;
-        im8[2 * t] = c.im;
-        im8[2 * t + 1] = c.re;
+    for (int bj = 0; bj < 4; ++bj) {
+      bf16x8 ch = zero8, cl = zero8;
+      if (nv[bj]) {
+        const size_t o = (size_t)nn[bj] * 2 * M_pad + 2 * m;
+        ch = *reinterpret_cast<const bf16x8*>(Cs + o);
+        cl = *reinterpret_cast<const bf16x8*>(Cs + plane + o);
       }
-      split8(re8, cr_hi[bj], cr_lo[bj]);
-      split8(im8, ci_hi[bj], ci_lo[bj]);
+      const bf16x8 rh = conj_b(ch), rl = conj_b(cl), ih = swap_b(ch), il = swap_b(cl);
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi) {
+        dre[bi][bj] = mfma(a_hi[bi], rh, dre[bi][bj]);
+        dre[bi][bj] = mfma(a_hi[bi], rl, dre[bi][bj]);
+        dre[bi][bj] = mfma(a_lo[bi], rh, dre[bi][bj]);
+        dim_[bi][bj] = mfma(a_hi[bi], ih, dim_[bi][bj]);
+        dim_[bi][bj] = mfma(a_hi[bi], il, dim_[bi][bj]);
+        dim_[bi][bj] = mfma(a_lo[bi], ih, dim_[bi][bj]);
+      }
     }
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int bj = 0; bj < 2; ++bj) {
-        dre[bi][bj] = mfma(a_hi[bi], cr_hi[bj], dre[bi][bj]);
-        dre[bi][bj] = mfma(a_hi[bi], cr_lo[bj], dre[bi][bj]);
-        dre[bi][bj] = mfma(a_lo[bi], cr_hi[bj], dre[bi][bj]);
-        dim_[bi][bj] = mfma(a_hi[bi], ci_hi[bj], dim_[bi][bj]);
-        dim_[bi][bj] = mfma(a_hi[bi], ci_lo[bj], dim_[bi][bj]);
-        dim_[bi][bj] = mfma(a_lo[bi], ci_hi[bj], dim_[bi][bj]);
-      }
   }
+  // D[i][j]: column j = lane % 16 (vector), rows i = 4 (lane / 16) + r: 4 consecutive k per lane
 #pragma unroll
-  for (int bj = 0; bj < 2; ++bj) {
+  for (int bj = 0; bj < 4; ++bj) {
     if (!nv[bj]) continue;
     Z32* y = Y + (size_t)(yidx ? yidx[nn[bj]] : nn[bj]) * ldy;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int k = k0 + 16 * bi + 4 * g + r;
-        const Z32 old = y[k];
-        y[k] = zmk(old.re + dre[bi][bj][r], old.im + dim_[bi][bj][r]);
-      }
+    for (int bi = 0; bi < 4; ++bi) {
+      float4* p = reinterpret_cast<float4*>(y + k0 + 16 * bi + 4 * g);
+      float4 u = p[0], w = p[1];
+      u.x += dre[bi][bj][0];
+      u.y += dim_[bi][bj][0];
+      u.z += dre[bi][bj][1];
+      u.w += dim_[bi][bj][1];
+      w.x += dre[bi][bj][2];
+      w.y += dim_[bi][bj][2];
+      w.z += dre[bi][bj][3];
+      w.w += dim_[bi][bj][3];
+      p[0] = u;
+      p[1] = w;
+    }
   }
 }
 
@@ -236,9 +331,9 @@ __global__ void k_split_rows(const Z64* __restrict__ A, int M, int K, __bf16* __
 }  // namespace
 
 int choose_nsplit_bf16(int M_pad, int ncols, int K) {
-  const int base = (M_pad / 64) * ((ncols + 63) / 64);
-  int ns = (2048 + base - 1) / base;
-  const int maxs = K / 512 > 0 ? K / 512 : 1;
+  const int base = ((M_pad + kWM - 1) / kWM) * ((ncols + kWN - 1) / kWN);
+  int ns = (kBf16TargetGroups + base - 1) / base;
+  const int maxs = K / 256 > 0 ? K / 256 : 1;
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;
   return ns;
@@ -255,21 +350,22 @@ void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z
   if (ncols <= 0) return;
   int kchunk = (K + nsplit - 1) / nsplit;
   kchunk = (kchunk + 15) / 16 * 16;
-  dim3 grid(M_pad / 64, (ncols + 63) / 64, nsplit);
-  k_reduce_bf16<<<grid, kThreads, 0, st>>>(Ahi, Alo, M_pad, X, ldx, xidx, ncols, K, kchunk, cpart);
+  dim3 grid((ncols + kWN - 1) / kWN, nsplit, (M_pad + kWM - 1) / kWM);
+  k_reduce_bf16w<<<grid, kThreads8, 0, st>>>(Ahi, Alo, M_pad, X, ldx, xidx, ncols, K, kchunk, cpart);
 }
 
-void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, Z32* C, hipStream_t st) {
+void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
+                        hipStream_t st) {
   const int total = ncols * M_pad;
   if (total <= 0) return;
-  k_sum_parts32<<<(total + 255) / 256, 256, 0, st>>>(cpart, nsplit, total, scale, C);
+  k_sum_split<<<(total + 255) / 256, 256, 0, st>>>(cpart, nsplit, ncols, M_pad, scale, Cs);
 }
 
-void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const Z32* C, Z32* Y, int ldy,
+void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
                         const int* yidx, int ncols, int K, hipStream_t st) {
   if (ncols <= 0) return;
-  dim3 grid(K / 64, (ncols + 63) / 64);
-  k_expand_bf16<<<grid, kThreads, 0, st>>>(ATh, ATl, M_pad, K, C, Y, ldy, yidx, ncols);
+  dim3 grid((K + kET - 1) / kET, (ncols + kEN - 1) / kEN);
+  k_expand_bf16s<<<grid, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols);
 }
 
 }  // namespace stern

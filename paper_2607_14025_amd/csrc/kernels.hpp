@@ -163,9 +163,10 @@ void launch_split_bf16(const Z64* A, int M, int K, __bf16* hi, __bf16* lo, __bf1
 // C[n][m] partial = sum_k conj(A[m][k]) X[xidx[n]][k] (BF16 split operands, FP32 accumulation)
 void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,
                         int ncols, int K, Z32* cpart, int nsplit, hipStream_t st);
-void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, Z32* C, hipStream_t st);
+void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
+                        hipStream_t st);
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A
-void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const Z32* C, Z32* Y, int ldy,
+void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
                         const int* yidx, int ncols, int K, hipStream_t st);
 
 }  // namespace stern

@@ -299,7 +299,7 @@ int apply_pc32_rows(stern_system* S, Z32* Y, const int* list, int n) {
   const double npw = S->hb.npw, m = S->n_occ;
   const int ns = choose_nsplit_bf16(S->nocc_pad, n, K);
   Z32* cp = S->cpart.as<Z32>();
-  Z32* cm = S->cmat.as<Z32>();
+  __bf16* cm = S->cmat.as<__bf16>();
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (n + m), 8.0 * m * npw * n, [&] {
     launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, Y, K, list, n, K, cp, ns,
                        S->stream);
@@ -335,7 +335,7 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
     const double na = S->n_atoms;
     const int ns = choose_nsplit_bf16(S->natoms_pad, n, K);
     Z32* cp = S->cpart.as<Z32>();
-    Z32* cm = S->cmat.as<Z32>();
+    __bf16* cm = S->cmat.as<__bf16>();
     CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
       launch_reduce_bf16(S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(), S->natoms_pad, in, K, list, n, K, cp, ns,
                          S->stream);
@@ -350,10 +350,12 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
   return 0;
 }
 
+// bytes of split-K partials for up to nmax columns (FP64 and FP32 partials)
 size_t cpart_capacity(int M_pad, int nmax, int K) {
   size_t best = 0;
   for (int n = 1; n <= nmax; ++n) {
-    const size_t c = (size_t)choose_nsplit(M_pad, n, K) * n;
+    const size_t c = std::max((size_t)choose_nsplit(M_pad, n, K) * sizeof(Z64),
+                              (size_t)choose_nsplit_bf16(M_pad, n, K) * sizeof(Z32)) * n;
     if (c > best) best = c;
   }
   return best * M_pad;
@@ -367,7 +369,7 @@ int ensure_workspace(stern_system* S, int ns) {
   CHECKED(S->pen.ensure((size_t)ns * S->hb.N * S->hb.ncol_pad * sizeof(Z64)));
   const int mp = std::max(S->nocc_pad, S->natoms_pad);
   CHECKED(S->cpart.ensure(std::max(cpart_capacity(std::max(S->nocc_pad, 64), ns, (int)K),
-                                   cpart_capacity(S->natoms_pad, ns, (int)K)) * sizeof(Z64)));
+                                   cpart_capacity(S->natoms_pad, ns, (int)K))));
   CHECKED(S->cmat.ensure((size_t)ns * mp * sizeof(Z64)));
   for (DBuf* d : {&S->sv_eps, &S->sv_invT, &S->sv_bb, &S->sv_rz, &S->sv_rr, &S->sv_tres})
     CHECKED(d->ensure((size_t)ns * sizeof(double)));
