@@ -117,6 +117,13 @@ typedef struct {
   int use_graph;
   /* trained stern_model for STERN_GUESS_LEARNED (not owned) */
   const struct stern_model* model;
+  /* STERN_MIXED only: operator of the inner solve. 0: P_c (H - eps_v) P_c
+     (two Psi GEMM pairs per iteration); nonzero: H - eps_v + alpha P_v
+     (alpha = twice the occupied band width, at least 0.01 Ha; one pair per
+     iteration, but with Teter's K, which does not commute with P_v, it needs
+     about twice the iterations on the mid cell). The outer FP64 residual
+     always uses the projected operator. */
+  int inner_shifted;
 } stern_opts;
 
 /* kernel classes of the per-launch profile */
@@ -255,6 +262,35 @@ int stern_model_num_params(void);
 int stern_model_get_weights(const stern_model* m, float* w, int n);
 int stern_model_set_weights(stern_model* m, const float* w, int n);
 void stern_model_free(stern_model* m);
+
+/* ---- kernel variants and the autotuner ----
+ * Tunables of a system (each keeps its value until set again):
+ *   STERN_TUNE_PLANE64   yz-plane kernel of the FP64 H apply: 0 the whole plane
+ *                        in LDS, 1 only the active z lines in LDS with per-wave
+ *                        transforms (the default when its LDS fits)
+ *   STERN_TUNE_PLANE32   the same for the FP32 H apply of the mixed inner solve
+ *   STERN_TUNE_GEMM64_WG workgroups the split-K FP64 reduces (Psi^H Y, B^H Y) aim
+ *                        for; 0 = built-in default (2048)
+ *   STERN_TUNE_GEMM16_WG the same for the split-BF16 reduces; 0 = default (512) */
+#define STERN_TUNE_PLANE64 0
+#define STERN_TUNE_PLANE32 1
+#define STERN_TUNE_GEMM64_WG 2
+#define STERN_TUNE_GEMM16_WG 3
+#define STERN_NTUNE 4
+
+/* value >= 0 sets tunable `which` (STERN_ERR_INVALID_ARG for an unknown
+ * tunable or a value the system cannot run, e.g. a plane kernel whose LDS does
+ * not fit); value < 0 only queries. Returns the tunable's value. */
+int stern_tunable(stern_system* sys, int which, int value);
+
+/* Times every candidate of every tunable on this system's shapes with n_vec
+ * synthetic rows (HIP events on the system's stream; needs set_occupied) and
+ * keeps the fastest. With cache_path != NULL, choices are read from / appended
+ * to that text file, keyed by (GPU arch, grid, active z lines, N_pw, padded
+ * N_occ, padded atom count, n_vec); a complete hit times nothing. chosen
+ * (optional, STERN_NTUNE ints) receives the values. Returns the number of
+ * candidates timed. Synchronous; uses the apply workspace. */
+int stern_autotune(stern_system* sys, int n_vec, const char* cache_path, int* chosen);
 
 /* out = (H - shift_k) c_k for n_vec coefficient rows (canonical order), host or
  * device memory; shift may be NULL (zero). Exposes the H apply of the solver. */

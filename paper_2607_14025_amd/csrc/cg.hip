@@ -66,22 +66,32 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __
 
 // q = A x for a guess x: r = b - q; keep the guess only when ||r|| is finite
 // and below ||b||, else x = 0, r = b. rejected[s] = 1 when dropped.
+// r = b - q for a guess x, with q = A x given in FP64 (q32 == null) or FP32;
+// the guess is kept only if ||r|| is finite and below ||b||, else x = 0, r = b.
 __global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int* __restrict__ act,
-                                                            int* __restrict__ rejected) {
+                                                            const Z32* __restrict__ q32, int* __restrict__ rejected) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   const size_t o = (size_t)s * S.npw_pad;
+  auto qv = [&](int k) -> Z64 {
+    if (q32) {
+      const Z32 v = q32[o + k];
+      return zmk((double)v.re, (double)v.im);
+    }
+    return S.q[o + k];
+  };
   double rr = 0.0;
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 b = S.b[o + k], q = S.q[o + k];
+    const Z64 b = S.b[o + k], q = qv(k);
     const double re = b.re - q.re, im = b.im - q.im;
     rr += re * re + im * im;
   }
   rr = block_sum(rr, sh);
   const bool ok = (rr == rr) && rr < S.bb[s];  // false for NaN
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 b = S.b[o + k], q = S.q[o + k];
+    const Z64 b = S.b[o + k];
     if (ok) {
+      const Z64 q = qv(k);
       S.r[o + k] = zmk(b.re - q.re, b.im - q.im);
     } else {
       S.r[o + k] = b;
@@ -91,6 +101,14 @@ __global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int
   if (threadIdx.x == 0) {
     rejected[s] = ok ? 0 : 1;
     S.tres[s] = ok ? sqrt(rr / S.bb[s]) : 1.0;
+  }
+}
+
+// y = (float) x on rows [0, n) of length ld
+__global__ void k_to32(const Z64* __restrict__ x, Z32* __restrict__ y, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const Z64 v = x[i];
+    y[i] = zmk((float)v.re, (float)v.im);
   }
 }
 
@@ -396,8 +414,12 @@ __global__ void k_fill_zero32(Z32* __restrict__ p, size_t n) {
 void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st) {
   if (n > 0) k_cg_init<<<n, kCgThreads, 0, st>>>(s, act, keep ? 1 : 0);
 }
-void launch_guess_resid(const CgState& s, const int* act, int n, int* rejected, hipStream_t st) {
-  if (n > 0) k_guess_resid<<<n, kCgThreads, 0, st>>>(s, act, rejected);
+void launch_guess_resid(const CgState& s, const int* act, int n, const Z32* q32, int* rejected, hipStream_t st) {
+  if (n > 0) k_guess_resid<<<n, kCgThreads, 0, st>>>(s, act, q32, rejected);
+}
+void launch_to32(const Z64* x, Z32* y, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  k_to32<<<(unsigned)std::min<size_t>((n + 255) / 256, 65536), 256, 0, st>>>(x, y, n);
 }
 void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg_init2<<<n, kCgThreads, 0, st>>>(s, act);

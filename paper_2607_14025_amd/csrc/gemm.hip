@@ -180,9 +180,12 @@ __global__ __launch_bounds__(kGemmThreads) void k_zgemm_expand(const Z64* __rest
 
 }  // namespace
 
-int choose_nsplit(int M_pad, int ncols, int K) {
+constexpr int kGemm64TargetGroups = 2048;  // workgroups a split-K reduce aims for by default
+
+int choose_nsplit(int M_pad, int ncols, int K, int target) {
+  if (target <= 0) target = kGemm64TargetGroups;
   const int base = (M_pad / 64) * ((ncols + 63) / 64);
-  int ns = (2048 + base - 1) / base;
+  int ns = (target + base - 1) / base;
   const int maxs = K / 256 > 0 ? K / 256 : 1;
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;

@@ -330,9 +330,10 @@ __global__ void k_split_rows(const Z64* __restrict__ A, int M, int K, __bf16* __
 
 }  // namespace
 
-int choose_nsplit_bf16(int M_pad, int ncols, int K) {
+int choose_nsplit_bf16(int M_pad, int ncols, int K, int target) {
+  if (target <= 0) target = kBf16TargetGroups;
   const int base = ((M_pad + kWM - 1) / kWM) * ((ncols + kWN - 1) / kWN);
-  int ns = (kBf16TargetGroups + base - 1) / base;
+  int ns = (target + base - 1) / base;
   const int maxs = K / 256 > 0 ? K / 256 : 1;
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;

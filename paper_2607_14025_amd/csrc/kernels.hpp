@@ -68,7 +68,8 @@ void launch_sum_parts(const Z64* cpart, int nsplit, int ncols, int M_pad, double
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m], k < K (multiple of 64).
 void launch_zgemm_expand(const Z64* A, int M_pad, const Z64* C, Z64* Y, int ldy, const int* yidx, int ncols, int K,
                          hipStream_t st);
-int choose_nsplit(int M_pad, int ncols, int K);
+// split-K factor for a reduce of ncols columns aiming at `target` workgroups (<= 0: default)
+int choose_nsplit(int M_pad, int ncols, int K, int target);
 
 // ---- CG vector kernels; one workgroup per solve s = act[b] ----
 struct CgState {
@@ -84,7 +85,8 @@ struct CgState {
   int npw_pad;
 };
 void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st);
-void launch_guess_resid(const CgState& s, const int* act, int n, int* rejected, hipStream_t st);
+void launch_guess_resid(const CgState& s, const int* act, int n, const Z32* q32, int* rejected, hipStream_t st);
+void launch_to32(const Z64* x, Z32* y, size_t n, hipStream_t st);
 void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st);
 void launch_cg_alpha(const CgState& s, const int* act, int n, double tol2, hipStream_t st);
 void launch_cg_beta(const CgState& s, const int* act, int n, hipStream_t st);
@@ -157,7 +159,7 @@ void launch_outer_resid(const CgState& s, const int* act, int n, double tol, hip
 void launch_outer_init(const CgState& s, const int* act, int n, hipStream_t st);
 void launch_fill_zero32(Z32* p, size_t n, hipStream_t st);
 
-int choose_nsplit_bf16(int M_pad, int ncols, int K);
+int choose_nsplit_bf16(int M_pad, int ncols, int K, int target);
 // hi/lo BF16 split of complex rows A [M][K] into [M][2K] and transposed [K][2M] layouts
 void launch_split_bf16(const Z64* A, int M, int K, __bf16* hi, __bf16* lo, __bf16* thi, __bf16* tlo, hipStream_t st);
 // C[n][m] partial = sum_k conj(A[m][k]) X[xidx[n]][k] (BF16 split operands, FP32 accumulation)

@@ -35,56 +35,86 @@ __device__ __forceinline__ int nbr_index(int x, int y, int z, int n, int Nc) {
   return (a * Nc + b) * Nc + c;
 }
 
-// out[s][p][co] = act(bias[co] + sum_{n, ci} W[co][n][ci] in[s][nbr(p, n)][ci])
-// One wave computes 16 points x 16 output channels. ACT: 0 none, 1 ReLU.
-// OUT_F32: write FP32 (last layer / gradients), else BF16. Activations are
-// stored with a per-solve stride of ldp >= npts points (ldp a multiple of 16);
-// the padding rows are computed from a clamped point and never stored.
+// out[s][p][co] = act(bias[co] + sum_{n, ci} W[co][n][ci] in[s][nbr(p, n)][ci]); ACT: 0 none, 1 ReLU;
+// OUT_F32: FP32 output (last layer, gradients), else BF16. Activations are
+// stored with a per-solve stride of ldp >= npts points.
+// Tiled form of the same convolution: a workgroup computes a 4 x 4 x 16 block
+// of output points (16 rows of 16 consecutive z) of one solve. The periodic
+// 6 x 6 x 18 halo of the input is staged once in LDS; wave w computes the
+// rows of x = x0 + w. The MFMA takes the weights as its A operand and the
+// activations as B, so D[cout][point] leaves 4 consecutive output channels of
+// one point in each lane (one 8- or 16-byte store). Points past Nc in a
+// partial tile are computed from wrapped inputs and not stored.
+constexpr int kTX = 4, kTY = 4, kTZ = 16;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+
 template <int ACT, bool OUT_F32>
-__global__ __launch_bounds__(256) void k_conv3(const __bf16* __restrict__ in, const __bf16* __restrict__ W,
-                                               const float* __restrict__ bias, void* __restrict__ out, int Nc,
-                                               int npts, int ldp, int nsolve) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int l16 = lane & 15, g = lane >> 4;
-  const long tile = (long)blockIdx.x * 4 + wave;  // 16-point tile over all solves
-  const int tiles_per_solve = ldp / 16;
-  const int s = (int)(tile / tiles_per_solve);
-  if (s >= nsolve) return;
-  const int p0 = (int)(tile - (long)s * tiles_per_solve) * 16;
-  const int p = min(p0 + l16, npts - 1);  // this lane's row point (clamped in the padding)
-  const int x = p / (Nc * Nc), y = (p / Nc) % Nc, z = p % Nc;
+__global__ __launch_bounds__(256) void k_conv3t(const __bf16* __restrict__ in, const __bf16* __restrict__ W,
+                                                const float* __restrict__ bias, void* __restrict__ out, int Nc,
+                                                int ldp) {
+  __shared__ bf16x8 halo[kHX * kHY * kHZ][2];  // [point][channel half]
+  const int s = blockIdx.y;
+  const int nty = (Nc + kTY - 1) / kTY, ntz = (Nc + kTZ - 1) / kTZ;
+  const int tile = blockIdx.x;
+  const int tx = tile / (nty * ntz), ty = (tile / ntz) % nty, tz = tile % ntz;
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
   const __bf16* ins = in + (size_t)s * ldp * C;
-  f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-  const int half = g & 1;  // which 8 channels of the neighbour this lane group carries
-#pragma unroll 2
+  for (int i = threadIdx.x; i < kHX * kHY * kHZ * 2; i += 256) {
+    const int h = i & 1, pt = i >> 1;
+    const int px = pt / (kHY * kHZ), py = (pt / kHZ) % kHY, pz = pt % kHZ;
+    int gx = x0 - 1 + px, gy = y0 - 1 + py, gz = z0 - 1 + pz;
+    gx = ((gx % Nc) + Nc) % Nc;
+    gy = ((gy % Nc) + Nc) % Nc;
+    gz = ((gz % Nc) + Nc) % Nc;
+    halo[pt][h] = *reinterpret_cast<const bf16x8*>(ins + (size_t)((gx * Nc + gy) * Nc + gz) * C + 8 * h);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, g = lane >> 4, half = g & 1;
+  bf16x8 wf[14];
+#pragma unroll
   for (int step = 0; step < 14; ++step) {
     const int n = 2 * step + (g >> 1);
-    bf16x8 a, b;
-    if (n < NB) {
-      a = *reinterpret_cast<const bf16x8*>(ins + (size_t)nbr_index(x, y, z, n, Nc) * C + 8 * half);
-      b = *reinterpret_cast<const bf16x8*>(W + ((size_t)l16 * NB + n) * C + 8 * half);
-    } else {
+    wf[step] = bf16x8{};
+    if (n < NB) wf[step] = *reinterpret_cast<const bf16x8*>(W + ((size_t)l16 * NB + n) * C + 8 * half);
+  }
+  float bj[4];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        a[e] = (__bf16)0.f;
-        b[e] = (__bf16)0.f;
+  for (int r = 0; r < 4; ++r) bj[r] = bias ? bias[4 * g + r] : 0.f;
+  __syncthreads();
+  const int xl = wave;
+  const int gxo = x0 + xl;
+  for (int yl = 0; yl < kTY; ++yl) {
+    f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int step = 0; step < 14; ++step) {
+      const int n = 2 * step + (g >> 1);
+      bf16x8 a = bf16x8{};
+      if (n < NB) {
+        const int dx = n / 9 - 1, dy = (n / 3) % 3 - 1, dz = n % 3 - 1;
+        a = halo[((xl + 1 + dx) * kHY + (yl + 1 + dy)) * kHZ + (l16 + 1 + dz)][half];
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wf[step], a, acc, 0, 0, 0);
+    }
+    // D[i][j]: column j = lane % 16 (point z0 + j), row i = 4 (lane / 16) + r (output channel)
+    const int gyo = y0 + yl, gzo = z0 + l16;
+    if (gxo < Nc && gyo < Nc && gzo < Nc) {
+      const size_t o = ((size_t)s * ldp + (size_t)(gxo * Nc + gyo) * Nc + gzo) * C + 4 * g;
+      float v[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        v[r] = acc[r] + bj[r];
+        if (ACT == 1) v[r] = v[r] > 0.f ? v[r] : 0.f;
+      }
+      if (OUT_F32) {
+        *reinterpret_cast<float4*>(reinterpret_cast<float*>(out) + o) = make_float4(v[0], v[1], v[2], v[3]);
+      } else {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        bf16x4 b;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) b[r] = (__bf16)v[r];
+        *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(out) + o) = b;
       }
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
-  }
-  // D[i][j]: column j = lane % 16 (output channel), row i = 4 (lane / 16) + r (point)
-  const float bj = bias ? bias[l16] : 0.f;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int pt = p0 + 4 * g + r;
-    if (pt >= npts) continue;
-    float v = acc[r] + bj;
-    if (ACT == 1) v = v > 0.f ? v : 0.f;
-    const size_t o = ((size_t)s * ldp + pt) * C + l16;
-    if (OUT_F32)
-      reinterpret_cast<float*>(out)[o] = v;
-    else
-      reinterpret_cast<__bf16*>(out)[o] = (__bf16)v;
   }
 }
 
@@ -427,17 +457,17 @@ int net_ldp(int Nc) { return (Nc * Nc * Nc + 15) / 16 * 16; }
 void launch_conv3(const __bf16* in, const __bf16* W, const float* bias, void* out, int Nc, int nsolve, int act,
                   bool out_f32, hipStream_t st) {
   if (nsolve <= 0) return;
-  const int npts = Nc * Nc * Nc, ldp = net_ldp(Nc);
-  const long tiles = (long)nsolve * (ldp / 16);
-  const unsigned blocks = (unsigned)((tiles + 3) / 4);
+  const int ldp = net_ldp(Nc);
+  const int ntiles = ((Nc + kTX - 1) / kTX) * ((Nc + kTY - 1) / kTY) * ((Nc + kTZ - 1) / kTZ);
+  const dim3 grid(ntiles, nsolve);
   if (act == 1 && !out_f32)
-    k_conv3<1, false><<<blocks, 256, 0, st>>>(in, W, bias, out, Nc, npts, ldp, nsolve);
+    k_conv3t<1, false><<<grid, 256, 0, st>>>(in, W, bias, out, Nc, ldp);
   else if (act == 0 && out_f32)
-    k_conv3<0, true><<<blocks, 256, 0, st>>>(in, W, bias, out, Nc, npts, ldp, nsolve);
+    k_conv3t<0, true><<<grid, 256, 0, st>>>(in, W, bias, out, Nc, ldp);
   else if (act == 0 && !out_f32)
-    k_conv3<0, false><<<blocks, 256, 0, st>>>(in, W, bias, out, Nc, npts, ldp, nsolve);
+    k_conv3t<0, false><<<grid, 256, 0, st>>>(in, W, bias, out, Nc, ldp);
   else
-    k_conv3<1, true><<<blocks, 256, 0, st>>>(in, W, bias, out, Nc, npts, ldp, nsolve);
+    k_conv3t<1, true><<<grid, 256, 0, st>>>(in, W, bias, out, Nc, ldp);
 }
 
 void launch_conv3_wgrad(const __bf16* in, const float* gout, float* part, float* grad, int Nc, int nsolve,

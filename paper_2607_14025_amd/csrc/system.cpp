@@ -96,11 +96,14 @@ struct stern_system {
   DBuf col_start, col_len, col_xmin, col_pos, zl, ycol, g2h, tw64, tw32, v_r, v_r32, v_t, v_t32, kb, perm;
   // yz-plane kernel of the H apply per precision: 0 full-plane, 1 compact wave-local
   int plane_var64 = 1, plane_var32 = 1;
+  // split-K workgroup targets of the FP64 and split-BF16 reduces (0 = default)
+  int gemm64_wg = 0, gemm16_wg = 0;
   size_t lds_max = 160 * 1024;
   // occupied states
   int n_occ = 0, nocc_pad = 0;
   bool have_occ = false;
   std::vector<double> eps, invT;
+  double alpha_pv = 0.0;  // shift of the occupied subspace in the mixed inner operator
   DBuf psi, psi_r;
   // split BF16 copies of Psi and of the KB rows (row and transposed layouts)
   DBuf psi_hi, psi_lo, psiT_hi, psiT_lo, kb_hi, kb_lo, kbT_hi, kbT_lo;
@@ -244,7 +247,7 @@ int apply_pc_rows(stern_system* S, Z64* Y, const int* list, int n) {
   if (n <= 0) return 0;
   const int K = S->hb.npw_pad;
   const double npw = S->hb.npw, m = S->n_occ, zb = sizeof(Z64);
-  const int ns = choose_nsplit(S->nocc_pad, n, K);
+  const int ns = choose_nsplit(S->nocc_pad, n, K, S->gemm64_wg);
   CHECKED(timed(S, STERN_K_PC_REDUCE, zb * npw * (n + m), 8.0 * m * npw * n, [&] {
     launch_zgemm_reduce(S->psi.as<Z64>(), S->nocc_pad, Y, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
   }));
@@ -276,7 +279,7 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
                 [&] { launch_xfwd(g, S->pen.as<Z64>(), list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
   if (S->n_atoms > 0) {
     const double na = S->n_atoms;
-    const int ns = choose_nsplit(S->natoms_pad, n, K);
+    const int ns = choose_nsplit(S->natoms_pad, n, K, S->gemm64_wg);
     CHECKED(timed(S, STERN_K_KB_REDUCE, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
       launch_zgemm_reduce(S->kb.as<Z64>(), S->natoms_pad, in, K, list, n, K, S->cpart.as<Z64>(), ns, S->stream);
     }));
@@ -293,19 +296,23 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
 // ---- mixed-precision operator pieces (FP32 vectors, split-BF16 GEMMs) ----
 
 // Y <- P_c Y (FP32 rows, BF16 MFMA)
-int apply_pc32_rows(stern_system* S, Z32* Y, const int* list, int n) {
+int apply_psi32_rows(stern_system* S, const Z32* X, Z32* Y, const int* list, int n, float scale);
+int apply_pc32_rows(stern_system* S, Z32* Y, const int* list, int n) { return apply_psi32_rows(S, Y, Y, list, n, -1.f); }
+
+// Y += scale Psi (Psi^H X) on rows `list` (FP32 rows, split-BF16 MFMA); X may be Y
+int apply_psi32_rows(stern_system* S, const Z32* X, Z32* Y, const int* list, int n, float scale) {
   if (n <= 0) return 0;
   const int K = S->hb.npw_pad;
   const double npw = S->hb.npw, m = S->n_occ;
-  const int ns = choose_nsplit_bf16(S->nocc_pad, n, K);
+  const int ns = choose_nsplit_bf16(S->nocc_pad, n, K, S->gemm16_wg);
   Z32* cp = S->cpart.as<Z32>();
   __bf16* cm = S->cmat.as<__bf16>();
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (n + m), 8.0 * m * npw * n, [&] {
-    launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, Y, K, list, n, K, cp, ns,
+    launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, X, K, list, n, K, cp, ns,
                        S->stream);
   }));
   CHECKED(timed(S, STERN_K_SUM_PARTS, 8.0 * m * n * (ns + 1), 0.0,
-                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, -1.f, cm, S->stream); }));
+                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, scale, cm, S->stream); }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (2.0 * n + m), 8.0 * m * npw * n, [&] {
     launch_expand_bf16(S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), S->nocc_pad, cm, Y, K, list, n, K,
                        S->stream);
@@ -333,7 +340,7 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
                 [&] { launch_xfwd<float>(g, pen32, list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
   if (S->n_atoms > 0) {
     const double na = S->n_atoms;
-    const int ns = choose_nsplit_bf16(S->natoms_pad, n, K);
+    const int ns = choose_nsplit_bf16(S->natoms_pad, n, K, S->gemm16_wg);
     Z32* cp = S->cpart.as<Z32>();
     __bf16* cm = S->cmat.as<__bf16>();
     CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
@@ -351,11 +358,11 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
 }
 
 // bytes of split-K partials for up to nmax columns (FP64 and FP32 partials)
-size_t cpart_capacity(int M_pad, int nmax, int K) {
+size_t cpart_capacity(const stern_system* S, int M_pad, int nmax, int K) {
   size_t best = 0;
   for (int n = 1; n <= nmax; ++n) {
-    const size_t c = std::max((size_t)choose_nsplit(M_pad, n, K) * sizeof(Z64),
-                              (size_t)choose_nsplit_bf16(M_pad, n, K) * sizeof(Z32)) * n;
+    const size_t c = std::max((size_t)choose_nsplit(M_pad, n, K, S->gemm64_wg) * sizeof(Z64),
+                              (size_t)choose_nsplit_bf16(M_pad, n, K, S->gemm16_wg) * sizeof(Z32)) * n;
     if (c > best) best = c;
   }
   return best * M_pad;
@@ -368,8 +375,8 @@ int ensure_workspace(stern_system* S, int ns) {
   for (DBuf* d : {&S->wx, &S->wr, &S->wp, &S->wq, &S->wz, &S->wb}) CHECKED(d->ensure(vec));
   CHECKED(S->pen.ensure((size_t)ns * S->hb.N * S->hb.ncol_pad * sizeof(Z64)));
   const int mp = std::max(S->nocc_pad, S->natoms_pad);
-  CHECKED(S->cpart.ensure(std::max(cpart_capacity(std::max(S->nocc_pad, 64), ns, (int)K),
-                                   cpart_capacity(S->natoms_pad, ns, (int)K))));
+  CHECKED(S->cpart.ensure(std::max(cpart_capacity(S, std::max(S->nocc_pad, 64), ns, (int)K),
+                                   cpart_capacity(S, S->natoms_pad, ns, (int)K))));
   CHECKED(S->cmat.ensure((size_t)ns * mp * sizeof(Z64)));
   for (DBuf* d : {&S->sv_eps, &S->sv_invT, &S->sv_bb, &S->sv_rz, &S->sv_rr, &S->sv_tres})
     CHECKED(d->ensure((size_t)ns * sizeof(double)));
@@ -499,7 +506,7 @@ void net_forward(const stern_model* M, const __bf16* a0, __bf16* a1, __bf16* a2,
 
 // x = P_c (net output mapped to the sphere) for all ns rows; then r = b - A x in FP64,
 // dropping guesses whose residual is non-finite or not below ||b||.
-int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, int& n_rej) {
+int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, int& n_rej, bool fp32_resid) {
   hipStream_t st = S->stream;
   const FftGeom gc = S->geom_c();
   const int Nc = gc.N, K = S->hb.npw_pad;
@@ -539,9 +546,18 @@ int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, in
     cs.kprec = S->kprec.as<float>();
   }
   CHECKED(apply_pc_rows(S, cs.x, nullptr, ns));
-  CHECKED(apply_h_rows(S, cs.x, cs.q, nullptr, ns, cs.eps));
-  CHECKED(apply_pc_rows(S, cs.q, nullptr, ns));
-  launch_guess_resid(cs, nullptr, ns, S->g_rej.as<int>(), st);
+  if (fp32_resid) {  // residual of the guess with the FP32 operator (it seeds a defect-correction step)
+    Z32* x32 = S->m_p.as<Z32>();
+    Z32* q32 = S->m_q.as<Z32>();
+    launch_to32(cs.x, x32, (size_t)ns * K, st);
+    CHECKED(apply_h32_rows(S, x32, q32, nullptr, ns, cs.eps));
+    CHECKED(apply_pc32_rows(S, q32, nullptr, ns));
+    launch_guess_resid(cs, nullptr, ns, q32, S->g_rej.as<int>(), st);
+  } else {
+    CHECKED(apply_h_rows(S, cs.x, cs.q, nullptr, ns, cs.eps));
+    CHECKED(apply_pc_rows(S, cs.q, nullptr, ns));
+    launch_guess_resid(cs, nullptr, ns, nullptr, S->g_rej.as<int>(), st);
+  }
   CHECKED(launch_check());
   std::vector<int> rej(ns);
   HIPOK(hipMemcpyAsync(rej.data(), S->g_rej.p, ns * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -689,9 +705,18 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
 //           (FP64 dots and scalars); x += d; x = P_c x (FP64); r = b - A x (FP64)
 //   until ||r|| <= tol ||b||; solves still above tol after max_outer steps are
 //   re-solved by FP64 PCG from zero.
+// The inner operator is either (default) the projected one, P_c (H - eps) P_c
+// with a projection of q and of z in every iteration, or the DFPT form
+// H - eps + alpha P_v (Baroni et al., Rev. Mod. Phys. 73, 515 (2001)), which is
+// positive definite for alpha above the occupied band width and needs one
+// Psi GEMM pair per iteration. On range(P_c) the two agree up to the
+// commutator of H with P_v, which the ground state makes small; the FP64
+// outer residual uses the projected operator, so the accepted solution is the
+// projected system's either way. With Teter's K, which does not commute with
+// P_v, the shifted form takes about twice the inner iterations.
 int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, double inner_tol,
               int max_outer, int max_iter, int check_every, int& n_restart, int& n_fallback, double vecb,
-              bool use_graph) {
+              bool use_graph, bool projected) {
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   const int K = S->hb.npw_pad;
@@ -709,7 +734,7 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
     HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
     const int* L = S->list_act.as<int>();
     CHECKED(timed(S, STERN_K_CG32, na * (vecb + 3.0 * vec32), 0.0, [&] { launch_cg32_init(c32, cs.r, L, na, st); }));
-    CHECKED(apply_pc32_rows(S, c32.z, L, na));
+    if (projected) CHECKED(apply_pc32_rows(S, c32.z, L, na));
     CHECKED(timed(S, STERN_K_CG32, na * 3.0 * vec32, 0.0, [&] { launch_cg32_init2(c32, L, na, st); }));
     CHECKED(launch_check());
     HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -725,10 +750,13 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       const int nsteps = std::min(check_every, max_inner - it);
       CHECKED(run_steps(S, nsteps, use_graph && (it > 0 || outer > 0), [&]() -> int {
         CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
-        CHECKED(apply_pc32_rows(S, c32.q, F, ni));
+        if (projected)
+          CHECKED(apply_pc32_rows(S, c32.q, F, ni));
+        else
+          CHECKED(apply_psi32_rows(S, c32.p, c32.q, F, ni, (float)S->alpha_pv));
         CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 7.0, 0.0,
                       [&] { launch_cg32_alpha(c32, F, ni, inner_tol * inner_tol, st); }));
-        CHECKED(apply_pc32_rows(S, c32.z, F, ni));
+        if (projected) CHECKED(apply_pc32_rows(S, c32.z, F, ni));
         CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 4.0, 0.0, [&] { launch_cg32_beta(c32, F, ni, st); }));
         return 0;
       }));
@@ -767,6 +795,32 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
 }  // namespace
 
 // ============================================================== C ABI ======
+
+namespace {
+
+// mean time (ms) of `reps` calls of fn on the system stream, after one warm-up call
+template <class F>
+int time_ms(stern_system* S, int reps, double& ms, F&& fn) {
+  hipEvent_t e0, e1;
+  HIPOK(hipEventCreate(&e0));
+  HIPOK(hipEventCreate(&e1));
+  int rc = fn();
+  if (rc >= 0) rc = launch_check();
+  (void)hipEventRecord(e0, S->stream);
+  for (int r = 0; r < reps && rc >= 0; ++r) rc = fn();
+  (void)hipEventRecord(e1, S->stream);
+  const hipError_t e = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (rc >= 0 && e == hipSuccess) (void)hipEventElapsedTime(&t, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc < 0) return rc;
+  if (e != hipSuccess) return fail(STERN_ERR_HIP, "autotune timing: %s", hipGetErrorString(e));
+  ms = t / reps;
+  return 0;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -946,6 +1000,10 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   }
   // kinetic energy per band, T_v = sum_G |G|^2/2 |c|^2, floored at (2 pi / L)^2 / 2
   S->eps = h_eps;
+  {  // alpha of the shifted inner operator: twice the occupied band width, at least 0.01 Ha
+    const auto mm = std::minmax_element(h_eps.begin(), h_eps.end());
+    S->alpha_pv = std::max(0.01, 2.0 * (*mm.second - *mm.first));
+  }
   S->invT.assign(n_occ, 0.0);
   const double floor_t = 0.5 * hb.b * hb.b;
   for (int v = 0; v < n_occ; ++v) {
@@ -1153,12 +1211,12 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     const int ns = (i1 - i0) * nb;
     CHECKED(setup_batch(S, i0, i1, v0, nb, dv_dev, vecb));
     const bool guess = opts->guess == STERN_GUESS_LEARNED;
-    if (guess) CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected));
+    if (guess) CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected, opts->precision == STERN_MIXED));
     std::vector<int> all(ns);
     for (int s = 0; s < ns; ++s) all[s] = s;
     if (opts->precision == STERN_MIXED) {
       CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
-                        use_graph));
+                        use_graph, opts->inner_shifted == 0));
     } else {
       CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph, guess));
       if (guess) {  // solves the learned start did not bring below tol: Teter-PCG from zero
@@ -1326,6 +1384,128 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
     *stats = a;
   }
   return out;
+}
+
+// ------------------------------------------------------------- autotuner ----
+
+int stern_tunable(stern_system* S, int which, int value) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  int* slot = nullptr;
+  switch (which) {
+    case STERN_TUNE_PLANE64: slot = &S->plane_var64; break;
+    case STERN_TUNE_PLANE32: slot = &S->plane_var32; break;
+    case STERN_TUNE_GEMM64_WG: slot = &S->gemm64_wg; break;
+    case STERN_TUNE_GEMM16_WG: slot = &S->gemm16_wg; break;
+    default: return fail(STERN_ERR_INVALID_ARG, "unknown tunable %d", which);
+  }
+  if (value >= 0) {
+    if (which == STERN_TUNE_PLANE64 || which == STERN_TUNE_PLANE32) {
+      if (value > 1) return fail(STERN_ERR_INVALID_ARG, "plane kernel variant must be 0 or 1");
+      if (value == 1 && plane_hw_lds(S->hb.N, S->hb.nza, which == STERN_TUNE_PLANE64) > S->lds_max)
+        return fail(STERN_ERR_INVALID_ARG, "the compact plane kernel does not fit in LDS for grid %d", S->hb.N);
+    } else if (value > 65536) {
+      return fail(STERN_ERR_INVALID_ARG, "workgroup target %d out of range", value);
+    }
+    *slot = value;
+  }
+  return *slot;
+}
+
+int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chosen) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
+  if (n_vec <= 0 || n_vec > 65536) return fail(STERN_ERR_INVALID_ARG, "n_vec must be in [1, 65536]");
+  Scope sc(S->device);
+  hipStream_t st = S->stream;
+  S->prof_on = false;
+  S->recs.clear();
+  S->ev_used = 0;
+  hipDeviceProp_t prop;
+  HIPOK(hipGetDeviceProperties(&prop, S->device));
+  char key[512];
+  std::snprintf(key, sizeof key, "%s N=%d nza=%d npw=%d nocc_pad=%d natoms_pad=%d nvec=%d", prop.gcnArchName,
+                S->hb.N, S->hb.nza, S->hb.npw, S->nocc_pad, S->natoms_pad, n_vec);
+  int* slots[STERN_NTUNE] = {&S->plane_var64, &S->plane_var32, &S->gemm64_wg, &S->gemm16_wg};
+  // cached choices
+  if (cache_path) {
+    std::FILE* f = std::fopen(cache_path, "r");
+    int found[STERN_NTUNE] = {-1, -1, -1, -1};
+    if (f) {
+      char line[768];
+      const size_t kl = std::strlen(key);
+      while (std::fgets(line, sizeof line, f)) {
+        if (std::strncmp(line, key, kl) != 0 || line[kl] != ' ') continue;
+        int w = -1, v = -1;
+        if (std::sscanf(line + kl, " tune=%d value=%d", &w, &v) == 2 && w >= 0 && w < STERN_NTUNE) found[w] = v;
+      }
+      std::fclose(f);
+    }
+    bool all = true;
+    for (int w = 0; w < STERN_NTUNE; ++w) all = all && found[w] >= 0;
+    if (all) {
+      for (int w = 0; w < STERN_NTUNE; ++w) CHECKED(stern_tunable(S, w, found[w]));
+      if (chosen)
+        for (int w = 0; w < STERN_NTUNE; ++w) chosen[w] = *slots[w];
+      return 0;
+    }
+  }
+  // synthetic rows: seeded complex values on the sphere, zero padding; eps of bands 0, 1, ...
+  const int K = S->hb.npw_pad, npw = S->hb.npw;
+  CHECKED(ensure_workspace(S, n_vec));
+  CHECKED(ensure_workspace32(S, n_vec));
+  {
+    std::mt19937_64 rng(12345);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<Z64> h((size_t)n_vec * K, zmk(0.0, 0.0));
+    std::vector<double> e(n_vec);
+    for (int v = 0; v < n_vec; ++v) {
+      for (int k = 0; k < npw; ++k) h[(size_t)v * K + k] = zmk(nd(rng), nd(rng));
+      e[v] = S->eps[v % S->n_occ];
+    }
+    HIPOK(hipMemcpyAsync(S->wp.p, h.data(), h.size() * sizeof(Z64), hipMemcpyHostToDevice, st));
+    HIPOK(hipMemcpyAsync(S->sv_eps.p, e.data(), n_vec * sizeof(double), hipMemcpyHostToDevice, st));
+    launch_to32(S->wp.as<Z64>(), S->m_p.as<Z32>(), h.size(), st);
+    HIPOK(hipStreamSynchronize(st));  // h and e are released at the end of this block
+  }
+  const double* eps = S->sv_eps.as<double>();
+  const int reps = 3;
+  int n_timed = 0;
+  auto tune = [&](int which, const std::vector<int>& cand, auto&& fn) -> int {
+    double best = 1e300;
+    int bestv = *slots[which];
+    for (int v : cand) {
+      if (stern_tunable(S, which, v) < 0) continue;  // not runnable here
+      CHECKED(ensure_workspace(S, n_vec));             // split-K partials for this target
+      double ms = 0.0;
+      CHECKED(time_ms(S, reps, ms, fn));
+      ++n_timed;
+      if (ms < best) {
+        best = ms;
+        bestv = v;
+      }
+    }
+    CHECKED(stern_tunable(S, which, bestv));
+    return 0;
+  };
+  CHECKED(tune(STERN_TUNE_PLANE64, {0, 1},
+               [&] { return apply_h_rows(S, S->wp.as<Z64>(), S->wq.as<Z64>(), nullptr, n_vec, eps); }));
+  CHECKED(tune(STERN_TUNE_PLANE32, {0, 1},
+               [&] { return apply_h32_rows(S, S->m_p.as<Z32>(), S->m_q.as<Z32>(), nullptr, n_vec, eps); }));
+  CHECKED(tune(STERN_TUNE_GEMM64_WG, {256, 512, 1024, 2048, 4096},
+               [&] { return apply_pc_rows(S, S->wq.as<Z64>(), nullptr, n_vec); }));
+  CHECKED(tune(STERN_TUNE_GEMM16_WG, {128, 256, 512, 1024, 2048},
+               [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
+  CHECKED(ensure_workspace(S, n_vec));
+  if (chosen)
+    for (int w = 0; w < STERN_NTUNE; ++w) chosen[w] = *slots[w];
+  if (cache_path) {
+    std::FILE* f = std::fopen(cache_path, "a");
+    if (f) {
+      for (int w = 0; w < STERN_NTUNE; ++w) std::fprintf(f, "%s tune=%d value=%d\n", key, w, *slots[w]);
+      std::fclose(f);
+    }
+  }
+  return n_timed;
 }
 
 // ---------------------------------------------------------- learned model ----
@@ -1634,7 +1814,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
           }
         if (rows.empty()) continue;
         CHECKED(setup_batch(S, i0, i1, 0, nb, dv_dev, vecb));
-        CHECKED(learned_guess(S, M, cs, ns, n_rej));  // x0, r0 and features; K is still Teter here
+        CHECKED(learned_guess(S, M, cs, ns, n_rej, false));  // x0, r0 and features; K is still Teter here
         const int nr = (int)rows.size();
         CHECKED(M->idx.ensure((size_t)nr * sizeof(int)));
         HIPOK(hipMemcpyAsync(M->idx.p, rows.data(), nr * sizeof(int), hipMemcpyHostToDevice, st2));

@@ -25,8 +25,15 @@ STERN_MEM_DEVICE = 1
 
 EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
             "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
-            "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_apply_h",
-            "stern_apply_pc", "stern_free", "stern_last_error"]
+            "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_tunable",
+            "stern_autotune", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
+
+TUNE_PLANE64 = 0
+TUNE_PLANE32 = 1
+TUNE_GEMM64_WG = 2
+TUNE_GEMM16_WG = 3
+NTUNE = 4
+TUNE_NAMES = ["plane64", "plane32", "gemm64_wg", "gemm16_wg"]
 
 
 class SternError(RuntimeError):
@@ -50,7 +57,8 @@ class Opts(C.Structure):
                 ("mem_kind", C.c_int), ("band_begin", C.c_int), ("band_end", C.c_int), ("max_batch", C.c_int),
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
                 ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
-                ("max_outer", C.c_int), ("use_graph", C.c_int), ("model", C.c_void_p)]
+                ("max_outer", C.c_int), ("use_graph", C.c_int), ("model", C.c_void_p),
+                ("inner_shifted", C.c_int)]
 
 
 NKERNEL = 17
@@ -104,6 +112,8 @@ def lib():
         L.stern_model_set_weights.argtypes = [C.c_void_p, P(C.c_float), C.c_int]
         L.stern_model_free.argtypes = [C.c_void_p]
         L.stern_model_free.restype = None
+        L.stern_tunable.argtypes = [C.c_void_p, C.c_int, C.c_int]
+        L.stern_autotune.argtypes = [C.c_void_p, C.c_int, C.c_char_p, P(C.c_int)]
         L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_free.argtypes = [C.c_void_p]
@@ -112,7 +122,7 @@ def lib():
         for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied",
                      "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc",
                      "stern_model_create", "stern_model_train", "stern_model_num_params", "stern_model_get_weights",
-                     "stern_model_set_weights"):
+                     "stern_model_set_weights", "stern_tunable", "stern_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -162,13 +172,14 @@ def _torch_stream():
 
 
 def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
-              inner_tol=0.0, max_outer=0, use_graph=False, model=None):
+              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False):
     o = Opts()
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
     o.guess = STERN_GUESS_ZERO if model is None else STERN_GUESS_LEARNED
     o.model = None if model is None else model._h
+    o.inner_shifted = 1 if inner_shifted else 0
     o.mem_kind = mem_kind
     o.band_begin, o.band_end = (0, 0) if band_range is None else (int(band_range[0]), int(band_range[1]))
     o.max_batch = int(max_batch)
@@ -187,7 +198,7 @@ def _kernels(st):
 
 
 def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, max_iter=0, check_every=0,
-                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None):
+                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False):
     """Batched apply over independent systems (stern_apply_chi0_many); returns (list of dn, info)."""
     n = len(systems)
     ptrs = [_ptr(d, False) for d in dvs]
@@ -205,7 +216,8 @@ def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, 
     npert = (C.c_int * n)(*[d.shape[0] for d in dvs])
     dvp = (C.c_void_p * n)(*[p[0] for p in ptrs])
     dnp = (C.c_void_p * n)(*[p[0] for p in outs])
-    o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph, model)
+    o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph, model,
+                  inner_shifted)
     st = Stats()
     rc = _check(lib().stern_apply_chi0_many(n, hs, npert, dvp, dnp, C.byref(o), C.byref(st)))
     info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
@@ -254,7 +266,7 @@ class System:
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
                    samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False,
-                   model=None):
+                   model=None, inner_shifted=False):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned.
@@ -271,7 +283,7 @@ class System:
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
         o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
-                      use_graph, model)
+                      use_graph, model, inner_shifted)
         keep = []
         sx = None
         if samples:
@@ -296,6 +308,18 @@ class System:
         if profile:
             info["kernels"] = _kernels(st)
         return dn_out, info
+
+    def tunable(self, which, value=-1):
+        """Query (value < 0) or set a kernel tunable (TUNE_*); returns its value."""
+        return _check(lib().stern_tunable(self._h, int(which), int(value)))
+
+    def autotune(self, n_vec=1024, cache_path=None):
+        """Time every candidate of every tunable on this system's shapes and keep the fastest.
+        Returns (number of candidates timed, {name: chosen value})."""
+        ch = (C.c_int * NTUNE)()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        n = _check(lib().stern_autotune(self._h, int(n_vec), path, ch))
+        return n, {TUNE_NAMES[k]: int(ch[k]) for k in range(NTUNE)}
 
     def apply_h(self, c, shift=None):
         c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.complex128)

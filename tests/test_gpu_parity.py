@@ -150,3 +150,15 @@ def test_mixed_fallback_path(tiny_gpu):
     assert info["n_fallback"] > 0
     assert info["n_converged"] == 32
     assert rel_l2(dn, t["ref"]["dn"][:2]).max() < 1e-6
+
+
+def test_mixed_shifted_inner_operator(tiny_gpu):
+    """The shifted inner operator H - eps + alpha P_v gives accepted solutions as the default
+    projected one does: both within the mixed bound of the oracle."""
+    from paper_2607_14025_amd import STERN_MIXED
+    t = tiny_gpu
+    a, ia = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED, inner_shifted=True)
+    b, ib = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED)
+    for dn, info in ((a, ia), (b, ib)):
+        assert info["n_converged"] == 128 and info["max_true_resid"] <= 1e-10
+        assert rel_l2(dn, t["ref"]["dn"]).max() < 1e-6
