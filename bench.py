@@ -128,9 +128,9 @@ def main():
         torch.cuda.synchronize()
         print(f"bench: training done: {train}", file=sys.stderr, flush=True)
 
-    def run(precision, steps, warmup, label, mdl=None):
+    def run(precision, steps, warmup, label, mdl=None, prec_only=False):
         for w in range(warmup):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl)
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl, prec_only=prec_only)
             print(f"bench: {label} warmup {w}: {info['n_converged']}/{info['n_solves']} converged in "
                   f"{info['wall_s']:.2f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -140,7 +140,8 @@ def main():
         fallback = 0
         t0 = time.perf_counter()
         for k in range(steps):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, precision=precision, model=mdl)
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, precision=precision, model=mdl,
+                                   prec_only=prec_only)
             conv += info["n_converged"]
             fallback += info["n_fallback"]
             iters.append(info["total_iters"] / max(1, info["n_solves"]))
@@ -155,7 +156,7 @@ def main():
         dt = time.perf_counter() - t0
         r = dict(value=conv / dt, dt=dt, kern=kern, iters=float(np.mean(iters)), fallback=fallback)
         if label != "fp64":  # dn against the plain FP64 path at the same tolerance
-            s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl)
+            s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl, prec_only=prec_only)
             torch.cuda.synchronize()
             r["dn_rel_err_vs_fp64"] = ((dn - ref).reshape(n_pert, -1).norm(dim=1)
                                        / ref.reshape(n_pert, -1).norm(dim=1)).max().item()
@@ -166,14 +167,15 @@ def main():
     torch.cuda.synchronize()
     plain = run(STERN_FP64, args.steps, args.warmup, "fp64")
     head = plain
-    mixed = learned = learned_fp64 = None
+    mixed = learned = learned_fp64 = learned_k = None
     if args.path in ("mixed", "learned-mixed"):
         mixed = run(STERN_MIXED, args.steps, args.warmup, "mixed")
         head = mixed
     if args.path == "learned-mixed":
         learned_fp64 = run(STERN_FP64, args.steps, args.warmup, "learned-fp64", model)
         learned = run(STERN_MIXED, args.steps, args.warmup, "learned-mixed", model)
-        head = learned
+        learned_k = run(STERN_MIXED, args.steps, args.warmup, "learnedK-mixed", model, prec_only=True)
+        head = learned_k if learned_k["value"] > learned["value"] else learned
     value = head["value"]
     dt = head["dt"]
     kern = head["kern"]
@@ -214,16 +216,21 @@ def main():
                    speedup_vs_plain_fp64=mixed["value"] / plain["value"])
         dtype = "f32+bf16/f64"
     if learned is not None:
-        cfg.update(path="learned guess + learned diagonal preconditioner (BF16 MFMA conv net on the coarse grid), "
-                        "FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction; Teter FP64 PCG fallback",
+        which = ("learned diagonal preconditioner (x0 = 0)" if head is learned_k else
+                 "learned guess + learned diagonal preconditioner")
+        cfg.update(path=which + " from the BF16 MFMA conv net on the coarse grid, FP32 FFT + split-BF16 MFMA GEMMs "
+                            "in FP64 defect correction; Teter FP64 PCG fallback",
                    learned_fp64=dict(solves_per_s=learned_fp64["value"], mean_cg_iters=learned_fp64["iters"],
                                      fallback_solves=learned_fp64["fallback"],
                                      dn_rel_err_vs_fp64=learned_fp64["dn_rel_err_vs_fp64"]),
                    learned_mixed=dict(solves_per_s=learned["value"], mean_inner_iters=learned["iters"],
                                       fallback_solves=learned["fallback"],
                                       dn_rel_err_vs_fp64=learned["dn_rel_err_vs_fp64"]),
+                   learned_k_mixed=dict(solves_per_s=learned_k["value"], mean_inner_iters=learned_k["iters"],
+                                        fallback_solves=learned_k["fallback"],
+                                        dn_rel_err_vs_fp64=learned_k["dn_rel_err_vs_fp64"]),
                    training=dict(cells="two other seeded mid cells (same L, Ecut, atom count)", **train),
-                   speedup_vs_plain_fp64=learned["value"] / plain["value"])
+                   speedup_vs_plain_fp64=head["value"] / plain["value"])
     if mixed is None:
         cfg.update(path="plain FP64 projected Teter-PCG")
         dtype = "f64"

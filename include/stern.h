@@ -57,7 +57,8 @@ extern "C" {
 
 /* initial guess: zero, or the learned guess of a trained stern_model */
 #define STERN_GUESS_ZERO 0
-#define STERN_GUESS_LEARNED 1
+#define STERN_GUESS_LEARNED 1    /* learned x0 and learned diagonal preconditioner */
+#define STERN_GUESS_LEARNED_K 2  /* learned diagonal preconditioner only, x0 = 0 */
 
 /* where pointer arguments live */
 #define STERN_MEM_HOST 0
@@ -90,7 +91,7 @@ typedef struct {
   double tol;          /* relative FP64 true residual ||b - A x|| / ||b|| to accept */
   int max_iter;        /* CG iterations per solve (0 = 1000) */
   int precision;       /* STERN_FP64 or STERN_MIXED */
-  int guess;           /* STERN_GUESS_ZERO or STERN_GUESS_LEARNED (needs model) */
+  int guess;           /* STERN_GUESS_ZERO, _LEARNED or _LEARNED_K (the last two need model) */
   int mem_kind;        /* STERN_MEM_HOST or STERN_MEM_DEVICE for dv_r / dn_r */
   int band_begin;      /* solve bands [band_begin, band_end); band_end <= 0 means n_occ.
                           P_c always uses every occupied band; dn is the partial sum. */
@@ -115,7 +116,7 @@ typedef struct {
      every active-set compaction and replay it check_every times (ignored when
      profile != 0) */
   int use_graph;
-  /* trained stern_model for STERN_GUESS_LEARNED (not owned) */
+  /* trained stern_model for STERN_GUESS_LEARNED / _LEARNED_K (not owned) */
   const struct stern_model* model;
   /* STERN_MIXED only: operator of the inner solve. 0: P_c (H - eps_v) P_c
      (two Psi GEMM pairs per iteration); nonzero: H - eps_v + alpha P_v
@@ -206,10 +207,14 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
  * wave-function sphere exactly. Input channels per (v, i): psi_v(r), the
  * right-hand side b_{v,i}(r) / ||b|| (the sphere part of -P_c dV_i psi_v) and
  * eps_v; output: x0(r) / ||b||, mapped back to the sphere and projected by
- * P_c. A linear head on the grid-averaged second hidden layer (plus eps_v and
- * T_v) gives 8 knot values z_k on u = log2(|G|^2 / 2 T_v) in [-6, 8]; the
- * solve's diagonal preconditioner is K(G) = Teter(G) softplus(z(u)) / ln 2,
- * positive, equal to Teter when the head is zero.
+ * P_c. A linear head on the grid-averaged second hidden layer of the same net
+ * evaluated on (psi_v, 0, eps_v) (one evaluation per band, shared by every
+ * field), plus eps_v and T_v, gives 8 knot values z_k on u = log2(|G|^2 / 2 T_v)
+ * in [-6, 8]; band v's diagonal preconditioner is
+ * K(G) = Teter(G) softplus(z(u)) / ln 2, positive, equal to Teter when the head
+ * is zero. STERN_GUESS_LEARNED uses x0 and K, STERN_GUESS_LEARNED_K only K
+ * (x0 = 0): a defect-correction inner solve runs to a tolerance relative to its
+ * own right-hand side, so there a guess saves little and K carries the gain.
  * The net is fitted to the solutions the plain FP64 path produces (relative L2
  * of x0); then the head to the error left after the guess, minimising
  * ||P_c (K o r0) - e0||^2 / ||e0||^2 with r0 = b - A x0 and e0 = x* - x0.

@@ -134,6 +134,7 @@ void launch_adam(float* w, float* m, float* v, const float* g, int n, float lr, 
                  hipStream_t st);
 void launch_pack_input(const Z64* psi_c, const Z64* b_c, const int* band, const double* eps, const double* bnorm2,
                        __bf16* out, int Nc, int nsolve, hipStream_t st);
+void launch_pack_band(const Z64* psi_c, const double* eps, __bf16* out, int Nc, int nband, hipStream_t st);
 void launch_pack_target(const Z64* x_c, const double* bnorm2, float* tgt, int Nc, int nsolve, hipStream_t st);
 void launch_unpack_output(const float* out, const double* bnorm2, Z64* x_c, int Nc, int nsolve, hipStream_t st);
 // yz planes, forward: full complex planes in[vec][ix][iy][iz] -> pencils (for the coarse grid)

@@ -253,6 +253,24 @@ __global__ void k_pack_input(const Z64* __restrict__ psi_c, const Z64* __restric
   for (int c = 0; c < C; ++c) o[c] = (__bf16)v[c];
 }
 
+// Band input of the preconditioner features: channels (Re psi_v, Im psi_v, 0, 0, eps_v, 0 ...)
+__global__ void k_pack_band(const Z64* __restrict__ psi_c, const double* __restrict__ eps,
+                            __bf16* __restrict__ out, int npts, int ldp) {
+  const int v = blockIdx.y;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npts) return;
+  const Z64 ps = psi_c[(size_t)v * npts + p];
+  __bf16* o = out + ((size_t)v * ldp + p) * C;
+  float w[C];
+#pragma unroll
+  for (int c = 0; c < C; ++c) w[c] = 0.f;
+  w[0] = (float)ps.re;
+  w[1] = (float)ps.im;
+  w[4] = (float)eps[v];
+#pragma unroll
+  for (int c = 0; c < C; ++c) o[c] = (__bf16)w[c];
+}
+
 // training target of solve s: x~(r) / |b| on the coarse grid, [s][P][2] float
 __global__ void k_pack_target(const Z64* __restrict__ x_c, const double* __restrict__ bnorm2,
                               float* __restrict__ tgt, int npts, int ldp) {
@@ -503,6 +521,10 @@ void launch_pack_input(const Z64* psi_c, const Z64* b_c, const int* band, const 
   if (nsolve > 0)
     k_pack_input<<<dim3((npts + 255) / 256, nsolve), 256, 0, st>>>(psi_c, b_c, band, eps, bnorm2, out, npts,
                                                                    net_ldp(Nc));
+}
+void launch_pack_band(const Z64* psi_c, const double* eps, __bf16* out, int Nc, int nband, hipStream_t st) {
+  const int npts = Nc * Nc * Nc;
+  if (nband > 0) k_pack_band<<<dim3((npts + 255) / 256, nband), 256, 0, st>>>(psi_c, eps, out, npts, net_ldp(Nc));
 }
 void launch_pack_target(const Z64* x_c, const double* bnorm2, float* tgt, int Nc, int nsolve, hipStream_t st) {
   const int npts = Nc * Nc * Nc;

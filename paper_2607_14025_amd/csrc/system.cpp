@@ -115,7 +115,7 @@ struct stern_system {
   bool have_coarse = false;
   HostBasis hbc;
   DBuf c_col_start, c_col_len, c_col_xmin, c_col_pos, c_zl, c_ycol, c_tw64, psi_c, c_pen, c_field, net_a0, net_a1,
-      net_a2, net_out, g_rej, net_feat, net_coef, kprec;
+      net_a2, net_out, g_rej, net_feat, net_coef, kprec, band_eps, band_invT, band_feat;
   int ws_solves = 0, ws32_solves = 0;
 
   // per-launch event profile (opts->profile)
@@ -184,7 +184,8 @@ struct stern_system {
                    &kbT_hi,    &kbT_lo,   &m_d,     &m_r,      &m_p,     &m_q,      &m_z,      &m_rz,
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
-                   &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32};
+                   &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
+                   &band_feat};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -497,6 +498,12 @@ int net_input(stern_system* S, const CgState& cs, int s0, int c, __bf16* a0) {
   return 0;
 }
 
+// the two hidden layers only (their output feeds the preconditioner features)
+void net_trunk(const stern_model* M, const __bf16* a0, __bf16* a1, __bf16* a2, int Nc, int c, hipStream_t st) {
+  launch_conv3(a0, M->wb(0), M->bias(0), a1, Nc, c, 1, false, st);
+  launch_conv3(a1, M->wb(1), M->bias(1), a2, Nc, c, 1, false, st);
+}
+
 void net_forward(const stern_model* M, const __bf16* a0, __bf16* a1, __bf16* a2, float* out, int Nc, int c,
                  hipStream_t st) {
   launch_conv3(a0, M->wb(0), M->bias(0), a1, Nc, c, 1, false, st);
@@ -506,12 +513,19 @@ void net_forward(const stern_model* M, const __bf16* a0, __bf16* a1, __bf16* a2,
 
 // x = P_c (net output mapped to the sphere) for all ns rows; then r = b - A x in FP64,
 // dropping guesses whose residual is non-finite or not below ||b||.
-int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, int& n_rej, bool fp32_resid) {
+// Learned start of the ns solves of the batch. The preconditioner features
+// come from the net's hidden layers evaluated per band on (psi_v, 0, eps_v)
+// (n_occ evaluations, shared by all fields); with_x0 also predicts x0 per solve
+// (x = P_c (net output mapped to the sphere)) and forms r = b - A x in FP64 or,
+// for a defect-correction start, FP32, dropping guesses whose residual is
+// non-finite or not below ||b||. Without x0 the batch keeps x = 0, r = b.
+int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, int& n_rej, bool fp32_resid,
+                  bool with_x0, bool want_feat = false) {
   hipStream_t st = S->stream;
   const FftGeom gc = S->geom_c();
   const int Nc = gc.N, K = S->hb.npw_pad;
   const size_t ldp = (size_t)net_ldp(Nc), nc3 = (size_t)Nc * Nc * Nc;
-  const int chunk = std::min(ns, 1024);
+  const int chunk = std::min(std::max(with_x0 ? ns : 0, S->n_occ), 1024);
   CHECKED(S->c_pen.ensure((size_t)chunk * Nc * gc.ncol_pad * sizeof(Z64)));
   CHECKED(S->c_field.ensure((size_t)chunk * nc3 * sizeof(Z64)));
   for (DBuf* d : {&S->net_a0, &S->net_a1, &S->net_a2})
@@ -519,15 +533,28 @@ int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, in
   CHECKED(S->net_out.ensure((size_t)chunk * ldp * kNetChannels * sizeof(float)));
   CHECKED(S->g_rej.ensure((size_t)S->ws_solves * sizeof(int)));
   CHECKED(S->net_feat.ensure((size_t)S->ws_solves * kPrecIn * sizeof(float)));
+  CHECKED(S->band_feat.ensure((size_t)S->n_occ * kPrecIn * sizeof(float)));
+  const double flops2 = 2.0 * 2.0 * kNetChannels * 27 * kNetChannels * (double)nc3;
+  if (M->prec_trained || want_feat) {  // per-band features, then per solve by its band
+    for (int b0 = 0; b0 < S->n_occ; b0 += chunk) {
+      const int c = std::min(chunk, S->n_occ - b0);
+      CHECKED(timed(S, STERN_K_NET, c * (double)(nc3 * 16 + ldp * 16 * 10), c * flops2, [&] {
+        launch_pack_band(S->psi_c.as<Z64>() + (size_t)b0 * nc3, S->band_eps.as<double>() + b0,
+                         S->net_a0.as<__bf16>(), Nc, c, st);
+        net_trunk(M, S->net_a0.as<__bf16>(), S->net_a1.as<__bf16>(), S->net_a2.as<__bf16>(), Nc, c, st);
+        launch_pool(S->net_a2.as<__bf16>(), S->band_eps.as<double>() + b0, S->band_invT.as<double>() + b0,
+                    S->band_feat.as<float>() + (size_t)b0 * kPrecIn, Nc, c, st);
+      }));
+    }
+    launch_gather_f32(S->net_feat.as<float>(), S->band_feat.as<float>(), S->sv_band.as<int>(), kPrecIn, ns, st);
+  }
   const double flops = 3.0 * 2.0 * kNetChannels * 27 * kNetChannels * (double)nc3;
-  for (int s0 = 0; s0 < ns; s0 += chunk) {
+  for (int s0 = 0; with_x0 && s0 < ns; s0 += chunk) {
     const int c = std::min(chunk, ns - s0);
     CHECKED(timed(S, STERN_K_NET, c * (double)(nc3 * 16 * 4 + ldp * 16 * 14), c * flops, [&] {
       (void)net_input(S, cs, s0, c, S->net_a0.as<__bf16>());
       net_forward(M, S->net_a0.as<__bf16>(), S->net_a1.as<__bf16>(), S->net_a2.as<__bf16>(),
                   S->net_out.as<float>(), Nc, c, st);
-      launch_pool(S->net_a2.as<__bf16>(), cs.eps + s0, cs.invT + s0, S->net_feat.as<float>() + (size_t)s0 * kPrecIn,
-                  Nc, c, st);
       launch_unpack_output(S->net_out.as<float>(), cs.bb + s0, S->c_field.as<Z64>(), Nc, c, st);
       launch_plane_full_fwd(gc, S->c_field.as<Z64>(), c, S->c_pen.as<Z64>(), st);
       launch_xfwd<double>(gc, S->c_pen.as<Z64>(), nullptr, c, cs.x + (size_t)s0 * K, 2, nullptr, nullptr,
@@ -545,6 +572,7 @@ int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, in
     }));
     cs.kprec = S->kprec.as<float>();
   }
+  if (!with_x0) return launch_check();
   CHECKED(apply_pc_rows(S, cs.x, nullptr, ns));
   if (fp32_resid) {  // residual of the guess with the FP32 operator (it seeds a defect-correction step)
     Z32* x32 = S->m_p.as<Z32>();
@@ -1016,6 +1044,8 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   }
   S->n_occ = n_occ;
   S->nocc_pad = std::max(64, (n_occ + 63) / 64 * 64);
+  CHECKED(upload(S->band_eps, S->eps.data(), n_occ * sizeof(double), st));
+  CHECKED(upload(S->band_invT, S->invT.data(), n_occ * sizeof(double), st));
   CHECKED(S->psi.ensure((size_t)S->nocc_pad * K * sizeof(Z64)));
   launch_fill_zero(S->psi.as<Z64>(), (size_t)S->nocc_pad * K, st);
   CHECKED(S->tmp_in.ensure((size_t)n_occ * npw * sizeof(Z64)));
@@ -1130,10 +1160,10 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->precision != STERN_FP64 && opts->precision != STERN_MIXED)
     return fail(STERN_ERR_INVALID_ARG, "precision must be STERN_FP64 or STERN_MIXED");
   if (opts->inner_tol < 0 || opts->max_outer < 0) return fail(STERN_ERR_INVALID_ARG, "bad inner_tol / max_outer");
-  if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED)
-    return fail(STERN_ERR_INVALID_ARG, "guess must be STERN_GUESS_ZERO or STERN_GUESS_LEARNED");
-  if (opts->guess == STERN_GUESS_LEARNED) {
-    if (!opts->model) return fail(STERN_ERR_INVALID_ARG, "STERN_GUESS_LEARNED needs a model");
+  if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED && opts->guess != STERN_GUESS_LEARNED_K)
+    return fail(STERN_ERR_INVALID_ARG, "guess must be STERN_GUESS_ZERO, STERN_GUESS_LEARNED or STERN_GUESS_LEARNED_K");
+  if (opts->guess != STERN_GUESS_ZERO) {
+    if (!opts->model) return fail(STERN_ERR_INVALID_ARG, "a learned start needs a model");
     if (!S->have_coarse) return fail(STERN_ERR_UNSUPPORTED, "grid %d has no coarse grid for the learned guess", S->hb.N);
     if (opts->model->device != S->device) return fail(STERN_ERR_INVALID_ARG, "model and system on different devices");
   }
@@ -1210,15 +1240,17 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     const int i1 = std::min(n_pert, i0 + per);
     const int ns = (i1 - i0) * nb;
     CHECKED(setup_batch(S, i0, i1, v0, nb, dv_dev, vecb));
-    const bool guess = opts->guess == STERN_GUESS_LEARNED;
-    if (guess) CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected, opts->precision == STERN_MIXED));
+    const bool guess = opts->guess != STERN_GUESS_ZERO;
+    const bool with_x0 = opts->guess == STERN_GUESS_LEARNED;
+    if (guess)
+      CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected, opts->precision == STERN_MIXED, with_x0));
     std::vector<int> all(ns);
     for (int s = 0; s < ns; ++s) all[s] = s;
     if (opts->precision == STERN_MIXED) {
       CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
                         use_graph, opts->inner_shifted == 0));
     } else {
-      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph, guess));
+      CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph, with_x0));
       if (guess) {  // solves the learned start did not bring below tol: Teter-PCG from zero
         HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPOK(hipStreamSynchronize(st));
@@ -1814,7 +1846,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
           }
         if (rows.empty()) continue;
         CHECKED(setup_batch(S, i0, i1, 0, nb, dv_dev, vecb));
-        CHECKED(learned_guess(S, M, cs, ns, n_rej, false));  // x0, r0 and features; K is still Teter here
+        CHECKED(learned_guess(S, M, cs, ns, n_rej, false, true, true));  // x0, r0, features; K still Teter
         const int nr = (int)rows.size();
         CHECKED(M->idx.ensure((size_t)nr * sizeof(int)));
         HIPOK(hipMemcpyAsync(M->idx.p, rows.data(), nr * sizeof(int), hipMemcpyHostToDevice, st2));

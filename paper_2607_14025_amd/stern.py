@@ -20,6 +20,7 @@ STERN_FP64 = 0
 STERN_MIXED = 1
 STERN_GUESS_ZERO = 0
 STERN_GUESS_LEARNED = 1
+STERN_GUESS_LEARNED_K = 2
 STERN_MEM_HOST = 0
 STERN_MEM_DEVICE = 1
 
@@ -172,12 +173,12 @@ def _torch_stream():
 
 
 def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
-              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False):
+              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False, prec_only=False):
     o = Opts()
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
-    o.guess = STERN_GUESS_ZERO if model is None else STERN_GUESS_LEARNED
+    o.guess = STERN_GUESS_ZERO if model is None else (STERN_GUESS_LEARNED_K if prec_only else STERN_GUESS_LEARNED)
     o.model = None if model is None else model._h
     o.inner_shifted = 1 if inner_shifted else 0
     o.mem_kind = mem_kind
@@ -198,7 +199,8 @@ def _kernels(st):
 
 
 def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, max_iter=0, check_every=0,
-                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False):
+                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False,
+                    prec_only=False):
     """Batched apply over independent systems (stern_apply_chi0_many); returns (list of dn, info)."""
     n = len(systems)
     ptrs = [_ptr(d, False) for d in dvs]
@@ -217,7 +219,7 @@ def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, 
     dvp = (C.c_void_p * n)(*[p[0] for p in ptrs])
     dnp = (C.c_void_p * n)(*[p[0] for p in outs])
     o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph, model,
-                  inner_shifted)
+                  inner_shifted, prec_only)
     st = Stats()
     rc = _check(lib().stern_apply_chi0_many(n, hs, npert, dvp, dnp, C.byref(o), C.byref(st)))
     info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
@@ -266,11 +268,12 @@ class System:
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
                    samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False,
-                   model=None, inner_shifted=False):
+                   model=None, inner_shifted=False, prec_only=False):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned.
-        model: a trained Model for the learned guess and preconditioner (None: zero guess, Teter)."""
+        model: a trained Model for the learned guess and preconditioner (None: zero guess, Teter);
+        prec_only: with a model, use only its preconditioner (x0 = 0)."""
         n_pert = dv_r.shape[0]
         dp, mk, k1 = _ptr(dv_r, False)
         if dn_out is None:
@@ -283,7 +286,7 @@ class System:
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
         o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
-                      use_graph, model, inner_shifted)
+                      use_graph, model, inner_shifted, prec_only)
         keep = []
         sx = None
         if samples:

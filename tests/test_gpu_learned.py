@@ -149,3 +149,16 @@ def test_model_needs_a_coarse_grid(learned):
         s.apply_chi0(np.zeros((1, 27, 27, 27)), model=learned["model"])
     s.close()
     assert e.value.code == -6
+
+
+def test_learned_preconditioner_only(learned):
+    """STERN_GUESS_LEARNED_K: x0 = 0 and the learned K; nothing is rejected and the
+    accepted solutions meet the oracle in FP64 and in mixed precision."""
+    from paper_2607_14025_amd import STERN_MIXED
+    dn, info = learned["sys"].apply_chi0(learned["dv"], tol=1e-10, model=learned["model"], prec_only=True)
+    assert info["n_converged"] == 128 and info["n_guess_rejected"] == 0
+    assert info["max_true_resid"] <= 1e-10
+    assert rel_l2(dn, learned["ref"]["dn"]).max() < 1e-9
+    dm, info = learned["sys"].apply_chi0(learned["dv"], tol=1e-10, model=learned["model"], prec_only=True,
+                                         precision=STERN_MIXED)
+    assert info["n_converged"] == 128 and rel_l2(dm, learned["ref"]["dn"]).max() < 1e-6
