@@ -28,10 +28,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_MFMA_PEAK_TFS = 78.6    # MI355X dense FP64 matrix
 BF16_MFMA_PEAK_TFS = 2500.0  # MI355X dense BF16 matrix
+FP32_VALU_PEAK_TFS = 157.3   # MI355X FP32 vector (256 CUs, 2.4 GHz; counts dual-issue/packed FP32)
+FP64_VALU_PEAK_TFS = 78.6    # MI355X FP64 vector
+# kernels whose work is vector-ALU arithmetic (FFT butterflies) rather than matrix-core products
+ALU_KERNELS = {"plane_h32": FP32_VALU_PEAK_TFS, "plane_h": FP64_VALU_PEAK_TFS}
+MFMA_KERNELS = {"gemm_bf16": BF16_MFMA_PEAK_TFS, "pc_reduce": FP64_MFMA_PEAK_TFS, "pc_expand": FP64_MFMA_PEAK_TFS,
+                "kb_reduce": FP64_MFMA_PEAK_TFS, "kb_expand": FP64_MFMA_PEAK_TFS, "net": BF16_MFMA_PEAK_TFS}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = {"plane_h": "fft.hip", "xinv": "fft.hip", "xfwd": "fft.hip", "rhs_plane": "fft.hip",
-                  "dn_plane": "fft.hip", "pc_reduce": "gemm.hip", "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip",
-                  "kb_expand": "gemm.hip", "sum_parts": "gemm.hip", "cg": "cg.hip"}
+KERNEL_SOURCES = {"plane_h": "fft.hip", "plane_h32": "fft.hip", "xinv": "fft.hip", "xfwd": "fft.hip",
+                  "x32": "fft.hip", "rhs_plane": "fft.hip", "dn_plane": "fft.hip", "pc_reduce": "gemm.hip",
+                  "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip", "kb_expand": "gemm.hip",
+                  "sum_parts": "gemm.hip", "cg": "cg.hip", "cg32": "cg.hip", "gemm_bf16": "gemm_bf16.hip",
+                  "net": "learn.hip"}
 
 
 def source_hash(kernel: str) -> str:
@@ -77,6 +85,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=["learned-mixed", "mixed", "fp64"], default="learned-mixed")
     ap.add_argument("--train-solves", type=int, default=8192)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (the chi0 apply of one cell runs on one MI355X); "
@@ -91,6 +101,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).normal_()
+        b = torch.empty_like(a)
+        torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        print("bench: copied 1 GiB device to device (counter reference)", file=sys.stderr, flush=True)
+        del a, b
     print("bench: loading mid cell inputs", file=sys.stderr, flush=True)
     wl = load_workload(MID)
     spec = wl["spec"]
@@ -184,11 +201,12 @@ def main():
     d = kern[dom]
     per_launch_s = d["ms"] / d["launches"] / 1e3
     traffic = measured_traffic(dom)
-    if d["flops"] > 0:
-        peak = BF16_MFMA_PEAK_TFS if dom == "gemm_bf16" else FP64_MFMA_PEAK_TFS
+    if dom in ALU_KERNELS or dom in MFMA_KERNELS:
+        peak = ALU_KERNELS.get(dom) or MFMA_KERNELS[dom]
         achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
-        roof = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                    traffic=traffic, kernel=dom)
+        roof = dict(bound="alu" if dom in ALU_KERNELS else "mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
+                    frac=achieved / peak, traffic=traffic, kernel=dom,
+                    hbm_GBps=d["bytes"] / d["launches"] / per_launch_s / 1e9)
     else:
         achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,

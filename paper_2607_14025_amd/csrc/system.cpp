@@ -261,6 +261,15 @@ int apply_pc_rows(stern_system* S, Z64* Y, const int* list, int n) {
   return 0;
 }
 
+// FFT flops of the yz pass of one vector's H apply, 5 L log2 L per length-L
+// transform: per plane the inverse and forward y transforms of the nza active z
+// lines and the inverse and forward z transforms of all N rows, plus the V
+// multiply (2 flops per complex point)
+double plane_flops(const stern_system* S) {
+  const double N = S->hb.N, nza = S->hb.nza;
+  return N * ((2.0 * nza + 2.0 * N) * 5.0 * N * std::log2(N) + 2.0 * N * N);
+}
+
 // out = (H - eps_s) in on rows list (without projection); eps per row index
 int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int n, const double* eps_rows) {
   if (n <= 0) return 0;
@@ -269,7 +278,7 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
   const double zb = sizeof(Z64), npw = S->hb.npw, N = S->hb.N, pen = N * S->hb.ncol * zb;
   CHECKED(timed(S, STERN_K_XINV, n * (npw * zb + pen), 0.0,
                 [&] { launch_xinv(g, in, list, n, S->pen.as<Z64>(), S->stream); }));
-  CHECKED(timed(S, STERN_K_PLANE_H, n * 2.0 * pen + N * N * N * sizeof(double), 0.0,
+  CHECKED(timed(S, STERN_K_PLANE_H, n * 2.0 * pen + N * N * N * sizeof(double), n * plane_flops(S),
                 [&] {
                   if (S->plane_var64 == 1)
                     launch_plane_hw<double>(g, S->pen.as<Z64>(), list, n, S->v_t.as<double>(), S->stream);
@@ -330,7 +339,7 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
   Z32* pen32 = S->pen.as<Z32>();
   CHECKED(timed(S, STERN_K_X32, n * (npw * zb + pen), 0.0,
                 [&] { launch_xinv<float>(g, in, list, n, pen32, S->stream); }));
-  CHECKED(timed(S, STERN_K_PLANE_H32, n * 2.0 * pen + N * N * N * sizeof(float), 0.0,
+  CHECKED(timed(S, STERN_K_PLANE_H32, n * 2.0 * pen + N * N * N * sizeof(float), n * plane_flops(S),
                 [&] {
                   if (S->plane_var32 == 1)
                     launch_plane_hw<float>(g, pen32, list, n, S->v_t32.as<float>(), S->stream);
