@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--cpu-bands", type=int, default=4)
+    ap.add_argument("--cpu-bands", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--path", choices=["learned-mixed", "mixed", "fp64"], default="learned-mixed")
     ap.add_argument("--train-solves", type=int, default=8192)

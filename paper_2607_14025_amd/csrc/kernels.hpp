@@ -124,8 +124,11 @@ void launch_gather_rows(Z64* dst, const Z64* src, const int* rows, int ld, int n
 void launch_gather_f32(float* dst, const float* src, const int* rows, int ld, int n, hipStream_t st);
 void launch_conv3(const __bf16* in, const __bf16* W, const float* bias, void* out, int Nc, int nsolve, int act,
                   bool out_f32, hipStream_t st);
+// weight and bias gradients of a layer into grad (kNetLayerParams floats); part holds
+// conv3_wgrad_parts(Nc) x kNetLayerParams floats of per-tile partials
+int conv3_wgrad_parts(int Nc);
 void launch_conv3_wgrad(const __bf16* in, const float* gout, float* part, float* grad, int Nc, int nsolve,
-                        int nslice, hipStream_t st);
+                        hipStream_t st);
 void launch_relu_bwd(float* g, const __bf16* act, size_t n, hipStream_t st);
 void launch_f32_to_bf16(const float* a, __bf16* b, size_t n, hipStream_t st);
 void launch_flip_weights(const float* W, __bf16* Wt, hipStream_t st);

@@ -118,28 +118,62 @@ __global__ __launch_bounds__(256) void k_conv3t(const __bf16* __restrict__ in, c
   }
 }
 
-// dW[co][n][ci] (+)= sum_{s, p} gout[s][p][co] in[s][nbr(p, n)][ci]; db[co] = sum gout.
-// One block per (n, slice of solves); 256 threads = 16 co x 16 ci, loop over points.
+// dW[co][n][ci] = sum_{s, p} gout[s][p][co] in[s][nbr(p, n)][ci]; db[co] = sum gout.
+// One workgroup per 4 x 4 x 16 tile of points, over all solves: the tile's
+// input halo and output gradients are staged in LDS (FP32) and thread (co, ci)
+// accumulates its 27 taps; the tile's partial goes to part[tile] and the tiles
+// are summed in a fixed order afterwards.
 __global__ __launch_bounds__(256) void k_conv3_wgrad(const __bf16* __restrict__ in, const float* __restrict__ gout,
-                                                     float* __restrict__ part, int Nc, int npts, int ldp,
-                                                     int nsolve, int nslice) {
-  const int n = blockIdx.x;       // neighbour
-  const int slice = blockIdx.y;   // slice of solves
+                                                     float* __restrict__ part, int Nc, int ldp, int nsolve,
+                                                     int ntiles) {
+  __shared__ float hs[kHX * kHY * kHZ][C + 1];
+  __shared__ float gs[kTX * kTY * kTZ][C + 1];
+  const int nty = (Nc + kTY - 1) / kTY, ntz = (Nc + kTZ - 1) / kTZ;
+  const int tile = blockIdx.x;
+  const int tx = tile / (nty * ntz), ty = (tile / ntz) % nty, tz = tile % ntz;
+  const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
   const int co = threadIdx.x >> 4, ci = threadIdx.x & 15;
-  float acc = 0.f, accb = 0.f;
-  for (int s = slice; s < nsolve; s += nslice) {
+  float acc[NB];
+#pragma unroll
+  for (int n = 0; n < NB; ++n) acc[n] = 0.f;
+  float accb = 0.f;
+  for (int s = 0; s < nsolve; ++s) {
     const __bf16* ins = in + (size_t)s * ldp * C;
-    const float* gs = gout + (size_t)s * ldp * C;
-    for (int p = 0; p < npts; ++p) {
-      const int x = p / (Nc * Nc), y = (p / Nc) % Nc, z = p % Nc;
-      const float gv = gs[(size_t)p * C + co];
-      acc += gv * (float)ins[(size_t)nbr_index(x, y, z, n, Nc) * C + ci];
-      if (n == 0 && ci == 0) accb += gv;
+    const float* gso = gout + (size_t)s * ldp * C;
+    __syncthreads();  // the previous solve's reads of hs / gs are done
+    for (int i = threadIdx.x; i < kHX * kHY * kHZ * C; i += 256) {
+      const int c = i % C, pt = i / C;
+      const int px = pt / (kHY * kHZ), py = (pt / kHZ) % kHY, pz = pt % kHZ;
+      int gx = x0 - 1 + px, gy = y0 - 1 + py, gz = z0 - 1 + pz;
+      gx = ((gx % Nc) + Nc) % Nc;
+      gy = ((gy % Nc) + Nc) % Nc;
+      gz = ((gz % Nc) + Nc) % Nc;
+      hs[pt][c] = (float)ins[(size_t)((gx * Nc + gy) * Nc + gz) * C + c];
+    }
+    for (int i = threadIdx.x; i < kTX * kTY * kTZ * C; i += 256) {
+      const int c = i % C, pt = i / C;
+      const int lx = pt / (kTY * kTZ), ly = (pt / kTZ) % kTY, lz = pt % kTZ;
+      const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+      float v = 0.f;  // points past Nc contribute nothing
+      if (gx < Nc && gy < Nc && gz < Nc) v = gso[(size_t)((gx * Nc + gy) * Nc + gz) * C + c];
+      gs[pt][c] = v;
+    }
+    __syncthreads();
+    for (int pt = 0; pt < kTX * kTY * kTZ; ++pt) {
+      const int lx = pt / (kTY * kTZ), ly = (pt / kTZ) % kTY, lz = pt % kTZ;
+      const float gv = gs[pt][co];
+      accb += gv;
+#pragma unroll
+      for (int n = 0; n < NB; ++n) {
+        const int dx = n / 9, dy = (n / 3) % 3, dz = n % 3;  // halo offsets 0..2 = d + 1
+        acc[n] += gv * hs[((lx + dx) * kHY + (ly + dy)) * kHZ + (lz + dz)][ci];
+      }
     }
   }
-  // part layout: [nslice][co][n][ci] then [nslice][co] biases after the weights
-  part[(((size_t)slice * C + co) * NB + n) * C + ci] = acc;
-  if (n == 0 && ci == 0) part[(size_t)nslice * C * NB * C + (size_t)slice * C + co] = accb;
+  // part layout: [ntiles][co][n][ci], then [ntiles][co] biases after the weights
+#pragma unroll
+  for (int n = 0; n < NB; ++n) part[(((size_t)tile * C + co) * NB + n) * C + ci] = acc[n];
+  if (ci == 0) part[(size_t)ntiles * C * NB * C + (size_t)tile * C + co] = accb;
 }
 
 // sum the slices in order; grad = sum
@@ -488,13 +522,16 @@ void launch_conv3(const __bf16* in, const __bf16* W, const float* bias, void* ou
     k_conv3t<1, true><<<grid, 256, 0, st>>>(in, W, bias, out, Nc, ldp);
 }
 
+int conv3_wgrad_parts(int Nc) {
+  return ((Nc + kTX - 1) / kTX) * ((Nc + kTY - 1) / kTY) * ((Nc + kTZ - 1) / kTZ);
+}
+
 void launch_conv3_wgrad(const __bf16* in, const float* gout, float* part, float* grad, int Nc, int nsolve,
-                        int nslice, hipStream_t st) {
-  const int npts = Nc * Nc * Nc, ldp = net_ldp(Nc);
-  dim3 grid(NB, nslice);
-  k_conv3_wgrad<<<grid, 256, 0, st>>>(in, gout, part, Nc, npts, ldp, nsolve, nslice);
+                        hipStream_t st) {
+  const int ntiles = conv3_wgrad_parts(Nc);
+  k_conv3_wgrad<<<ntiles, 256, 0, st>>>(in, gout, part, Nc, net_ldp(Nc), nsolve, ntiles);
   const int nelem = C * NB * C + C;
-  k_sum_slices<<<(nelem + 255) / 256, 256, 0, st>>>(part, nslice, nelem, grad);
+  k_sum_slices<<<(nelem + 255) / 256, 256, 0, st>>>(part, ntiles, nelem, grad);
 }
 
 void launch_relu_bwd(float* g, const __bf16* act, size_t n, hipStream_t st) {

@@ -1739,7 +1739,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
   for (DBuf* d : {&M->out, &M->g3, &M->g2}) CHECKED(d->ensure((size_t)B * ldp * C * sizeof(float)));
   CHECKED(M->tgt.ensure((size_t)B * ldp * 2 * sizeof(float)));
   CHECKED(M->loss.ensure((size_t)B * sizeof(float)));
-  CHECKED(M->part.ensure((size_t)B * (stern_model::LP) * sizeof(float)));
+  CHECKED(M->part.ensure((size_t)conv3_wgrad_parts(Nc) * stern_model::LP * sizeof(float)));
   const int np_layer = stern_model::LP;
   std::vector<int> order(nsamp);
   std::iota(order.begin(), order.end(), 0);
@@ -1764,21 +1764,19 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
       const size_t nact = (size_t)nb_ * ldp * C;
       float* gw = M->grad.as<float>();
       // layer 3 (index 2)
-      launch_conv3_wgrad(M->a2.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw + 2 * np_layer, Nc, nb_, nb_,
-                         st);
+      launch_conv3_wgrad(M->a2.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw + 2 * np_layer, Nc, nb_, st);
       launch_flip_weights(M->w.as<float>() + 2 * np_layer, M->wtf.as<__bf16>(), st);
       launch_f32_to_bf16(M->g3.as<float>(), M->gbf.as<__bf16>(), nact, st);
       launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g2.as<float>(), Nc, nb_, 0, true, st);
       launch_relu_bwd(M->g2.as<float>(), M->a2.as<__bf16>(), nact, st);
       // layer 2 (index 1)
-      launch_conv3_wgrad(M->a1.as<__bf16>(), M->g2.as<float>(), M->part.as<float>(), gw + 1 * np_layer, Nc, nb_, nb_,
-                         st);
+      launch_conv3_wgrad(M->a1.as<__bf16>(), M->g2.as<float>(), M->part.as<float>(), gw + 1 * np_layer, Nc, nb_, st);
       launch_flip_weights(M->w.as<float>() + 1 * np_layer, M->wtf.as<__bf16>(), st);
       launch_f32_to_bf16(M->g2.as<float>(), M->gbf.as<__bf16>(), nact, st);
       launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g3.as<float>(), Nc, nb_, 0, true, st);
       launch_relu_bwd(M->g3.as<float>(), M->a1.as<__bf16>(), nact, st);
       // layer 1 (index 0)
-      launch_conv3_wgrad(M->a0.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw, Nc, nb_, nb_, st);
+      launch_conv3_wgrad(M->a0.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw, Nc, nb_, st);
       ++M->step;
       launch_adam(M->w.as<float>(), M->m.as<float>(), M->v.as<float>(), gw, stern_model_num_params(), lr, M->step,
                   1.f / (float)nb_, st);
