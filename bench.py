@@ -121,7 +121,9 @@ def main():
     s = make_system(wl)
     dv = torch.from_numpy(wl["dv"]).to(dev)
     n_timed, tuned = s.autotune(n_vec=1024)  # setup, like init and set_occupied: not timed
-    print(f"bench: autotuned {n_timed} kernel candidates: {tuned}", file=sys.stderr, flush=True)
+    tune_ms = s.autotune_report()
+    print(f"bench: autotuned {n_timed} kernel candidates: {tuned}; ms per candidate on 1,024 rows: {tune_ms}",
+          file=sys.stderr, flush=True)
     dn = torch.empty_like(dv)
     n_pert = dv.shape[0]
     n_solves = n_pert * s.n_occ
@@ -226,6 +228,7 @@ def main():
 
     cfg = dict(workload=spec.name, L_bohr=spec.L, ecut_ry=spec.ecut, atoms=spec.n_atoms, n_pw=s.n_pw,
                grid=s.fft_n, n_occ=s.n_occ, n_pert=n_pert, solves_per_step=n_solves, tol=args.tol, autotuned=tuned,
+               autotune_ms=tune_ms,
                plain_fp64=dict(solves_per_s=plain["value"], mean_cg_iters=plain["iters"]))
     if mixed is not None:
         cfg.update(path="FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction (fallback: FP64 PCG)",

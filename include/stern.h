@@ -272,7 +272,8 @@ void stern_model_free(stern_model* m);
  * Tunables of a system (each keeps its value until set again):
  *   STERN_TUNE_PLANE64   yz-plane kernel of the FP64 H apply: 0 the whole plane
  *                        in LDS, 1 only the active z lines in LDS with per-wave
- *                        transforms (the default when its LDS fits)
+ *                        transforms (the default when its LDS fits), 2 as 1 with
+ *                        the next pair's loads issued ahead (more registers)
  *   STERN_TUNE_PLANE32   the same for the FP32 H apply of the mixed inner solve
  *   STERN_TUNE_GEMM64_WG workgroups the split-K FP64 reduces (Psi^H Y, B^H Y) aim
  *                        for; 0 = built-in default (2048)
@@ -296,6 +297,10 @@ int stern_tunable(stern_system* sys, int which, int value);
  * (optional, STERN_NTUNE ints) receives the values. Returns the number of
  * candidates timed. Synchronous; uses the apply workspace. */
 int stern_autotune(stern_system* sys, int n_vec, const char* cache_path, int* chosen);
+/* Mean time (ms) of every candidate the calling thread's last stern_autotune
+ * timed, as JSON text {"plane64": {"0": t, ...}, ...} ("{}" after a cache hit
+ * or before any tuning). Valid until the thread's next autotune call. */
+const char* stern_autotune_report(void);
 
 /* out = (H - shift_k) c_k for n_vec coefficient rows (canonical order), host or
  * device memory; shift may be NULL (zero). Exposes the H apply of the solver. */

@@ -447,7 +447,7 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int N, class T, int W, int ZR>
+template <int N, class T, int W, int ZR, bool PF>
 __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, const int* __restrict__ vidx, int nvec,
                                                      const T* __restrict__ vt, FftGeom g) {
   using C = PlaneWCfg<N, T, W, ZR>;
@@ -473,23 +473,39 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   const int y0w = min(N, wave * RPW), nr = min(N, y0w + RPW) - y0w;
   const int* __restrict__ yc = g.ycol;
   const long total = (long)N * nvec;
-  for (long q = blockIdx.x; q < total; q += gridDim.x) {
+  auto pencils = [&](long q) {
     const int ix = (int)(q / nvec), b = (int)(q - (long)ix * nvec);
     const int vec = vidx ? vidx[b] : b;
-    Z<T>* tp = pen + ((size_t)vec * N + ix) * g.ncol_pad;
+    return pen + ((size_t)vec * N + ix) * g.ncol_pad;
+  };
+  // the first inverse-y item of this lane (it = lane), loaded one pair ahead
+  Z<T> pre[R1];
+  auto gather = [&](const Z<T>* tp, int it, Z<T>(&v)[R1]) {
+    const int j = it % R2, f = f0 + it / R2;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int y = j + r * R2;
+      v[r] = zero;
+      if (act(y)) {
+        const int col = yc[y * nza + f];
+        if (col >= 0) v[r] = tp[col];
+      }
+    }
+  };
+  if (PF && blockIdx.x < total && lane < nl * R2) gather(pencils(blockIdx.x), lane, pre);
+  for (long q = blockIdx.x; q < total; q += gridDim.x) {
+    const int ix = (int)(q / nvec);
+    Z<T>* tp = pencils(q);
     const T* __restrict__ vx = vt + (size_t)ix * N * N;
     // ---- inverse y on this wave's lines, in place in Q ----
     for (int it = lane; it < nl * R2; it += 64) {
       const int j = it % R2, f = f0 + it / R2;
       Z<T> v[R1];
+      if (PF && it == lane) {
 #pragma unroll
-      for (int r = 0; r < R1; ++r) {
-        const int y = j + r * R2;
-        v[r] = zero;
-        if (act(y)) {
-          const int col = yc[y * nza + f];
-          if (col >= 0) v[r] = tp[col];
-        }
+        for (int r = 0; r < R1; ++r) v[r] = pre[r];
+      } else {
+        gather(tp, it, v);
       }
       dft<R1, +1>(v);
 #pragma unroll
@@ -508,9 +524,21 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       for (int r = 0; r < R2; ++r) Q[f * QLD + j + r * R1] = v[r];
     }
     __syncthreads();
+    if (PF && q + gridDim.x < total && lane < nl * R2) gather(pencils(q + gridDim.x), lane, pre);  // in flight
     // ---- z transforms of this wave's rows, ZR at a time ----
     for (int m0 = 0; m0 < nr; m0 += ZR) {
       const int nz = min(ZR, nr - m0), y0 = y0w + m0;
+      // V of this lane's middle-stage item, loaded before the first stage of the round (PF)
+      T vreg[MAXZ][R2];
+#pragma unroll
+      for (int k = 0; k < MAXZ; ++k) {
+        const int it = lane + 64 * k;
+        if (PF && it < nz * R1) {
+          const int l = it % nz, j = it / nz;
+#pragma unroll
+          for (int r = 0; r < R2; ++r) vreg[k][r] = vx[(size_t)(j + r * R1) * N + y0 + l];
+        }
+      }
       // inverse stage 1 (radix R1) from the active z of Q
       for (int it = lane; it < nz * R2; it += 64) {
         const int l = it % nz, j = it / nz;
@@ -548,7 +576,8 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
             for (int r = 1; r < R2; ++r) v[k][r] = v[k][r] * twid<+1>(tw, r * j);
             dft<R2, +1>(v[k]);
 #pragma unroll
-            for (int r = 0; r < R2; ++r) v[k][r] = zscale(v[k][r], vx[(size_t)(j + r * R1) * N + y0 + l]);
+            for (int r = 0; r < R2; ++r)
+              v[k][r] = zscale(v[k][r], PF ? vreg[k][r] : vx[(size_t)(j + r * R1) * N + y0 + l]);
             dft<R2, -1>(v[k]);
 #pragma unroll
             for (int r = 0; r < R2; ++r) Sw[(j * R2 + r) * ZR + l] = v[k][r];
@@ -869,19 +898,30 @@ int blocks_per_cu(const void* kernel, int nt, size_t lds) {
 }
 }  // namespace
 
+template <int NN, class T, bool PF>
+void launch_plane_hw_n(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, hipStream_t st) {
+  constexpr int W = 4;
+  constexpr int RM = PlaneWCfg<NN, T, W, 1>::RM;
+  constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
+  const size_t lds = planew_lds_bytes<NN, T, W, ZR>(g.nza);
+  const void* kp = (const void*)k_plane_hw<NN, T, W, ZR, PF>;
+  const int per_cu = blocks_per_cu(kp, 64 * W, lds);
+  const long pairs = (long)NN * nvec;
+  const int grid = (int)std::min<long>(pairs, (long)g.n_cu * per_cu);
+  k_plane_hw<NN, T, W, ZR, PF><<<grid, 64 * W, lds, st>>>(pen, vidx, nvec, vt, g);
+}
+
+// prefetch: also load the next pair's first inverse-y items and each round's V
+// ahead of use (more registers, fewer exposed load latencies)
 template <class T>
-void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, hipStream_t st) {
+void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, bool prefetch,
+                     hipStream_t st) {
   if (nvec <= 0) return;
   STERN_DISPATCH_N(g.N, ({
-                     constexpr int W = 4;
-                     constexpr int RM = PlaneWCfg<NN, T, W, 1>::RM;
-                     constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
-                     const size_t lds = planew_lds_bytes<NN, T, W, ZR>(g.nza);
-                     const void* kp = (const void*)k_plane_hw<NN, T, W, ZR>;
-                     const int per_cu = blocks_per_cu(kp, 64 * W, lds);
-                     const long pairs = (long)NN * nvec;
-                     const int grid = (int)std::min<long>(pairs, (long)g.n_cu * per_cu);
-                     k_plane_hw<NN, T, W, ZR><<<grid, 64 * W, lds, st>>>(pen, vidx, nvec, vt, g);
+                     if (prefetch)
+                       launch_plane_hw_n<NN, T, true>(g, pen, vidx, nvec, vt, st);
+                     else
+                       launch_plane_hw_n<NN, T, false>(g, pen, vidx, nvec, vt, st);
                    }));
 }
 size_t plane_hw_lds(int N, int nza, bool fp64) {
@@ -893,8 +933,8 @@ size_t plane_hw_lds(int N, int nza, bool fp64) {
                    }));
   return r;
 }
-template void launch_plane_hw<double>(const FftGeom&, Z64*, const int*, int, const double*, hipStream_t);
-template void launch_plane_hw<float>(const FftGeom&, Z32*, const int*, int, const float*, hipStream_t);
+template void launch_plane_hw<double>(const FftGeom&, Z64*, const int*, int, const double*, bool, hipStream_t);
+template void launch_plane_hw<float>(const FftGeom&, Z32*, const int*, int, const float*, bool, hipStream_t);
 
 template void launch_plane_vloc<float>(const FftGeom&, Z32*, const int*, int, const float*, hipStream_t);
 

@@ -48,7 +48,8 @@ template <class T>
 void launch_plane_vloc(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* v_r, hipStream_t st);
 // same operation, compact-LDS wave-local kernel; vt = V_loc as [x][z][y]
 template <class T>
-void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, hipStream_t st);
+void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, bool prefetch,
+                     hipStream_t st);
 size_t plane_hw_lds(int N, int nza, bool fp64);  // its LDS bytes per workgroup
 // yz planes of the right-hand side: pencils[s] = forward planes of psi_r[band[s]] * dv[pert[s]].
 void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,

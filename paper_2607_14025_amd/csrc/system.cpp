@@ -22,6 +22,7 @@ using namespace stern;
 namespace {
 
 thread_local std::string g_err;
+thread_local std::string g_tune_report = "{}";  // per-candidate times of this thread's last autotune
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];
@@ -280,8 +281,9 @@ int apply_h_rows(stern_system* S, const Z64* in, Z64* out, const int* list, int 
                 [&] { launch_xinv(g, in, list, n, S->pen.as<Z64>(), S->stream); }));
   CHECKED(timed(S, STERN_K_PLANE_H, n * 2.0 * pen + N * N * N * sizeof(double), n * plane_flops(S),
                 [&] {
-                  if (S->plane_var64 == 1)
-                    launch_plane_hw<double>(g, S->pen.as<Z64>(), list, n, S->v_t.as<double>(), S->stream);
+                  if (S->plane_var64 >= 1)
+                    launch_plane_hw<double>(g, S->pen.as<Z64>(), list, n, S->v_t.as<double>(), S->plane_var64 == 2,
+                                            S->stream);
                   else
                     launch_plane_vloc(g, S->pen.as<Z64>(), list, n, S->v_r.as<double>(), S->stream);
                 }));
@@ -341,8 +343,8 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
                 [&] { launch_xinv<float>(g, in, list, n, pen32, S->stream); }));
   CHECKED(timed(S, STERN_K_PLANE_H32, n * 2.0 * pen + N * N * N * sizeof(float), n * plane_flops(S),
                 [&] {
-                  if (S->plane_var32 == 1)
-                    launch_plane_hw<float>(g, pen32, list, n, S->v_t32.as<float>(), S->stream);
+                  if (S->plane_var32 >= 1)
+                    launch_plane_hw<float>(g, pen32, list, n, S->v_t32.as<float>(), S->plane_var32 == 2, S->stream);
                   else
                     launch_plane_vloc<float>(g, pen32, list, n, S->v_r32.as<float>(), S->stream);
                 }));
@@ -1429,6 +1431,8 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
 
 // ------------------------------------------------------------- autotuner ----
 
+const char* stern_autotune_report(void) { return g_tune_report.c_str(); }
+
 int stern_tunable(stern_system* S, int which, int value) {
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   int* slot = nullptr;
@@ -1441,8 +1445,8 @@ int stern_tunable(stern_system* S, int which, int value) {
   }
   if (value >= 0) {
     if (which == STERN_TUNE_PLANE64 || which == STERN_TUNE_PLANE32) {
-      if (value > 1) return fail(STERN_ERR_INVALID_ARG, "plane kernel variant must be 0 or 1");
-      if (value == 1 && plane_hw_lds(S->hb.N, S->hb.nza, which == STERN_TUNE_PLANE64) > S->lds_max)
+      if (value > 2) return fail(STERN_ERR_INVALID_ARG, "plane kernel variant must be 0, 1 or 2");
+      if (value >= 1 && plane_hw_lds(S->hb.N, S->hb.nza, which == STERN_TUNE_PLANE64) > S->lds_max)
         return fail(STERN_ERR_INVALID_ARG, "the compact plane kernel does not fit in LDS for grid %d", S->hb.N);
     } else if (value > 65536) {
       return fail(STERN_ERR_INVALID_ARG, "workgroup target %d out of range", value);
@@ -1511,32 +1515,42 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
   const double* eps = S->sv_eps.as<double>();
   const int reps = 3;
   int n_timed = 0;
+  static const char* names[STERN_NTUNE] = {"plane64", "plane32", "gemm64_wg", "gemm16_wg"};
+  std::string report = "{";
   auto tune = [&](int which, const std::vector<int>& cand, auto&& fn) -> int {
     double best = 1e300;
     int bestv = *slots[which];
+    report += std::string(which ? ", \"" : "\"") + names[which] + "\": {";
+    bool first = true;
     for (int v : cand) {
       if (stern_tunable(S, which, v) < 0) continue;  // not runnable here
       CHECKED(ensure_workspace(S, n_vec));             // split-K partials for this target
       double ms = 0.0;
       CHECKED(time_ms(S, reps, ms, fn));
       ++n_timed;
+      char item[64];
+      std::snprintf(item, sizeof item, "%s\"%d\": %.4f", first ? "" : ", ", v, ms);
+      report += item;
+      first = false;
       if (ms < best) {
         best = ms;
         bestv = v;
       }
     }
+    report += "}";
     CHECKED(stern_tunable(S, which, bestv));
     return 0;
   };
-  CHECKED(tune(STERN_TUNE_PLANE64, {0, 1},
+  CHECKED(tune(STERN_TUNE_PLANE64, {0, 1, 2},
                [&] { return apply_h_rows(S, S->wp.as<Z64>(), S->wq.as<Z64>(), nullptr, n_vec, eps); }));
-  CHECKED(tune(STERN_TUNE_PLANE32, {0, 1},
+  CHECKED(tune(STERN_TUNE_PLANE32, {0, 1, 2},
                [&] { return apply_h32_rows(S, S->m_p.as<Z32>(), S->m_q.as<Z32>(), nullptr, n_vec, eps); }));
   CHECKED(tune(STERN_TUNE_GEMM64_WG, {256, 512, 1024, 2048, 4096},
                [&] { return apply_pc_rows(S, S->wq.as<Z64>(), nullptr, n_vec); }));
   CHECKED(tune(STERN_TUNE_GEMM16_WG, {128, 256, 512, 1024, 2048},
                [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
   CHECKED(ensure_workspace(S, n_vec));
+  g_tune_report = report + "}";
   if (chosen)
     for (int w = 0; w < STERN_NTUNE; ++w) chosen[w] = *slots[w];
   if (cache_path) {

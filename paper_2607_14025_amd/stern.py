@@ -27,7 +27,7 @@ STERN_MEM_DEVICE = 1
 EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
             "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_tunable",
-            "stern_autotune", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
+            "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -115,6 +115,8 @@ def lib():
         L.stern_model_free.restype = None
         L.stern_tunable.argtypes = [C.c_void_p, C.c_int, C.c_int]
         L.stern_autotune.argtypes = [C.c_void_p, C.c_int, C.c_char_p, P(C.c_int)]
+        L.stern_autotune_report.argtypes = []
+        L.stern_autotune_report.restype = C.c_char_p
         L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_free.argtypes = [C.c_void_p]
@@ -323,6 +325,12 @@ class System:
         path = None if cache_path is None else os.fsencode(cache_path)
         n = _check(lib().stern_autotune(self._h, int(n_vec), path, ch))
         return n, {TUNE_NAMES[k]: int(ch[k]) for k in range(NTUNE)}
+
+    @staticmethod
+    def autotune_report():
+        """{tunable: {value: mean ms}} of the calling thread's last autotune (empty after a cache hit)."""
+        import json
+        return json.loads(lib().stern_autotune_report().decode())
 
     def apply_h(self, c, shift=None):
         c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.complex128)
