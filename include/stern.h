@@ -97,7 +97,8 @@ typedef struct {
                           P_c always uses every occupied band; dn is the partial sum. */
   int band_end;
   int max_batch;       /* solves held in flight at once (0 = choose from free memory) */
-  int check_every;     /* iterations between convergence checks (0 = 4) */
+  int check_every;     /* iterations between convergence checks and active-set compaction
+                          (0 = 1: every iteration; converged solves stop costing work at once) */
   /* optional per-solve outputs for a list of (band, perturbation) pairs:
      sample_pairs[2k] = v, sample_pairs[2k+1] = i; sample_x receives
      n_sample x n_pw complex solutions in canonical order (host memory). */

@@ -1197,7 +1197,7 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   const size_t n3 = (size_t)N * N * N;
   const int nb = v1 - v0;
   const int max_iter = opts->max_iter > 0 ? opts->max_iter : 1000;
-  const int check_every = opts->check_every > 0 ? opts->check_every : 4;
+  const int check_every = opts->check_every > 0 ? opts->check_every : 1;
   const double tol = opts->tol;
   const double inner_tol = opts->inner_tol > 0 ? opts->inner_tol : 1e-4;
   const int max_outer = opts->max_outer > 0 ? opts->max_outer : 8;
@@ -1722,7 +1722,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
       CHECKED(setup_batch(S, i0, i1, 0, nb, dv_dev, vecb));
       std::vector<int> all(ns);
       std::iota(all.begin(), all.end(), 0);
-      CHECKED(run_pcg64(S, cs, all, tol, 1000, 4, n_restart, vecb, false));
+      CHECKED(run_pcg64(S, cs, all, tol, 1000, 1, n_restart, vecb, false));
       for (int s0 = 0; s0 < ns; s0 += chunk) {
         const int c = std::min(chunk, ns - s0);
         CHECKED(net_input(S, cs, s0, c, S->net_a0.as<__bf16>()));
@@ -1880,7 +1880,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
                           kPrecIn, nr, st2);
         std::vector<int> all(ns);
         std::iota(all.begin(), all.end(), 0);
-        CHECKED(run_pcg64(S, cs, all, tol, 1000, 4, n_restart, vecb, false, true));
+        CHECKED(run_pcg64(S, cs, all, tol, 1000, 1, n_restart, vecb, false, true));
         launch_gather_rows(E0, cs.x, M->idx.as<int>(), K, nr, true, st2);  // e0 = x* - x0
         CHECKED(launch_check());
         HIPOK(hipStreamSynchronize(st2));
