@@ -278,12 +278,15 @@ void stern_model_free(stern_model* m);
  *   STERN_TUNE_PLANE32   the same for the FP32 H apply of the mixed inner solve
  *   STERN_TUNE_GEMM64_WG workgroups the split-K FP64 reduces (Psi^H Y, B^H Y) aim
  *                        for; 0 = built-in default (2048)
- *   STERN_TUNE_GEMM16_WG the same for the split-BF16 reduces; 0 = default (512) */
+ *   STERN_TUNE_GEMM16_WG the same for the split-BF16 reduces; 0 = default (512)
+ *   STERN_TUNE_GEMM16_EXPAND tile of the split-BF16 expand (Y += Psi C, B D P):
+ *                        0 = 256 x 128 per workgroup, 1 = 128 x 128 (two per CU) */
 #define STERN_TUNE_PLANE64 0
 #define STERN_TUNE_PLANE32 1
 #define STERN_TUNE_GEMM64_WG 2
 #define STERN_TUNE_GEMM16_WG 3
-#define STERN_NTUNE 4
+#define STERN_TUNE_GEMM16_EXPAND 4
+#define STERN_NTUNE 5
 
 /* value >= 0 sets tunable `which` (STERN_ERR_INVALID_ARG for an unknown
  * tunable or a value the system cannot run, e.g. a plane kernel whose LDS does

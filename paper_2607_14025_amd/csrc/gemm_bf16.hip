@@ -224,16 +224,19 @@ __device__ __forceinline__ bf16x8 swap_b(bf16x8 c) {
 
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m], A given transposed (AT [K][2 M_pad]
 // hi/lo) and C as k_sum_split writes it. 8 waves: wave (wk, wn) owns rows
-// [64 wk, 64 wk + 64) and columns [64 wn, 64 wn + 64) of the 256 x 128 tile.
-// Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
-__global__ __launch_bounds__(kThreads8) void k_expand_bf16s(const __bf16* __restrict__ ATh,
+// [16 KB wk, 16 KB (wk + 1)) and columns [64 wn, 64 wn + 64) of the
+// (64 KB) x 128 tile; KB = 4 (256 x 128, 1 workgroup per CU) or 2 (128 x 128,
+// fewer registers, 2 workgroups per CU, so one's Y update overlaps another's
+// products). Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
+template <int KB>
+__global__ __launch_bounds__(kThreads8, KB == 4 ? 2 : 4) void k_expand_bf16s(const __bf16* __restrict__ ATh,
                                                             const __bf16* __restrict__ ATl, int M_pad, int K,
                                                             const __bf16* __restrict__ Cs, Z32* __restrict__ Y,
                                                             int ldy, const int* __restrict__ yidx, int ncols) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int wk = wave & 3, wn = wave >> 2;
-  const int k0 = blockIdx.x * kET + wk * 64;
+  const int k0 = blockIdx.x * (64 * KB) + wk * 16 * KB;
   if (k0 >= K) return;  // K is a multiple of 64; no barrier below
   const int n0 = blockIdx.y * kEN + wn * 64;
   const size_t plane = (size_t)ncols * M_pad * 2;
@@ -244,9 +247,9 @@ __global__ __launch_bounds__(kThreads8) void k_expand_bf16s(const __bf16* __rest
     nn[bj] = n0 + 16 * bj + l16;
     nv[bj] = nn[bj] < ncols;
   }
-  f32x4 dre[4][4], dim_[4][4];
+  f32x4 dre[KB][4], dim_[KB][4];
 #pragma unroll
-  for (int bi = 0; bi < 4; ++bi)
+  for (int bi = 0; bi < KB; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 4; ++bj) {
       dre[bi][bj] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -255,9 +258,9 @@ __global__ __launch_bounds__(kThreads8) void k_expand_bf16s(const __bf16* __rest
   const bf16x8 zero8 = bf16x8{};
   for (int mc = 0; mc < M_pad; mc += 16) {
     const int m = mc + 4 * g;  // this lane group's 4 complex m
-    bf16x8 a_hi[4], a_lo[4];
+    bf16x8 a_hi[KB], a_lo[KB];
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < KB; ++bi) {
       const size_t row = (size_t)(k0 + 16 * bi + l16) * 2 * M_pad + 2 * m;
       a_hi[bi] = *reinterpret_cast<const bf16x8*>(ATh + row);
       a_lo[bi] = *reinterpret_cast<const bf16x8*>(ATl + row);
@@ -272,7 +275,7 @@ __global__ __launch_bounds__(kThreads8) void k_expand_bf16s(const __bf16* __rest
       }
       const bf16x8 rh = conj_b(ch), rl = conj_b(cl), ih = swap_b(ch), il = swap_b(cl);
 #pragma unroll
-      for (int bi = 0; bi < 4; ++bi) {
+      for (int bi = 0; bi < KB; ++bi) {
         dre[bi][bj] = mfma(a_hi[bi], rh, dre[bi][bj]);
         dre[bi][bj] = mfma(a_hi[bi], rl, dre[bi][bj]);
         dre[bi][bj] = mfma(a_lo[bi], rh, dre[bi][bj]);
@@ -288,7 +291,7 @@ __global__ __launch_bounds__(kThreads8) void k_expand_bf16s(const __bf16* __rest
     if (!nv[bj]) continue;
     Z32* y = Y + (size_t)(yidx ? yidx[nn[bj]] : nn[bj]) * ldy;
 #pragma unroll
-    for (int bi = 0; bi < 4; ++bi) {
+    for (int bi = 0; bi < KB; ++bi) {
       float4* p = reinterpret_cast<float4*>(y + k0 + 16 * bi + 4 * g);
       float4 u = p[0], w = p[1];
       u.x += dre[bi][bj][0];
@@ -363,10 +366,15 @@ void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, floa
 }
 
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
-                        const int* yidx, int ncols, int K, hipStream_t st) {
+                        const int* yidx, int ncols, int K, int variant, hipStream_t st) {
   if (ncols <= 0) return;
-  dim3 grid((K + kET - 1) / kET, (ncols + kEN - 1) / kEN);
-  k_expand_bf16s<<<grid, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols);
+  if (variant == 1) {
+    dim3 grid((K + 127) / 128, (ncols + kEN - 1) / kEN);
+    k_expand_bf16s<2><<<grid, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols);
+  } else {
+    dim3 grid((K + kET - 1) / kET, (ncols + kEN - 1) / kEN);
+    k_expand_bf16s<4><<<grid, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols);
+  }
 }
 
 }  // namespace stern

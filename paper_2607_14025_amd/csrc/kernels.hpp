@@ -173,7 +173,8 @@ void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z
 void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
                         hipStream_t st);
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A
+// Y += A C for the split-BF16 operands; variant 0: 256 x 128 tiles, 1: 128 x 128 tiles
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
-                        const int* yidx, int ncols, int K, hipStream_t st);
+                        const int* yidx, int ncols, int K, int variant, hipStream_t st);
 
 }  // namespace stern

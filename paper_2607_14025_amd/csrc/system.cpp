@@ -99,6 +99,7 @@ struct stern_system {
   int plane_var64 = 1, plane_var32 = 1;
   // split-K workgroup targets of the FP64 and split-BF16 reduces (0 = default)
   int gemm64_wg = 0, gemm16_wg = 0;
+  int gemm16_expand = 0;  // tile variant of the split-BF16 expand
   size_t lds_max = 160 * 1024;
   // occupied states
   int n_occ = 0, nocc_pad = 0;
@@ -327,7 +328,7 @@ int apply_psi32_rows(stern_system* S, const Z32* X, Z32* Y, const int* list, int
                 [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, scale, cm, S->stream); }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (2.0 * n + m), 8.0 * m * npw * n, [&] {
     launch_expand_bf16(S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), S->nocc_pad, cm, Y, K, list, n, K,
-                       S->stream);
+                       S->gemm16_expand, S->stream);
   }));
   return 0;
 }
@@ -363,7 +364,7 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
                   [&] { launch_sum_parts32(cp, ns, n, S->natoms_pad, (float)S->cell.D, cm, S->stream); }));
     CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (2.0 * n + na), 8.0 * na * npw * n, [&] {
       launch_expand_bf16(S->kbT_hi.as<__bf16>(), S->kbT_lo.as<__bf16>(), S->natoms_pad, cm, out, K, list, n, K,
-                         S->stream);
+                         S->gemm16_expand, S->stream);
     }));
   }
   return 0;
@@ -1441,10 +1442,13 @@ int stern_tunable(stern_system* S, int which, int value) {
     case STERN_TUNE_PLANE32: slot = &S->plane_var32; break;
     case STERN_TUNE_GEMM64_WG: slot = &S->gemm64_wg; break;
     case STERN_TUNE_GEMM16_WG: slot = &S->gemm16_wg; break;
+    case STERN_TUNE_GEMM16_EXPAND: slot = &S->gemm16_expand; break;
     default: return fail(STERN_ERR_INVALID_ARG, "unknown tunable %d", which);
   }
   if (value >= 0) {
-    if (which == STERN_TUNE_PLANE64 || which == STERN_TUNE_PLANE32) {
+    if (which == STERN_TUNE_GEMM16_EXPAND) {
+      if (value > 1) return fail(STERN_ERR_INVALID_ARG, "expand variant must be 0 or 1");
+    } else if (which == STERN_TUNE_PLANE64 || which == STERN_TUNE_PLANE32) {
       if (value > 2) return fail(STERN_ERR_INVALID_ARG, "plane kernel variant must be 0, 1 or 2");
       if (value >= 1 && plane_hw_lds(S->hb.N, S->hb.nza, which == STERN_TUNE_PLANE64) > S->lds_max)
         return fail(STERN_ERR_INVALID_ARG, "the compact plane kernel does not fit in LDS for grid %d", S->hb.N);
@@ -1470,11 +1474,12 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
   char key[512];
   std::snprintf(key, sizeof key, "%s N=%d nza=%d npw=%d nocc_pad=%d natoms_pad=%d nvec=%d", prop.gcnArchName,
                 S->hb.N, S->hb.nza, S->hb.npw, S->nocc_pad, S->natoms_pad, n_vec);
-  int* slots[STERN_NTUNE] = {&S->plane_var64, &S->plane_var32, &S->gemm64_wg, &S->gemm16_wg};
+  int* slots[STERN_NTUNE] = {&S->plane_var64, &S->plane_var32, &S->gemm64_wg, &S->gemm16_wg, &S->gemm16_expand};
   // cached choices
   if (cache_path) {
     std::FILE* f = std::fopen(cache_path, "r");
-    int found[STERN_NTUNE] = {-1, -1, -1, -1};
+    int found[STERN_NTUNE];
+    for (int w = 0; w < STERN_NTUNE; ++w) found[w] = -1;
     if (f) {
       char line[768];
       const size_t kl = std::strlen(key);
@@ -1515,7 +1520,7 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
   const double* eps = S->sv_eps.as<double>();
   const int reps = 3;
   int n_timed = 0;
-  static const char* names[STERN_NTUNE] = {"plane64", "plane32", "gemm64_wg", "gemm16_wg"};
+  static const char* names[STERN_NTUNE] = {"plane64", "plane32", "gemm64_wg", "gemm16_wg", "gemm16_expand"};
   std::string report = "{";
   auto tune = [&](int which, const std::vector<int>& cand, auto&& fn) -> int {
     double best = 1e300;
@@ -1548,6 +1553,8 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
   CHECKED(tune(STERN_TUNE_GEMM64_WG, {256, 512, 1024, 2048, 4096},
                [&] { return apply_pc_rows(S, S->wq.as<Z64>(), nullptr, n_vec); }));
   CHECKED(tune(STERN_TUNE_GEMM16_WG, {128, 256, 512, 1024, 2048},
+               [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
+  CHECKED(tune(STERN_TUNE_GEMM16_EXPAND, {0, 1},
                [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
   CHECKED(ensure_workspace(S, n_vec));
   g_tune_report = report + "}";

@@ -33,8 +33,9 @@ TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
 TUNE_GEMM64_WG = 2
 TUNE_GEMM16_WG = 3
-NTUNE = 4
-TUNE_NAMES = ["plane64", "plane32", "gemm64_wg", "gemm16_wg"]
+TUNE_GEMM16_EXPAND = 4
+NTUNE = 5
+TUNE_NAMES = ["plane64", "plane32", "gemm64_wg", "gemm16_wg", "gemm16_expand"]
 
 
 class SternError(RuntimeError):

@@ -60,14 +60,16 @@ def test_plane_variants_match_oracle(L, ecut, natoms, tiny_system):
 
 def test_every_variant_keeps_parity(tuned_tiny):
     from paper_2607_14025_amd import STERN_MIXED
-    from paper_2607_14025_amd.stern import TUNE_PLANE64, TUNE_PLANE32, TUNE_GEMM64_WG, TUNE_GEMM16_WG
+    from paper_2607_14025_amd.stern import (TUNE_PLANE64, TUNE_PLANE32, TUNE_GEMM64_WG, TUNE_GEMM16_WG,
+                                            TUNE_GEMM16_EXPAND)
     t = tuned_tiny
     s = t["sys"]
-    for p64, p32, g64, g16 in ((0, 0, 256, 128), (1, 1, 4096, 2048), (2, 2, 0, 0), (1, 0, 0, 0)):
+    for p64, p32, g64, g16, ex in ((0, 0, 256, 128, 0), (1, 1, 4096, 2048, 1), (2, 2, 0, 0, 1), (1, 0, 0, 0, 0)):
         s.tunable(TUNE_PLANE64, p64)
         s.tunable(TUNE_PLANE32, p32)
         s.tunable(TUNE_GEMM64_WG, g64)
         s.tunable(TUNE_GEMM16_WG, g16)
+        s.tunable(TUNE_GEMM16_EXPAND, ex)
         dn, info = s.apply_chi0(t["dv"], tol=1e-10)
         assert info["n_converged"] == 48 and rel_l2(dn, t["ref"]["dn"]).max() < 1e-9
         dm, info = s.apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED)
@@ -80,11 +82,12 @@ def test_autotune_and_cache(tuned_tiny, tmp_path):
     s = t["sys"]
     cache = tmp_path / "tune.txt"
     n, chosen = s.autotune(n_vec=64, cache_path=str(cache))
-    assert n >= 14
+    assert n >= 16
     assert chosen["plane64"] in (0, 1, 2) and chosen["plane32"] in (0, 1, 2)
     assert chosen["gemm64_wg"] in (256, 512, 1024, 2048, 4096)
     assert chosen["gemm16_wg"] in (128, 256, 512, 1024, 2048)
-    assert len(cache.read_text().splitlines()) == 4
+    assert chosen["gemm16_expand"] in (0, 1)
+    assert len(cache.read_text().splitlines()) == 5
     n2, chosen2 = s.autotune(n_vec=64, cache_path=str(cache))
     assert n2 == 0 and chosen2 == chosen
     dn, info = s.apply_chi0(t["dv"], tol=1e-10)
