@@ -102,3 +102,38 @@ def test_mixed_precision_full_size(mid):
     ax = project(psi, cell.h_apply(px) - wl["eps"][bands][:, None] * px)
     res = np.linalg.norm(b - ax, axis=1) / np.linalg.norm(b, axis=1)
     assert res.max() <= 1.05e-8, res
+
+
+@pytest.mark.parametrize("precision_name,prec_only", [("mixed", True), ("fp64", False)])
+def test_learned_full_size(mid, precision_name, prec_only):
+    """The learned start on the bench workload (model trained on another seeded mid cell): every
+    solve accepted at 1e-8, dn within 1e-6 of the plain FP64 path, sampled solutions satisfy the
+    oracle's equation."""
+    import torch
+    from paper_2607_14025_amd import Model, System, STERN_FP64, STERN_MIXED
+    from synth.cells import MID
+    from synth.inputs import load_workload
+    if "model" not in mid:
+        w = load_workload(MID.with_system(1))
+        sp = w["spec"]
+        dev = torch.device("cuda:0")
+        tr = System(sp.L, sp.ecut, w["pos"], sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width)
+        tr.set_occupied(torch.from_numpy(np.ascontiguousarray(w["psi"])).to(dev), torch.from_numpy(w["eps"]).to(dev))
+        m = Model(seed=0)
+        st = m.train([tr], [torch.from_numpy(w["dv"][:16]).to(dev)], epochs=2, max_solves=2048, tol=1e-10, seed=1)
+        tr.close()
+        assert np.isfinite(st["loss_last"]) and np.isfinite(st["prec_loss_last"])
+        mid["model"] = m
+    cell, psi, wl = mid["cell"], mid["psi"], mid["wl"]
+    prec = STERN_MIXED if precision_name == "mixed" else STERN_FP64
+    dn, info = mid["s"].apply_chi0(mid["dv_t"], tol=1e-8, precision=prec, model=mid["model"], prec_only=prec_only,
+                                   samples=PAIRS)
+    assert info["n_converged"] == 8192 and info["max_true_resid"] <= 1e-8
+    assert rel_l2(dn.cpu().numpy(), mid["dn"]).max() < 1e-6
+    x = cell.take(info["samples"], wl["miller"])
+    bands = [v for v, _ in PAIRS]
+    b = rhs(cell, psi, wl["dv"], bands, [i for _, i in PAIRS])
+    px = project(psi, x)
+    ax = project(psi, cell.h_apply(px) - wl["eps"][bands][:, None] * px)
+    res = np.linalg.norm(b - ax, axis=1) / np.linalg.norm(b, axis=1)
+    assert res.max() <= 1.05e-8, res
