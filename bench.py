@@ -95,7 +95,8 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2607_14025_amd import Model, System, STERN_FP64, STERN_MIXED
+    from paper_2607_14025_amd import (Model, System, STERN_FP64, STERN_MIXED, STERN_INNER_PROJECTED,
+                                      STERN_INNER_INVARIANT)
     from synth.cells import MID
     from synth.inputs import load_workload
 
@@ -147,9 +148,10 @@ def main():
         torch.cuda.synchronize()
         print(f"bench: training done: {train}", file=sys.stderr, flush=True)
 
-    def run(precision, steps, warmup, label, mdl=None, prec_only=False):
+    def run(precision, steps, warmup, label, mdl=None, prec_only=False, inner_op=STERN_INNER_PROJECTED):
+        kw = dict(precision=precision, model=mdl, prec_only=prec_only, inner_op=inner_op)
         for w in range(warmup):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl, prec_only=prec_only)
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, **kw)
             print(f"bench: {label} warmup {w}: {info['n_converged']}/{info['n_solves']} converged in "
                   f"{info['wall_s']:.2f} s", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
@@ -159,8 +161,7 @@ def main():
         fallback = 0
         t0 = time.perf_counter()
         for k in range(steps):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, precision=precision, model=mdl,
-                                   prec_only=prec_only)
+            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, **kw)
             conv += info["n_converged"]
             fallback += info["n_fallback"]
             iters.append(info["total_iters"] / max(1, info["n_solves"]))
@@ -175,7 +176,7 @@ def main():
         dt = time.perf_counter() - t0
         r = dict(value=conv / dt, dt=dt, kern=kern, iters=float(np.mean(iters)), fallback=fallback)
         if label != "fp64":  # dn against the plain FP64 path at the same tolerance
-            s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=precision, model=mdl, prec_only=prec_only)
+            s.apply_chi0(dv, tol=args.tol, dn_out=dn, **kw)
             torch.cuda.synchronize()
             r["dn_rel_err_vs_fp64"] = ((dn - ref).reshape(n_pert, -1).norm(dim=1)
                                        / ref.reshape(n_pert, -1).norm(dim=1)).max().item()
@@ -186,9 +187,10 @@ def main():
     torch.cuda.synchronize()
     plain = run(STERN_FP64, args.steps, args.warmup, "fp64")
     head = plain
-    mixed = learned = learned_fp64 = learned_k = None
+    mixed = mixed_inv = learned = learned_fp64 = learned_k = None
     if args.path in ("mixed", "learned-mixed"):
         mixed = run(STERN_MIXED, args.steps, args.warmup, "mixed")
+        mixed_inv = run(STERN_MIXED, args.steps, args.warmup, "mixed-invariant", inner_op=STERN_INNER_INVARIANT)
         head = mixed
     if args.path == "learned-mixed":
         learned_fp64 = run(STERN_FP64, args.steps, args.warmup, "learned-fp64", model)
@@ -234,6 +236,9 @@ def main():
         cfg.update(path="FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction (fallback: FP64 PCG)",
                    mixed=dict(solves_per_s=mixed["value"], mean_inner_iters=mixed["iters"],
                               fallback_solves=mixed["fallback"], dn_rel_err_vs_fp64=mixed["dn_rel_err_vs_fp64"]),
+                   mixed_invariant_teter=dict(solves_per_s=mixed_inv["value"], mean_inner_iters=mixed_inv["iters"],
+                                              fallback_solves=mixed_inv["fallback"],
+                                              dn_rel_err_vs_fp64=mixed_inv["dn_rel_err_vs_fp64"]),
                    speedup_vs_plain_fp64=mixed["value"] / plain["value"])
         dtype = "f32+bf16/f64"
     if learned is not None:

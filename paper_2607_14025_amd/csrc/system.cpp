@@ -745,18 +745,25 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
 //           (FP64 dots and scalars); x += d; x = P_c x (FP64); r = b - A x (FP64)
 //   until ||r|| <= tol ||b||; solves still above tol after max_outer steps are
 //   re-solved by FP64 PCG from zero.
-// The inner operator is either (default) the projected one, P_c (H - eps) P_c
-// with a projection of q and of z in every iteration, or the DFPT form
-// H - eps + alpha P_v (Baroni et al., Rev. Mod. Phys. 73, 515 (2001)), which is
-// positive definite for alpha above the occupied band width and needs one
-// Psi GEMM pair per iteration. On range(P_c) the two agree up to the
-// commutator of H with P_v, which the ground state makes small; the FP64
-// outer residual uses the projected operator, so the accepted solution is the
-// projected system's either way. With Teter's K, which does not commute with
-// P_v, the shifted form takes about twice the inner iterations.
+// Inner operators (inner_op):
+//  projected: q = P_c (H - eps) p and z = P_c K r.
+//  invariant: q = (H - eps) p and z = P_c K r. With p in range(P_c) and Psi an
+//    invariant subspace of H, (H - eps) p lies in range(P_c) in exact
+//    arithmetic, so the projection of q is left out. What the FP32 H apply and
+//    the BF16 projection of z leave in span(Psi) then stays in r, and K carries
+//    it back into z through P_c K Psi: harmless when K is nearly constant on
+//    the occupied states (Teter's), a stall when it is not (a learned K).
+//  shifted: H - eps + alpha P_v (Baroni et al., Rev. Mod. Phys. 73, 515 (2001)),
+//    positive definite for alpha above the occupied band width. On range(P_c)
+//    it agrees with the projected operator up to the commutator of H with P_v;
+//    with Teter's K, which does not commute with P_v, it takes about twice the
+//    inner iterations.
+// The FP64 outer residual uses the projected operator, so the accepted
+// solution is the projected system's whichever operator runs inside.
 int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, double inner_tol,
               int max_outer, int max_iter, int check_every, int& n_restart, int& n_fallback, double vecb,
-              bool use_graph, bool projected) {
+              bool use_graph, int inner_op) {
+  const bool projected = inner_op != STERN_INNER_SHIFTED;  // z = P_c K r
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   const int K = S->hb.npw_pad;
@@ -790,9 +797,9 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       const int nsteps = std::min(check_every, max_inner - it);
       CHECKED(run_steps(S, nsteps, use_graph && (it > 0 || outer > 0), [&]() -> int {
         CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
-        if (projected)
+        if (inner_op == STERN_INNER_PROJECTED)
           CHECKED(apply_pc32_rows(S, c32.q, F, ni));
-        else
+        else if (inner_op == STERN_INNER_SHIFTED)
           CHECKED(apply_psi32_rows(S, c32.p, c32.q, F, ni, (float)S->alpha_pv));
         CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 7.0, 0.0,
                       [&] { launch_cg32_alpha(c32, F, ni, inner_tol * inner_tol, st); }));
@@ -1172,6 +1179,8 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->precision != STERN_FP64 && opts->precision != STERN_MIXED)
     return fail(STERN_ERR_INVALID_ARG, "precision must be STERN_FP64 or STERN_MIXED");
   if (opts->inner_tol < 0 || opts->max_outer < 0) return fail(STERN_ERR_INVALID_ARG, "bad inner_tol / max_outer");
+  if (opts->inner_op < STERN_INNER_PROJECTED || opts->inner_op > STERN_INNER_SHIFTED)
+    return fail(STERN_ERR_INVALID_ARG, "inner_op %d is not one of STERN_INNER_*", opts->inner_op);
   if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED && opts->guess != STERN_GUESS_LEARNED_K)
     return fail(STERN_ERR_INVALID_ARG, "guess must be STERN_GUESS_ZERO, STERN_GUESS_LEARNED or STERN_GUESS_LEARNED_K");
   if (opts->guess != STERN_GUESS_ZERO) {
@@ -1260,7 +1269,7 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     for (int s = 0; s < ns; ++s) all[s] = s;
     if (opts->precision == STERN_MIXED) {
       CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
-                        use_graph, opts->inner_shifted == 0));
+                        use_graph, opts->inner_op));
     } else {
       CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph, with_x0));
       if (guess) {  // solves the learned start did not bring below tol: Teter-PCG from zero

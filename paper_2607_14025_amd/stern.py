@@ -21,6 +21,9 @@ STERN_MIXED = 1
 STERN_GUESS_ZERO = 0
 STERN_GUESS_LEARNED = 1
 STERN_GUESS_LEARNED_K = 2
+STERN_INNER_PROJECTED = 0
+STERN_INNER_INVARIANT = 1
+STERN_INNER_SHIFTED = 2
 STERN_MEM_HOST = 0
 STERN_MEM_DEVICE = 1
 
@@ -60,7 +63,7 @@ class Opts(C.Structure):
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
                 ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int), ("use_graph", C.c_int), ("model", C.c_void_p),
-                ("inner_shifted", C.c_int)]
+                ("inner_op", C.c_int)]
 
 
 NKERNEL = 17
@@ -176,14 +179,14 @@ def _torch_stream():
 
 
 def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
-              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False, prec_only=False):
+              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False):
     o = Opts()
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
     o.guess = STERN_GUESS_ZERO if model is None else (STERN_GUESS_LEARNED_K if prec_only else STERN_GUESS_LEARNED)
     o.model = None if model is None else model._h
-    o.inner_shifted = 1 if inner_shifted else 0
+    o.inner_op = int(inner_op)
     o.mem_kind = mem_kind
     o.band_begin, o.band_end = (0, 0) if band_range is None else (int(band_range[0]), int(band_range[1]))
     o.max_batch = int(max_batch)
@@ -202,7 +205,7 @@ def _kernels(st):
 
 
 def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, max_iter=0, check_every=0,
-                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_shifted=False,
+                    profile=False, inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_op=STERN_INNER_PROJECTED,
                     prec_only=False):
     """Batched apply over independent systems (stern_apply_chi0_many); returns (list of dn, info)."""
     n = len(systems)
@@ -222,7 +225,7 @@ def apply_chi0_many(systems, dvs, tol=1e-8, dn_outs=None, precision=STERN_FP64, 
     dvp = (C.c_void_p * n)(*[p[0] for p in ptrs])
     dnp = (C.c_void_p * n)(*[p[0] for p in outs])
     o = make_opts(tol, max_iter, precision, mk, None, 0, check_every, profile, inner_tol, max_outer, use_graph, model,
-                  inner_shifted, prec_only)
+                  inner_op, prec_only)
     st = Stats()
     rc = _check(lib().stern_apply_chi0_many(n, hs, npert, dvp, dnp, C.byref(o), C.byref(st)))
     info = dict(rc=rc, n_solves=st.n_solves, n_converged=st.n_converged, n_fallback=st.n_fallback,
@@ -271,7 +274,7 @@ class System:
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
                    samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False,
-                   model=None, inner_shifted=False, prec_only=False):
+                   model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned.
@@ -289,7 +292,7 @@ class System:
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
         o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
-                      use_graph, model, inner_shifted, prec_only)
+                      use_graph, model, inner_op, prec_only)
         keep = []
         sx = None
         if samples:

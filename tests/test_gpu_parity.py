@@ -152,13 +152,46 @@ def test_mixed_fallback_path(tiny_gpu):
     assert rel_l2(dn, t["ref"]["dn"][:2]).max() < 1e-6
 
 
-def test_mixed_shifted_inner_operator(tiny_gpu):
-    """The shifted inner operator H - eps + alpha P_v gives accepted solutions as the default
-    projected one does: both within the mixed bound of the oracle."""
-    from paper_2607_14025_amd import STERN_MIXED
+@pytest.mark.parametrize("op", ["invariant", "projected", "shifted"])
+def test_mixed_inner_operators(tiny_gpu, op):
+    """Every inner operator of the mixed solve gives accepted solutions within the mixed
+    bound of the oracle; the invariant one takes the projected one's iterations up to
+    rounding (for exact eigenpairs the two are the same iteration)."""
+    import paper_2607_14025_amd as P
     t = tiny_gpu
-    a, ia = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED, inner_shifted=True)
-    b, ib = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED)
-    for dn, info in ((a, ia), (b, ib)):
-        assert info["n_converged"] == 128 and info["max_true_resid"] <= 1e-10
-        assert rel_l2(dn, t["ref"]["dn"]).max() < 1e-6
+    code = {"invariant": P.STERN_INNER_INVARIANT, "projected": P.STERN_INNER_PROJECTED,
+            "shifted": P.STERN_INNER_SHIFTED}[op]
+    dn, info = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=P.STERN_MIXED, inner_op=code)
+    assert info["n_converged"] == 128 and info["max_true_resid"] <= 1e-10 and info["n_fallback"] == 0
+    assert rel_l2(dn, t["ref"]["dn"]).max() < 1e-6
+    if op == "invariant":
+        _, ip = t["sys"].apply_chi0(t["dv"], tol=1e-10, precision=P.STERN_MIXED, inner_op=P.STERN_INNER_PROJECTED)
+        print("iterations", op, info["total_iters"], "projected", ip["total_iters"])
+        assert abs(info["total_iters"] - ip["total_iters"]) <= 0.02 * ip["total_iters"]
+
+
+def test_bad_inner_operator_is_refused(tiny_gpu):
+    from paper_2607_14025_amd import STERN_MIXED, SternError
+    with pytest.raises(SternError):
+        tiny_gpu["sys"].apply_chi0(tiny_gpu["dv"][:1], tol=1e-10, precision=STERN_MIXED, inner_op=7)
+
+def test_mixed_without_atoms(torch_cuda):
+    """Free electrons (no atoms, V = 0, the top band a degenerate shell): no KB GEMMs run,
+    and every inner operator meets the oracle."""
+    import paper_2607_14025_amd as P
+    from synth.cells import random_dv
+    from synth.ground import ground_state
+    spec = CellSpec("free_L10_10Ry", 7, 10.0, 10.0, 0, 7, 4)
+    gs = ground_state(spec)
+    cell = OracleCell(spec.L, spec.ecut, gs["pos"])
+    _, _, dv = random_dv(spec)
+    ref = apply_chi0(cell, cell.take(gs["psi"], gs["miller"]), gs["eps"], dv, tol=1e-12)
+    s = _system(spec, gs["pos"], torch_cuda)
+    s.set_occupied(gs["psi"], gs["eps"])
+    try:
+        for op in (P.STERN_INNER_INVARIANT, P.STERN_INNER_PROJECTED, P.STERN_INNER_SHIFTED):
+            dn, info = s.apply_chi0(dv, tol=1e-10, precision=P.STERN_MIXED, inner_op=op)
+            assert info["n_converged"] == 28 and info["max_true_resid"] <= 1e-10
+            assert rel_l2(dn, ref["dn"]).max() < 1e-6
+    finally:
+        s.close()
