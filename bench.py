@@ -95,8 +95,7 @@ def main():
 
     import numpy as np
     import torch
-    from paper_2607_14025_amd import (Model, System, STERN_FP64, STERN_MIXED, STERN_INNER_PROJECTED,
-                                      STERN_INNER_INVARIANT)
+    from paper_2607_14025_amd import Model, System, STERN_FP64, STERN_MIXED, STERN_INNER_PROJECTED
     from synth.cells import MID
     from synth.inputs import load_workload
 
@@ -187,10 +186,9 @@ def main():
     torch.cuda.synchronize()
     plain = run(STERN_FP64, args.steps, args.warmup, "fp64")
     head = plain
-    mixed = mixed_inv = learned = learned_fp64 = learned_k = None
+    mixed = learned = learned_fp64 = learned_k = None
     if args.path in ("mixed", "learned-mixed"):
         mixed = run(STERN_MIXED, args.steps, args.warmup, "mixed")
-        mixed_inv = run(STERN_MIXED, args.steps, args.warmup, "mixed-invariant", inner_op=STERN_INNER_INVARIANT)
         head = mixed
     if args.path == "learned-mixed":
         learned_fp64 = run(STERN_FP64, args.steps, args.warmup, "learned-fp64", model)
@@ -236,9 +234,6 @@ def main():
         cfg.update(path="FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction (fallback: FP64 PCG)",
                    mixed=dict(solves_per_s=mixed["value"], mean_inner_iters=mixed["iters"],
                               fallback_solves=mixed["fallback"], dn_rel_err_vs_fp64=mixed["dn_rel_err_vs_fp64"]),
-                   mixed_invariant_teter=dict(solves_per_s=mixed_inv["value"], mean_inner_iters=mixed_inv["iters"],
-                                              fallback_solves=mixed_inv["fallback"],
-                                              dn_rel_err_vs_fp64=mixed_inv["dn_rel_err_vs_fp64"]),
                    speedup_vs_plain_fp64=mixed["value"] / plain["value"])
         dtype = "f32+bf16/f64"
     if learned is not None:

@@ -127,24 +127,14 @@ typedef struct {
    residual always uses P_c (H - eps_v) P_c, so the choice changes only how many
    inner iterations a solve takes and what each costs, never which solutions
    are accepted.
-   PROJECTED: q = P_c (H - eps_v) p and z = P_c K r, three split-BF16 GEMM
-     pairs per iteration (KB projectors, P_c q, P_c z). Robust for any K.
-   INVARIANT: q = (H - eps_v) p and z = P_c K r, two pairs per iteration. When
-     the psi_v, eps_v are eigenpairs of H (the assumption of the linear-response
-     equations, Sec. 2), span(Psi) is invariant under H, so (H - eps_v) p is in
-     range(P_c) for p in range(P_c) and is not projected again. The rounding
-     of the FP32 H apply and of the BF16 P_c z leaves small components in
-     span(Psi) that accumulate in r and reach z through P_c K Psi: with Teter's
-     K, nearly constant on the occupied states, the iterations equal
-     PROJECTED's (6% faster on the mid cell); with a learned K some solves
-     stall until max_iter. Meant for Teter's K only.
+   PROJECTED: q = P_c (H - eps_v) p and z = P_c K r; the projection of z and
+     the direction update p = P_c z + beta p share one split-BF16 GEMM pair.
    SHIFTED: H - eps_v + alpha P_v (alpha = twice the occupied band width, at
-     least 0.01 Ha; Baroni et al., Rev. Mod. Phys. 73, 515 (2001)); two pairs
-     per iteration, but with Teter's K, which does not commute with P_v, about
-     twice the iterations on the mid cell. */
+     least 0.01 Ha; Baroni et al., Rev. Mod. Phys. 73, 515 (2001)) and z = K r;
+     fewer GEMMs per iteration, but with Teter's K, which does not commute with
+     P_v, more than twice the iterations on the mid cell. */
 #define STERN_INNER_PROJECTED 0
-#define STERN_INNER_INVARIANT 1
-#define STERN_INNER_SHIFTED 2
+#define STERN_INNER_SHIFTED 1
 
 /* kernel classes of the per-launch profile */
 #define STERN_K_XINV 0        /* x pencils, inverse (sphere -> pencils) */

@@ -301,6 +301,10 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_init2(Cg32State S, const in
   if (threadIdx.x == 0) S.rz[s] = rz;
 }
 
+// alpha = (r, z) / (p, q); d += alpha p; r -= alpha q; z = K r; the new (r, z)
+// and beta = (r, z) new / old for the direction update that follows; inner
+// flag 1 once ||r||^2 <= tol2 ||r0||^2. (r, z) is taken with z before any
+// projection: r stays in range(P_c), so it equals (r, P_c z).
 __global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const int* __restrict__ act, double tol2) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
@@ -312,9 +316,10 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const in
     pq += (double)p.re * q.re + (double)p.im * q.im;
   }
   pq = block_sum(pq, sh);
-  const float alpha = (float)((pq > 0.0) ? S.rz[s] / pq : 0.0);
+  const double rz_old = S.rz[s];
+  const float alpha = (float)((pq > 0.0) ? rz_old / pq : 0.0);
   const double iT = S.invT[s];
-  double rr = 0.0;
+  double rr = 0.0, rz = 0.0;
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
     const Z32 p = S.p[o + k], q = S.q[o + k];
     Z32 d = S.d[o + k], r = S.r[o + k];
@@ -324,32 +329,30 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const in
     S.r[o + k] = r;
     rr += (double)r.re * r.re + (double)r.im * r.im;
     const float t = (float)precond(S, s, k, iT);
-    S.z[o + k] = zmk(r.re * t, r.im * t);
+    const Z32 z = zmk(r.re * t, r.im * t);
+    S.z[o + k] = z;
+    rz += (double)r.re * z.re + (double)r.im * z.im;
   }
   rr = block_sum(rr, sh);
+  rz = block_sum(rz, sh);
   if (threadIdx.x == 0) {
     S.iters[s] += 1;
     if (rr <= tol2 * S.rr0[s] || !(pq > 0.0)) S.flag[s] = 1;
+    S.beta[s] = rz_old != 0.0 ? rz / rz_old : 0.0;
+    S.rz[s] = rz;
   }
 }
 
+// p = z + beta p (beta from the alpha step)
 __global__ __launch_bounds__(kCgThreads) void k_cg32_beta(Cg32State S, const int* __restrict__ act) {
-  __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
-  double rz = 0.0;
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z32 r = S.r[o + k], z = S.z[o + k];
-    rz += (double)r.re * z.re + (double)r.im * z.im;
-  }
-  rz = block_sum(rz, sh);
-  const float beta = (float)(rz / S.rz[s]);
+  const float beta = (float)S.beta[s];
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
     const Z32 z = S.z[o + k], p = S.p[o + k];
     S.p[o + k] = zmk(z.re + beta * p.re, z.im + beta * p.im);
   }
-  if (threadIdx.x == 0) S.rz[s] = rz;
 }
 
 // x64 += d32

@@ -223,16 +223,19 @@ __device__ __forceinline__ bf16x8 swap_b(bf16x8 c) {
 }
 
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m], A given transposed (AT [K][2 M_pad]
-// hi/lo) and C as k_sum_split writes it. 8 waves: wave (wk, wn) owns rows
+// hi/lo) and C as k_sum_split writes it. PUPD: Y is left as it is and the sum
+// goes into the search direction instead, P[s] = (Y[s] + A C) + beta[s] P[s]
+// (s = yidx[n]), the CG direction update from the projected z. 8 waves: wave (wk, wn) owns rows
 // [16 KB wk, 16 KB (wk + 1)) and columns [64 wn, 64 wn + 64) of the
 // (64 KB) x 128 tile; KB = 4 (256 x 128, 1 workgroup per CU) or 2 (128 x 128,
 // fewer registers, 2 workgroups per CU, so one's Y update overlaps another's
 // products). Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
-template <int KB>
+template <int KB, bool PUPD>
 __global__ __launch_bounds__(kThreads8, KB == 4 ? 2 : 4) void k_expand_bf16s(const __bf16* __restrict__ ATh,
                                                             const __bf16* __restrict__ ATl, int M_pad, int K,
                                                             const __bf16* __restrict__ Cs, Z32* __restrict__ Y,
-                                                            int ldy, const int* __restrict__ yidx, int ncols) {
+                                                            int ldy, const int* __restrict__ yidx, int ncols,
+                                                            Z32* __restrict__ P, const double* __restrict__ beta) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int wk = wave & 3, wn = wave >> 2;
@@ -289,7 +292,10 @@ __global__ __launch_bounds__(kThreads8, KB == 4 ? 2 : 4) void k_expand_bf16s(con
 #pragma unroll
   for (int bj = 0; bj < 4; ++bj) {
     if (!nv[bj]) continue;
-    Z32* y = Y + (size_t)(yidx ? yidx[nn[bj]] : nn[bj]) * ldy;
+    const size_t row = (size_t)(yidx ? yidx[nn[bj]] : nn[bj]);
+    Z32* y = Y + row * ldy;
+    float bt = 0.f;
+    if constexpr (PUPD) bt = (float)beta[row];
 #pragma unroll
     for (int bi = 0; bi < KB; ++bi) {
       float4* p = reinterpret_cast<float4*>(y + k0 + 16 * bi + 4 * g);
@@ -302,16 +308,24 @@ __global__ __launch_bounds__(kThreads8, KB == 4 ? 2 : 4) void k_expand_bf16s(con
       w.y += dim_[bi][bj][2];
       w.z += dre[bi][bj][3];
       w.w += dim_[bi][bj][3];
-      p[0] = u;
-      p[1] = w;
+      if constexpr (PUPD) {
+        float4* d = reinterpret_cast<float4*>(P + row * ldy + k0 + 16 * bi + 4 * g);
+        const float4 a = d[0], c = d[1];
+        d[0] = make_float4(u.x + bt * a.x, u.y + bt * a.y, u.z + bt * a.z, u.w + bt * a.w);
+        d[1] = make_float4(w.x + bt * c.x, w.y + bt * c.y, w.z + bt * c.z, w.w + bt * c.w);
+      } else {
+        p[0] = u;
+        p[1] = w;
+      }
     }
   }
 }
 
-// hi/lo split of complex double rows [M][K] into row layout [M][2K] and the
-// transposed layout [K][2 M] (both interleaved re, im)
-__global__ void k_split_rows(const Z64* __restrict__ A, int M, int K, __bf16* __restrict__ hi, __bf16* __restrict__ lo,
-                             __bf16* __restrict__ thi, __bf16* __restrict__ tlo) {
+// hi/lo split of complex double rows [M][K] into rows [row0, row0 + M) of a
+// matrix of Mt rows, in row layout [Mt][2K] (skipped when hi is null) and
+// transposed layout [K][2 Mt] (both interleaved re, im)
+__global__ void k_split_rows(const Z64* __restrict__ A, int M, int K, int row0, int Mt, __bf16* __restrict__ hi,
+                             __bf16* __restrict__ lo, __bf16* __restrict__ thi, __bf16* __restrict__ tlo) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (size_t)M * K) return;
   const int m = (int)(i / K), k = (int)(i - (size_t)m * K);
@@ -320,15 +334,65 @@ __global__ void k_split_rows(const Z64* __restrict__ A, int M, int K, __bf16* __
   const __bf16 hr = (__bf16)re, hm = (__bf16)im;
   const __bf16 lr = (__bf16)(float)(v.re - (double)(float)hr);
   const __bf16 lm = (__bf16)(float)(v.im - (double)(float)hm);
-  hi[2 * i] = hr;
-  hi[2 * i + 1] = hm;
-  lo[2 * i] = lr;
-  lo[2 * i + 1] = lm;
-  const size_t t = (size_t)k * 2 * M + 2 * m;
+  if (hi) {
+    const size_t r = ((size_t)(row0 + m) * K + k) * 2;
+    hi[r] = hr;
+    hi[r + 1] = hm;
+    lo[r] = lr;
+    lo[r + 1] = lm;
+  }
+  const size_t t = (size_t)k * 2 * Mt + 2 * (row0 + m);
   thi[t] = hr;
   thi[t + 1] = hm;
   tlo[t] = lr;
   tlo[t + 1] = lm;
+}
+
+__device__ __forceinline__ void put_split(__bf16* __restrict__ Cs, size_t plane, size_t i, float re, float im) {
+  const __bf16 rh = (__bf16)re, ih = (__bf16)im;
+  Cs[2 * i] = rh;
+  Cs[2 * i + 1] = ih;
+  Cs[plane + 2 * i] = (__bf16)(re - (float)rh);
+  Cs[plane + 2 * i + 1] = (__bf16)(im - (float)ih);
+}
+
+// Coefficients of (H - eps) p projected, for one expand over the stacked rows
+// [KB (Ma rows); Psi (Mb rows)], from the split partials of c_a = <beta_a|p>
+// and of <psi_b|q_loc>, q_loc the local part of (H - eps) p:
+//   rows a: D c_a;  rows Ma + b: -(<psi_b|q_loc> + sum_a G[a][b] D c_a),
+// G[a][b] = <psi_b|beta_a>, so that the Psi rows remove Psi^H of the whole
+// (H - eps) p. One workgroup per column n; output as k_sum_split writes it
+// for M_pad = Ma + Mb.
+__global__ void k_sum_proj(const Z32* __restrict__ cp_a, int ns_a, const Z32* __restrict__ cp_b, int ns_b,
+                           int ncols, int Ma, int Mb, float D, const Z32* __restrict__ G, __bf16* __restrict__ Cs) {
+  extern __shared__ Z32 ca[];
+  const int n = blockIdx.x, Mt = Ma + Mb;
+  const size_t plane = (size_t)ncols * Mt * 2, row = (size_t)n * Mt;
+  for (int a = threadIdx.x; a < Ma; a += blockDim.x) {
+    float re = 0.f, im = 0.f;
+    for (int s = 0; s < ns_a; ++s) {
+      const Z32 v = cp_a[((size_t)s * ncols + n) * Ma + a];
+      re += v.re;
+      im += v.im;
+    }
+    ca[a] = zmk(D * re, D * im);
+    put_split(Cs, plane, row + a, D * re, D * im);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < Mb; b += blockDim.x) {
+    float re = 0.f, im = 0.f;
+    for (int s = 0; s < ns_b; ++s) {
+      const Z32 v = cp_b[((size_t)s * ncols + n) * Mb + b];
+      re += v.re;
+      im += v.im;
+    }
+    for (int a = 0; a < Ma; ++a) {
+      const Z32 g = G[(size_t)a * Mb + b], c = ca[a];
+      re += g.re * c.re - g.im * c.im;
+      im += g.re * c.im + g.im * c.re;
+    }
+    put_split(Cs, plane, row + Ma + b, -re, -im);
+  }
 }
 
 }  // namespace
@@ -344,9 +408,20 @@ int choose_nsplit_bf16(int M_pad, int ncols, int K, int target) {
 }
 
 void launch_split_bf16(const Z64* A, int M, int K, __bf16* hi, __bf16* lo, __bf16* thi, __bf16* tlo, hipStream_t st) {
+  launch_split_bf16_rows(A, M, K, 0, M, hi, lo, thi, tlo, st);
+}
+
+void launch_split_bf16_rows(const Z64* A, int M, int K, int row0, int Mt, __bf16* hi, __bf16* lo, __bf16* thi,
+                            __bf16* tlo, hipStream_t st) {
   const size_t n = (size_t)M * K;
   if (n == 0) return;
-  k_split_rows<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(A, M, K, hi, lo, thi, tlo);
+  k_split_rows<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(A, M, K, row0, Mt, hi, lo, thi, tlo);
+}
+
+void launch_sum_proj32(const Z32* cp_a, int ns_a, const Z32* cp_b, int ns_b, int ncols, int Ma, int Mb, float D,
+                       const Z32* G, __bf16* Cs, hipStream_t st) {
+  if (ncols <= 0) return;
+  k_sum_proj<<<ncols, 256, (size_t)Ma * sizeof(Z32), st>>>(cp_a, ns_a, cp_b, ns_b, ncols, Ma, Mb, D, G, Cs);
 }
 
 void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,
@@ -366,15 +441,17 @@ void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, floa
 }
 
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
-                        const int* yidx, int ncols, int K, int variant, hipStream_t st) {
+                        const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P, const double* beta) {
   if (ncols <= 0) return;
-  if (variant == 1) {
-    dim3 grid((K + 127) / 128, (ncols + kEN - 1) / kEN);
-    k_expand_bf16s<2><<<grid, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols);
-  } else {
-    dim3 grid((K + kET - 1) / kET, (ncols + kEN - 1) / kEN);
-    k_expand_bf16s<4><<<grid, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols);
-  }
+  const dim3 g2((K + 127) / 128, (ncols + kEN - 1) / kEN), g4((K + kET - 1) / kET, (ncols + kEN - 1) / kEN);
+  if (variant == 1 && P)
+    k_expand_bf16s<2, true><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+  else if (variant == 1)
+    k_expand_bf16s<2, false><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+  else if (P)
+    k_expand_bf16s<4, true><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+  else
+    k_expand_bf16s<4, false><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
 }
 
 }  // namespace stern

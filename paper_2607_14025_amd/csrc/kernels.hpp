@@ -147,7 +147,7 @@ void launch_plane_full_fwd(const FftGeom& g, const Z64* in, int nvec, Z64* pen, 
 // ---- mixed precision (FP32 vectors, BF16 MFMA GEMMs, FP64 scalars) ----
 struct Cg32State {
   Z32 *d, *r, *p, *q, *z;      // [nbatch][npw_pad]
-  double *rz, *rr0;            // [nbatch]
+  double *rz, *rr0, *beta;     // [nbatch]; beta = (r, z) new / old, set with rz by the alpha step
   int* flag;                   // inner: 0 active, 1 reached the inner tolerance, 2 nothing to do
   int* iters;
   const double* invT;
@@ -167,14 +167,23 @@ void launch_fill_zero32(Z32* p, size_t n, hipStream_t st);
 int choose_nsplit_bf16(int M_pad, int ncols, int K, int target);
 // hi/lo BF16 split of complex rows A [M][K] into [M][2K] and transposed [K][2M] layouts
 void launch_split_bf16(const Z64* A, int M, int K, __bf16* hi, __bf16* lo, __bf16* thi, __bf16* tlo, hipStream_t st);
+// the same into rows [row0, row0 + M) of a split matrix of Mt rows (row layout skipped when hi is null)
+void launch_split_bf16_rows(const Z64* A, int M, int K, int row0, int Mt, __bf16* hi, __bf16* lo, __bf16* thi,
+                            __bf16* tlo, hipStream_t st);
+// coefficients of the projected (H - eps) p over the stacked rows [KB (Ma); Psi (Mb)]:
+// rows a: D <beta_a|p>; rows Ma + b: -(<psi_b|q_loc> + sum_a G[a][b] D <beta_a|p>), G[a][b] = <psi_b|beta_a>
+void launch_sum_proj32(const Z32* cp_a, int ns_a, const Z32* cp_b, int ns_b, int ncols, int Ma, int Mb, float D,
+                       const Z32* G, __bf16* Cs, hipStream_t st);
 // C[n][m] partial = sum_k conj(A[m][k]) X[xidx[n]][k] (BF16 split operands, FP32 accumulation)
 void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,
                         int ncols, int K, Z32* cpart, int nsplit, hipStream_t st);
 void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
                         hipStream_t st);
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A
-// Y += A C for the split-BF16 operands; variant 0: 256 x 128 tiles, 1: 128 x 128 tiles
+// Y += A C for the split-BF16 operands; variant 0: 256 x 128 tiles, 1: 128 x 128 tiles.
+// With P: Y is not written, P[s] = (Y[s] + A C) + beta[s] P[s] for s = yidx[n] instead.
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
-                        const int* yidx, int ncols, int K, int variant, hipStream_t st);
+                        const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P = nullptr,
+                        const double* beta = nullptr);
 
 }  // namespace stern

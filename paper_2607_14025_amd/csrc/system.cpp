@@ -109,10 +109,14 @@ struct stern_system {
   DBuf psi, psi_r;
   // split BF16 copies of Psi and of the KB rows (row and transposed layouts)
   DBuf psi_hi, psi_lo, psiT_hi, psiT_lo, kb_hi, kb_lo, kbT_hi, kbT_lo;
+  // projected FP32 operator: transposed split of the stacked rows [KB (natoms_pad); Psi (nocc_pad)]
+  // and G[a][b] = <psi_b|beta_a> (FP32, [natoms_pad][nocc_pad]); proj_m = 0 without atoms
+  DBuf projT_hi, projT_lo, proj_g;
+  int proj_m = 0;
   // workspace
-  DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
+  DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cpart2, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
       sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
-  DBuf m_d, m_r, m_p, m_q, m_z, m_rz, m_rr0, m_flag;  // mixed inner solve
+  DBuf m_d, m_r, m_p, m_q, m_z, m_rz, m_rr0, m_beta, m_flag;  // mixed inner solve
   // coarse (N/2)^3 grid of the learned guess, when it holds the sphere
   bool have_coarse = false;
   HostBasis hbc;
@@ -183,11 +187,11 @@ struct stern_system {
                    &pen,       &cpart,    &cmat,     &sv_eps,  &sv_invT,  &sv_band, &sv_pert,  &sv_bb,    &sv_rz,
                    &sv_rr,     &sv_flag,  &sv_iters, &sv_tres, &list_act, &list_f,  &pert_out, &dv_dev,   &dn_dev,
                    &tmp_in,    &tmp_out,  &psi_hi,  &psi_lo,   &psiT_hi, &psiT_lo,  &kb_hi,    &kb_lo,
-                   &kbT_hi,    &kbT_lo,   &m_d,     &m_r,      &m_p,     &m_q,      &m_z,      &m_rz,
+                   &kbT_hi,    &kbT_lo,   &m_d,     &m_r,      &m_p,     &m_q,      &m_z,      &m_rz,  &m_beta,
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
-                   &band_feat};
+                   &band_feat, &projT_hi, &projT_lo, &proj_g, &cpart2};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -333,6 +337,77 @@ int apply_psi32_rows(stern_system* S, const Z32* X, Z32* Y, const int* list, int
   return 0;
 }
 
+// p = P_c z + beta p on rows `list` (FP32 rows, split-BF16 MFMA): the projection
+// of z and the CG direction update in one reduce and one expand; z is left as it is
+int apply_pc32_update(stern_system* S, const Z32* Z, Z32* P, const double* beta, const int* list, int n) {
+  if (n <= 0) return 0;
+  const int K = S->hb.npw_pad;
+  const double npw = S->hb.npw, m = S->n_occ;
+  const int ns = choose_nsplit_bf16(S->nocc_pad, n, K, S->gemm16_wg);
+  Z32* cp = S->cpart.as<Z32>();
+  __bf16* cm = S->cmat.as<__bf16>();
+  CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (n + m), 8.0 * m * npw * n, [&] {
+    launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, Z, K, list, n, K, cp, ns,
+                       S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_SUM_PARTS, 8.0 * m * n * (ns + 1), 0.0,
+                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, -1.f, cm, S->stream); }));
+  CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (3.0 * n + m), 8.0 * m * npw * n, [&] {
+    launch_expand_bf16(S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), S->nocc_pad, cm, const_cast<Z32*>(Z), K,
+                       list, n, K, S->gemm16_expand, S->stream, P, beta);
+  }));
+  return 0;
+}
+
+// out = P_c (H - eps_s) in for FP32 rows: FP32 FFTs, then one split-BF16 expand
+// over the stacked rows [KB; Psi] that adds the KB term and removes Psi^H of
+// the whole product. Psi^H of the KB term is G^T D <beta|in> with the
+// precomputed G = <psi_b|beta_a>, so the two reduces (KB rows against `in`,
+// Psi against the local part) are independent of each other.
+int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, int n, const double* eps_rows);
+int apply_hproj32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, int n, const double* eps_rows) {
+  if (n <= 0) return 0;
+  if (S->proj_m == 0) {  // no atoms: local part, then P_c
+    CHECKED(apply_h32_rows(S, in, out, list, n, eps_rows));
+    return apply_pc32_rows(S, out, list, n);
+  }
+  const FftGeom g = S->geom();
+  const int K = S->hb.npw_pad;
+  const double zb = sizeof(Z32), npw = S->hb.npw, N = S->hb.N, pen = N * S->hb.ncol * zb;
+  const double na = S->n_atoms, m = S->n_occ;
+  Z32* pen32 = S->pen.as<Z32>();
+  CHECKED(timed(S, STERN_K_X32, n * (npw * zb + pen), 0.0,
+                [&] { launch_xinv<float>(g, in, list, n, pen32, S->stream); }));
+  CHECKED(timed(S, STERN_K_PLANE_H32, n * 2.0 * pen + N * N * N * sizeof(float), n * plane_flops(S),
+                [&] {
+                  if (S->plane_var32 >= 1)
+                    launch_plane_hw<float>(g, pen32, list, n, S->v_t32.as<float>(), S->plane_var32 == 2, S->stream);
+                  else
+                    launch_plane_vloc<float>(g, pen32, list, n, S->v_r32.as<float>(), S->stream);
+                }));
+  CHECKED(timed(S, STERN_K_X32, n * (pen + 2.0 * npw * zb), 0.0,
+                [&] { launch_xfwd<float>(g, pen32, list, n, out, 1, in, eps_rows, 0.0, S->stream); }));
+  const int Ma = S->natoms_pad, Mb = S->nocc_pad;
+  const int ns_a = choose_nsplit_bf16(Ma, n, K, S->gemm16_wg), ns_b = choose_nsplit_bf16(Mb, n, K, S->gemm16_wg);
+  Z32 *cpa = S->cpart.as<Z32>(), *cpb = S->cpart2.as<Z32>();
+  __bf16* cm = S->cmat.as<__bf16>();
+  CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
+    launch_reduce_bf16(S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(), Ma, in, K, list, n, K, cpa, ns_a, S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + m), 8.0 * m * npw * n, [&] {
+    launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), Mb, out, K, list, n, K, cpb, ns_b,
+                       S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_SUM_PARTS, zb * n * (na * (ns_a + 1) + m * (ns_b + 1)), 8.0 * n * na * m, [&] {
+    launch_sum_proj32(cpa, ns_a, cpb, ns_b, n, Ma, Mb, (float)S->cell.D, S->proj_g.as<Z32>(), cm, S->stream);
+  }));
+  CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (2.0 * n + na + m), 8.0 * (na + m) * npw * n, [&] {
+    launch_expand_bf16(S->projT_hi.as<__bf16>(), S->projT_lo.as<__bf16>(), S->proj_m, cm, out, K, list, n, K,
+                       S->gemm16_expand, S->stream);
+  }));
+  return 0;
+}
+
 // out = (H - eps_s) in for FP32 rows: FP32 FFTs, BF16 KB projectors
 int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, int n, const double* eps_rows) {
   if (n <= 0) return 0;
@@ -391,6 +466,7 @@ int ensure_workspace(stern_system* S, int ns) {
   CHECKED(S->cpart.ensure(std::max(cpart_capacity(S, std::max(S->nocc_pad, 64), ns, (int)K),
                                    cpart_capacity(S, S->natoms_pad, ns, (int)K))));
   CHECKED(S->cmat.ensure((size_t)ns * mp * sizeof(Z64)));
+  CHECKED(S->cpart2.ensure(cpart_capacity(S, std::max(S->nocc_pad, 64), ns, (int)K)));
   for (DBuf* d : {&S->sv_eps, &S->sv_invT, &S->sv_bb, &S->sv_rz, &S->sv_rr, &S->sv_tres})
     CHECKED(d->ensure((size_t)ns * sizeof(double)));
   for (DBuf* d : {&S->sv_band, &S->sv_pert, &S->sv_flag, &S->sv_iters, &S->list_act, &S->list_f})
@@ -407,7 +483,7 @@ int ensure_workspace(stern_system* S, int ns) {
 int ensure_workspace32(stern_system* S, int ns) {
   const size_t K = S->hb.npw_pad;
   for (DBuf* d : {&S->m_d, &S->m_r, &S->m_p, &S->m_q, &S->m_z}) CHECKED(d->ensure((size_t)ns * K * sizeof(Z32)));
-  for (DBuf* d : {&S->m_rz, &S->m_rr0}) CHECKED(d->ensure((size_t)ns * sizeof(double)));
+  for (DBuf* d : {&S->m_rz, &S->m_rr0, &S->m_beta}) CHECKED(d->ensure((size_t)ns * sizeof(double)));
   CHECKED(S->m_flag.ensure((size_t)ns * sizeof(int)));
   if (S->ws32_solves < ns) {
     for (DBuf* d : {&S->m_d, &S->m_r, &S->m_p, &S->m_q, &S->m_z})
@@ -426,6 +502,7 @@ Cg32State cg32_state(stern_system* S, int* iters) {
   c.z = S->m_z.as<Z32>();
   c.rz = S->m_rz.as<double>();
   c.rr0 = S->m_rr0.as<double>();
+  c.beta = S->m_beta.as<double>();
   c.flag = S->m_flag.as<int>();
   c.iters = iters;
   c.invT = S->sv_invT.as<double>();
@@ -746,24 +823,21 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
 //   until ||r|| <= tol ||b||; solves still above tol after max_outer steps are
 //   re-solved by FP64 PCG from zero.
 // Inner operators (inner_op):
-//  projected: q = P_c (H - eps) p and z = P_c K r.
-//  invariant: q = (H - eps) p and z = P_c K r. With p in range(P_c) and Psi an
-//    invariant subspace of H, (H - eps) p lies in range(P_c) in exact
-//    arithmetic, so the projection of q is left out. What the FP32 H apply and
-//    the BF16 projection of z leave in span(Psi) then stays in r, and K carries
-//    it back into z through P_c K Psi: harmless when K is nearly constant on
-//    the occupied states (Teter's), a stall when it is not (a learned K).
+//  projected: q = P_c (H - eps) p and z = P_c K r. The alpha step takes the new
+//    (r, z) before z is projected, which equals (r, P_c z) as r stays in
+//    range(P_c); so beta is known before the projection, and the projection
+//    of z and p = P_c z + beta p run as one GEMM pair.
 //  shifted: H - eps + alpha P_v (Baroni et al., Rev. Mod. Phys. 73, 515 (2001)),
-//    positive definite for alpha above the occupied band width. On range(P_c)
-//    it agrees with the projected operator up to the commutator of H with P_v;
-//    with Teter's K, which does not commute with P_v, it takes about twice the
-//    inner iterations.
+//    positive definite for alpha above the occupied band width, and z = K r.
+//    On range(P_c) it agrees with the projected operator up to the commutator
+//    of H with P_v; with Teter's K, which does not commute with P_v, it takes
+//    more than twice the inner iterations.
 // The FP64 outer residual uses the projected operator, so the accepted
 // solution is the projected system's whichever operator runs inside.
 int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, double tol, double inner_tol,
               int max_outer, int max_iter, int check_every, int& n_restart, int& n_fallback, double vecb,
               bool use_graph, int inner_op) {
-  const bool projected = inner_op != STERN_INNER_SHIFTED;  // z = P_c K r
+  const bool projected = inner_op == STERN_INNER_PROJECTED;
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   const int K = S->hb.npw_pad;
@@ -796,15 +870,18 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       const int* F = S->list_f.as<int>();
       const int nsteps = std::min(check_every, max_inner - it);
       CHECKED(run_steps(S, nsteps, use_graph && (it > 0 || outer > 0), [&]() -> int {
-        CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
-        if (inner_op == STERN_INNER_PROJECTED)
-          CHECKED(apply_pc32_rows(S, c32.q, F, ni));
-        else if (inner_op == STERN_INNER_SHIFTED)
+        if (projected) {
+          CHECKED(apply_hproj32_rows(S, c32.p, c32.q, F, ni, cs.eps));
+        } else {
+          CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
           CHECKED(apply_psi32_rows(S, c32.p, c32.q, F, ni, (float)S->alpha_pv));
+        }
         CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 7.0, 0.0,
                       [&] { launch_cg32_alpha(c32, F, ni, inner_tol * inner_tol, st); }));
-        if (projected) CHECKED(apply_pc32_rows(S, c32.z, F, ni));
-        CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 4.0, 0.0, [&] { launch_cg32_beta(c32, F, ni, st); }));
+        if (projected)  // p = P_c z + beta p
+          CHECKED(apply_pc32_update(S, c32.z, c32.p, c32.beta, F, ni));
+        else
+          CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 3.0, 0.0, [&] { launch_cg32_beta(c32, F, ni, st); }));
         return 0;
       }));
       it += nsteps;
@@ -1074,6 +1151,24 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   for (DBuf* d : {&S->psi_hi, &S->psi_lo, &S->psiT_hi, &S->psiT_lo}) CHECKED(d->ensure(psn));
   launch_split_bf16(S->psi.as<Z64>(), S->nocc_pad, K, S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(),
                     S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), st);
+  S->proj_m = 0;
+  if (S->n_atoms > 0) {  // stacked rows [KB; Psi] and G = Psi^H KB (FP64 GEMM, kept in FP32)
+    const int Ma = S->natoms_pad, Mb = S->nocc_pad, Mt = Ma + Mb;
+    const size_t tn = (size_t)Mt * K * 2 * sizeof(__bf16);
+    for (DBuf* d : {&S->projT_hi, &S->projT_lo}) CHECKED(d->ensure(tn));
+    __bf16 *th = S->projT_hi.as<__bf16>(), *tl = S->projT_lo.as<__bf16>();
+    launch_split_bf16_rows(S->kb.as<Z64>(), Ma, K, 0, Mt, nullptr, nullptr, th, tl, st);
+    launch_split_bf16_rows(S->psi.as<Z64>(), Mb, K, Ma, Mt, nullptr, nullptr, th, tl, st);
+    const int ns = choose_nsplit(Mb, Ma, K, S->gemm64_wg);
+    CHECKED(S->cpart.ensure((size_t)ns * Ma * Mb * sizeof(Z64)));
+    CHECKED(S->cmat.ensure((size_t)Ma * Mb * sizeof(Z64)));
+    CHECKED(S->proj_g.ensure((size_t)Ma * Mb * sizeof(Z32)));
+    launch_zgemm_reduce(S->psi.as<Z64>(), Mb, S->kb.as<Z64>(), K, nullptr, Ma, K, S->cpart.as<Z64>(), ns, st);
+    launch_sum_parts(S->cpart.as<Z64>(), ns, Ma, Mb, 1.0, S->cmat.as<Z64>(), st);
+    launch_to32(S->cmat.as<Z64>(), S->proj_g.as<Z32>(), (size_t)Ma * Mb, st);
+    CHECKED(launch_check());
+    S->proj_m = Mt;
+  }
   // psi_v(r) on the grid (unnormalised sum_G c_G e^{iG.r}) for the RHS and dn
   CHECKED(S->psi_r.ensure((size_t)n_occ * N * N * N * sizeof(Z64)));
   CHECKED(S->pen.ensure((size_t)n_occ * N * hb.ncol_pad * sizeof(Z64)));
@@ -1179,7 +1274,7 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->precision != STERN_FP64 && opts->precision != STERN_MIXED)
     return fail(STERN_ERR_INVALID_ARG, "precision must be STERN_FP64 or STERN_MIXED");
   if (opts->inner_tol < 0 || opts->max_outer < 0) return fail(STERN_ERR_INVALID_ARG, "bad inner_tol / max_outer");
-  if (opts->inner_op < STERN_INNER_PROJECTED || opts->inner_op > STERN_INNER_SHIFTED)
+  if (opts->inner_op != STERN_INNER_PROJECTED && opts->inner_op != STERN_INNER_SHIFTED)
     return fail(STERN_ERR_INVALID_ARG, "inner_op %d is not one of STERN_INNER_*", opts->inner_op);
   if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED && opts->guess != STERN_GUESS_LEARNED_K)
     return fail(STERN_ERR_INVALID_ARG, "guess must be STERN_GUESS_ZERO, STERN_GUESS_LEARNED or STERN_GUESS_LEARNED_K");
@@ -1621,6 +1716,7 @@ int stern_model_create(int device, unsigned long long seed, stern_model** out) {
     HIPOK(hipMemcpy(M->w.p, w.data(), np * sizeof(float), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(M->m.p, z.data(), np * sizeof(float), hipMemcpyHostToDevice));
     HIPOK(hipMemcpy(M->v.p, z.data(), np * sizeof(float), hipMemcpyHostToDevice));
+    HIPOK(hipMemcpy(M->grad.p, z.data(), np * sizeof(float), hipMemcpyHostToDevice));
     CHECKED(model_refresh_bf16(M, nullptr));
     HIPOK(hipDeviceSynchronize());
     return 0;
@@ -1807,8 +1903,8 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
       launch_relu_bwd(M->g3.as<float>(), M->a1.as<__bf16>(), nact, st);
       // layer 1 (index 0)
       launch_conv3_wgrad(M->a0.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw, Nc, nb_, st);
-      ++M->step;
-      launch_adam(M->w.as<float>(), M->m.as<float>(), M->v.as<float>(), gw, stern_model_num_params(), lr, M->step,
+      ++M->step;  // the trunk only: the head's gradient is not formed here
+      launch_adam(M->w.as<float>(), M->m.as<float>(), M->v.as<float>(), gw, stern_model::HEAD, lr, M->step,
                   1.f / (float)nb_, st);
       CHECKED(model_refresh_bf16(M, st));
       HIPOK(hipMemcpyAsync(hl.data(), M->loss.p, nb_ * sizeof(float), hipMemcpyDeviceToHost, st));

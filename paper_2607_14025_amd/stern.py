@@ -22,8 +22,7 @@ STERN_GUESS_ZERO = 0
 STERN_GUESS_LEARNED = 1
 STERN_GUESS_LEARNED_K = 2
 STERN_INNER_PROJECTED = 0
-STERN_INNER_INVARIANT = 1
-STERN_INNER_SHIFTED = 2
+STERN_INNER_SHIFTED = 1
 STERN_MEM_HOST = 0
 STERN_MEM_DEVICE = 1
 

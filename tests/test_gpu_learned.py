@@ -162,3 +162,23 @@ def test_learned_preconditioner_only(learned):
     dm, info = learned["sys"].apply_chi0(learned["dv"], tol=1e-10, model=learned["model"], prec_only=True,
                                          precision=STERN_MIXED)
     assert info["n_converged"] == 128 and rel_l2(dm, learned["ref"]["dn"]).max() < 1e-6
+
+
+def test_guess_training_leaves_the_head_alone(tiny_system):
+    """Training the guess only (prec_epochs < 0: no preconditioner stage) updates the trunk and leaves the
+    head weights exactly as they were (zero for a fresh model), whatever the device memory
+    held before: the head's gradient is not formed in that stage."""
+    from paper_2607_14025_amd import Model
+    t = tiny_system
+    s = _system(t["spec"], t["gs"])
+    m = Model(seed=3)
+    n_head = 8 * 18 + 8
+    w0 = m.get_weights()
+    assert np.all(w0[-n_head:] == 0.0)
+    m.train([s], [t["dv"]], epochs=2, batch=16, lr=1e-3, tol=1e-10, seed=1, prec_epochs=-1)
+    w1 = m.get_weights()
+    s.close()
+    m.close()
+    assert np.isfinite(w1).all()
+    assert not np.array_equal(w1[:-n_head], w0[:-n_head])
+    assert np.all(w1[-n_head:] == 0.0)
