@@ -785,6 +785,279 @@ __global__ __launch_bounds__(plane_nt<N>()) void k_plane_dn(const Z64* __restric
   }
 }
 
+// ---- FP64 full-plane transforms for grids whose plane does not fit in LDS ----
+//
+// The right-hand side, psi_v(r) and dn kernels above hold a whole N x N plane
+// in LDS. For the larger grids (108, 128) they run in the compact layout of
+// the H-apply kernel instead: only the nza active z lines of the plane sit in
+// LDS (Q[f][y]), the y transforms run wave-locally on them, and each wave
+// takes its block of rows y through the z transform ZR rows at a time via its
+// own scratch, reading or writing the full-grid row directly in HBM.
+
+// inverse y of this wave's active lines [f0, f0 + nl) from the pencils tp
+template <int N>
+__device__ __forceinline__ void cw_y_inverse(Z64* __restrict__ Q, const Z64* __restrict__ tw, const Z64* __restrict__ tp,
+                                             const int* __restrict__ yc, int nza, int nm, int f0, int nl, int lane) {
+  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2, QLD = N + 1;
+  const Z64 zero = zmk(0.0, 0.0);
+  for (int it = lane; it < nl * R2; it += 64) {
+    const int j = it % R2, f = f0 + it / R2;
+    Z64 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int y = j + r * R2;
+      v[r] = zero;
+      if (y <= nm || y >= N - nm) {
+        const int col = yc[y * nza + f];
+        if (col >= 0) v[r] = tp[col];
+      }
+    }
+    dft<R1, +1>(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) Q[f * QLD + j * R1 + r] = v[r];
+  }
+  wave_sync();
+  for (int it = lane; it < nl * R1; it += 64) {
+    const int j = it % R1, f = f0 + it / R1;
+    Z64 v[R2];
+#pragma unroll
+    for (int r = 0; r < R2; ++r) v[r] = Q[f * QLD + j + r * R1];
+#pragma unroll
+    for (int r = 1; r < R2; ++r) v[r] = v[r] * twid<+1>(tw, r * j);
+    dft<R2, +1>(v);
+#pragma unroll
+    for (int r = 0; r < R2; ++r) Q[f * QLD + j + r * R1] = v[r];
+  }
+}
+
+// forward y of this wave's active lines to the pencils tp (decimation in frequency, in place)
+template <int N>
+__device__ __forceinline__ void cw_y_forward(Z64* __restrict__ Q, const Z64* __restrict__ tw, Z64* __restrict__ tp,
+                                             const int* __restrict__ yc, int nza, int nm, int f0, int nl, int lane) {
+  constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2, QLD = N + 1;
+  for (int it = lane; it < nl * R2; it += 64) {
+    const int j = it % R2, f = f0 + it / R2;
+    Z64 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) v[r] = Q[f * QLD + j + r * R2];
+    dft<R1, -1>(v);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) v[k1] = v[k1] * twid<-1>(tw, j * k1);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) Q[f * QLD + j + k1 * R2] = v[k1];
+  }
+  wave_sync();
+  for (int it = lane; it < nl * R1; it += 64) {
+    const int k1 = it % R1, f = f0 + it / R1;
+    Z64 v[R2];
+#pragma unroll
+    for (int jj = 0; jj < R2; ++jj) v[jj] = Q[f * QLD + k1 * R2 + jj];
+    dft<R2, -1>(v);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      const int y = k2 * R1 + k1;
+      if (y <= nm || y >= N - nm) {
+        const int col = yc[y * nza + f];
+        if (col >= 0) tp[col] = v[k2];
+      }
+    }
+  }
+}
+
+template <int N>
+struct CwCfg {
+  static constexpr int W = 4;
+  static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  static constexpr int RM = R1 > R2 ? R1 : R2;
+  static constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
+  static constexpr int RPW = (N + W - 1) / W;               // rows y per wave
+  static constexpr int RND = (RPW + ZR - 1) / ZR;           // z rounds per wave
+  static constexpr int MAXZ = (ZR * RM + 63) / 64;          // items per lane in a z stage
+};
+
+// shared set-up: LDS carve-out, twiddles, this wave's lines and rows
+#define STERN_CW_SETUP                                                          \
+  using C = CwCfg<N>;                                                           \
+  constexpr int R1 = C::R1, R2 = C::R2, ZR = C::ZR, QLD = N + 1;                \
+  extern __shared__ unsigned char smem_raw[];                                   \
+  const int nza = g.nza, nm = g.zact_lo;                                        \
+  Z64* Q = reinterpret_cast<Z64*>(smem_raw);                                    \
+  Z64* tw = Q + (size_t)nza * QLD;                                              \
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;                \
+  Z64* Sw = tw + N + (size_t)wave * N * ZR;                                     \
+  for (int i = tid; i < N; i += 64 * C::W) tw[i] = g.tw64[i];                   \
+  const int lpw = (nza + C::W - 1) / C::W;                                      \
+  const int f0 = min(nza, wave * lpw), nl = min(nza, f0 + lpw) - f0;            \
+  const int y0w = min(N, wave * C::RPW), nr = min(N, y0w + C::RPW) - y0w;       \
+  (void)nr;                                                                     \
+  auto act = [nm](int i) { return i <= nm || i >= N - nm; };                    \
+  auto fz = [nm](int z) { return z <= nm ? z : z - N + 2 * nm + 1; };           \
+  (void)act;                                                                    \
+  (void)fz;                                                                     \
+  __syncthreads();
+
+// right-hand side: pencils[s] of plane ix = forward yz DFT of psi_r[band[s]] * dv[pert[s]]
+template <int N>
+__global__ __launch_bounds__(256) void k_plane_rhs_c(const Z64* __restrict__ psi_r, const double* __restrict__ dv,
+                                                    const int* __restrict__ band, const int* __restrict__ pert,
+                                                    Z64* __restrict__ pen, FftGeom g) {
+  STERN_CW_SETUP
+  const int ix = blockIdx.x, s = blockIdx.y;
+  const Z64* __restrict__ ps = psi_r + ((size_t)band[s] * N + ix) * N * N;
+  const double* __restrict__ dp = dv + ((size_t)pert[s] * N + ix) * N * N;
+  for (int m0 = 0; m0 < nr; m0 += ZR) {
+    const int nz = min(ZR, nr - m0), y0 = y0w + m0;
+    // forward stage 1 (radix R2) over z = j + R1 r of the product row
+#pragma unroll
+    for (int k = 0; k < C::MAXZ; ++k) {
+      const int it = lane + 64 * k;
+      if (it < nz * R1) {
+        const int l = it % nz, j = it / nz;
+        const size_t row = (size_t)(y0 + l) * N;
+        Z64 v[R2];
+#pragma unroll
+        for (int r = 0; r < R2; ++r) v[r] = zscale(ps[row + j + r * R1], dp[row + j + r * R1]);
+        dft<R2, -1>(v);
+#pragma unroll
+        for (int r = 0; r < R2; ++r) Sw[(j * R2 + r) * ZR + l] = v[r];
+      }
+    }
+    wave_sync();
+    // forward stage 2 (radix R1), active z into Q
+    for (int it = lane; it < nz * R2; it += 64) {
+      const int l = it % nz, j = it / nz;
+      Z64 v[R1];
+#pragma unroll
+      for (int r = 0; r < R1; ++r) v[r] = Sw[(j + r * R2) * ZR + l];
+#pragma unroll
+      for (int r = 1; r < R1; ++r) v[r] = v[r] * twid<-1>(tw, r * j);
+      dft<R1, -1>(v);
+#pragma unroll
+      for (int r = 0; r < R1; ++r) {
+        const int z = j + r * R2;
+        if (act(z)) Q[fz(z) * QLD + y0 + l] = v[r];
+      }
+    }
+    wave_sync();
+  }
+  __syncthreads();
+  cw_y_forward<N>(Q, tw, pen + ((size_t)s * N + ix) * g.ncol_pad, g.ycol, nza, nm, f0, nl, lane);
+}
+
+// inverse z of one round of this wave's rows, from the active lines in Q; calls
+// emit(k, l, j, v) with v[r] the value at row y0 + l, z = j + R1 r
+template <int N, class Emit>
+__device__ __forceinline__ void cw_z_inverse_round(const Z64* __restrict__ Q, const Z64* __restrict__ tw,
+                                                   Z64* __restrict__ Sw, int nm, int y0, int nz, int lane,
+                                                   Emit&& emit) {
+  using C = CwCfg<N>;
+  constexpr int R1 = C::R1, R2 = C::R2, ZR = C::ZR, QLD = N + 1;
+  const Z64 zero = zmk(0.0, 0.0);
+  for (int it = lane; it < nz * R2; it += 64) {
+    const int l = it % nz, j = it / nz;
+    Z64 v[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+      const int z = j + r * R2;
+      v[r] = zero;
+      if (z <= nm || z >= N - nm) v[r] = Q[(z <= nm ? z : z - N + 2 * nm + 1) * QLD + y0 + l];
+    }
+    dft<R1, +1>(v);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) Sw[(j * R1 + r) * ZR + l] = v[r];
+  }
+  wave_sync();
+#pragma unroll
+  for (int k = 0; k < C::MAXZ; ++k) {
+    const int it = lane + 64 * k;
+    if (it < nz * R1) {
+      const int l = it % nz, j = it / nz;
+      Z64 v[R2];
+#pragma unroll
+      for (int r = 0; r < R2; ++r) v[r] = Sw[(j + r * R1) * ZR + l];
+#pragma unroll
+      for (int r = 1; r < R2; ++r) v[r] = v[r] * twid<+1>(tw, r * j);
+      dft<R2, +1>(v);
+      emit(k, l, j, v);
+    }
+  }
+  wave_sync();  // the next round rewrites Sw
+}
+
+// inverse yz DFT of the pencils of vector `vec` to the full plane out[vec][ix][iy][iz]
+template <int N>
+__global__ __launch_bounds__(256) void k_plane_full_inv_c(const Z64* __restrict__ pen, Z64* __restrict__ out,
+                                                         FftGeom g) {
+  STERN_CW_SETUP
+  const int ix = blockIdx.x, vec = blockIdx.y;
+  cw_y_inverse<N>(Q, tw, pen + ((size_t)vec * N + ix) * g.ncol_pad, g.ycol, nza, nm, f0, nl, lane);
+  __syncthreads();
+  Z64* __restrict__ op = out + ((size_t)vec * N + ix) * N * N;
+  for (int m0 = 0; m0 < nr; m0 += ZR) {
+    const int y0 = y0w + m0;
+    cw_z_inverse_round<N>(Q, tw, Sw, nm, y0, min(ZR, nr - m0), lane, [&](int, int l, int j, const Z64(&v)[R2]) {
+#pragma unroll
+      for (int r = 0; r < R2; ++r) op[(size_t)(y0 + l) * N + j + r * R1] = v[r];
+    });
+  }
+}
+
+// dn of perturbation pl over nb bands: as k_plane_dn, with each wave's rows
+// accumulated in registers across the bands (RND rounds x MAXZ items x R2 values)
+template <int N>
+__global__ __launch_bounds__(256) void k_plane_dn_c(const Z64* __restrict__ pen, const Z64* __restrict__ psi_r,
+                                                   int band0, int nb, const int* __restrict__ pert_out, double scale,
+                                                   double* __restrict__ dn, FftGeom g) {
+  STERN_CW_SETUP
+  const int ix = blockIdx.x, pl = blockIdx.y;
+  double acc[C::RND][C::MAXZ][R2];
+#pragma unroll
+  for (int m = 0; m < C::RND; ++m)
+#pragma unroll
+    for (int k = 0; k < C::MAXZ; ++k)
+#pragma unroll
+      for (int r = 0; r < R2; ++r) acc[m][k][r] = 0.0;
+  for (int bb = 0; bb < nb; ++bb) {
+    const int s = pl * nb + bb;
+    cw_y_inverse<N>(Q, tw, pen + ((size_t)s * N + ix) * g.ncol_pad, g.ycol, nza, nm, f0, nl, lane);
+    __syncthreads();
+    const Z64* __restrict__ ps = psi_r + ((size_t)(band0 + bb) * N + ix) * N * N;
+#pragma unroll
+    for (int m = 0; m < C::RND; ++m) {
+      const int m0 = m * ZR;
+      if (m0 < nr) {
+        const int y0 = y0w + m0;
+        cw_z_inverse_round<N>(Q, tw, Sw, nm, y0, min(ZR, nr - m0), lane, [&](int k, int l, int j, const Z64(&v)[R2]) {
+#pragma unroll
+          for (int r = 0; r < R2; ++r) {
+            const Z64 w = ps[(size_t)(y0 + l) * N + j + r * R1];
+            acc[m][k][r] += w.re * v[r].re + w.im * v[r].im;
+          }
+        });
+      }
+    }
+    __syncthreads();  // Q is rewritten by the next band
+  }
+  double* __restrict__ dp = dn + ((size_t)pert_out[pl] * N + ix) * N * N;
+#pragma unroll
+  for (int m = 0; m < C::RND; ++m) {
+    const int m0 = m * ZR;
+    if (m0 < nr) {
+      const int nz = min(ZR, nr - m0), y0 = y0w + m0;
+#pragma unroll
+      for (int k = 0; k < C::MAXZ; ++k) {
+        const int it = lane + 64 * k;
+        if (it < nz * R1) {
+          const int l = it % nz, j = it / nz;
+#pragma unroll
+          for (int r = 0; r < R2; ++r) dp[(size_t)(y0 + l) * N + j + r * R1] = scale * acc[m][k][r];
+        }
+      }
+    }
+  }
+}
+#undef STERN_CW_SETUP
+
 // Raise the dynamic LDS limit of a plane kernel once per instantiation
 // (thread-safe: several host threads may launch concurrently).
 void set_lds(const void* kernel, size_t bytes) {
@@ -938,21 +1211,47 @@ template void launch_plane_hw<float>(const FftGeom&, Z32*, const int*, int, cons
 
 template void launch_plane_vloc<float>(const FftGeom&, Z32*, const int*, int, const float*, hipStream_t);
 
+// FP64 full-plane kernels hold the whole plane when it fits in LDS, else the compact layout
+template <int N>
+constexpr bool full_plane_fits() {
+  return ((size_t)N * (N + 1) + N) * sizeof(Z64) <= 160 * 1024;
+}
+template <int N>
+size_t cw_lds_bytes(int nza) {
+  return ((size_t)nza * (N + 1) + N + (size_t)CwCfg<N>::W * N * CwCfg<N>::ZR) * sizeof(Z64);
+}
+
 void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
                       int nvec, Z64* pen, hipStream_t st) {
   if (nvec <= 0) return;
-  const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
   dim3 grid(g.N, nvec);
-  STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_rhs<NN>, lds),
-                         k_plane_rhs<NN><<<grid, plane_nt<NN>(), lds, st>>>(psi_r, dv, band, pert, pen, g)));
+  STERN_DISPATCH_N(g.N, ({
+                     if constexpr (full_plane_fits<NN>()) {
+                       const size_t lds = plane_lds_bytes(NN, sizeof(Z64));
+                       set_lds((const void*)k_plane_rhs<NN>, lds);
+                       k_plane_rhs<NN><<<grid, plane_nt<NN>(), lds, st>>>(psi_r, dv, band, pert, pen, g);
+                     } else {
+                       const size_t lds = cw_lds_bytes<NN>(g.nza);
+                       set_lds((const void*)k_plane_rhs_c<NN>, lds);
+                       k_plane_rhs_c<NN><<<grid, 256, lds, st>>>(psi_r, dv, band, pert, pen, g);
+                     }
+                   }));
 }
 
 void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out, hipStream_t st) {
   if (nvec <= 0) return;
-  const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
   dim3 grid(g.N, nvec);
-  STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_full_inv<NN>, lds),
-                         k_plane_full_inv<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, out, g)));
+  STERN_DISPATCH_N(g.N, ({
+                     if constexpr (full_plane_fits<NN>()) {
+                       const size_t lds = plane_lds_bytes(NN, sizeof(Z64));
+                       set_lds((const void*)k_plane_full_inv<NN>, lds);
+                       k_plane_full_inv<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, out, g);
+                     } else {
+                       const size_t lds = cw_lds_bytes<NN>(g.nza);
+                       set_lds((const void*)k_plane_full_inv_c<NN>, lds);
+                       k_plane_full_inv_c<NN><<<grid, 256, lds, st>>>(pen, out, g);
+                     }
+                   }));
 }
 
 void launch_plane_full_fwd(const FftGeom& g, const Z64* in, int nvec, Z64* pen, hipStream_t st) {
@@ -966,11 +1265,31 @@ void launch_plane_full_fwd(const FftGeom& g, const Z64* in, int nvec, Z64* pen, 
 void launch_plane_dn(const FftGeom& g, const Z64* pen, const Z64* psi_r, int band0, int nb, int npert,
                      const int* pert_out, double scale, double* dn, hipStream_t st) {
   if (npert <= 0 || nb <= 0) return;
-  const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));
   dim3 grid(g.N, npert);
-  STERN_DISPATCH_N(g.N, (set_lds((const void*)k_plane_dn<NN>, lds),
-                         k_plane_dn<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, psi_r, band0, nb, pert_out, scale,
-                                                                          dn, g)));
+  STERN_DISPATCH_N(g.N, ({
+                     if constexpr (full_plane_fits<NN>()) {
+                       const size_t lds = plane_lds_bytes(NN, sizeof(Z64));
+                       set_lds((const void*)k_plane_dn<NN>, lds);
+                       k_plane_dn<NN><<<grid, plane_nt<NN>(), lds, st>>>(pen, psi_r, band0, nb, pert_out, scale,
+                                                                        dn, g);
+                     } else {
+                       const size_t lds = cw_lds_bytes<NN>(g.nza);
+                       set_lds((const void*)k_plane_dn_c<NN>, lds);
+                       k_plane_dn_c<NN><<<grid, 256, lds, st>>>(pen, psi_r, band0, nb, pert_out, scale, dn, g);
+                     }
+                   }));
+}
+
+// LDS of the FP64 plane kernels of the RHS, psi_v(r) and dn for grid N
+size_t plane_fp64_lds(int N, int nza) {
+  size_t r = 0;
+  STERN_DISPATCH_N(N, ({
+                     if constexpr (full_plane_fits<NN>())
+                       r = plane_lds_bytes(NN, sizeof(Z64));
+                     else
+                       r = cw_lds_bytes<NN>(nza);
+                   }));
+  return r;
 }
 
 }  // namespace stern

@@ -32,6 +32,8 @@ constexpr int kColBlock = 16;  // columns per workgroup in the x-pencil passes
 
 bool fft_size_supported(int N);
 size_t plane_lds_bytes(int N, int elem_bytes);
+// LDS of the FP64 RHS / psi_v(r) / dn plane kernels (full plane, or the compact layout when that does not fit)
+size_t plane_fp64_lds(int N, int nza);
 
 // x pass, inverse: sphere coefficients of vectors vidx[b] (b < nvec) -> pencils.
 template <class T>

@@ -1004,15 +1004,18 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     delete S;
     return fail(STERN_ERR_HIP, "hipGetDeviceProperties failed");
   }
-  const size_t lds = plane_lds_bytes(hb.N, sizeof(Z64));
-  if (lds > prop.sharedMemPerBlock && lds > (size_t)prop.maxSharedMemoryPerMultiProcessor) {
-    delete S;
-    return fail(STERN_ERR_UNSUPPORTED, "FP64 plane of grid %d needs %zu bytes of LDS", hb.N, lds);
-  }
-  {  // yz-plane kernel of the H apply: the compact one when its LDS fits
+  {  // yz-plane kernels: the compact H apply when its LDS fits, else the full plane
     const size_t lds_max = std::max((size_t)prop.sharedMemPerBlock, (size_t)prop.maxSharedMemoryPerMultiProcessor);
-    S->plane_var64 = plane_hw_lds(hb.N, hb.nza, true) <= lds_max ? 1 : 0;
-    S->plane_var32 = plane_hw_lds(hb.N, hb.nza, false) <= lds_max ? 1 : 0;
+    const bool c64 = plane_hw_lds(hb.N, hb.nza, true) <= lds_max, c32 = plane_hw_lds(hb.N, hb.nza, false) <= lds_max;
+    const bool f64 = plane_lds_bytes(hb.N, sizeof(Z64)) <= lds_max, f32 = plane_lds_bytes(hb.N, sizeof(Z32)) <= lds_max;
+    const size_t rhs = plane_fp64_lds(hb.N, hb.nza);
+    if (!(c64 || f64) || !(c32 || f32) || rhs > lds_max) {
+      delete S;
+      return fail(STERN_ERR_UNSUPPORTED, "the yz-plane kernels of grid %d do not fit in %zu bytes of LDS", hb.N,
+                  lds_max);
+    }
+    S->plane_var64 = c64 ? 1 : 0;
+    S->plane_var32 = c32 ? 1 : 0;
     S->lds_max = lds_max;
   }
   S->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -1554,8 +1557,11 @@ int stern_tunable(stern_system* S, int which, int value) {
       if (value > 1) return fail(STERN_ERR_INVALID_ARG, "expand variant must be 0 or 1");
     } else if (which == STERN_TUNE_PLANE64 || which == STERN_TUNE_PLANE32) {
       if (value > 2) return fail(STERN_ERR_INVALID_ARG, "plane kernel variant must be 0, 1 or 2");
-      if (value >= 1 && plane_hw_lds(S->hb.N, S->hb.nza, which == STERN_TUNE_PLANE64) > S->lds_max)
+      const bool fp64 = which == STERN_TUNE_PLANE64;
+      if (value >= 1 && plane_hw_lds(S->hb.N, S->hb.nza, fp64) > S->lds_max)
         return fail(STERN_ERR_INVALID_ARG, "the compact plane kernel does not fit in LDS for grid %d", S->hb.N);
+      if (value == 0 && plane_lds_bytes(S->hb.N, fp64 ? sizeof(Z64) : sizeof(Z32)) > S->lds_max)
+        return fail(STERN_ERR_INVALID_ARG, "the full-plane kernel does not fit in LDS for grid %d", S->hb.N);
     } else if (value > 65536) {
       return fail(STERN_ERR_INVALID_ARG, "workgroup target %d out of range", value);
     }
