@@ -16,7 +16,6 @@ stream) and the CPU oracle timed on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -35,29 +34,20 @@ ALU_KERNELS = {"plane_h32": FP32_VALU_PEAK_TFS, "plane_h": FP64_VALU_PEAK_TFS}
 MFMA_KERNELS = {"gemm_bf16": BF16_MFMA_PEAK_TFS, "pc_reduce": FP64_MFMA_PEAK_TFS, "pc_expand": FP64_MFMA_PEAK_TFS,
                 "kb_reduce": FP64_MFMA_PEAK_TFS, "kb_expand": FP64_MFMA_PEAK_TFS, "net": BF16_MFMA_PEAK_TFS}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
-KERNEL_SOURCES = {"plane_h": "fft.hip", "plane_h32": "fft.hip", "xinv": "fft.hip", "xfwd": "fft.hip",
-                  "x32": "fft.hip", "rhs_plane": "fft.hip", "dn_plane": "fft.hip", "pc_reduce": "gemm.hip",
-                  "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip", "kb_expand": "gemm.hip",
-                  "sum_parts": "gemm.hip", "cg": "cg.hip", "cg32": "cg.hip", "gemm_bf16": "gemm_bf16.hip",
-                  "net": "learn.hip"}
 
 
-def source_hash(kernel: str) -> str:
-    f = KERNEL_SOURCES.get(kernel)
-    if f is None:
-        return ""
-    with open(os.path.join(ROOT, "paper_2607_14025_amd", "csrc", f), "rb") as fh:
-        return hashlib.sha1(fh.read()).hexdigest()[:12]
-
-
-def measured_traffic(kernel: str):
-    """Per-launch HBM bytes of `kernel` from committed rocprofv3 counters, if the kernel source is unchanged."""
+def measured_traffic(kernel: str, algorithmic_bytes_per_launch: float):
+    """HBM bytes per launch of `kernel` in this run: the ratio of measured (rocprofv3 FETCH_SIZE +
+    WRITE_SIZE, calibrated on a plain copy) to algorithmic bytes over the same launches of a
+    committed counter run, times this run's algorithmic bytes per launch; None when the kernel
+    source has changed since the counters were taken."""
+    from paper_2607_14025_amd.rocprof_summary import source_hash
     if not os.path.exists(TRAFFIC_FILE):
         return None
     t = json.load(open(TRAFFIC_FILE)).get(kernel)
-    if not t or t.get("source_sha1") != source_hash(kernel):
+    if not t or t.get("source_sha1") != source_hash(kernel) or not t.get("measured_over_algorithmic"):
         return None
-    return t.get("bytes_per_launch")
+    return t["measured_over_algorithmic"] * algorithmic_bytes_per_launch
 
 
 def cpu_baseline(wl, n_bands: int, tol: float):
@@ -202,7 +192,7 @@ def main():
     dom = max(kern, key=lambda n: kern[n]["ms"])
     d = kern[dom]
     per_launch_s = d["ms"] / d["launches"] / 1e3
-    traffic = measured_traffic(dom)
+    traffic = measured_traffic(dom, d["bytes"] / d["launches"])
     if dom in ALU_KERNELS or dom in MFMA_KERNELS:
         peak = ALU_KERNELS.get(dom) or MFMA_KERNELS[dom]
         achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
@@ -216,7 +206,8 @@ def main():
     roof["launches"] = d["launches"]
     roof["ms_per_launch"] = d["ms"] / d["launches"]
     total_ms = sum(v["ms"] for v in kern.values())
-    breakdown = {n: dict(share=round(v["ms"] / total_ms, 4), ms_per_launch=round(v["ms"] / v["launches"], 4),
+    breakdown = {n: dict(share=round(v["ms"] / total_ms, 4), launches=v["launches"],
+                         bytes_per_launch=round(v["bytes"] / v["launches"]), ms_per_launch=round(v["ms"] / v["launches"], 4),
                          GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
                          TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["flops"] > 0 else None)
                  for n, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}

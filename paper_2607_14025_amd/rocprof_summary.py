@@ -1,0 +1,181 @@
+"""Short text summaries of rocprofv3 output for the profiles kept with the library.
+
+  python3 -m paper_2607_14025_amd.rocprof_summary stats DB TITLE COMMAND [BENCH_LOG LABEL KERNEL] > summary.md
+      kernel table (calls, total and average duration, share) of a --kernel-trace --stats
+      results database; with the bench's log, the traced durations of the bench's timed
+      launches of KERNEL against the bench's own HIP-event time per launch.
+
+  python3 -m paper_2607_14025_amd.rocprof_summary traffic FETCH_CSV WRITE_CSV BENCH_LOG LABEL KERNEL
+          TITLE FETCH_COMMAND WRITE_COMMAND [TRAFFIC_JSON] > summary.md
+      HBM bytes per launch of one kernel from two --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
+      `bench.py --steps 1 --warmup 0 --copy-calibration`. Each counter is scaled by what it reads
+      for the 1 GiB elementwise copy that run starts with. The kernel's last launches are matched
+      to the bench's final apply, which repeats the timed step's launches (the solve is
+      deterministic), and so to the bench's algorithmic bytes for them; the ratio
+      measured / algorithmic goes to TRAFFIC_JSON under LABEL, with the source hash bench.py
+      checks.
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+COPY_KERNEL = "MulFunctor<double>"
+COPY_BYTES = float(1 << 30)
+# source file of each kernel class of the per-launch profile (stern_stats)
+KERNEL_SOURCES = {"plane_h": "fft.hip", "plane_h32": "fft.hip", "xinv": "fft.hip", "xfwd": "fft.hip",
+                  "x32": "fft.hip", "rhs_plane": "fft.hip", "dn_plane": "fft.hip", "pc_reduce": "gemm.hip",
+                  "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip", "kb_expand": "gemm.hip",
+                  "sum_parts": "gemm.hip", "cg": "cg.hip", "cg32": "cg.hip", "gemm_bf16": "gemm_bf16.hip",
+                  "net": "learn.hip"}
+
+
+def source_hash(label: str) -> str:
+    """sha1 prefix of the source of kernel class `label` ("" if unknown)."""
+    f = KERNEL_SOURCES.get(label)
+    if f is None:
+        return ""
+    with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+        return hashlib.sha1(fh.read()).hexdigest()[:12]
+
+
+def short_name(n: str) -> str:
+    n = n.replace("stern::(anonymous namespace)::", "").replace("stern::", "")
+    n = re.sub(r"\(.*\)$", "", n).replace("void ", "")
+    return n
+
+
+def stats(db: str, title: str, cmd: str) -> str:
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    out = [f"# {title}\n", "Command (run from the repository root on one MI355X, with TMPDIR=/tmp):\n",
+           f"```\n{cmd}\n```\n", "| kernel | calls | total (us) | average (us) | share |", "|---|---:|---:|---:|---:|"]
+    for n, c, t, a, p in rows:
+        if p < 0.005:
+            continue
+        out.append(f"| `{short_name(n)}` | {c} | {t:.0f} | {a:.1f} | {p:.2f}% |")  # the view is in us
+    return "\n".join(out) + "\n"
+
+
+def launch_agreement(db: str, bench_log: str, label: str, kernel: str) -> str:
+    """rocprofv3 durations of the bench's timed launches of `kernel` against the bench's own
+    HIP-event time per launch. The head path runs last: its timed steps, then one untimed
+    apply with the same launches, so the timed ones are the kernel's last launches but one
+    step's worth."""
+    bench = _bench_line(bench_log)
+    k = bench["kernels"][label]
+    n = int(k["launches"])
+    per_step = n // bench["steps"]
+    con = sqlite3.connect(db)
+    rows = [(dur, nm) for dur, nm in con.execute("select duration, name from kernels order by start")]
+    mine = [dur for dur, nm in rows if kernel in short_name(nm)]
+    timed = mine[len(mine) - per_step - n:len(mine) - per_step]
+    avg_us = sum(timed) / len(timed) / 1e3  # durations are in ns
+    return (f"Agreement for `{kernel}` ({label}, the kernel the bench's roofline reports): the bench's HIP "
+            f"events give {k['ms_per_launch'] * 1e3:.1f} us per launch over its {n} timed launches; this trace "
+            f"gives {avg_us:.1f} us for the same launches (ratio {avg_us / (k['ms_per_launch'] * 1e3):.3f}).\n")
+
+
+def _counter(path: str, counter: str):
+    """[(dispatch id, kernel name, value)] of one counter, in dispatch order."""
+    rows = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def _bench_line(log: str) -> dict:
+    with open(log) as fh:
+        for line in fh:
+            if line.startswith("{") and '"metric"' in line:
+                return json.loads(line)
+    raise SystemExit(f"no bench JSON line in {log}")
+
+
+def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w, traffic_json=None) -> str:
+    bench = _bench_line(bench_log)
+    k = bench["kernels"][label]
+    n_launch = int(k["launches"] // bench["steps"])
+    algo = float(k["bytes_per_launch"])
+    res = {}
+    for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter(path, counter)
+        copy = [v for _, n, v in rows if COPY_KERNEL in n]
+        if not copy:
+            raise SystemExit(f"{path}: no calibration copy kernel ({COPY_KERNEL})")
+        scale = COPY_BYTES / (copy[0] * 1024.0)
+        mine = [v for _, n, v in rows if kernel in short_name(n)]
+        if len(mine) < n_launch:
+            raise SystemExit(f"{path}: {len(mine)} dispatches of {kernel}, the bench step has {n_launch}")
+        last = mine[-n_launch:]
+        res[name] = dict(copy_kib=copy[0], scale=scale, kib=sum(last) / len(last),
+                         bytes=scale * 1024.0 * sum(last) / len(last), n_all=len(mine))
+    measured = res["fetch"]["bytes"] + res["write"]["bytes"]
+    ratio = measured / algo
+    sha = source_hash(label)
+    if traffic_json:
+        t = json.load(open(traffic_json)) if os.path.exists(traffic_json) else {}
+        t[label] = dict(measured_over_algorithmic=ratio, source_sha1=sha, kernel=kernel, launches_matched=n_launch,
+                        algorithmic_bytes_per_launch=algo, measured_bytes_per_launch=measured,
+                        read_bytes_per_launch=res["fetch"]["bytes"], write_bytes_per_launch=res["write"]["bytes"])
+        with open(traffic_json, "w") as fh:
+            json.dump(t, fh, indent=1)
+            fh.write("\n")
+    f, w = res["fetch"], res["write"]
+    # every kernel of the run, for context (all its dispatches, the autotuner's included)
+    per = {}
+    for key, path, counter in (("r", fetch_csv, "FETCH_SIZE"), ("w", write_csv, "WRITE_SIZE")):
+        sc = res["fetch" if key == "r" else "write"]["scale"] * 1024.0
+        for _, n, v in _counter(path, counter):
+            e = per.setdefault(short_name(n), {"r": [], "w": []})
+            e[key].append(v * sc)
+    table = ["| kernel | dispatches | read MB / dispatch | write MB / dispatch |", "|---|---:|---:|---:|"]
+    for n, e in sorted(per.items(), key=lambda kv: -(sum(kv[1]["r"]) + sum(kv[1]["w"]))):
+        if not e["r"] or not e["w"] or sum(e["r"]) + sum(e["w"]) < 1e8:
+            continue
+        table.append(f"| `{n[:70]}` | {len(e['r'])} | {sum(e['r']) / len(e['r']) / 1e6:.1f} | "
+                     f"{sum(e['w']) / len(e['w']) / 1e6:.1f} |")
+    return "\n".join([
+        f"# {title}\n",
+        "Commands (repository root, one MI355X, TMPDIR=/tmp), one counter per run:\n",
+        f"```\n{cmd_f}\n{cmd_w}\n```\n",
+        f"Calibration: the run starts with one elementwise kernel (`{COPY_KERNEL}`) that reads 1 GiB and writes "
+        f"1 GiB. It reads FETCH_SIZE = {f['copy_kib']:.1f} KiB and WRITE_SIZE = {w['copy_kib']:.1f} KiB, so "
+        f"bytes = FETCH_SIZE x 1024 x {f['scale']:.4f} and WRITE_SIZE x 1024 x {w['scale']:.4f}.\n",
+        f"`{kernel}` ({label}): {f['n_all']} dispatches in the run; the last {n_launch} are the bench's final "
+        f"apply, whose launches repeat the timed step's.\n",
+        "| per launch (average of those) | bytes |", "|---|---:|",
+        f"| FETCH_SIZE {f['kib']:.0f} KiB, calibrated | {f['bytes'] / 1e6:.1f} MB |",
+        f"| WRITE_SIZE {w['kib']:.0f} KiB, calibrated | {w['bytes'] / 1e6:.1f} MB |",
+        f"| measured total | {measured / 1e6:.1f} MB |",
+        f"| algorithmic (pencils read and written once, V_loc once) | {algo / 1e6:.1f} MB |",
+        f"| measured / algorithmic | {ratio:.3f} |\n",
+        f"Source `paper_2607_14025_amd/csrc/{KERNEL_SOURCES.get(label)}` sha1 prefix at measurement: {sha}\n",
+        "All kernels of the run with more than 100 MB of traffic in total (calibrated, per dispatch):\n",
+    ] + table) + "\n"
+
+
+def main(argv):
+    if len(argv) >= 4 and argv[0] == "stats":
+        sys.stdout.write(stats(argv[1], argv[2], argv[3]))
+        if len(argv) >= 7:  # BENCH_LOG LABEL KERNEL: agreement with the bench's event timing
+            sys.stdout.write("\n" + launch_agreement(argv[1], argv[4], argv[5], argv[6]))
+    elif len(argv) >= 9 and argv[0] == "traffic":
+        sys.stdout.write(traffic(*argv[1:10]))
+    else:
+        sys.stdout.write(__doc__)
+        return 2
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))
