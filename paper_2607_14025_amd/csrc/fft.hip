@@ -639,40 +639,62 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   }
 }
 
-// right-hand side: pencils[s] of plane ix = forward yz DFT of psi_r[band[s]] * dv[pert[s]]
+// Right-hand sides of one band for every field of a batch: workgroup (ix, bb) keeps
+// plane ix of psi_{v0 + bb}(r) in registers (the items of its first stage) and, for
+// each field pl, forms psi * dv, transforms the plane and writes the pencils of solve
+// pl * nb + bb. psi_v(r) is read once per band instead of once per (band, field).
 template <int N>
-__global__ __launch_bounds__(plane_nt<N>()) void k_plane_rhs(const Z64* __restrict__ psi_r,
-                                                            const double* __restrict__ dv,
-                                                            const int* __restrict__ band,
-                                                            const int* __restrict__ pert, Z64* __restrict__ pen,
-                                                            FftGeom g) {
+__global__ __launch_bounds__(plane_nt<N>()) void k_plane_rhs_bands(const Z64* __restrict__ psi_r,
+                                                                  const double* __restrict__ dv, int v0, int nb,
+                                                                  int i0, int npert, Z64* __restrict__ pen,
+                                                                  FftGeom g) {
   using C = PlaneCtx<N, double>;
   constexpr int LD = C::LD, R1 = C::R1, R2 = C::R2, NT = C::NT;
+  constexpr int MAXIT = (N * R2 + NT - 1) / NT;
   extern __shared__ unsigned char smem_raw[];
   C c{reinterpret_cast<Z64*>(smem_raw), g.zl, g.ycol, g.nza, g.zact_lo, g.zact_hi,
       plane_twiddles<N, double>(smem_raw, g)};
   Z64* P = c.P;
-  const int ix = blockIdx.x;
-  const int s = blockIdx.y;
-  const Z64* __restrict__ ps = psi_r + ((size_t)band[s] * N + ix) * N * N;
-  const double* __restrict__ dp = dv + ((size_t)pert[s] * N + ix) * N * N;
-  stage<N, R1, -1, false, false, false, NT, N>(
-      N,
-      [&](int y, int j, int r) {
-        const int o = y * N + j + r * R2;
-        return zscale(ps[o], dp[o]);
-      },
-      [&](int y, int j, int r, Z64 v) { P[y * LD + j * R1 + r] = v; }, c.tw);
-  __syncthreads();
-  stage<N, R2, -1, true, false, false, NT, N>(
-      N, [&](int y, int j, int r) { return P[y * LD + j + r * R1]; },
-      [&](int y, int j, int r, Z64 v) {
-        const int z = j + r * R1;
-        if (c.zact(z)) P[y * LD + z] = v;
-      },
-      c.tw);
-  __syncthreads();
-  y_forward_to_pencils<N, double>(c, pen + ((size_t)s * N + ix) * g.ncol_pad);
+  const int ix = blockIdx.x, bb = blockIdx.y, tid = threadIdx.x;
+  const Z64* __restrict__ ps = psi_r + ((size_t)(v0 + bb) * N + ix) * N * N;
+  Z64 pc[MAXIT][R1];
+#pragma unroll
+  for (int k = 0; k < MAXIT; ++k) {
+    const int it = tid + k * NT;
+    if (it < N * R2) {
+      const int y = it / R2, j = it % R2;
+#pragma unroll
+      for (int r = 0; r < R1; ++r) pc[k][r] = ps[y * N + j + r * R2];
+    }
+  }
+  for (int pl = 0; pl < npert; ++pl) {
+    const double* __restrict__ dp = dv + ((size_t)(i0 + pl) * N + ix) * N * N;
+    // z forward stage 1 (radix R1 over z = j + R2 r) of the product row
+#pragma unroll
+    for (int k = 0; k < MAXIT; ++k) {
+      const int it = tid + k * NT;
+      if (it < N * R2) {
+        const int y = it / R2, j = it % R2;
+        Z64 v[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) v[r] = zscale(pc[k][r], dp[y * N + j + r * R2]);
+        dft<R1, -1>(v);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) P[y * LD + j * R1 + r] = v[r];
+      }
+    }
+    __syncthreads();
+    stage<N, R2, -1, true, false, false, NT, N>(
+        N, [&](int y, int j, int r) { return P[y * LD + j + r * R1]; },
+        [&](int y, int j, int r, Z64 v) {
+          const int z = j + r * R1;
+          if (c.zact(z)) P[y * LD + z] = v;
+        },
+        c.tw);
+    __syncthreads();
+    y_forward_to_pencils<N, double>(c, pen + ((size_t)(pl * nb + bb) * N + ix) * g.ncol_pad);
+    __syncthreads();  // P is rewritten by the next field
+  }
 }
 
 // inverse yz DFT of the pencils of vector `vec` to the full plane out[vec][ix][iy][iz]
@@ -1221,19 +1243,19 @@ size_t cw_lds_bytes(int nza) {
   return ((size_t)nza * (N + 1) + N + (size_t)CwCfg<N>::W * N * CwCfg<N>::ZR) * sizeof(Z64);
 }
 
-void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
-                      int nvec, Z64* pen, hipStream_t st) {
-  if (nvec <= 0) return;
-  dim3 grid(g.N, nvec);
+void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, int v0, int nb, int i0, int npert,
+                      const int* band, const int* pert, Z64* pen, hipStream_t st) {
+  if (nb <= 0 || npert <= 0) return;
   STERN_DISPATCH_N(g.N, ({
                      if constexpr (full_plane_fits<NN>()) {
                        const size_t lds = plane_lds_bytes(NN, sizeof(Z64));
-                       set_lds((const void*)k_plane_rhs<NN>, lds);
-                       k_plane_rhs<NN><<<grid, plane_nt<NN>(), lds, st>>>(psi_r, dv, band, pert, pen, g);
+                       set_lds((const void*)k_plane_rhs_bands<NN>, lds);
+                       k_plane_rhs_bands<NN><<<dim3(NN, nb), plane_nt<NN>(), lds, st>>>(psi_r, dv, v0, nb, i0,
+                                                                                      npert, pen, g);
                      } else {
                        const size_t lds = cw_lds_bytes<NN>(g.nza);
                        set_lds((const void*)k_plane_rhs_c<NN>, lds);
-                       k_plane_rhs_c<NN><<<grid, 256, lds, st>>>(psi_r, dv, band, pert, pen, g);
+                       k_plane_rhs_c<NN><<<dim3(NN, nb * npert), 256, lds, st>>>(psi_r, dv, band, pert, pen, g);
                      }
                    }));
 }

@@ -53,9 +53,11 @@ template <class T>
 void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, bool prefetch,
                      hipStream_t st);
 size_t plane_hw_lds(int N, int nza, bool fp64);  // its LDS bytes per workgroup
-// yz planes of the right-hand side: pencils[s] = forward planes of psi_r[band[s]] * dv[pert[s]].
-void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, const int* band, const int* pert,
-                      int nvec, Z64* pen, hipStream_t st);
+// yz planes of the right-hand sides of a batch of bands [v0, v0 + nb) x fields [i0, i0 + npert), solve
+// s = (i - i0) nb + (v - v0) (band[s], pert[s] give the same): pencils[s] = forward planes of
+// psi_r[v] * dv[i].
+void launch_plane_rhs(const FftGeom& g, const Z64* psi_r, const double* dv, int v0, int nb, int i0, int npert,
+                      const int* band, const int* pert, Z64* pen, hipStream_t st);
 // yz planes, inverse to a full real-space grid: out[vec] = [N][N][N] complex.
 void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out, hipStream_t st);
 // dn[pert_out[p]] = scale * Re sum_{b < nb} conj(psi_r[band0 + b]) * x_r[p * nb + b], from pencils.

@@ -705,9 +705,10 @@ int setup_batch(stern_system* S, int i0, int i1, int v0, int nb, const double* d
   HIPOK(hipMemcpyAsync(S->sv_invT.p, h_invT.data(), ns * sizeof(double), hipMemcpyHostToDevice, st));
   const CgState cs = cg_state(S);
   const FftGeom g = S->geom();
-  CHECKED(timed(S, STERN_K_RHS, ns * ((double)n3 * 24.0 + (double)N * hb.ncol * 16.0), 0.0, [&] {
-    launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, S->sv_band.as<int>(), S->sv_pert.as<int>(), ns,
-                     S->pen.as<Z64>(), st);
+  // psi_v(r) once per band, dV_i(r) and the pencils once per solve
+  CHECKED(timed(S, STERN_K_RHS, nb * (double)n3 * 16.0 + ns * ((double)n3 * 8.0 + (double)N * hb.ncol * 16.0), 0.0, [&] {
+    launch_plane_rhs(g, S->psi_r.as<Z64>(), dv_dev, v0, nb, i0, i1 - i0, S->sv_band.as<int>(),
+                     S->sv_pert.as<int>(), S->pen.as<Z64>(), st);
   }));
   CHECKED(timed(S, STERN_K_XFWD, ns * ((double)N * hb.ncol * 16.0 + vecb), 0.0, [&] {
     launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
