@@ -99,30 +99,65 @@ __device__ __forceinline__ void stage(int F, Ld ld, St st, const Z<T>* __restric
 }
 
 // ---------------------------------------------------------------- x pass ----
+// A workgroup takes CB consecutive x-pencil columns. Their sphere coefficients are one
+// contiguous range of the vector (column order), so the sphere side of both passes is
+// a single coalesced sweep of that range through LDS: each coefficient finds its
+// column by a binary search over the block's column starts (kept in LDS; padding
+// columns hold INT_MAX) and its x from the column's smallest n_x.
+template <int N, class T>
+struct XBlock {
+  static constexpr int CB = kColBlock, LDX = N + 1;
+  int s0, s1;  // sphere range of the block
+  __device__ __forceinline__ void load(const FftGeom& g, int c0, int* bs, int* bx) {
+    const int tid = threadIdx.x;
+    if (tid < CB) {
+      const int c = c0 + tid, len = g.col_len[c];
+      bs[tid] = len > 0 ? g.col_start[c] : 0x7fffffff;
+      bx[tid] = g.col_xmin[c];
+    }
+  }
+  // after a barrier that follows load(): the block's range
+  __device__ __forceinline__ void range(const FftGeom& g, int c0, const int* bs) {
+    s0 = bs[0];
+    s1 = s0;
+#pragma unroll
+    for (int cc = 0; cc < CB; ++cc)
+      if (bs[cc] != 0x7fffffff) s1 = g.col_start[c0 + cc] + g.col_len[c0 + cc];
+  }
+  // LDS slot (column cc, x) of sphere index gi in [s0, s1)
+  __device__ __forceinline__ int slot(int gi, const int* bs, const int* bx) const {
+    int cc = 0;
+#pragma unroll
+    for (int step = CB / 2; step > 0; step >>= 1)
+      if (bs[cc + step] <= gi) cc += step;
+    const int nx = bx[cc] + (gi - bs[cc]);
+    return cc * LDX + (nx < 0 ? nx + N : nx);
+  }
+};
+
 // inverse: sphere coefficients -> pencils [vec][ix][ncol_pad]
 template <int N, class T>
 __global__ __launch_bounds__(kXThreads) void k_xinv(const Z<T>* __restrict__ sph, const int* __restrict__ vidx,
                                                     Z<T>* __restrict__ pen, FftGeom g) {
-  constexpr int CB = kColBlock, LDX = N + 1;
+  using B = XBlock<N, T>;
+  constexpr int CB = B::CB, LDX = B::LDX;
   constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
   __shared__ Z<T> P[CB * LDX];
+  __shared__ int bs[CB], bx[CB];
   const Z<T>* tw = twtab<T>(g);
   const int c0 = blockIdx.x * CB;
   const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
   const Z<T>* src = sph + (size_t)vec * g.npw_pad;
-  const int* __restrict__ cstart = g.col_start;
-  const int* __restrict__ clen = g.col_len;
-  const int* __restrict__ cxmin = g.col_xmin;
-  stage<N, R1, +1, false, false, true, kXThreads, CB>(
-      CB,
-      [&](int cc, int j, int r) {
-        const int x = j + r * R2;
-        const int nx = (2 * x < N) ? x : x - N;
-        const int t = nx - cxmin[c0 + cc];
-        Z<T> v = zmk(T(0), T(0));
-        if (t >= 0 && t < clen[c0 + cc]) v = src[cstart[c0 + cc] + t];
-        return v;
-      },
+  B blk;
+  blk.load(g, c0, bs, bx);
+  for (int i = threadIdx.x; i < CB * LDX; i += kXThreads) P[i] = zmk(T(0), T(0));
+  __syncthreads();
+  blk.range(g, c0, bs);
+  for (int gi = blk.s0 + (int)threadIdx.x; gi < blk.s1; gi += kXThreads) P[blk.slot(gi, bs, bx)] = src[gi];
+  __syncthreads();
+  // stage 1 in place (all loads before the barrier inside, then the stores)
+  stage<N, R1, +1, false, true, true, kXThreads, CB>(
+      CB, [&](int cc, int j, int r) { return P[cc * LDX + j + r * R2]; },
       [&](int cc, int j, int r, Z<T> v) { P[cc * LDX + j * R1 + r] = v; }, tw);
   __syncthreads();
   Z<T>* dst = pen + (size_t)vec * N * g.ncol_pad + c0;
@@ -137,45 +172,44 @@ template <int N, class T, int MODE>
 __global__ __launch_bounds__(kXThreads) void k_xfwd(const Z<T>* __restrict__ pen, const int* __restrict__ vidx,
                                                     Z<T>* __restrict__ out, const Z<T>* __restrict__ pin,
                                                     const double* __restrict__ eps, double scale, FftGeom g) {
-  constexpr int CB = kColBlock, LDX = N + 1;
+  using B = XBlock<N, T>;
+  constexpr int CB = B::CB, LDX = B::LDX;
   constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
   __shared__ Z<T> P[CB * LDX];
+  __shared__ int bs[CB], bx[CB];
   const Z<T>* tw = twtab<T>(g);
   const int c0 = blockIdx.x * CB;
   const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
   const Z<T>* src = pen + (size_t)vec * N * g.ncol_pad + c0;
   const int ld = g.ncol_pad;
+  B blk;
+  blk.load(g, c0, bs, bx);
   stage<N, R1, -1, false, false, true, kXThreads, CB>(
       CB, [&](int cc, int j, int r) { return src[(size_t)(j + r * R2) * ld + cc]; },
       [&](int cc, int j, int r, Z<T> v) { P[cc * LDX + j * R1 + r] = v; }, tw);
   __syncthreads();
+  // stage 2 in place: each item reads and writes the same slots x = j + R1 r
+  stage<N, R2, -1, true, false, true, kXThreads, CB>(
+      CB, [&](int cc, int j, int r) { return P[cc * LDX + j + r * R1]; },
+      [&](int cc, int j, int r, Z<T> v) { P[cc * LDX + j + r * R1] = v; }, tw);
+  __syncthreads();
+  blk.range(g, c0, bs);
   Z<T>* dst = out + (size_t)vec * g.npw_pad;
   const Z<T>* pv = (MODE == 1) ? pin + (size_t)vec * g.npw_pad : nullptr;
   const T e = (MODE == 1) ? T(eps[vec]) : T(0);
   const T sc = T(scale);
-  const int* __restrict__ cstart = g.col_start;
-  const int* __restrict__ clen = g.col_len;
-  const int* __restrict__ cxmin = g.col_xmin;
   const double* __restrict__ g2h = g.g2h;
-  stage<N, R2, -1, true, false, true, kXThreads, CB>(
-      CB, [&](int cc, int j, int r) { return P[cc * LDX + j + r * R1]; },
-      [&](int cc, int j, int r, Z<T> v) {
-        const int x = j + r * R1;
-        const int nx = (2 * x < N) ? x : x - N;
-        const int t = nx - cxmin[c0 + cc];
-        if (t >= 0 && t < clen[c0 + cc]) {
-          const int gi = cstart[c0 + cc] + t;
-          if (MODE == 1) {
-            const T d = T(g2h[gi]) - e;
-            const Z<T> pp = pv[gi];
-            v = zmk(v.re + d * pp.re, v.im + d * pp.im);
-          } else if (MODE == 2) {
-            v = zscale(v, sc);
-          }
-          dst[gi] = v;
-        }
-      },
-      tw);
+  for (int gi = blk.s0 + (int)threadIdx.x; gi < blk.s1; gi += kXThreads) {
+    Z<T> v = P[blk.slot(gi, bs, bx)];
+    if (MODE == 1) {
+      const T d = T(g2h[gi]) - e;
+      const Z<T> pp = pv[gi];
+      v = zmk(v.re + d * pp.re, v.im + d * pp.im);
+    } else if (MODE == 2) {
+      v = zscale(v, sc);
+    }
+    dst[gi] = v;
+  }
   // the row padding [npw, npw_pad) is kept at zero: the GEMMs reduce over it
   if (blockIdx.x == 0)
     for (int k = g.npw + threadIdx.x; k < g.npw_pad; k += kXThreads) dst[k] = zmk(T(0), T(0));
