@@ -36,6 +36,24 @@ template <class St>
 __device__ __forceinline__ double precond(const St& S, int s, int k, double iT) {
   return S.kprec ? (double)S.kprec[(size_t)s * S.npw_pad + k] : teter(S.g2h[k], iT);
 }
+// the same in two steps, so that the load can be issued with the vector loads; LK: the
+// learned K is given (a launch-wide choice, a template parameter so no branch splits the loads)
+template <bool LK, class St>
+__device__ __forceinline__ double precond_load(const St& S, int s, int k) {
+  if constexpr (LK) return (double)S.kprec[(size_t)s * S.npw_pad + k];
+  else return S.g2h[k];
+}
+template <bool LK>
+__device__ __forceinline__ double precond_eval(double raw, double iT) {
+  if constexpr (LK) return raw;
+  else return teter(raw, iT);
+}
+
+// The vector loops below take kU coefficients per thread per trip, all loaded before
+// any is used (kU independent loads in flight instead of one). A thread still visits
+// k = tid, tid + kCgThreads, tid + 2 kCgThreads, ... in order, so every FP64 sum has
+// the order of the one-at-a-time loop.
+constexpr int kU = 4;
 
 // keep == 0: x = 0, r = b. keep != 0: x and r = b - A x are given (a guess).
 // z = K r; ||b||^2; flag 0 (2 when b = 0).
@@ -127,29 +145,58 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init2(CgState S, const int* _
 }
 
 // alpha = <r,z> / <p,q>; x += alpha p; r -= alpha q; z = K r; flag on ||r|| <= tol ||b||
+template <bool LK>
 __global__ __launch_bounds__(kCgThreads) void k_cg_alpha(CgState S, const int* __restrict__ act, double tol2) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
+  const int n = S.npw_pad;
   double pq = 0.0;
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 p = S.p[o + k], q = S.q[o + k];
-    pq += p.re * q.re + p.im * q.im;
+  for (int k0 = threadIdx.x; k0 < n; k0 += kCgThreads * kU) {
+    Z64 p[kU], q[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        p[u] = S.p[o + k];
+        q[u] = S.q[o + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u * kCgThreads < n) pq += p[u].re * q[u].re + p[u].im * q[u].im;
   }
   pq = block_sum(pq, sh);
   const double alpha = (pq > 0.0) ? S.rz[s] / pq : 0.0;
   const double iT = S.invT[s];
   double rr = 0.0;
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 p = S.p[o + k], q = S.q[o + k];
-    Z64 x = S.x[o + k], r = S.r[o + k];
-    x = zmk(x.re + alpha * p.re, x.im + alpha * p.im);
-    r = zmk(r.re - alpha * q.re, r.im - alpha * q.im);
-    S.x[o + k] = x;
-    S.r[o + k] = r;
-    rr += r.re * r.re + r.im * r.im;
-    S.z[o + k] = zscale(r, precond(S, s, k, iT));
+  for (int k0 = threadIdx.x; k0 < n; k0 += kCgThreads * kU) {
+    Z64 p[kU], q[kU], x[kU], r[kU];
+    double t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        p[u] = S.p[o + k];
+        q[u] = S.q[o + k];
+        x[u] = S.x[o + k];
+        r[u] = S.r[o + k];
+        t[u] = precond_load<LK>(S, s, k);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        const Z64 xn = zmk(x[u].re + alpha * p[u].re, x[u].im + alpha * p[u].im);
+        const Z64 rn = zmk(r[u].re - alpha * q[u].re, r[u].im - alpha * q[u].im);
+        S.x[o + k] = xn;
+        S.r[o + k] = rn;
+        rr += rn.re * rn.re + rn.im * rn.im;
+        S.z[o + k] = zscale(rn, precond_eval<LK>(t[u], iT));
+      }
+    }
   }
   rr = block_sum(rr, sh);
   if (threadIdx.x == 0) {
@@ -165,16 +212,39 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_beta(CgState S, const int* __
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
+  const int n = S.npw_pad;
   double rz = 0.0;
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 r = S.r[o + k], z = S.z[o + k];
-    rz += r.re * z.re + r.im * z.im;
+  for (int k0 = threadIdx.x; k0 < n; k0 += kCgThreads * kU) {
+    Z64 r[kU], z[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        r[u] = S.r[o + k];
+        z[u] = S.z[o + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u * kCgThreads < n) rz += r[u].re * z[u].re + r[u].im * z[u].im;
   }
   rz = block_sum(rz, sh);
   const double beta = rz / S.rz[s];
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 z = S.z[o + k], p = S.p[o + k];
-    S.p[o + k] = zmk(z.re + beta * p.re, z.im + beta * p.im);
+  for (int k0 = threadIdx.x; k0 < n; k0 += kCgThreads * kU) {
+    Z64 z[kU], p[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        z[u] = S.z[o + k];
+        p[u] = S.p[o + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) S.p[o + k] = zmk(z[u].re + beta * p[u].re, z[u].im + beta * p[u].im);
+    }
   }
   if (threadIdx.x == 0) S.rz[s] = rz;
 }
@@ -305,33 +375,62 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_init2(Cg32State S, const in
 // and beta = (r, z) new / old for the direction update that follows; inner
 // flag 1 once ||r||^2 <= tol2 ||r0||^2. (r, z) is taken with z before any
 // projection: r stays in range(P_c), so it equals (r, P_c z).
+template <bool LK>
 __global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const int* __restrict__ act, double tol2) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
+  const int n = S.npw_pad;
   double pq = 0.0;
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z32 p = S.p[o + k], q = S.q[o + k];
-    pq += (double)p.re * q.re + (double)p.im * q.im;
+  for (int k0 = threadIdx.x; k0 < n; k0 += kCgThreads * kU) {
+    Z32 p[kU], q[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        p[u] = S.p[o + k];
+        q[u] = S.q[o + k];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u * kCgThreads < n) pq += (double)p[u].re * q[u].re + (double)p[u].im * q[u].im;
   }
   pq = block_sum(pq, sh);
   const double rz_old = S.rz[s];
   const float alpha = (float)((pq > 0.0) ? rz_old / pq : 0.0);
   const double iT = S.invT[s];
   double rr = 0.0, rz = 0.0;
-  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z32 p = S.p[o + k], q = S.q[o + k];
-    Z32 d = S.d[o + k], r = S.r[o + k];
-    d = zmk(d.re + alpha * p.re, d.im + alpha * p.im);
-    r = zmk(r.re - alpha * q.re, r.im - alpha * q.im);
-    S.d[o + k] = d;
-    S.r[o + k] = r;
-    rr += (double)r.re * r.re + (double)r.im * r.im;
-    const float t = (float)precond(S, s, k, iT);
-    const Z32 z = zmk(r.re * t, r.im * t);
-    S.z[o + k] = z;
-    rz += (double)r.re * z.re + (double)r.im * z.im;
+  for (int k0 = threadIdx.x; k0 < n; k0 += kCgThreads * kU) {
+    Z32 p[kU], q[kU], d[kU], r[kU];
+    double t[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        p[u] = S.p[o + k];
+        q[u] = S.q[o + k];
+        d[u] = S.d[o + k];
+        r[u] = S.r[o + k];
+        t[u] = precond_load<LK>(S, s, k);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int k = k0 + u * kCgThreads;
+      if (k < n) {
+        const Z32 dn = zmk(d[u].re + alpha * p[u].re, d[u].im + alpha * p[u].im);
+        const Z32 rn = zmk(r[u].re - alpha * q[u].re, r[u].im - alpha * q[u].im);
+        S.d[o + k] = dn;
+        S.r[o + k] = rn;
+        rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+        const float tk = (float)precond_eval<LK>(t[u], iT);
+        const Z32 z = zmk(rn.re * tk, rn.im * tk);
+        S.z[o + k] = z;
+        rz += (double)rn.re * z.re + (double)rn.im * z.im;
+      }
+    }
   }
   rr = block_sum(rr, sh);
   rz = block_sum(rz, sh);
@@ -428,7 +527,11 @@ void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg_init2<<<n, kCgThreads, 0, st>>>(s, act);
 }
 void launch_cg_alpha(const CgState& s, const int* act, int n, double tol2, hipStream_t st) {
-  if (n > 0) k_cg_alpha<<<n, kCgThreads, 0, st>>>(s, act, tol2);
+  if (n <= 0) return;
+  if (s.kprec)
+    k_cg_alpha<true><<<n, kCgThreads, 0, st>>>(s, act, tol2);
+  else
+    k_cg_alpha<false><<<n, kCgThreads, 0, st>>>(s, act, tol2);
 }
 void launch_cg_beta(const CgState& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg_beta<<<n, kCgThreads, 0, st>>>(s, act);
@@ -474,7 +577,11 @@ void launch_cg32_init2(const Cg32State& s, const int* act, int n, hipStream_t st
   if (n > 0) k_cg32_init2<<<n, kCgThreads, 0, st>>>(s, act);
 }
 void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st) {
-  if (n > 0) k_cg32_alpha<<<n, kCgThreads, 0, st>>>(s, act, tol2);
+  if (n <= 0) return;
+  if (s.kprec)
+    k_cg32_alpha<true><<<n, kCgThreads, 0, st>>>(s, act, tol2);
+  else
+    k_cg32_alpha<false><<<n, kCgThreads, 0, st>>>(s, act, tol2);
 }
 void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg32_beta<<<n, kCgThreads, 0, st>>>(s, act);
