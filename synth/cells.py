@@ -55,6 +55,8 @@ LARGE = CellSpec("large_L32_512at_30Ry", 4, 32.0, 30.0, 512, 1024, 32)
 # 32 occupied bands and 4 fields: its ground state takes minutes on the host, where the
 # 1024-band one takes hours.
 LARGE_GRID = CellSpec("large_grid_L32_512at_30Ry", 4, 32.0, 30.0, 512, 32, 4)
+# A 108^3 grid (radices 12 x 9), the other size whose FP64 plane exceeds LDS.
+GRID108 = CellSpec("grid108_L24_64at_38Ry", 5, 24.0, 38.0, 64, 16, 4)
 
 
 def batched_specs(n_systems: int = 32) -> list[CellSpec]:
