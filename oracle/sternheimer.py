@@ -4,7 +4,10 @@ Sec. II.A states that the density response is evaluated within DFPT by
 solving the Sternheimer equation; the steps below are the standard DFPT
 definitions that statement refers to, written out plainly:
 
-  b_{v,i}  = -P_c [dV_i psi_v]            (product formed on the grid, exact)
+  b_{v,i}  = -P_c [dV_i psi_v]            (product formed on the grid, exact);
+             a b of norm <= 1e-12 ||dV_i psi_v|| is zero (reading: dV_i psi_v then
+             lies in the occupied span, e.g. dV_i constant, and what the projection
+             leaves is its rounding, which the projected operator cannot resolve)
   A_v      = P_c (H - eps_v) P_c          (SPD on range(P_c) when eps_v < eps_LUMO)
   solve A_v x = b by preconditioned CG from x = 0 with z = P_c (K_v o r), where
   K_v(G)   = (27 + 18y + 12y^2 + 8y^3) / (27 + 18y + 12y^2 + 8y^3 + 16y^4),
@@ -39,12 +42,18 @@ def band_kinetic(cell: OracleCell, psi: np.ndarray) -> np.ndarray:
     return np.maximum(t, 0.5 * cell.b ** 2)
 
 
+RHS_CUT = 1e-12
+
+
 def rhs(cell: OracleCell, psi: np.ndarray, dv_r: np.ndarray, bands, perts) -> np.ndarray:
-    """b for the pairs (bands[k], perts[k]): -P_c of the sphere part of dV_i psi_v."""
+    """b for the pairs (bands[k], perts[k]): -P_c of the sphere part of dV_i psi_v, or zero
+    when that is at most RHS_CUT of the unprojected product."""
     out = np.empty((len(bands), cell.npw), dtype=np.complex128)
     for k, (v, i) in enumerate(zip(bands, perts)):
-        f = dv_r[i][None] * cell.to_grid(psi[v])
-        out[k] = -project(psi, cell.from_grid(f))[0]
+        f = cell.from_grid(dv_r[i][None] * cell.to_grid(psi[v]))
+        out[k] = -project(psi, f)[0]
+        if np.linalg.norm(out[k]) <= RHS_CUT * np.linalg.norm(f):
+            out[k] = 0.0
     return out
 
 

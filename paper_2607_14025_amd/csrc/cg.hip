@@ -82,8 +82,6 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __
   }
 }
 
-// q = A x for a guess x: r = b - q; keep the guess only when ||r|| is finite
-// and below ||b||, else x = 0, r = b. rejected[s] = 1 when dropped.
 // r = b - q for a guess x, with q = A x given in FP64 (q32 == null) or FP32;
 // the guess is kept only if ||r|| is finite and below ||b||, else x = 0, r = b.
 __global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int* __restrict__ act,
@@ -117,8 +115,9 @@ __global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int
     }
   }
   if (threadIdx.x == 0) {
-    rejected[s] = ok ? 0 : 1;
-    S.tres[s] = ok ? sqrt(rr / S.bb[s]) : 1.0;
+    const bool zero_b = !(S.bb[s] > 0.0);  // b = 0: x = 0 is exact, nothing was rejected
+    rejected[s] = (ok || zero_b) ? 0 : 1;
+    S.tres[s] = ok ? sqrt(rr / S.bb[s]) : (zero_b ? 0.0 : 1.0);
   }
 }
 
@@ -486,10 +485,27 @@ __global__ __launch_bounds__(kCgThreads) void k_outer_resid(CgState S, const int
 }
 
 // x = 0, r = b, bb = ||b||^2 (outer loop start); flag 2 when b = 0
-__global__ __launch_bounds__(kCgThreads) void k_outer_init(CgState S, const int* __restrict__ act) {
+// bb[s] = ||y_s||^2 over one row (the right-hand side before its projection).
+__global__ __launch_bounds__(kCgThreads) void k_row_norm2(const Z64* __restrict__ y, int ld, double* __restrict__ out) {
+  __shared__ double sh[kCgThreads / 64];
+  const size_t o = (size_t)blockIdx.x * ld;
+  double t = 0.0;
+  for (int k = threadIdx.x; k < ld; k += kCgThreads) {
+    const Z64 v = y[o + k];
+    t += v.re * v.re + v.im * v.im;
+  }
+  t = block_sum(t, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = t;
+}
+
+// x = 0, r = b, counters. S.bb holds ||dV psi_v||^2 of the unprojected product on entry:
+// a projected b with ||b||^2 <= cut2 ||dV psi_v||^2 is rounding left by the projection
+// of a product that lies in the occupied span, and is set to zero (x = 0, done).
+__global__ __launch_bounds__(kCgThreads) void k_outer_init(CgState S, const int* __restrict__ act, double cut2) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   const size_t o = (size_t)s * S.npw_pad;
+  const double raw = S.bb[s];
   double bb = 0.0;
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
     const Z64 b = S.b[o + k];
@@ -498,6 +514,13 @@ __global__ __launch_bounds__(kCgThreads) void k_outer_init(CgState S, const int*
     S.r[o + k] = b;
   }
   bb = block_sum(bb, sh);
+  if (bb <= cut2 * raw) {
+    for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+      S.b[o + k] = zmk(0.0, 0.0);
+      S.r[o + k] = zmk(0.0, 0.0);
+    }
+    bb = 0.0;
+  }
   if (threadIdx.x == 0) {
     S.bb[s] = bb;
     S.iters[s] = 0;
@@ -592,8 +615,11 @@ void launch_add_d(Z64* x, const Z32* d, int ld, const int* act, int n, hipStream
 void launch_outer_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st) {
   if (n > 0) k_outer_resid<<<n, kCgThreads, 0, st>>>(s, act, tol);
 }
-void launch_outer_init(const CgState& s, const int* act, int n, hipStream_t st) {
-  if (n > 0) k_outer_init<<<n, kCgThreads, 0, st>>>(s, act);
+void launch_row_norm2(const Z64* y, int ld, int n, double* out, hipStream_t st) {
+  if (n > 0) k_row_norm2<<<n, kCgThreads, 0, st>>>(y, ld, out);
+}
+void launch_outer_init(const CgState& s, const int* act, int n, double cut, hipStream_t st) {
+  if (n > 0) k_outer_init<<<n, kCgThreads, 0, st>>>(s, act, cut * cut);
 }
 void launch_fill_zero32(Z32* p, size_t n, hipStream_t st) {
   if (n == 0) return;

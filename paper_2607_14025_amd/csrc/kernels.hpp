@@ -165,7 +165,8 @@ void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, h
 void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st);
 void launch_add_d(Z64* x, const Z32* d, int ld, const int* act, int n, hipStream_t st);
 void launch_outer_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st);
-void launch_outer_init(const CgState& s, const int* act, int n, hipStream_t st);
+void launch_row_norm2(const Z64* y, int ld, int n, double* out, hipStream_t st);
+void launch_outer_init(const CgState& s, const int* act, int n, double cut, hipStream_t st);
 void launch_fill_zero32(Z32* p, size_t n, hipStream_t st);
 
 int choose_nsplit_bf16(int M_pad, int ncols, int K, int target);

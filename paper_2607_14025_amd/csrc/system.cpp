@@ -685,6 +685,12 @@ int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, in
 
 // Per-solve arrays, right-hand sides b = -P_c [dV psi_v] and x = 0, r = b for the
 // solves of perturbations [i0, i1) x bands [v0, v0 + nb) (row s = (i - i0) nb + v - v0).
+// A right-hand side P_c dV psi_v whose norm is at most this fraction of ||dV psi_v|| is
+// zero: dV psi_v lies in the occupied span (dV constant, for one), and what the FP64
+// projection leaves is rounding, about n_occ * 1e-16 of the product at most. Left in,
+// part of it lies along the occupied states, which the projected operator cannot reduce.
+constexpr double kRhsCut = 1e-12;
+
 int setup_batch(stern_system* S, int i0, int i1, int v0, int nb, const double* dv_dev, double vecb) {
   hipStream_t st = S->stream;
   const HostBasis& hb = S->hb;
@@ -713,8 +719,9 @@ int setup_batch(stern_system* S, int i0, int i1, int v0, int nb, const double* d
   CHECKED(timed(S, STERN_K_XFWD, ns * ((double)N * hb.ncol * 16.0 + vecb), 0.0, [&] {
     launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, ns, cs.b, 2, nullptr, nullptr, -1.0 / (double)n3, st);
   }));
+  launch_row_norm2(cs.b, cs.npw_pad, ns, cs.bb, st);  // ||dV psi_v|| before the projection
   CHECKED(apply_pc_rows(S, cs.b, nullptr, ns));
-  launch_outer_init(cs, nullptr, ns, st);  // x = 0, r = b, ||b||, counters
+  launch_outer_init(cs, nullptr, ns, kRhsCut, st);  // x = 0, r = b, ||b||, counters
   HIPOK(hipStreamSynchronize(st));         // the host arrays above are released on return
   return 0;
 }

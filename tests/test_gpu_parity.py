@@ -189,3 +189,28 @@ def test_mixed_without_atoms(torch_cuda):
             assert rel_l2(dn, ref["dn"]).max() < 1e-6
     finally:
         s.close()
+
+
+def test_degenerate_fields(tiny_gpu):
+    """Fields the method maps to zero, mixed into one call with ordinary ones: an all-zero
+    field (b = 0: dn exactly 0, nothing to solve) and a constant field (P_c annihilates
+    c psi_v, and chi0 . const = 0); the ordinary fields still meet the oracle. Empty
+    inputs are refused."""
+    import paper_2607_14025_amd as P
+    t = tiny_gpu
+    s = t["sys"]
+    dv = np.concatenate([np.zeros_like(t["dv"][:1]), t["dv"][:2], np.full_like(t["dv"][:1], 0.7)])
+    for prec, bound in ((P.STERN_FP64, 1e-9), (P.STERN_MIXED, 1e-6)):
+        dn, info = s.apply_chi0(dv, tol=1e-10, precision=prec)
+        assert info["n_converged"] == info["n_solves"] == 4 * 16
+        assert np.isfinite(dn).all()
+        assert np.all(dn[0] == 0.0)
+        assert np.all(dn[3] == 0.0)  # every P_c (c psi_v) cut to zero: x = 0
+        assert info["max_true_resid"] <= 1e-10
+        assert rel_l2(dn[1:3], t["ref"]["dn"][:2]).max() < bound
+    with pytest.raises(P.SternError) as e:
+        s.apply_chi0(t["dv"][:0])
+    assert e.value.code == -1
+    with pytest.raises(P.SternError) as e:
+        s.apply_chi0(t["dv"][:1], band_range=(3, 3))
+    assert e.value.code == -1
