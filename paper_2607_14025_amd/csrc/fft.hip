@@ -567,15 +567,16 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
 #pragma unroll
       for (int k = 0; k < MAXZ; ++k) {
         const int it = lane + 64 * k;
-        if (PF && it < nz * R1) {
-          const int l = it % nz, j = it / nz;
+        const int l = it % ZR, j = it / ZR;
+        if (PF && it < ZR * R1 && l < nz) {
 #pragma unroll
           for (int r = 0; r < R2; ++r) vreg[k][r] = vx[(size_t)(j + r * R1) * N + y0 + l];
         }
       }
       // inverse stage 1 (radix R1) from the active z of Q
-      for (int it = lane; it < nz * R2; it += 64) {
-        const int l = it % nz, j = it / nz;
+      for (int it = lane; it < ZR * R2; it += 64) {
+        const int l = it % ZR, j = it / ZR;
+        if (l >= nz) continue;
         Z<T> v[R1];
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
@@ -594,8 +595,8 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
 #pragma unroll
         for (int k = 0; k < MAXZ; ++k) {
           const int it = lane + 64 * k;
-          if (it < nz * R1) {
-            const int l = it % nz, j = it / nz;
+          const int l = it % ZR, j = it / ZR;
+          if (it < ZR * R1 && l < nz) {
 #pragma unroll
             for (int r = 0; r < R2; ++r) v[k][r] = Sw[(j + r * R1) * ZR + l];
           }
@@ -604,8 +605,8 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
 #pragma unroll
         for (int k = 0; k < MAXZ; ++k) {
           const int it = lane + 64 * k;
-          if (it < nz * R1) {
-            const int l = it % nz, j = it / nz;
+          const int l = it % ZR, j = it / ZR;
+          if (it < ZR * R1 && l < nz) {
 #pragma unroll
             for (int r = 1; r < R2; ++r) v[k][r] = v[k][r] * twid<+1>(tw, r * j);
             dft<R2, +1>(v[k]);
@@ -620,8 +621,9 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       }
       wave_sync();
       // forward stage 2 (radix R1), active z back into Q
-      for (int it = lane; it < nz * R2; it += 64) {
-        const int l = it % nz, j = it / nz;
+      for (int it = lane; it < ZR * R2; it += 64) {
+        const int l = it % ZR, j = it / ZR;
+        if (l >= nz) continue;
         Z<T> v[R1];
 #pragma unroll
         for (int r = 0; r < R1; ++r) v[r] = Sw[(j + r * R2) * ZR + l];
