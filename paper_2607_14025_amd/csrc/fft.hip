@@ -469,6 +469,16 @@ struct PlaneWCfg {
   static constexpr int MAXZ = (ZR * RM + 63) / 64;         // items per lane in a z stage
 };
 
+// Indices [lo, hi] of a y or z transform that no sphere function reaches on any grid
+// the basis builds: the grid holds products of two of them (N >= 4 nmax + 1), so the
+// active indices [0, nmax] and [N - nmax, N) lie within [0, m] and [N - m, N) for
+// m = (N - 1) / 4. Inside unrolled stage loops this is a compile-time constant, and
+// the inputs it zeroes and the outputs it drops take no arithmetic.
+template <int N>
+__device__ constexpr bool idle_range(int lo, int hi) {
+  return lo > (N - 1) / 4 && hi < N - (N - 1) / 4;
+}
+
 template <int N, class T, int W, int ZR>
 constexpr size_t planew_lds_bytes(int nza) {
   return ((size_t)nza * (N + 1) + N + (size_t)W * N * ZR) * sizeof(Z<T>);
@@ -520,7 +530,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
     for (int r = 0; r < R1; ++r) {
       const int y = j + r * R2;
       v[r] = zero;
-      if (act(y)) {
+      if (!idle_range<N>(r * R2, r * R2 + R2 - 1) && act(y)) {
         const int col = yc[y * nza + f];
         if (col >= 0) v[r] = tp[col];
       }
@@ -582,7 +592,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
         for (int r = 0; r < R1; ++r) {
           const int z = j + r * R2;
           v[r] = zero;
-          if (act(z)) v[r] = Q[fz(z) * QLD + y0 + l];
+          if (!idle_range<N>(r * R2, r * R2 + R2 - 1) && act(z)) v[r] = Q[fz(z) * QLD + y0 + l];
         }
         dft<R1, +1>(v);
 #pragma unroll
@@ -633,7 +643,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
 #pragma unroll
         for (int r = 0; r < R1; ++r) {
           const int z = j + r * R2;
-          if (act(z)) Q[fz(z) * QLD + y0 + l] = v[r];
+          if (!idle_range<N>(r * R2, r * R2 + R2 - 1) && act(z)) Q[fz(z) * QLD + y0 + l] = v[r];
         }
       }
       wave_sync();
@@ -665,7 +675,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) {
         const int y = k2 * R1 + k1;
-        if (act(y)) {
+        if (!idle_range<N>(k2 * R1, k2 * R1 + R1 - 1) && act(y)) {
           const int col = yc[y * nza + f];
           if (col >= 0) tp[col] = v[k2];
         }
