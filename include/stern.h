@@ -288,7 +288,8 @@ void stern_model_free(stern_model* m);
  *                        for; 0 = built-in default (2048)
  *   STERN_TUNE_GEMM16_WG the same for the split-BF16 reduces; 0 = default (512)
  *   STERN_TUNE_GEMM16_EXPAND tile of the split-BF16 expand (Y += Psi C, B D P):
- *                        0 = 256 x 128 per workgroup, 1 = 128 x 128 (two per CU) */
+ *                        0 = 256 x 128 per workgroup, 1 = 128 x 128 (two per CU),
+ *                        2 = 256 x 64 (two per CU) */
 #define STERN_TUNE_PLANE64 0
 #define STERN_TUNE_PLANE32 1
 #define STERN_TUNE_GEMM64_WG 2

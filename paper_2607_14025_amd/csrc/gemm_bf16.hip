@@ -225,13 +225,14 @@ __device__ __forceinline__ bf16x8 swap_b(bf16x8 c) {
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m], A given transposed (AT [K][2 M_pad]
 // hi/lo) and C as k_sum_split writes it. PUPD: Y is left as it is and the sum
 // goes into the search direction instead, P[s] = (Y[s] + A C) + beta[s] P[s]
-// (s = yidx[n]), the CG direction update from the projected z. 8 waves: wave (wk, wn) owns rows
-// [16 KB wk, 16 KB (wk + 1)) and columns [64 wn, 64 wn + 64) of the
-// (64 KB) x 128 tile; KB = 4 (256 x 128, 1 workgroup per CU) or 2 (128 x 128,
-// fewer registers, 2 workgroups per CU, so one's Y update overlaps another's
-// products). Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
-template <int KB, bool PUPD>
-__global__ __launch_bounds__(kThreads8, KB == 4 ? 2 : 4) void k_expand_bf16s(const __bf16* __restrict__ ATh,
+// (s = yidx[n]), the CG direction update from the projected z. 4 WN waves: wave (wk, wn) owns
+// rows [16 KB wk, 16 KB (wk + 1)) and columns [64 wn, 64 wn + 64) of the
+// (64 KB) x (64 WN) tile: KB = 4, WN = 2 (256 x 128, 1 workgroup per CU); KB = 2, WN = 2
+// (128 x 128, fewer registers, 2 workgroups per CU); KB = 4, WN = 1 (256 x 64, 2 workgroups
+// per CU). With two workgroups on a CU one's Y update overlaps the other's products.
+// Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
+template <int KB, bool PUPD, int WN>
+__global__ __launch_bounds__(256 * WN, KB == 4 ? 2 : 4) void k_expand_bf16s(const __bf16* __restrict__ ATh,
                                                             const __bf16* __restrict__ ATl, int M_pad, int K,
                                                             const __bf16* __restrict__ Cs, Z32* __restrict__ Y,
                                                             int ldy, const int* __restrict__ yidx, int ncols,
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(kThreads8, KB == 4 ? 2 : 4) void k_expand_bf16s(con
   const int wk = wave & 3, wn = wave >> 2;
   const int k0 = blockIdx.x * (64 * KB) + wk * 16 * KB;
   if (k0 >= K) return;  // K is a multiple of 64; no barrier below
-  const int n0 = blockIdx.y * kEN + wn * 64;
+  const int n0 = blockIdx.y * (64 * WN) + wn * 64;
   const size_t plane = (size_t)ncols * M_pad * 2;
   int nn[4];
   bool nv[4];
@@ -443,15 +444,20 @@ void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, floa
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
                         const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P, const double* beta) {
   if (ncols <= 0) return;
-  const dim3 g2((K + 127) / 128, (ncols + kEN - 1) / kEN), g4((K + kET - 1) / kET, (ncols + kEN - 1) / kEN);
+  const dim3 g2((K + 127) / 128, (ncols + kEN - 1) / kEN), g4((K + kET - 1) / kET, (ncols + kEN - 1) / kEN),
+      g41((K + kET - 1) / kET, (ncols + 63) / 64);
   if (variant == 1 && P)
-    k_expand_bf16s<2, true><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+    k_expand_bf16s<2, true, 2><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
   else if (variant == 1)
-    k_expand_bf16s<2, false><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+    k_expand_bf16s<2, false, 2><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+  else if (variant == 2 && P)
+    k_expand_bf16s<4, true, 1><<<g41, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+  else if (variant == 2)
+    k_expand_bf16s<4, false, 1><<<g41, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
   else if (P)
-    k_expand_bf16s<4, true><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+    k_expand_bf16s<4, true, 2><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
   else
-    k_expand_bf16s<4, false><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+    k_expand_bf16s<4, false, 2><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
 }
 
 }  // namespace stern

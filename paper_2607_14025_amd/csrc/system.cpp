@@ -1562,7 +1562,7 @@ int stern_tunable(stern_system* S, int which, int value) {
   }
   if (value >= 0) {
     if (which == STERN_TUNE_GEMM16_EXPAND) {
-      if (value > 1) return fail(STERN_ERR_INVALID_ARG, "expand variant must be 0 or 1");
+      if (value > 2) return fail(STERN_ERR_INVALID_ARG, "expand variant must be 0, 1 or 2");
     } else if (which == STERN_TUNE_PLANE64 || which == STERN_TUNE_PLANE32) {
       if (value > 2) return fail(STERN_ERR_INVALID_ARG, "plane kernel variant must be 0, 1 or 2");
       const bool fp64 = which == STERN_TUNE_PLANE64;
@@ -1672,7 +1672,7 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
                [&] { return apply_pc_rows(S, S->wq.as<Z64>(), nullptr, n_vec); }));
   CHECKED(tune(STERN_TUNE_GEMM16_WG, {128, 256, 512, 1024, 2048},
                [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
-  CHECKED(tune(STERN_TUNE_GEMM16_EXPAND, {0, 1},
+  CHECKED(tune(STERN_TUNE_GEMM16_EXPAND, {0, 1, 2},
                [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
   CHECKED(ensure_workspace(S, n_vec));
   g_tune_report = report + "}";

@@ -32,7 +32,8 @@ def test_tunable_round_trip_and_errors(tuned_tiny):
     s.tunable(TUNE_PLANE64, old)
     assert s.tunable(TUNE_GEMM16_WG, 256) == 256
     s.tunable(TUNE_GEMM16_WG, 0)
-    for which, value in ((7, 0), (TUNE_PLANE64, 3), (TUNE_GEMM16_WG, 1 << 20)):
+    from paper_2607_14025_amd.stern import TUNE_GEMM16_EXPAND
+    for which, value in ((7, 0), (TUNE_PLANE64, 3), (TUNE_GEMM16_WG, 1 << 20), (TUNE_GEMM16_EXPAND, 3)):
         with pytest.raises(SternError) as e:
             s.tunable(which, value)
         assert e.value.code == -1
@@ -64,7 +65,7 @@ def test_every_variant_keeps_parity(tuned_tiny):
                                             TUNE_GEMM16_EXPAND)
     t = tuned_tiny
     s = t["sys"]
-    for p64, p32, g64, g16, ex in ((0, 0, 256, 128, 0), (1, 1, 4096, 2048, 1), (2, 2, 0, 0, 1), (1, 0, 0, 0, 0)):
+    for p64, p32, g64, g16, ex in ((0, 0, 256, 128, 0), (1, 1, 4096, 2048, 1), (2, 2, 0, 0, 2), (1, 0, 0, 0, 0)):
         s.tunable(TUNE_PLANE64, p64)
         s.tunable(TUNE_PLANE32, p32)
         s.tunable(TUNE_GEMM64_WG, g64)
@@ -74,6 +75,13 @@ def test_every_variant_keeps_parity(tuned_tiny):
         assert info["n_converged"] == 48 and rel_l2(dn, t["ref"]["dn"]).max() < 1e-9
         dm, info = s.apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED)
         assert info["n_converged"] == 48 and rel_l2(dm, t["ref"]["dn"]).max() < 1e-6
+    # the expand tiles differ only in how outputs are spread over workgroups: each output
+    # takes the same products in the same order, so the mixed path is bitwise the same
+    out = []
+    for ex in (0, 1, 2):
+        s.tunable(TUNE_GEMM16_EXPAND, ex)
+        out.append(s.apply_chi0(t["dv"], tol=1e-10, precision=STERN_MIXED)[0])
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
 
 
 def test_autotune_and_cache(tuned_tiny, tmp_path):
@@ -86,7 +94,7 @@ def test_autotune_and_cache(tuned_tiny, tmp_path):
     assert chosen["plane64"] in (0, 1, 2) and chosen["plane32"] in (0, 1, 2)
     assert chosen["gemm64_wg"] in (256, 512, 1024, 2048, 4096)
     assert chosen["gemm16_wg"] in (128, 256, 512, 1024, 2048)
-    assert chosen["gemm16_expand"] in (0, 1)
+    assert chosen["gemm16_expand"] in (0, 1, 2)
     assert len(cache.read_text().splitlines()) == 5
     n2, chosen2 = s.autotune(n_vec=64, cache_path=str(cache))
     assert n2 == 0 and chosen2 == chosen
