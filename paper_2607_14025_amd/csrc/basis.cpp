@@ -43,9 +43,12 @@ std::string build_basis(const CellParams& c, HostBasis& hb, bool sphere_only) {
   const double r2 = c.ecut * c.L * c.L / (kTwoPi * kTwoPi);
   const int nm = isqrt_floor(r2);
   const int N = hb.N;
-  // The compact plane kernels take N >= 4 nm + 1 as given: they skip the y and z
+  // The grid holds the 4 Ecut sphere of V_loc (|n| <= nq = floor(2 sqrt(r2))) without
+  // aliasing, so V_loc(r) is exact in the basis. As nq >= 2 nm this also gives
+  // N >= 4 nm + 1, which the compact plane kernels take as given: they skip the y and z
   // ranges outside [0, (N - 1) / 4] and [N - (N - 1) / 4, N) without a test.
-  if (N < (sphere_only ? 2 * nm + 1 : 2 * (2 * nm) + 1)) return "fft_n too small for the 4 ecut sphere";
+  const int nq = isqrt_floor(4.0 * r2);
+  if (N < (sphere_only ? 2 * nm + 1 : 2 * nq + 1)) return "fft_n too small for the 4 ecut sphere";
 
   // canonical order: |n|^2, then n_x, n_y, n_z
   std::vector<std::tuple<int, int, int, int>> pts;

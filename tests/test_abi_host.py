@@ -58,6 +58,11 @@ def test_invalid_arguments_rejected():
     assert e.value.code == -1
     with pytest.raises(stern.SternError):
         stern.basis_info(10.0, 10.0, fft_n=12)  # too small for the 4 Ecut sphere
+    with pytest.raises(stern.SternError):
+        # 4 nmax + 1 = 9 holds the differences of sphere points, but the 4 Ecut sphere of
+        # V_loc reaches |n| = 5, which a 9-point grid would alias
+        stern.basis_info(10.0, 2.5, fft_n=9)
+    assert stern.basis_info(10.0, 2.0, fft_n=9)[1] == 9
     L = stern.lib()
     assert L.stern_basis_info(None, None, None, None) == -1
     assert b"NULL" in L.stern_last_error()
