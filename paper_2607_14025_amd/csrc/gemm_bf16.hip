@@ -67,17 +67,18 @@ constexpr int kThreads8 = 512;
 
 // C[n][m] partial over this split's K range = sum_k conj(A[m][k]) X[xidx[n]][k].
 // 8 waves: wave (wm, wn) owns rows [32 wm, 32 wm + 32) and columns
-// [64 wn, 64 wn + 64) of the 128 x 128 tile. The 128 x 16 slice of X of a K
-// step is split into bf16 hi/lo once and staged in LDS (double-buffered);
-// A's fragments of the next step are loaded while this step's MFMAs run.
-// Re C = A . X and Im C = A' . X along the interleaved reduction index, with
-// A' = (-a_im, a_re) formed from A in registers.
+// [64 wn, 64 wn + 64) of the 128 x 128 tile. A K step covers 32 complex, two MFMA
+// sub-steps of 16: the 128 x 32 slice of X is split into bf16 hi/lo once and staged
+// in LDS (double-buffered, [sub-step][column][group of 4 complex]); A's fragments of
+// the next step are loaded while this step's MFMAs run. Re C = A . X and
+// Im C = A' . X along the interleaved reduction index, with A' = (-a_im, a_re)
+// formed from A in registers.
 __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __restrict__ Ahi,
                                                             const __bf16* __restrict__ Alo, int M_pad,
                                                             const Z32* __restrict__ X, int ldx,
                                                             const int* __restrict__ xidx, int ncols, int K,
                                                             int kchunk, Z32* __restrict__ cpart) {
-  __shared__ bf16x8 xs[2][2][kWN * 4];  // [buffer][hi, lo][column * 4 + group of 4 complex]
+  __shared__ bf16x8 xs[2][2][2][kWN * 4];  // [buffer][hi, lo][sub-step][column * 4 + group of 4 complex]
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int wm = wave & 3, wn = wave >> 2;
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
   const bool live = m0 < M_pad;
   const int kb = split * kchunk;
   const int ke = min(K, kb + kchunk);
-  // staging: thread -> (column tn, group tq of 4 complex)
+  // staging: thread -> (column tn, 8 complex from 8 tq): groups 2 tq and 2 tq + 1 of the step
   const int tn = threadIdx.x >> 2, tq = threadIdx.x & 3;
   const int ncol = n0 + tn;
   const bool xval = ncol < ncols;
@@ -108,27 +109,34 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
       cre[bi][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
       cim[bi][nb] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-  Z32 xv[4];
+  Z32 xv[8];
   auto load_x = [&](int kc) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < 8; ++t) {
       xv[t] = zmk(0.f, 0.f);
-      if (xval) xv[t] = xrow[kc + 4 * tq + t];
+      if (xval) xv[t] = xrow[kc + 8 * tq + t];
     }
   };
   auto put_x = [&](int buf) {
-    bf16x8 hi, lo;
-    split_z4(xv, hi, lo);
-    xs[buf][0][tn * 4 + tq] = hi;
-    xs[buf][1][tn * 4 + tq] = lo;
-  };
-  bf16x8 a_hi[2], a_lo[2];
-  auto load_a = [&](int kc) {
-    const int k = kc + 4 * g;
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi) {
-      a_hi[bi] = *reinterpret_cast<const bf16x8*>(ah[bi] + 2 * k);
-      a_lo[bi] = *reinterpret_cast<const bf16x8*>(al[bi] + 2 * k);
+    for (int h = 0; h < 2; ++h) {
+      const int G = 2 * tq + h;  // group of 4 complex within the step
+      bf16x8 hi, lo;
+      split_z4(*reinterpret_cast<const Z32(*)[4]>(xv + 4 * h), hi, lo);
+      xs[buf][0][G >> 2][tn * 4 + (G & 3)] = hi;
+      xs[buf][1][G >> 2][tn * 4 + (G & 3)] = lo;
+    }
+  };
+  bf16x8 a_hi[2][2], a_lo[2][2];
+  auto load_a = [&](int kc) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      const int k = kc + 16 * kk + 4 * g;
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        a_hi[kk][bi] = *reinterpret_cast<const bf16x8*>(ah[bi] + 2 * k);
+        a_lo[kk][bi] = *reinterpret_cast<const bf16x8*>(al[bi] + 2 * k);
+      }
     }
   };
   if (kb < ke) {
@@ -138,34 +146,38 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
   }
   __syncthreads();
   int buf = 0;
-  for (int kc = kb; kc < ke; kc += 16) {
-    const bool more = kc + 16 < ke;
-    if (more) load_x(kc + 16);  // in flight during the MFMAs
+  for (int kc = kb; kc < ke; kc += 32) {
+    const bool more = kc + 32 < ke;
+    if (more) load_x(kc + 32);  // in flight during the MFMAs
     if (live) {
-      bf16x8 c_hi[2], c_lo[2], b_hi[2], b_lo[2];
+      bf16x8 c_hi[2][2], c_lo[2][2], b_hi[2][2], b_lo[2][2];
 #pragma unroll
-      for (int bi = 0; bi < 2; ++bi) {
-        c_hi[bi] = a_hi[bi];
-        c_lo[bi] = a_lo[bi];
-        b_hi[bi] = rot_neg(c_hi[bi]);
-        b_lo[bi] = rot_neg(c_lo[bi]);
-      }
-      if (more) load_a(kc + 16);
-#pragma unroll
-      for (int nb = 0; nb < 4; ++nb) {
-        const int col = wn * 64 + nb * 16 + l16;
-        const bf16x8 x_hi = xs[buf][0][col * 4 + g];
-        const bf16x8 x_lo = xs[buf][1][col * 4 + g];
+      for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi) {
-          cre[bi][nb] = mfma(c_hi[bi], x_hi, cre[bi][nb]);
-          cre[bi][nb] = mfma(c_hi[bi], x_lo, cre[bi][nb]);
-          cre[bi][nb] = mfma(c_lo[bi], x_hi, cre[bi][nb]);
-          cim[bi][nb] = mfma(b_hi[bi], x_hi, cim[bi][nb]);
-          cim[bi][nb] = mfma(b_hi[bi], x_lo, cim[bi][nb]);
-          cim[bi][nb] = mfma(b_lo[bi], x_hi, cim[bi][nb]);
+          c_hi[kk][bi] = a_hi[kk][bi];
+          c_lo[kk][bi] = a_lo[kk][bi];
+          b_hi[kk][bi] = rot_neg(c_hi[kk][bi]);
+          b_lo[kk][bi] = rot_neg(c_lo[kk][bi]);
         }
-      }
+      if (more) load_a(kc + 32);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+        for (int nb = 0; nb < 4; ++nb) {
+          const int col = wn * 64 + nb * 16 + l16;
+          const bf16x8 x_hi = xs[buf][0][kk][col * 4 + g];
+          const bf16x8 x_lo = xs[buf][1][kk][col * 4 + g];
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi) {
+            cre[bi][nb] = mfma(c_hi[kk][bi], x_hi, cre[bi][nb]);
+            cre[bi][nb] = mfma(c_hi[kk][bi], x_lo, cre[bi][nb]);
+            cre[bi][nb] = mfma(c_lo[kk][bi], x_hi, cre[bi][nb]);
+            cim[bi][nb] = mfma(b_hi[kk][bi], x_hi, cim[bi][nb]);
+            cim[bi][nb] = mfma(b_hi[kk][bi], x_lo, cim[bi][nb]);
+            cim[bi][nb] = mfma(b_lo[kk][bi], x_hi, cim[bi][nb]);
+          }
+        }
     }
     if (more) put_x(buf ^ 1);
     __syncthreads();
@@ -429,7 +441,7 @@ void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z
                         int ncols, int K, Z32* cpart, int nsplit, hipStream_t st) {
   if (ncols <= 0) return;
   int kchunk = (K + nsplit - 1) / nsplit;
-  kchunk = (kchunk + 15) / 16 * 16;
+  kchunk = (kchunk + 31) / 32 * 32;  // whole K steps of 32 complex; K is a multiple of 64
   dim3 grid((ncols + kWN - 1) / kWN, nsplit, (M_pad + kWM - 1) / kWM);
   k_reduce_bf16w<<<grid, kThreads8, 0, st>>>(Ahi, Alo, M_pad, X, ldx, xidx, ncols, K, kchunk, cpart);
 }
