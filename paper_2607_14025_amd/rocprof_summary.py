@@ -14,6 +14,16 @@
       deterministic), and so to the bench's algorithmic bytes for them; the ratio
       measured / algorithmic goes to TRAFFIC_JSON under LABEL, with the source hash bench.py
       checks.
+
+  python3 -m paper_2607_14025_amd.rocprof_summary mfma CSV TITLE COMMAND [SIMDS] > summary.md
+      MFMA use of the GEMM and net kernels from one --pmc run with SQ_INSTS_VALU_MFMA_MOPS_BF16,
+      SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE over the bench's
+      final apply (the dispatches after the last but one Delta n launch): MFMA FLOPs per dispatch
+      (MOPS x 512) and the busy fraction of the matrix units, busy cycles / (active cycles x SIMDS).
+      The CSV sums GRBM_GUI_ACTIVE over the XCDs, so it is divided by their count (the
+      counter set's own expression takes the largest instance). SIMDS, the XCD count and the
+      clock come from the run's agent file (run_agent_info.csv beside CSV), else 1024, 8 and
+      2.4 GHz.
 """
 from __future__ import annotations
 
@@ -164,6 +174,66 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
     ] + table) + "\n"
 
 
+MFMA_KERNELS = ("k_reduce_bf16w", "k_expand_bf16s", "k_zgemm_reduce", "k_zgemm_expand", "k_conv3")
+
+
+def _gpu_agent(csv_path: str):
+    """(SIMDs, XCDs, clock in GHz) of the GPU agent of a rocprofv3 run, or None."""
+    path = csv_path.replace("counter_collection", "agent_info")
+    if path == csv_path or not os.path.exists(path):
+        return None
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Agent_Type", "").strip('"') == "GPU":
+                return int(r["Simd_Count"]), int(r["Num_Xcc"]), float(r["Max_Engine_Clk_Fcompute"]) / 1e3
+    return None
+
+
+def mfma(csv_path: str, title: str, cmd: str, simds: int = 1024, xcds: int = 8, clock_ghz: float = 2.4) -> str:
+    agent = _gpu_agent(csv_path)
+    if agent:
+        simds, xcds, clock_ghz = agent
+    per = {}
+    with open(csv_path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            d = per.setdefault(int(r["Dispatch_Id"]), {"name": short_name(r["Kernel_Name"])})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    order = sorted(per)
+    dn = [i for i in order if per[i]["name"].startswith("k_plane_dn")]
+    if len(dn) < 2:
+        raise SystemExit(f"{csv_path}: fewer than two Delta n dispatches")
+    last = [i for i in order if dn[-2] < i <= dn[-1]]
+    agg = {}
+    for i in last:
+        d = per[i]
+        if not d["name"].startswith(MFMA_KERNELS):
+            continue
+        a = agg.setdefault(d["name"], {"n": 0, "bf16": 0.0, "f64": 0.0, "busy": 0.0, "active": 0.0})
+        a["n"] += 1
+        a["bf16"] += 512.0 * d.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0)
+        a["f64"] += 512.0 * d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        a["busy"] += d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        a["active"] += d.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+    rows = ["| kernel | dispatches | BF16 MFMA GFLOP / dispatch | FP64 MFMA GFLOP / dispatch | matrix units busy | "
+            f"MFMA TFLOP/s over the active cycles (at {clock_ghz:g} GHz) |", "|---|---:|---:|---:|---:|---:|"]
+    for n, a in sorted(agg.items(), key=lambda kv: -kv[1]["active"]):
+        busy = a["busy"] / (a["active"] * simds) if a["active"] > 0 else 0.0
+        secs = a["active"] / (clock_ghz * 1e9)
+        rate = (a["bf16"] + a["f64"]) / secs / 1e12 if secs > 0 else 0.0
+        rows.append(f"| `{n[:60]}` | {a['n']} | {a['bf16'] / a['n'] / 1e9:.2f} | {a['f64'] / a['n'] / 1e9:.2f} | "
+                    f"{100 * busy:.1f}% | {rate:.0f} |")
+    return "\n".join([
+        f"# {title}\n",
+        "Command (repository root, one MI355X, TMPDIR=/tmp):\n",
+        f"```\n{cmd}\n```\n",
+        f"Dispatches of the bench's final apply ({len(last)} in all, between the last two Delta n launches). "
+        "FLOPs are the counters' MFMA operations x 512. The busy fraction is the matrix units' busy cycles over "
+        f"the kernel's active cycles x {simds} SIMDs, the counter set's own MFMA-utilisation expression; the "
+        f"active cycles are GRBM_GUI_ACTIVE / {xcds}, as the CSV sums it over the XCDs. "
+        "Peaks: 2.5 PFLOP/s BF16 and 78.6 TFLOP/s FP64 (dense MFMA).\n",
+    ] + rows) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         sys.stdout.write(stats(argv[1], argv[2], argv[3]))
@@ -171,6 +241,8 @@ def main(argv):
             sys.stdout.write("\n" + launch_agreement(argv[1], argv[4], argv[5], argv[6]))
     elif len(argv) >= 9 and argv[0] == "traffic":
         sys.stdout.write(traffic(*argv[1:10]))
+    elif len(argv) >= 4 and argv[0] == "mfma":
+        sys.stdout.write(mfma(argv[1], argv[2], argv[3], *([int(argv[4])] if len(argv) > 4 else [])))
     else:
         sys.stdout.write(__doc__)
         return 2
