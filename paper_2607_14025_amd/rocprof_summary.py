@@ -94,12 +94,19 @@ def launch_agreement(db: str, bench_log: str, label: str, kernel: str) -> str:
 
 def _counter(path: str, counter: str):
     """[(dispatch id, kernel name, value)] of one counter, in dispatch order."""
+    return [(d, n, v) for d, n, v, _ in _counter_timed(path, counter)]
+
+
+def _counter_timed(path: str, counter: str):
+    """[(dispatch id, kernel name, value, duration in ns or None)] of one counter, in dispatch order."""
     rows = []
     with open(path, newline="") as fh:
         for r in csv.DictReader(fh):
             if r["Counter_Name"] == counter:
-                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
-    rows.sort()
+                t0, t1 = r.get("Start_Timestamp"), r.get("End_Timestamp")
+                dur = float(t1) - float(t0) if t0 and t1 else None
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"]), dur))
+    rows.sort(key=lambda x: x[0])
     return rows
 
 
@@ -145,15 +152,21 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
     per = {}
     for key, path, counter in (("r", fetch_csv, "FETCH_SIZE"), ("w", write_csv, "WRITE_SIZE")):
         sc = res["fetch" if key == "r" else "write"]["scale"] * 1024.0
-        for _, n, v in _counter(path, counter):
-            e = per.setdefault(short_name(n), {"r": [], "w": []})
+        for _, n, v, dur in _counter_timed(path, counter):
+            e = per.setdefault(short_name(n), {"r": [], "w": [], "tr": [], "tw": []})
             e[key].append(v * sc)
-    table = ["| kernel | dispatches | read MB / dispatch | write MB / dispatch |", "|---|---:|---:|---:|"]
+            if dur is not None:
+                e["t" + key].append(dur)
+    table = ["| kernel | dispatches | read MB / dispatch | write MB / dispatch | HBM GB/s |", "|---|---:|---:|---:|---:|"]
     for n, e in sorted(per.items(), key=lambda kv: -(sum(kv[1]["r"]) + sum(kv[1]["w"]))):
         if not e["r"] or not e["w"] or sum(e["r"]) + sum(e["w"]) < 1e8:
             continue
-        table.append(f"| `{n[:70]}` | {len(e['r'])} | {sum(e['r']) / len(e['r']) / 1e6:.1f} | "
-                     f"{sum(e['w']) / len(e['w']) / 1e6:.1f} |")
+        rd, wr = sum(e["r"]) / len(e["r"]), sum(e["w"]) / len(e["w"])
+        # each counter's bytes over the durations of the run it was taken in
+        gbs = ""
+        if e["tr"] and e["tw"] and sum(e["tr"]) > 0 and sum(e["tw"]) > 0:
+            gbs = f"{sum(e['r']) / sum(e['tr']) + sum(e['w']) / sum(e['tw']):.0f}"
+        table.append(f"| `{n[:70]}` | {len(e['r'])} | {rd / 1e6:.1f} | {wr / 1e6:.1f} | {gbs} |")
     return "\n".join([
         f"# {title}\n",
         "Commands (repository root, one MI355X, TMPDIR=/tmp), one counter per run:\n",
@@ -170,7 +183,8 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
         f"| algorithmic (pencils read and written once, V_loc once) | {algo / 1e6:.1f} MB |",
         f"| measured / algorithmic | {ratio:.3f} |\n",
         f"Source `paper_2607_14025_amd/csrc/{KERNEL_SOURCES.get(label)}` sha1 prefix at measurement: {sha}\n",
-        "All kernels of the run with more than 100 MB of traffic in total (calibrated, per dispatch):\n",
+        "All kernels of the run with more than 100 MB of traffic in total (calibrated, per dispatch; HBM GB/s = "
+        "bytes over the dispatch durations rocprofv3 recorded in the same counter runs, which serialise kernels):\n",
     ] + table) + "\n"
 
 
