@@ -157,7 +157,7 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
             e[key].append(v * sc)
             if dur is not None:
                 e["t" + key].append(dur)
-    table = ["| kernel | dispatches | read MB / dispatch | write MB / dispatch | HBM GB/s |", "|---|---:|---:|---:|---:|"]
+    table = ["| kernel | dispatches | read MB / dispatch | write MB / dispatch | GB/s past L2 |", "|---|---:|---:|---:|---:|"]
     for n, e in sorted(per.items(), key=lambda kv: -(sum(kv[1]["r"]) + sum(kv[1]["w"]))):
         if not e["r"] or not e["w"] or sum(e["r"]) + sum(e["w"]) < 1e8:
             continue
@@ -183,8 +183,9 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
         f"| algorithmic (pencils read and written once, V_loc once) | {algo / 1e6:.1f} MB |",
         f"| measured / algorithmic | {ratio:.3f} |\n",
         f"Source `paper_2607_14025_amd/csrc/{KERNEL_SOURCES.get(label)}` sha1 prefix at measurement: {sha}\n",
-        "All kernels of the run with more than 100 MB of traffic in total (calibrated, per dispatch; HBM GB/s = "
-        "bytes over the dispatch durations rocprofv3 recorded in the same counter runs, which serialise kernels):\n",
+        "All kernels of the run with more than 100 MB of traffic in total (calibrated, per dispatch). The counters "
+        "count L2 misses, which the Infinity Cache may serve, so these bytes bound HBM traffic from above. GB/s = "
+        "those bytes over the dispatch durations rocprofv3 recorded in the same counter runs (kernels serialised):\n",
     ] + table) + "\n"
 
 
