@@ -85,7 +85,7 @@ std::string build_basis(const CellParams& c, HostBasis& hb, bool sphere_only) {
       ++hb.ncol;
     }
   if (start != hb.npw) return "internal error: column count mismatch";
-  hb.ncol_pad = (hb.ncol + 15) / 16 * 16;
+  hb.ncol_pad = (hb.ncol + kColPad - 1) / kColPad * kColPad;
   hb.col_start.resize(hb.ncol_pad, 0);
   hb.col_len.resize(hb.ncol_pad, 0);
   hb.col_xmin.resize(hb.ncol_pad, 0);

@@ -8,6 +8,10 @@
 
 namespace stern {
 
+// the x-pencil column count is padded to a multiple of this (whole column blocks of the
+// x passes, 32 FP32 or 16 FP64 columns)
+constexpr int kColPad = 32;
+
 struct CellParams {
   double L = 0, ecut = 0;
   std::vector<double> pos;  // [n_atoms][3]

@@ -106,7 +106,7 @@ __device__ __forceinline__ void stage(int F, Ld ld, St st, const Z<T>* __restric
 // columns hold INT_MAX) and its x from the column's smallest n_x.
 template <int N, class T>
 struct XBlock {
-  static constexpr int CB = kColBlock, LDX = N + 1;
+  static constexpr int CB = col_block<T>(), LDX = N + 1;
   int s0, s1;  // sphere range of the block
   __device__ __forceinline__ void load(const FftGeom& g, int c0, int* bs, int* bx) {
     const int tid = threadIdx.x;
@@ -116,8 +116,14 @@ struct XBlock {
       bx[tid] = g.col_xmin[c];
     }
   }
-  // after a barrier that follows load(): the block's range
+  // after a barrier that follows load(): the block's range. Columns are padded to whole
+  // blocks of the widest block size, so a narrower block may hold padding only: its range
+  // is empty (starting it at the padding marker would overflow the sphere index).
   __device__ __forceinline__ void range(const FftGeom& g, int c0, const int* bs) {
+    if (bs[0] == 0x7fffffff) {
+      s0 = s1 = 0;
+      return;
+    }
     s0 = bs[0];
     s1 = s0;
 #pragma unroll
@@ -1179,7 +1185,7 @@ size_t plane_lds_bytes(int N, int elem_bytes) { return ((size_t)N * (N + 1) + N)
 template <class T>
 void launch_xinv(const FftGeom& g, const Z<T>* sph, const int* vidx, int nvec, Z<T>* pen, hipStream_t st) {
   if (nvec <= 0) return;
-  dim3 grid(g.ncol_pad / kColBlock, nvec);
+  dim3 grid(g.ncol_pad / col_block<T>(), nvec);
   STERN_DISPATCH_N(g.N, (k_xinv<NN, T><<<grid, kXThreads, 0, st>>>(sph, vidx, pen, g)));
 }
 template void launch_xinv<double>(const FftGeom&, const Z64*, const int*, int, Z64*, hipStream_t);
@@ -1189,7 +1195,7 @@ template <class T>
 void launch_xfwd(const FftGeom& g, const Z<T>* pen, const int* vidx, int nvec, Z<T>* out, int mode, const Z<T>* pin,
                  const double* eps, double scale, hipStream_t st) {
   if (nvec <= 0) return;
-  dim3 grid(g.ncol_pad / kColBlock, nvec);
+  dim3 grid(g.ncol_pad / col_block<T>(), nvec);
   if (mode == 0) {
     STERN_DISPATCH_N(g.N, (k_xfwd<NN, T, 0><<<grid, kXThreads, 0, st>>>(pen, vidx, out, pin, eps, scale, g)));
   } else if (mode == 1) {

@@ -1,5 +1,6 @@
 // Host-side launchers of the gfx950 kernels (defined in fft.hip, gemm.hip, cg.hip).
 #pragma once
+#include "basis.hpp"
 #include "common.hpp"
 
 namespace stern {
@@ -28,7 +29,13 @@ struct FftGeom {
   const Z32* tw32;
 };
 
-constexpr int kColBlock = 16;  // columns per workgroup in the x-pencil passes
+// columns per workgroup in the x-pencil passes: 32 FP32 or 16 FP64 columns, about the same
+// bytes per workgroup; the basis pads the column count to kColPad (basis.hpp), a multiple of both
+template <class T>
+constexpr int col_block() {
+  return sizeof(T) == 4 ? 32 : 16;
+}
+static_assert(kColPad % 32 == 0 && kColPad % 16 == 0, "column padding must hold whole column blocks");
 
 bool fft_size_supported(int N);
 size_t plane_lds_bytes(int N, int elem_bytes);
