@@ -1668,9 +1668,9 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
                [&] { return apply_h_rows(S, S->wp.as<Z64>(), S->wq.as<Z64>(), nullptr, n_vec, eps); }));
   CHECKED(tune(STERN_TUNE_PLANE32, {0, 1, 2},
                [&] { return apply_h32_rows(S, S->m_p.as<Z32>(), S->m_q.as<Z32>(), nullptr, n_vec, eps); }));
-  CHECKED(tune(STERN_TUNE_GEMM64_WG, {256, 512, 1024, 2048, 4096},
+  CHECKED(tune(STERN_TUNE_GEMM64_WG, {256, 384, 512, 768, 1024, 2048, 4096},
                [&] { return apply_pc_rows(S, S->wq.as<Z64>(), nullptr, n_vec); }));
-  CHECKED(tune(STERN_TUNE_GEMM16_WG, {128, 256, 512, 1024, 2048},
+  CHECKED(tune(STERN_TUNE_GEMM16_WG, {128, 192, 256, 384, 512, 1024, 2048},
                [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));
   CHECKED(tune(STERN_TUNE_GEMM16_EXPAND, {0, 1, 2},
                [&] { return apply_pc32_rows(S, S->m_q.as<Z32>(), nullptr, n_vec); }));

@@ -92,8 +92,8 @@ def test_autotune_and_cache(tuned_tiny, tmp_path):
     n, chosen = s.autotune(n_vec=64, cache_path=str(cache))
     assert n >= 16
     assert chosen["plane64"] in (0, 1, 2) and chosen["plane32"] in (0, 1, 2)
-    assert chosen["gemm64_wg"] in (256, 512, 1024, 2048, 4096)
-    assert chosen["gemm16_wg"] in (128, 256, 512, 1024, 2048)
+    assert chosen["gemm64_wg"] in (256, 384, 512, 768, 1024, 2048, 4096)
+    assert chosen["gemm16_wg"] in (128, 192, 256, 384, 512, 1024, 2048)
     assert chosen["gemm16_expand"] in (0, 1, 2)
     assert len(cache.read_text().splitlines()) == 5
     n2, chosen2 = s.autotune(n_vec=64, cache_path=str(cache))
