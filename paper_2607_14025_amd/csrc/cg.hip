@@ -441,6 +441,79 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const in
   }
 }
 
+// The alpha step above with the whole row in one workgroup of kAlphaThreads: each thread
+// keeps its PER elements of p and q in registers from the (p, q) sum to the update, so p
+// and q are read once instead of twice. For rows up to kAlphaThreads * PER elements
+// (PER <= 17 keeps p and q within 68 VGPRs, four waves per SIMD).
+constexpr int kAlphaThreads = 1024;
+constexpr int kAlphaMaxPer = 17;
+
+__device__ __forceinline__ double block_sum_a(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < kAlphaThreads / 64; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+template <bool LK, int PER>
+__global__ __launch_bounds__(kAlphaThreads) void k_cg32_alpha_row(Cg32State S, const int* __restrict__ act,
+                                                                   double tol2) {
+  __shared__ double sh[kAlphaThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  const int n = S.npw_pad;
+  Z32 p[PER], q[PER];
+  double pq = 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int k = threadIdx.x + u * kAlphaThreads;
+    if (k < n) {
+      p[u] = S.p[o + k];
+      q[u] = S.q[o + k];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u)
+    if (threadIdx.x + u * kAlphaThreads < n) pq += (double)p[u].re * q[u].re + (double)p[u].im * q[u].im;
+  pq = block_sum_a(pq, sh);
+  const double rz_old = S.rz[s];
+  const float alpha = (float)((pq > 0.0) ? rz_old / pq : 0.0);
+  const double iT = S.invT[s];
+  double rr = 0.0, rz = 0.0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int k = threadIdx.x + u * kAlphaThreads;
+    if (k < n) {
+      const Z32 d = S.d[o + k], r = S.r[o + k];
+      const double t = precond_load<LK>(S, s, k);
+      const Z32 dn = zmk(d.re + alpha * p[u].re, d.im + alpha * p[u].im);
+      const Z32 rn = zmk(r.re - alpha * q[u].re, r.im - alpha * q[u].im);
+      S.d[o + k] = dn;
+      S.r[o + k] = rn;
+      rr += (double)rn.re * rn.re + (double)rn.im * rn.im;
+      const float tk = (float)precond_eval<LK>(t, iT);
+      const Z32 z = zmk(rn.re * tk, rn.im * tk);
+      S.z[o + k] = z;
+      rz += (double)rn.re * z.re + (double)rn.im * z.im;
+    }
+  }
+  rr = block_sum_a(rr, sh);
+  rz = block_sum_a(rz, sh);
+  if (threadIdx.x == 0) {
+    S.iters[s] += 1;
+    if (rr <= tol2 * S.rr0[s] || !(pq > 0.0)) S.flag[s] = 1;
+    S.beta[s] = rz_old != 0.0 ? rz / rz_old : 0.0;
+    S.rz[s] = rz;
+  }
+}
+
 // p = z + beta p (beta from the alpha step)
 __global__ __launch_bounds__(kCgThreads) void k_cg32_beta(Cg32State S, const int* __restrict__ act) {
   const int s = act ? act[blockIdx.x] : blockIdx.x;
@@ -601,10 +674,16 @@ void launch_cg32_init2(const Cg32State& s, const int* act, int n, hipStream_t st
 }
 void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st) {
   if (n <= 0) return;
-  if (s.kprec)
+  if (s.npw_pad <= kAlphaThreads * kAlphaMaxPer) {  // the row fits in one workgroup's registers
+    if (s.kprec)
+      k_cg32_alpha_row<true, kAlphaMaxPer><<<n, kAlphaThreads, 0, st>>>(s, act, tol2);
+    else
+      k_cg32_alpha_row<false, kAlphaMaxPer><<<n, kAlphaThreads, 0, st>>>(s, act, tol2);
+  } else if (s.kprec) {
     k_cg32_alpha<true><<<n, kCgThreads, 0, st>>>(s, act, tol2);
-  else
+  } else {
     k_cg32_alpha<false><<<n, kCgThreads, 0, st>>>(s, act, tol2);
+  }
 }
 void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg32_beta<<<n, kCgThreads, 0, st>>>(s, act);
