@@ -276,6 +276,19 @@ int stern_model_num_params(void);
 int stern_model_get_weights(const stern_model* m, float* w, int n);
 int stern_model_set_weights(stern_model* m, const float* w, int n);
 void stern_model_free(stern_model* m);
+/* One Adam step of the net on caller-given coarse-grid data, host memory:
+ * in [n][Nc][Nc][Nc][5] floats (per point: Re psi_v, Im psi_v, Re b / |b|,
+ * Im b / |b|, eps_v), target [n][Nc][Nc][Nc][2] (Re, Im of x / |b|). Runs the
+ * forward pass (out, optional [n][Nc^3][2]: the output before the step), the
+ * relative L2 loss per solve (loss, optional [n]), the gradient of the summed
+ * loss with respect to the three conv layers (grad, optional: the first
+ * 3 x (16 x 27 x 16 + 16) parameters in the get_weights layout), then one Adam
+ * step of those parameters with learning rate lr and the gradient averaged over
+ * the n solves; the head is untouched. Nc >= 4; synchronous. This is how
+ * stern_model_train fits the net, exposed for training on data of the
+ * caller's own. */
+int stern_model_fit_step(stern_model* m, int Nc, int n, const float* in, const float* target, double lr,
+                         float* out, float* loss, float* grad);
 
 /* ---- kernel variants and the autotuner ----
  * Tunables of a system (each keeps its value until set again):

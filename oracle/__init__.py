@@ -21,6 +21,8 @@ Modules:
   model        basis, local potential, KB projectors, H apply and dense H
   sternheimer  RHS, projected PCG, density response
   closed_form  sum over all empty states, finite field, free-electron Lindhard sum
+  net          one training step of the learned-start net (forward, loss, gradients, Adam)
+               in float64 over BF16-rounded values, for checking the net's kernels
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: a brute-force lattice count, the real-space Gaussian sum, the dense

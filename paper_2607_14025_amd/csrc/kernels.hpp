@@ -114,6 +114,7 @@ void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st);
 
 // ---- learned initial guess (coarse-grid 3-D conv net, learn.hip) ----
 constexpr int kNetChannels = 16;
+constexpr int kNetInputs = 5;  // live input channels: Re, Im psi_v; Re, Im b / |b|; eps_v
 constexpr int kNetLayers = 3;
 constexpr int kNetLayerParams = kNetChannels * 27 * kNetChannels + kNetChannels;  // weights + bias
 int net_ldp(int Nc);  // per-solve point stride of the activations (multiple of 16)

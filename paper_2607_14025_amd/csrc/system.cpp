@@ -1774,6 +1774,89 @@ void stern_model_free(stern_model* M) {
   delete M;
 }
 
+// One Adam step of the net on the nb solves staged in M->a0 (inputs) and M->tgt
+// (targets): forward, relative-L2 loss (per-solve values in M->loss, dL/dout in
+// M->g3), backward through the three layers (weight gradients summed over the
+// solves into M->grad, data gradients by the flipped-weight convolution, ReLU
+// masks from the stored BF16 activations), then Adam on the conv weights with
+// the gradient averaged over the solves. The preconditioner head is untouched.
+static int net_fit_step(stern_model* M, int Nc, int nb_, float lr, hipStream_t st) {
+  const size_t ldp = (size_t)net_ldp(Nc), C = kNetChannels;
+  const int np_layer = stern_model::LP;
+  net_forward(M, M->a0.as<__bf16>(), M->a1.as<__bf16>(), M->a2.as<__bf16>(), M->out.as<float>(), Nc, nb_, st);
+  launch_loss(M->out.as<float>(), M->tgt.as<float>(), M->g3.as<float>(), M->loss.as<float>(), Nc, nb_, st);
+  const size_t nact = (size_t)nb_ * ldp * C;
+  float* gw = M->grad.as<float>();
+  // layer 3 (index 2)
+  launch_conv3_wgrad(M->a2.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw + 2 * np_layer, Nc, nb_, st);
+  launch_flip_weights(M->w.as<float>() + 2 * np_layer, M->wtf.as<__bf16>(), st);
+  launch_f32_to_bf16(M->g3.as<float>(), M->gbf.as<__bf16>(), nact, st);
+  launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g2.as<float>(), Nc, nb_, 0, true, st);
+  launch_relu_bwd(M->g2.as<float>(), M->a2.as<__bf16>(), nact, st);
+  // layer 2 (index 1)
+  launch_conv3_wgrad(M->a1.as<__bf16>(), M->g2.as<float>(), M->part.as<float>(), gw + 1 * np_layer, Nc, nb_, st);
+  launch_flip_weights(M->w.as<float>() + 1 * np_layer, M->wtf.as<__bf16>(), st);
+  launch_f32_to_bf16(M->g2.as<float>(), M->gbf.as<__bf16>(), nact, st);
+  launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g3.as<float>(), Nc, nb_, 0, true, st);
+  launch_relu_bwd(M->g3.as<float>(), M->a1.as<__bf16>(), nact, st);
+  // layer 1 (index 0)
+  launch_conv3_wgrad(M->a0.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw, Nc, nb_, st);
+  ++M->step;  // the trunk only: the head's gradient is not formed here
+  launch_adam(M->w.as<float>(), M->m.as<float>(), M->v.as<float>(), gw, stern_model::HEAD, lr, M->step,
+              1.f / (float)nb_, st);
+  return model_refresh_bf16(M, st);
+}
+
+// training workspace of mini-batches of B solves on an Nc^3 coarse grid
+static int net_train_workspace(stern_model* M, int Nc, int B) {
+  const size_t ldp = (size_t)net_ldp(Nc), C = kNetChannels;
+  CHECKED(M->a0.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  CHECKED(M->a1.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  CHECKED(M->a2.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  CHECKED(M->gbf.ensure((size_t)B * ldp * C * sizeof(__bf16)));
+  for (DBuf* d : {&M->out, &M->g3, &M->g2}) CHECKED(d->ensure((size_t)B * ldp * C * sizeof(float)));
+  CHECKED(M->tgt.ensure((size_t)B * ldp * 2 * sizeof(float)));
+  CHECKED(M->loss.ensure((size_t)B * sizeof(float)));
+  CHECKED(M->part.ensure((size_t)conv3_wgrad_parts(Nc) * stern_model::LP * sizeof(float)));
+  return 0;
+}
+
+int stern_model_fit_step(stern_model* M, int Nc, int n, const float* in, const float* target, double lr,
+                         float* out, float* loss, float* grad) {
+  if (!M || !in || !target || n <= 0 || Nc < 4 || !(lr >= 0))
+    return fail(STERN_ERR_INVALID_ARG, "need a model, n > 0, Nc >= 4, lr >= 0, inputs and targets");
+  Scope sc(M->device);
+  const size_t P = (size_t)Nc * Nc * Nc, ldp = (size_t)net_ldp(Nc), C = kNetChannels;
+  CHECKED(net_train_workspace(M, Nc, n));
+  // channels-last staging: inputs [n][ldp][16] (5 live channels), targets [n][ldp][2]
+  std::vector<float> a((size_t)n * ldp * C, 0.f), t((size_t)n * ldp * 2, 0.f);
+  for (size_t s = 0; s < (size_t)n; ++s)
+    for (size_t p = 0; p < P; ++p) {
+      for (int c = 0; c < kNetInputs; ++c) a[(s * ldp + p) * C + c] = in[(s * P + p) * kNetInputs + c];
+      for (int c = 0; c < 2; ++c) t[(s * ldp + p) * 2 + c] = target[(s * P + p) * 2 + c];
+    }
+  CHECKED(M->g2.ensure(a.size() * sizeof(float)));
+  hipStream_t st = nullptr;
+  HIPOK(hipMemcpyAsync(M->g2.p, a.data(), a.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  launch_f32_to_bf16(M->g2.as<float>(), M->a0.as<__bf16>(), a.size(), st);
+  HIPOK(hipMemcpyAsync(M->tgt.p, t.data(), t.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  CHECKED(net_fit_step(M, Nc, n, (float)lr, st));
+  CHECKED(launch_check());
+  if (loss) HIPOK(hipMemcpyAsync(loss, M->loss.p, n * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (grad) HIPOK(hipMemcpyAsync(grad, M->grad.p, stern_model::HEAD * sizeof(float), hipMemcpyDeviceToHost, st));
+  if (out) {
+    std::vector<float> o((size_t)n * ldp * C);
+    HIPOK(hipMemcpyAsync(o.data(), M->out.p, o.size() * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    for (size_t s = 0; s < (size_t)n; ++s)
+      for (size_t p = 0; p < P; ++p)
+        for (int c = 0; c < 2; ++c) out[(s * P + p) * 2 + c] = o[(s * ldp + p) * C + c];
+  }
+  HIPOK(hipStreamSynchronize(st));
+  M->trained = true;
+  return STERN_OK;
+}
+
 int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const int* n_pert, const double* const* dv_r,
                       int mem_kind, const stern_train_opts* o, stern_train_stats* tstats) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -1872,15 +1955,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
   }
   // ---- training: Adam on mini-batches of B solves ----
   hipStream_t st = sys[0]->stream;
-  CHECKED(M->a0.ensure((size_t)B * ldp * C * sizeof(__bf16)));
-  CHECKED(M->a1.ensure((size_t)B * ldp * C * sizeof(__bf16)));
-  CHECKED(M->a2.ensure((size_t)B * ldp * C * sizeof(__bf16)));
-  CHECKED(M->gbf.ensure((size_t)B * ldp * C * sizeof(__bf16)));
-  for (DBuf* d : {&M->out, &M->g3, &M->g2}) CHECKED(d->ensure((size_t)B * ldp * C * sizeof(float)));
-  CHECKED(M->tgt.ensure((size_t)B * ldp * 2 * sizeof(float)));
-  CHECKED(M->loss.ensure((size_t)B * sizeof(float)));
-  CHECKED(M->part.ensure((size_t)conv3_wgrad_parts(Nc) * stern_model::LP * sizeof(float)));
-  const int np_layer = stern_model::LP;
+  CHECKED(net_train_workspace(M, Nc, B));
   std::vector<int> order(nsamp);
   std::iota(order.begin(), order.end(), 0);
   std::vector<float> hl(B);
@@ -1899,28 +1974,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
         HIPOK(hipMemcpyAsync(M->tgt.as<float>() + (size_t)t * ldp * 2, M->dtgt.as<float>() + (size_t)id * ldp * 2,
                              ldp * 2 * sizeof(float), hipMemcpyDeviceToDevice, st));
       }
-      net_forward(M, M->a0.as<__bf16>(), M->a1.as<__bf16>(), M->a2.as<__bf16>(), M->out.as<float>(), Nc, nb_, st);
-      launch_loss(M->out.as<float>(), M->tgt.as<float>(), M->g3.as<float>(), M->loss.as<float>(), Nc, nb_, st);
-      const size_t nact = (size_t)nb_ * ldp * C;
-      float* gw = M->grad.as<float>();
-      // layer 3 (index 2)
-      launch_conv3_wgrad(M->a2.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw + 2 * np_layer, Nc, nb_, st);
-      launch_flip_weights(M->w.as<float>() + 2 * np_layer, M->wtf.as<__bf16>(), st);
-      launch_f32_to_bf16(M->g3.as<float>(), M->gbf.as<__bf16>(), nact, st);
-      launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g2.as<float>(), Nc, nb_, 0, true, st);
-      launch_relu_bwd(M->g2.as<float>(), M->a2.as<__bf16>(), nact, st);
-      // layer 2 (index 1)
-      launch_conv3_wgrad(M->a1.as<__bf16>(), M->g2.as<float>(), M->part.as<float>(), gw + 1 * np_layer, Nc, nb_, st);
-      launch_flip_weights(M->w.as<float>() + 1 * np_layer, M->wtf.as<__bf16>(), st);
-      launch_f32_to_bf16(M->g2.as<float>(), M->gbf.as<__bf16>(), nact, st);
-      launch_conv3(M->gbf.as<__bf16>(), M->wtf.as<__bf16>(), nullptr, M->g3.as<float>(), Nc, nb_, 0, true, st);
-      launch_relu_bwd(M->g3.as<float>(), M->a1.as<__bf16>(), nact, st);
-      // layer 1 (index 0)
-      launch_conv3_wgrad(M->a0.as<__bf16>(), M->g3.as<float>(), M->part.as<float>(), gw, Nc, nb_, st);
-      ++M->step;  // the trunk only: the head's gradient is not formed here
-      launch_adam(M->w.as<float>(), M->m.as<float>(), M->v.as<float>(), gw, stern_model::HEAD, lr, M->step,
-                  1.f / (float)nb_, st);
-      CHECKED(model_refresh_bf16(M, st));
+      CHECKED(net_fit_step(M, Nc, nb_, lr, st));
       HIPOK(hipMemcpyAsync(hl.data(), M->loss.p, nb_ * sizeof(float), hipMemcpyDeviceToHost, st));
       HIPOK(hipStreamSynchronize(st));
       for (int t = 0; t < nb_; ++t) ep_loss += hl[t];

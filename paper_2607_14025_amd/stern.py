@@ -28,7 +28,7 @@ STERN_MEM_DEVICE = 1
 
 EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
             "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
-            "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_tunable",
+            "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
 
 TUNE_PLANE64 = 0
@@ -114,6 +114,8 @@ def lib():
         L.stern_model_num_params.argtypes = []
         L.stern_model_get_weights.argtypes = [C.c_void_p, P(C.c_float), C.c_int]
         L.stern_model_set_weights.argtypes = [C.c_void_p, P(C.c_float), C.c_int]
+        L.stern_model_fit_step.argtypes = [C.c_void_p, C.c_int, C.c_int, P(C.c_float), P(C.c_float), C.c_double,
+                                           P(C.c_float), P(C.c_float), P(C.c_float)]
         L.stern_model_free.argtypes = [C.c_void_p]
         L.stern_model_free.restype = None
         L.stern_tunable.argtypes = [C.c_void_p, C.c_int, C.c_int]
@@ -128,7 +130,7 @@ def lib():
         for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied",
                      "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc",
                      "stern_model_create", "stern_model_train", "stern_model_num_params", "stern_model_get_weights",
-                     "stern_model_set_weights", "stern_tunable", "stern_autotune"):
+                     "stern_model_set_weights", "stern_model_fit_step", "stern_tunable", "stern_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -336,6 +338,19 @@ class System:
         return json.loads(lib().stern_autotune_report().decode())
 
     def apply_h(self, c, shift=None):
+        """(H - shift_k) c_k for rows c [n, n_pw] complex in canonical order: a numpy array (host), or a
+        contiguous complex128 CUDA tensor (device; the result is a new tensor on the device)."""
+        if _is_torch(c):
+            import torch
+            if not c.is_cuda or not c.is_contiguous() or c.dtype != torch.complex128:
+                raise ValueError("device rows must be a contiguous complex128 CUDA tensor")
+            c = c.reshape(-1, self.n_pw)
+            out = torch.empty_like(c)
+            sh = None if shift is None else torch.as_tensor(shift, dtype=torch.float64, device=c.device).contiguous()
+            _check(lib().stern_apply_h(self._h, c.shape[0], C.c_void_p(c.data_ptr()),
+                                       None if sh is None else C.c_void_p(sh.data_ptr()), C.c_void_p(out.data_ptr()),
+                                       STERN_MEM_DEVICE))
+            return out
         c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.complex128)
         out = np.empty_like(c)
         sh = None if shift is None else np.ascontiguousarray(shift, dtype=np.float64)
@@ -345,6 +360,16 @@ class System:
         return out
 
     def apply_pc(self, c):
+        """P_c c for rows c [n, n_pw] (canonical order), host array or complex128 CUDA tensor."""
+        if _is_torch(c):
+            import torch
+            if not c.is_cuda or not c.is_contiguous() or c.dtype != torch.complex128:
+                raise ValueError("device rows must be a contiguous complex128 CUDA tensor")
+            c = c.reshape(-1, self.n_pw)
+            out = torch.empty_like(c)
+            _check(lib().stern_apply_pc(self._h, c.shape[0], C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr()),
+                                        STERN_MEM_DEVICE))
+            return out
         c = np.ascontiguousarray(np.atleast_2d(c), dtype=np.complex128)
         out = np.empty_like(c)
         _check(lib().stern_apply_pc(self._h, c.shape[0], C.c_void_p(c.ctypes.data), C.c_void_p(out.ctypes.data),
@@ -391,6 +416,23 @@ class Model:
     def set_weights(self, w):
         w = np.ascontiguousarray(w, dtype=np.float32)
         _check(lib().stern_model_set_weights(self._h, w.ctypes.data_as(C.POINTER(C.c_float)), len(w)))
+
+    def fit_step(self, inp, target, lr, want_out=True, want_grad=True):
+        """One Adam step on caller data: inp [n, Nc, Nc, Nc, 5], target [n, Nc, Nc, Nc, 2] (float32, host).
+        Returns (out [n, Nc, Nc, Nc, 2] before the step, loss [n], grad of the three conv layers)."""
+        inp = np.ascontiguousarray(inp, dtype=np.float32)
+        target = np.ascontiguousarray(target, dtype=np.float32)
+        n, Nc = inp.shape[0], inp.shape[1]
+        if inp.shape != (n, Nc, Nc, Nc, 5) or target.shape != (n, Nc, Nc, Nc, 2):
+            raise ValueError("inp must be [n, Nc, Nc, Nc, 5] and target [n, Nc, Nc, Nc, 2]")
+        fp = C.POINTER(C.c_float)
+        out = np.zeros((n, Nc, Nc, Nc, 2), dtype=np.float32) if want_out else None
+        loss = np.zeros(n, dtype=np.float32)
+        grad = np.zeros(3 * (16 * 27 * 16 + 16), dtype=np.float32) if want_grad else None
+        _check(lib().stern_model_fit_step(self._h, Nc, n, inp.ctypes.data_as(fp), target.ctypes.data_as(fp),
+                                          float(lr), out.ctypes.data_as(fp) if want_out else None,
+                                          loss.ctypes.data_as(fp), grad.ctypes.data_as(fp) if want_grad else None))
+        return out, loss, grad
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1,0 +1,171 @@
+"""Occupied states of the large cell on the GPU (input preparation only).
+
+The host eigensolver of ground.py needs hours for 1,024 bands on a 128^3 grid.
+Here the same model Hamiltonian is applied by the library's FP64 H apply on
+device memory (stern_apply_h), and a block is driven to the lowest eigenpairs by
+Chebyshev-filtered subspace iteration (Zhou, Saad, Tiago and Chelikowsky,
+J. Comput. Phys. 219, 172 (2006)). Each pass
+  - filters the block with a degree-m Chebyshev polynomial of H that is small on
+    [a, b] (a: the block's top Ritz value, b: an upper bound of the spectrum) and
+    scaled to 1 at the lowest Ritz value, so that components above a die out,
+  - orthonormalises it by Cholesky QR, twice,
+  - rotates it to Ritz vectors (Rayleigh-Ritz),
+until the lowest n_occ + 1 Ritz pairs have residual norm ||H x - theta x|| <= tol.
+The block products run as torch GEMMs on the GPU; the small dense Cholesky and
+eigen-decompositions run on the host in numpy.
+
+Nothing here is trusted blindly: the oracle re-checks eigen-residuals of a
+sample of bands with its own H, and the density response is judged against the
+oracle on sampled pairs. This module is not part of the product path; it only
+prepares inputs, like ground.py.
+"""
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+
+from .cells import CellSpec, place_atoms, random_dv, STREAM_EIG
+
+
+def _seed(spec: CellSpec) -> int:
+    return int(np.random.SeedSequence([spec.config_id, spec.system_id, STREAM_EIG]).generate_state(1)[0])
+
+
+def _orthonormalise(Y):
+    """Rows of Y made orthonormal: Y <- conj(L)^-1 Y with Y conj(Y)^T = L L^H (Cholesky QR)."""
+    import torch
+    G = (Y.conj() @ Y.T).cpu().numpy()
+    G = 0.5 * (G + G.conj().T)
+    L = np.linalg.cholesky(G)
+    M = np.linalg.inv(np.conj(L))
+    return torch.from_numpy(np.ascontiguousarray(M)).to(Y.device) @ Y
+
+
+def _rayleigh_ritz(Y, HY):
+    """Ritz values (ascending) and the rotated rows of Y and H Y."""
+    import torch
+    A = (Y.conj() @ HY.T).cpu().numpy()
+    A = 0.5 * (A + A.conj().T)
+    th, Q = np.linalg.eigh(A)
+    Qt = torch.from_numpy(np.ascontiguousarray(Q.T)).to(Y.device)
+    return th, (Qt @ Y).contiguous(), (Qt @ HY).contiguous()
+
+
+def _upper_bound(apply_h, npw, dev, gen, steps=24):
+    """Upper bound of the spectrum of H: the largest Ritz value of a short Lanczos run
+    plus the norm of its last residual."""
+    import torch
+    q = torch.randn(npw, dtype=torch.complex128, device=dev, generator=gen)
+    q /= torch.linalg.vector_norm(q)
+    q_prev = torch.zeros_like(q)
+    beta = 0.0
+    al, be = [], []
+    for _ in range(steps):
+        w = apply_h(q.reshape(1, -1).contiguous(), None).reshape(-1)
+        a = float(torch.vdot(q, w).real)
+        w = w - a * q - beta * q_prev
+        beta = float(torch.linalg.vector_norm(w))
+        al.append(a)
+        be.append(beta)
+        q_prev, q = q, w / beta
+    T = np.diag(al) + np.diag(be[:-1], 1) + np.diag(be[:-1], -1)
+    return float(np.linalg.eigvalsh(T).max()) + be[-1]
+
+
+def _filter(apply_h, X, HX, degree, a, b, a0):
+    """p(H) X for the degree-`degree` Chebyshev polynomial of the first kind mapped from [a, b]
+    to [-1, 1], scaled to one at a0 (< a); H X of the input is given."""
+    e = 0.5 * (b - a)
+    c = 0.5 * (b + a)
+    sigma = e / (a0 - c)
+    tau = 2.0 / sigma
+    Y = (HX - c * X) * (sigma / e)
+    Xp = X
+    for _ in range(2, degree + 1):
+        sn = 1.0 / (tau - sigma)
+        HY = apply_h(Y, np.full(Y.shape[0], c))
+        Yn = HY * (2.0 * sn / e) - (sigma * sn) * Xp
+        Xp, Y, sigma = Y, Yn, sn
+    return Y
+
+
+def chebyshev_eigs(apply_h, X, want: int, tol: float, degree: int = 20, max_pass: int = 80, gen=None,
+                   verbose: bool = False):
+    """Lowest `want` eigenpairs of a Hermitian operator from the starting rows X [nb, n] (nb > want).
+
+    apply_h(Y, shift) returns (H - shift_k) Y_k for rows Y (shift None: zero). Returns (theta [nb]
+    ascending, rows X [nb, n] (Ritz vectors), residual norms of the lowest `want`, passes)."""
+    t0 = time.perf_counter()
+    X = _orthonormalise(_orthonormalise(X))
+    th, X, HX = _rayleigh_ritz(X, apply_h(X, None))
+    b = _upper_bound(apply_h, X.shape[1], X.device, gen)
+    res = None
+    passes = 0
+    for passes in range(1, max_pass + 1):
+        Y = _filter(apply_h, X, HX, degree, float(th[-1]), b, float(th[0]))
+        del X, HX
+        Y = _orthonormalise(_orthonormalise(Y))
+        th, X, HX = _rayleigh_ritz(Y, apply_h(Y, None))
+        del Y
+        R = HX[:want] - X.new_tensor(th[:want]).real.to(X.dtype)[:, None] * X[:want]
+        res = R.abs().pow(2).sum(dim=1).sqrt().cpu().numpy()
+        del R
+        if verbose:
+            print(f"  chebyshev pass {passes}: max residual of the lowest {want} {res.max():.2e} "
+                  f"(theta {th[0]:.4f} .. {th[-1]:.4f}, bound {b:.3f}), {time.perf_counter() - t0:.1f} s",
+                  flush=True)
+        if res.max() <= tol:
+            break
+    return th, X, res, passes
+
+
+def ground_state_gpu(spec: CellSpec, tol: float = 1e-9, buffer: int | None = None, degree: int = 20,
+                     max_pass: int = 80, device: int = 0, verbose: bool = False, max_reseed: int = 4):
+    """Lowest n_occ + 1 eigenpairs of one cell by Chebyshev-filtered subspace iteration on the GPU.
+
+    Returns dict(spec, pos, miller [npw, 3] (canonical order), psi [n_occ, npw] complex128 CUDA
+    tensor, eps [n_occ], eps_lumo, gap, resid [n_occ], N, system (the library System used for
+    the H applies, reusable for the chi0 apply), passes, wall_s). A HOMO-LUMO gap below 1e-4 Ha
+    re-seeds the cell (system id + 1000 k), as ground.py does."""
+    import torch
+    from paper_2607_14025_amd import System
+    from paper_2607_14025_amd.stern import basis_info
+    dev = torch.device(f"cuda:{device}")
+    for k in range(max_reseed):
+        t0 = time.perf_counter()
+        sp = spec.with_system(spec.system_id + 1000 * k)
+        pos = place_atoms(sp)
+        sysm = System(sp.L, sp.ecut, pos, sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width, device=device)
+        npw, N, mil = basis_info(sp.L, sp.ecut)
+        nb = sp.n_occ + (buffer if buffer is not None else max(16, sp.n_occ // 8))
+        gen = torch.Generator(device=dev)
+        gen.manual_seed(_seed(sp))
+        g2 = torch.from_numpy((mil.astype(np.float64) ** 2).sum(axis=1) * (2.0 * math.pi / sp.L) ** 2).to(dev)
+        X = torch.randn(nb, npw, dtype=torch.complex128, device=dev, generator=gen) / (1.0 + 0.5 * g2)[None, :]
+        th, X, res, passes = chebyshev_eigs(lambda Y, sh: sysm.apply_h(Y, shift=sh), X, sp.n_occ + 1, tol,
+                                            degree, max_pass, gen, verbose)
+        if res.max() > tol:
+            raise RuntimeError(f"Chebyshev subspace iteration stopped at residual {res.max():.2e} > {tol:g}")
+        gap = float(th[sp.n_occ] - th[sp.n_occ - 1])
+        if gap >= 1e-4:
+            psi = X[:sp.n_occ].contiguous()
+            del X
+            torch.cuda.synchronize()
+            return dict(spec=sp, pos=pos, miller=mil.astype(np.int64), psi=psi, eps=th[:sp.n_occ].copy(),
+                        eps_lumo=float(th[sp.n_occ]), gap=gap, resid=res[:sp.n_occ].copy(), N=N, system=sysm,
+                        passes=passes, wall_s=time.perf_counter() - t0)
+        if verbose:
+            print(f"  gap {gap:.2e} < 1e-4 Ha, reseeding", flush=True)
+        sysm.close()
+    raise RuntimeError("no cell with a usable gap")
+
+
+def large_workload(spec: CellSpec, n_pert: int, **kw) -> dict:
+    """Ground state (on the GPU) plus the first n_pert seeded fields of one cell."""
+    gs = ground_state_gpu(spec, **kw)
+    _, coeff, dv = random_dv(gs["spec"], n_pert=n_pert, N=gs["N"])
+    gs["dv"] = dv
+    gs["dv_coeff"] = coeff
+    return gs

@@ -52,17 +52,40 @@ def test_sampled_solutions_satisfy_oracle_equation(mid):
     assert np.max(np.abs(x @ psi.conj().T)) < 1e-12 * np.abs(x).max() * psi.shape[1]
 
 
-def test_sampled_solutions_match_oracle_at_tight_tolerance(mid):
-    """Field 0 solved to 1e-12 on the GPU; sampled x equal the oracle's PCG solutions."""
+@pytest.fixture(scope="module")
+def field0_oracle(mid):
+    """The oracle's dn of field 0 over all 128 bands, and every x, at tolerance 1e-12."""
     cell, psi, wl = mid["cell"], mid["psi"], mid["wl"]
+    return apply_chi0(cell, psi, wl["eps"], wl["dv"][:1], tol=1e-12)
+
+
+def test_field0_dn_matches_oracle_fp64(mid, field0_oracle):
+    """Field 0 over all 128 bands, element by element: the plain path at 1e-11 is within 1e-9 of the
+    oracle at 1e-12 (this pins the 72^3 right-hand-side and dn plane kernels), sampled x too; the
+    bench call's field 0 (1e-8) is within 1e-7."""
+    cell, wl, ref = mid["cell"], mid["wl"], field0_oracle
     pairs = [(0, 0), (127, 0), (64, 0)]
-    _, info = mid["s"].apply_chi0(mid["dv_t"][:1].contiguous(), tol=1e-12, samples=pairs)
+    dn, info = mid["s"].apply_chi0(mid["dv_t"][:1].contiguous(), tol=1e-11, samples=pairs)
     assert info["n_converged"] == 128
-    ref = apply_chi0(cell, psi, wl["eps"], wl["dv"][:1], tol=1e-12, bands=[0, 127, 64], perts=[0])
+    err = rel_l2(dn.cpu().numpy(), ref["dn"]).max()
+    print(f"mid field 0: FP64 at 1e-11 vs oracle {err:.2e}; bench call {rel_l2(mid['dn'][:1], ref['dn']).max():.2e}")
+    assert err <= 1e-9
+    assert rel_l2(mid["dn"][:1], ref["dn"]).max() <= 1e-7
     x = cell.take(info["samples"], wl["miller"])
     for k, pr in enumerate(pairs):
         r = ref["x"][ref["pairs"].index(pr)]
         assert np.linalg.norm(x[k] - r) / np.linalg.norm(r) < 1e-9, pr
+
+
+def test_field0_dn_matches_oracle_mixed(mid, field0_oracle):
+    """The mixed path (FP32 FFTs, split-BF16 GEMMs, FP64 defect correction) at the metric's 1e-8 is
+    within 1e-6 of the oracle on field 0, element by element."""
+    from paper_2607_14025_amd import STERN_MIXED
+    dn, info = mid["s"].apply_chi0(mid["dv_t"][:1].contiguous(), tol=1e-8, precision=STERN_MIXED)
+    assert info["n_converged"] == 128
+    err = rel_l2(dn.cpu().numpy(), field0_oracle["dn"]).max()
+    print(f"mid field 0: mixed at 1e-8 vs oracle {err:.2e}")
+    assert err <= 1e-6
 
 
 def test_chi0_properties_at_full_size(mid):

@@ -1,11 +1,16 @@
 """Pins of the oracle's Sternheimer solve and density response (CPU only)."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
 
-from oracle import OracleCell, apply_chi0, finite_field_dn, lindhard_dn, sum_over_states, teter
+from oracle import OracleCell, apply_chi0, band_kinetic, finite_field_dn, lindhard_dn, sum_over_states, teter
 from oracle.sternheimer import chi0_matrix, rel_l2
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -24,6 +29,33 @@ def test_teter_limits():
     z = np.linspace(1e-3, 50, 1000)
     k = teter(z)
     assert np.all((k > 0) & (k < 1)) and np.all(np.diff(k) < 0)
+
+
+def test_teter_exact_values():
+    """The preconditioner at fractions of y where the published formula was evaluated exactly
+    (tests/golden/teter_exact.json): a wrong coefficient in any power of y fails here."""
+    pts = json.load(open(os.path.join(GOLDEN, "teter_exact.json")))["points"]
+    y = np.array([p["y_num"] / p["y_den"] for p in pts])
+    want = np.array([p["K_num"] / p["K_den"] for p in pts])
+    assert np.allclose(teter(y), want, rtol=1e-15, atol=0)
+
+
+def test_band_kinetic_and_its_floor():
+    """T_v of single plane waves is |G|^2 / 2 exactly; the G = 0 wave (T = 0) and a band
+    below the floor take the kinetic energy of the smallest nonzero G, (2 pi / L)^2 / 2."""
+    L = 10.0
+    cell = OracleCell(L, 10.0, np.zeros((0, 3)))
+    b2h = 0.5 * (2.0 * math.pi / L) ** 2
+    mil = [tuple(m) for m in cell.miller.tolist()]
+    psi = np.zeros((5, cell.npw), dtype=np.complex128)
+    psi[0, mil.index((0, 0, 0))] = 1.0                       # T = 0 -> floor
+    psi[1, mil.index((1, 0, 0))] = 1j                        # T = b^2/2 (the floor itself)
+    psi[2, mil.index((2, 0, 0))] = -1.0                      # T = 4 b^2/2
+    psi[3, mil.index((1, 1, 1))] = np.exp(0.3j)              # T = 3 b^2/2
+    psi[4, mil.index((0, 0, 0))] = math.sqrt(0.9)            # T = 0.1 b^2/2, below the floor
+    psi[4, mil.index((0, 1, 0))] = math.sqrt(0.1)
+    t = band_kinetic(cell, psi)
+    assert np.allclose(t, b2h * np.array([1.0, 1.0, 4.0, 3.0, 1.0]), rtol=1e-14, atol=0)
 
 
 def test_pcg_dn_equals_sum_over_states(tiny_system, tiny_ref):
