@@ -81,10 +81,22 @@ typedef struct {
   int fft_n;
 } stern_cell;
 
-/* device: HIP ordinal; stream: hipStream_t to run on (NULL = default stream). */
+/* device: HIP ordinal; stream: hipStream_t to run on (NULL = default stream).
+ * dev_alloc / dev_free (both or neither; NULL = hipMalloc / hipFree): the
+ * caller's device allocator, e.g. a framework's caching allocator. The library
+ * takes every device buffer of the system from dev_alloc(bytes, alloc_ctx),
+ * which must return memory on `device` aligned to at least 256 bytes, or NULL
+ * (the call then fails with STERN_ERR_OOM); it hands each one back with
+ * dev_free(ptr, alloc_ctx) once the work that used it has completed (it
+ * synchronises the device first), at the latest in stern_free. The callbacks
+ * may run on any thread that calls into the library for this system,
+ * including the worker threads of stern_apply_chi0_many. */
 typedef struct {
   int device;
   void* stream;
+  void* (*dev_alloc)(size_t bytes, void* ctx);
+  void (*dev_free)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } stern_runtime;
 
 typedef struct {
@@ -178,27 +190,47 @@ typedef struct {
   double kernel_flops[STERN_NKERNEL];
 } stern_stats;
 
-/* Host only, no GPU needed: basis size, FFT grid and (if miller != NULL) the
+/* Plane-wave basis of the wave functions (the representation of Sec. II, whose
+ * cost N_pw enters the N_occ^2 x N_PDEP x N_pw count of Sec. II.A).
+ * Host only, no GPU needed: basis size, FFT grid and (if miller != NULL) the
  * [n_pw][3] Miller triples in canonical order. */
 int stern_basis_info(const stern_cell* cell, int* n_pw, int* fft_n, int32_t* miller);
 
-/* Builds the basis, V_loc on the grid and the projectors on the GPU.
- * Returns STERN_ERR_UNSUPPORTED for grids other than 2^a 3^b in [8, 128]. */
+/* The Hamiltonian of eq. ks for one cell (Sec. II: the ground-state code
+ * supplies it; here the model above stands in for it). Builds the basis, V_loc
+ * on the grid and the projectors on the GPU. *out receives a system the caller
+ * releases with stern_free. Returns STERN_ERR_INVALID_ARG for a bad cell or
+ * runtime, STERN_ERR_UNSUPPORTED for grids other than 2^a 3^b in [8, 128] or
+ * whose plane kernels do not fit in LDS, STERN_ERR_OOM / _HIP on device errors. */
 int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_system** out);
 
+/* Sizes of the system's basis (Sec. II): plane waves, FFT grid N, cell volume
+ * Omega (bohr^3). Any output pointer may be NULL. Host only. */
 int stern_query(const stern_system* sys, int* n_pw, int* fft_n, double* omega);
 
-/* Occupied states: psi [n_occ][n_pw] complex in canonical order (orthonormal),
- * eps [n_occ] Ha. Both host (mem_kind = STERN_MEM_HOST) or device pointers. */
+/* The Miller triples n (G = 2 pi n / L) of the system's canonical order, as
+ * [n_pw][3] int32 into caller memory: the order every coefficient array of
+ * this ABI uses (psi, sample_x, apply_h / apply_pc rows). Host only. */
+int stern_get_miller(const stern_system* sys, int32_t* miller);
+
+/* The occupied Kohn-Sham states psi_v and energies eps_v of eq. ks, the input
+ * of the density response of Sec. II.A. psi [n_occ][n_pw] complex in canonical
+ * order (orthonormal), eps [n_occ] Ha, both host (mem_kind = STERN_MEM_HOST) or
+ * both device pointers; copied. Replaces earlier states. Errors:
+ * STERN_ERR_INVALID_ARG, STERN_ERR_OOM, STERN_ERR_HIP. */
 int stern_set_occupied(stern_system* sys, int n_occ, const double* psi, const double* eps, int mem_kind);
 
-/* dn_r[i] = chi0 dv_r[i] for i < n_pert, summed over bands [band_begin, band_end).
+/* The density response chi0 dV that PDEP iterates on (Sec. II.A, eq. pdep):
+ * one Sternheimer solve per (band, field), then dn = 4 Re sum_v psi_v* x_v.
+ * dn_r[i] = chi0 dv_r[i] for i < n_pert, summed over bands [band_begin, band_end).
  * dv_r, dn_r: [n_pert][N][N][N] real, host or device per opts->mem_kind.
  * Returns STERN_OK, STERN_WARN_NOT_CONVERGED, or an error. stats may be NULL. */
 int stern_apply_chi0(stern_system* sys, int n_pert, const double* dv_r, double* dn_r,
                      const stern_opts* opts, stern_stats* stats);
 
-/* Batched apply over n_sys independent cells of uneven size (e.g. different L,
+/* Sec. III.A treats images and bands as independent units of work; this
+ * batches independent cells in one call.
+ * Batched apply over n_sys independent cells of uneven size (e.g. different L,
  * atom counts, bands and grids): dn_r[k] = chi0_k dv_r[k] for each system k,
  * with n_pert[k] fields. The systems are spread over concurrent HIP streams
  * (one per worker thread, default priority), each system keeping its own
@@ -328,16 +360,23 @@ int stern_autotune(stern_system* sys, int n_vec, const char* cache_path, int* ch
  * or before any tuning). Valid until the thread's next autotune call. */
 const char* stern_autotune_report(void);
 
-/* out = (H - shift_k) c_k for n_vec coefficient rows (canonical order), host or
- * device memory; shift may be NULL (zero). Exposes the H apply of the solver. */
+/* The Hamiltonian of eq. ks applied as the solver applies it (FFT stage plus
+ * projectors): out = (H - shift_k) c_k for n_vec coefficient rows (canonical
+ * order), host or device memory per mem_kind; shift [n_vec] may be NULL (zero).
+ * Synchronous. */
 int stern_apply_h(stern_system* sys, int n_vec, const double* c, const double* shift, double* out, int mem_kind);
 
-/* out = P_c c for n_vec rows (canonical order). Requires set_occupied. */
+/* The projector onto the empty states, P_c = 1 - sum_v |psi_v><psi_v|, that the
+ * DFPT route of Sec. II.A uses to avoid empty states: out = P_c c for n_vec rows
+ * (canonical order, host or device per mem_kind). STERN_ERR_STATE before
+ * set_occupied. Synchronous. */
 int stern_apply_pc(stern_system* sys, int n_vec, const double* c, double* out, int mem_kind);
 
-/* NULL-safe. */
+/* Releases the system and every device buffer it holds (through the caller's
+ * dev_free when one was given). NULL-safe. */
 void stern_free(stern_system* sys);
 
+/* Message of the last failing call on the calling thread (never NULL). */
 const char* stern_last_error(void);
 
 #ifdef __cplusplus

@@ -48,28 +48,55 @@ int fail(int code, const char* fmt, ...) {
     if (rc_ < 0) return rc_;  \
   } while (0)
 
+// Device allocator of a system: the caller's callbacks (stern_runtime) or, when
+// they are NULL, hipMalloc / hipFree. Entry points make their system's allocator
+// the current one of the calling thread (Scope); a buffer remembers the allocator
+// that gave it its memory and returns the memory there.
+struct Alloc {
+  void* (*alloc)(size_t, void*) = nullptr;
+  void (*free)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+thread_local const Alloc* tl_alloc = nullptr;
+
 // A device allocation that only grows.
 struct DBuf {
   void* p = nullptr;
   size_t n = 0;
+  Alloc al;  // where p came from (al.alloc == nullptr: hipMalloc)
   int ensure(size_t bytes) {
     if (bytes <= n) return 0;
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
+    release();
     if (bytes == 0) return 0;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) {
-      p = nullptr;
-      return fail(STERN_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    if (tl_alloc && tl_alloc->alloc) {
+      p = tl_alloc->alloc(bytes, tl_alloc->ctx);
+      if (!p) return fail(STERN_ERR_OOM, "the caller's dev_alloc(%zu) returned NULL", bytes);
+      al = *tl_alloc;
+    } else {
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        p = nullptr;
+        return fail(STERN_ERR_OOM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+      }
+      al = Alloc();
     }
     n = bytes;
     return 0;
   }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p) {
+      if (al.free) {
+        // hipFree waits for the work that may still use the memory; a caller's
+        // allocator may hand it out again at once, so wait here instead
+        (void)hipDeviceSynchronize();
+        al.free(p, al.ctx);
+      } else {
+        (void)hipFree(p);
+      }
+    }
     p = nullptr;
     n = 0;
+    al = Alloc();
   }
   template <class T>
   T* as() const {
@@ -87,6 +114,7 @@ int upload(DBuf& d, const void* src, size_t bytes, hipStream_t st) {
 
 struct stern_system {
   int device = 0;
+  Alloc alloc;  // device allocator of every buffer of this system
   int n_cu = 256;
   hipStream_t stream = nullptr;
   hipStream_t own_stream = nullptr;  // non-blocking stream for graph capture (created on demand)
@@ -550,14 +578,19 @@ int launch_check() {
   return 0;
 }
 
+// Makes `dev` the current device and `al` the current allocator of the calling
+// thread for the lifetime of the object.
 struct Scope {
   int dev_prev = -1;
-  explicit Scope(int dev) {
+  const Alloc* al_prev = nullptr;
+  explicit Scope(int dev, const Alloc* al = nullptr) : al_prev(tl_alloc) {
     (void)hipGetDevice(&dev_prev);
     (void)hipSetDevice(dev);
+    tl_alloc = al;
   }
   ~Scope() {
     if (dev_prev >= 0) (void)hipSetDevice(dev_prev);
+    tl_alloc = al_prev;
   }
 };
 
@@ -852,7 +885,8 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
   const double vec32 = vecb / 2;
   Cg32State c32 = cg32_state(S, cs.iters);
   c32.kprec = cs.kprec;
-  std::vector<int> h_flag(ns_all), h_iflag(ns_all), act, iact;
+  const int ns32 = S->ws32_solves;  // rows of the FP32 workspace (the FP64 one may hold more)
+  std::vector<int> h_flag(ns_all), h_iflag(ns32), act, iact;
   HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
   for (int s : list)
@@ -866,7 +900,7 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
     if (projected) CHECKED(apply_pc32_rows(S, c32.z, L, na));
     CHECKED(timed(S, STERN_K_CG32, na * 3.0 * vec32, 0.0, [&] { launch_cg32_init2(c32, L, na, st); }));
     CHECKED(launch_check());
-    HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns32 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPOK(hipStreamSynchronize(st));
     iact.clear();
     for (int s : act)
@@ -894,7 +928,7 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       }));
       it += nsteps;
       CHECKED(launch_check());
-      HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns32 * sizeof(int), hipMemcpyDeviceToHost, st));
       HIPOK(hipStreamSynchronize(st));
       std::vector<int> nxt;
       for (int s : iact)
@@ -992,9 +1026,16 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
   *out = nullptr;
   CellParams p;
   CHECKED(cell_from_abi(cell, p));
+  if (rt && (rt->dev_alloc == nullptr) != (rt->dev_free == nullptr))
+    return fail(STERN_ERR_INVALID_ARG, "dev_alloc and dev_free must be given together");
   stern_system* S = new stern_system();
   S->device = rt ? rt->device : 0;
   S->stream = rt ? (hipStream_t)rt->stream : nullptr;
+  if (rt && rt->dev_alloc) {
+    S->alloc.alloc = rt->dev_alloc;
+    S->alloc.free = rt->dev_free;
+    S->alloc.ctx = rt->alloc_ctx;
+  }
   S->cell = p;
   std::string e = build_basis(p, S->hb);
   if (!e.empty()) {
@@ -1006,7 +1047,7 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     delete S;
     return fail(STERN_ERR_UNSUPPORTED, "FFT grid %d is not a supported 2^a 3^b size", hb.N);
   }
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) {
     delete S;
@@ -1115,11 +1156,17 @@ int stern_query(const stern_system* S, int* n_pw, int* fft_n, double* omega) {
   return STERN_OK;
 }
 
+int stern_get_miller(const stern_system* S, int32_t* miller) {
+  if (!S || !miller) return fail(STERN_ERR_INVALID_ARG, "system and miller must not be NULL");
+  std::memcpy(miller, S->hb.miller.data(), S->hb.miller.size() * sizeof(int32_t));
+  return STERN_OK;
+}
+
 int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const double* eps, int mem_kind) {
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   if (n_occ <= 0 || !psi || !eps) return fail(STERN_ERR_INVALID_ARG, "need n_occ > 0, psi and eps");
   if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   const HostBasis& hb = S->hb;
   hipStream_t st = S->stream;
   const int npw = hb.npw, K = hb.npw_pad, N = hb.N;
@@ -1228,7 +1275,7 @@ int stern_apply_h(stern_system* S, int n_vec, const double* c, const double* shi
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   if (n_vec <= 0) return STERN_OK;
   if (!c || !out) return fail(STERN_ERR_INVALID_ARG, "NULL array");
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   CHECKED(ensure_workspace(S, std::max(n_vec, S->ws_solves)));
   CHECKED(rows_in(S, n_vec, c, mem_kind, S->wp));
   std::vector<double> sh(n_vec, 0.0);
@@ -1249,7 +1296,7 @@ int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int
   if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
   if (n_vec <= 0) return STERN_OK;
   if (!c || !out) return fail(STERN_ERR_INVALID_ARG, "NULL array");
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   CHECKED(ensure_workspace(S, std::max(n_vec, S->ws_solves)));
   CHECKED(rows_in(S, n_vec, c, mem_kind, S->wp));
   CHECKED(apply_pc_rows(S, S->wp.as<Z64>(), nullptr, n_vec));
@@ -1264,7 +1311,7 @@ int stern_apply_chi0(stern_system* S, int n_pert, const double* dv_r, double* dn
                      stern_stats* stats) {
   if (!S || !opts || !opts->use_graph || opts->profile) return apply_chi0_impl(S, n_pert, dv_r, dn_r, opts, stats);
   // stream capture is not allowed on the legacy default stream: run on the system's own stream
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   if (!S->own_stream) HIPOK(hipStreamCreateWithFlags(&S->own_stream, hipStreamNonBlocking));
   HIPOK(hipStreamSynchronize(S->stream));
   hipStream_t caller = S->stream;
@@ -1306,7 +1353,7 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     const int v = opts->sample_pairs[2 * k], i = opts->sample_pairs[2 * k + 1];
     if (v < v0 || v >= v1 || i < 0 || i >= n_pert) return fail(STERN_ERR_INVALID_ARG, "sample pair %d out of range", k);
   }
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   hipStream_t st = S->stream;
   const HostBasis& hb = S->hb;
   const int N = hb.N, K = hb.npw_pad;
@@ -1481,7 +1528,7 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
   std::vector<hipStream_t> streams(workers, nullptr);
   std::vector<hipStream_t> saved(n_sys);
   for (int k = 0; k < n_sys; ++k) {  // inputs were produced on the systems' own streams
-    Scope sc(sys[k]->device);
+    Scope sc(sys[k]->device, &sys[k]->alloc);
     HIPOK(hipStreamSynchronize(sys[k]->stream));
     saved[k] = sys[k]->stream;
   }
@@ -1582,7 +1629,7 @@ int stern_autotune(stern_system* S, int n_vec, const char* cache_path, int* chos
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
   if (n_vec <= 0 || n_vec > 65536) return fail(STERN_ERR_INVALID_ARG, "n_vec must be in [1, 65536]");
-  Scope sc(S->device);
+  Scope sc(S->device, &S->alloc);
   hipStream_t st = S->stream;
   S->prof_on = false;
   S->recs.clear();
@@ -1900,6 +1947,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
   // ---- dataset: plain FP64 solutions of every system ----
   for (int k = 0; k < n_sys; ++k) {
     stern_system* S = sys[k];
+    Scope ssc(S->device, &S->alloc);
     hipStream_t st = S->stream;
     const HostBasis& hb = S->hb;
     const size_t n3 = (size_t)hb.N * hb.N * hb.N;
@@ -2019,6 +2067,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
     CHECKED(M->fset.ensure((size_t)ncap * kPrecIn * sizeof(float)));
     for (int k = 0; k < n_sys; ++k) {
       stern_system* S = sys[k];
+      Scope ssc(S->device, &S->alloc);
       hipStream_t st2 = S->stream;
       const HostBasis& hb = S->hb;
       const int nb = S->n_occ, K = hb.npw_pad;
@@ -2077,6 +2126,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
     CHECKED(M->idx.ensure((size_t)2 * Bp * sizeof(int)));
     std::vector<std::pair<int, int>> batches;  // (system, first sample)
     for (int k = 0; k < n_sys; ++k) {
+      Scope ssc(sys[k]->device, &sys[k]->alloc);
       CHECKED(ensure_workspace(sys[k], std::max(sys[k]->ws_solves, Bp)));
       for (int j = sys_begin[k]; j < sys_begin[k + 1]; j += Bp) batches.push_back({k, j});
     }
@@ -2139,7 +2189,7 @@ int stern_model_train(stern_model* M, int n_sys, stern_system* const* sys, const
 void stern_free(stern_system* S) {
   if (!S) return;
   {
-    Scope sc(S->device);
+    Scope sc(S->device, &S->alloc);
     if (S->stream) (void)hipStreamSynchronize(S->stream);
     else (void)hipDeviceSynchronize();
     S->release_all();

@@ -26,7 +26,7 @@ STERN_INNER_SHIFTED = 1
 STERN_MEM_HOST = 0
 STERN_MEM_DEVICE = 1
 
-EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied", "stern_apply_chi0",
+EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_miller", "stern_set_occupied", "stern_apply_chi0",
             "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
@@ -52,8 +52,13 @@ class Cell(C.Structure):
                 ("kb_width", C.c_double), ("fft_n", C.c_int)]
 
 
+DEV_ALLOC = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEV_FREE = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class Runtime(C.Structure):
-    _fields_ = [("device", C.c_int), ("stream", C.c_void_p)]
+    _fields_ = [("device", C.c_int), ("stream", C.c_void_p), ("dev_alloc", DEV_ALLOC), ("dev_free", DEV_FREE),
+                ("alloc_ctx", C.c_void_p)]
 
 
 class Opts(C.Structure):
@@ -104,6 +109,7 @@ def lib():
         L.stern_basis_info.argtypes = [P(Cell), P(C.c_int), P(C.c_int), P(C.c_int32)]
         L.stern_init_system.argtypes = [P(Cell), P(Runtime), P(C.c_void_p)]
         L.stern_query.argtypes = [C.c_void_p, P(C.c_int), P(C.c_int), P(C.c_double)]
+        L.stern_get_miller.argtypes = [C.c_void_p, P(C.c_int32)]
         L.stern_set_occupied.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_chi0.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, P(Opts), P(Stats)]
         L.stern_apply_chi0_many.argtypes = [C.c_int, P(C.c_void_p), P(C.c_int), P(C.c_void_p), P(C.c_void_p),
@@ -127,7 +133,7 @@ def lib():
         L.stern_free.argtypes = [C.c_void_p]
         L.stern_free.restype = None
         L.stern_last_error.restype = C.c_char_p
-        for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_set_occupied",
+        for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_get_miller", "stern_set_occupied",
                      "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc",
                      "stern_model_create", "stern_model_train", "stern_model_num_params", "stern_model_get_weights",
                      "stern_model_set_weights", "stern_model_fit_step", "stern_tunable", "stern_autotune"):
@@ -241,9 +247,26 @@ class System:
     """One cell on one GPU (stern_init_system ... stern_free)."""
 
     def __init__(self, L, ecut, pos, vloc_amp=-2.0, vloc_sigma=1.0, kb_D=1.0, kb_width=1.0, fft_n=0, device=0,
-                 stream=None):
+                 stream=None, torch_allocator=False):
+        """torch_allocator: take every device buffer of the system from torch's caching allocator
+        (stern_runtime.dev_alloc / dev_free) instead of hipMalloc."""
         c, self._pos = _cell(L, ecut, pos, vloc_amp, vloc_sigma, kb_D, kb_width, fft_n)
         rt = Runtime(int(device), stream if stream is not None else _torch_stream())
+        if torch_allocator:
+            import torch
+            st = torch.cuda.current_stream(int(device)) if stream is None else None
+
+            def _alloc(nbytes, ctx):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), int(device), st)
+                except RuntimeError:
+                    return None
+
+            def _free(ptr, ctx):
+                torch.cuda.caching_allocator_delete(ptr)
+
+            self._alloc_cbs = (DEV_ALLOC(_alloc), DEV_FREE(_free))  # kept alive with the system
+            rt.dev_alloc, rt.dev_free = self._alloc_cbs
         h = C.c_void_p()
         _check(lib().stern_init_system(C.byref(c), C.byref(rt), C.byref(h)))
         self._h = h
@@ -262,6 +285,12 @@ class System:
             self.close()
         except Exception:
             pass
+
+    def miller(self):
+        """Miller triples [n_pw, 3] of the system's canonical order (stern_get_miller)."""
+        mil = np.zeros((self.n_pw, 3), dtype=np.int32)
+        _check(lib().stern_get_miller(self._h, mil.ctypes.data_as(C.POINTER(C.c_int32))))
+        return mil
 
     def set_occupied(self, psi, eps):
         """psi [n_occ, n_pw] complex (canonical order), eps [n_occ]; numpy or CUDA tensors."""

@@ -26,3 +26,21 @@ def tiny_system():
     _, coeff, dv = random_dv(sp)
     psi = cell.take(gs["psi"], gs["miller"])
     return dict(gs=gs, spec=sp, cell=cell, dv=dv, dv_coeff=coeff, psi=psi, eps=gs["eps"])
+
+
+@pytest.fixture(scope="session")
+def large_cell():
+    """The large cell at full size (L=32 bohr, 512 atoms, 30 Ry: 91,047 PWs, 128^3, 1,024 occupied
+    bands), ground state from the GPU eigensolver of the input generator, the first 8 seeded
+    fields (0-3 the solved ones, 4-7 for training), and the library system that made it."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from synth.cells import LARGE
+    from synth.ground_gpu import large_workload
+    wl = large_workload(LARGE, n_pert=8)
+    print(f"large cell ground state: {wl['passes']} passes, {wl['wall_s']:.1f} s, gap {wl['gap']:.2e} Ha, "
+          f"max eigen-residual {wl['resid'].max():.2e}", flush=True)
+    s = wl["system"]
+    s.set_occupied(wl["psi"], torch.from_numpy(wl["eps"]).to(wl["psi"].device))
+    yield wl
+    s.close()
