@@ -372,6 +372,24 @@ int stern_apply_h(stern_system* sys, int n_vec, const double* c, const double* s
  * set_occupied. Synchronous. */
 int stern_apply_pc(stern_system* sys, int n_vec, const double* c, double* out, int mem_kind);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): out = P_c c as
+ * stern_apply_pc computes it (the same kernels, so bitwise the same result),
+ * device pointers only, c and out [n_vec][n_pw] complex in canonical order
+ * (they may not overlap). Every temporary lives in a fixed scratch area of
+ * STERN_NOALLOC_SCRATCH_BYTES per device, held from the first stern_init_system
+ * on that device to the end of the process: 16 n_vec (npw_pad + (s + 1)
+ * nocc_pad) bytes, with npw_pad and nocc_pad the plane-wave and band counts
+ * rounded up to multiples of 64 and s the split-K factor of the reduce;
+ * STERN_ERR_INVALID_ARG when that exceeds the area (about 230 rows of the
+ * 72^3, 128-band cell). Enqueued on the system's stream without any
+ * synchronisation or allocation; the result is ready when that stream's work
+ * is. All calls on one GPU share its area and it keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other
+ * threads) race, so issue them on one stream. */
+#define STERN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int stern_apply_pc_noalloc(stern_system* sys, int n_vec, const double* c, double* out);
+
 /* Releases the system and every device buffer it holds (through the caller's
  * dev_free when one was given). NULL-safe. */
 void stern_free(stern_system* sys);

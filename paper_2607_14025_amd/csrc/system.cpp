@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <numeric>
+#include <mutex>
 #include <random>
 #include <string>
 #include <thread>
@@ -110,6 +111,34 @@ int upload(DBuf& d, const void* src, size_t bytes, hipStream_t st) {
   return 0;
 }
 
+}  // namespace
+
+// Fixed per-device scratch area of stern_apply_pc_noalloc: every temporary of
+// that entry point lives here, so it never allocates. In host code the array's
+// name is only a stand-in; its device address comes from hipGetSymbolAddress,
+// taken once per device with that device current and kept in g_scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[STERN_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // [device] address of `scratch` on that device
+
+// Device address of the scratch area on `device` (which must be current).
+int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (device < 0) return fail(STERN_ERR_INVALID_ARG, "bad device %d", device);
+  if ((size_t)device >= g_scratch_ptr.size()) g_scratch_ptr.resize(device + 1, nullptr);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(STERN_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d failed: %s", device,
+                  hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return 0;
+}
 }  // namespace
 
 struct stern_system {
@@ -1048,6 +1077,14 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     return fail(STERN_ERR_UNSUPPORTED, "FFT grid %d is not a supported 2^a 3^b size", hb.N);
   }
   Scope sc(S->device, &S->alloc);
+  {
+    void* scr = nullptr;
+    const int rc = scratch_address(S->device, &scr);
+    if (rc < 0) {
+      delete S;
+      return rc;
+    }
+  }
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, S->device) != hipSuccess) {
     delete S;
@@ -1302,6 +1339,39 @@ int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int
   CHECKED(apply_pc_rows(S, S->wp.as<Z64>(), nullptr, n_vec));
   CHECKED(launch_check());
   return rows_out(S, n_vec, S->wp.as<Z64>(), nullptr, out, mem_kind);
+}
+
+int stern_apply_pc_noalloc(stern_system* S, int n_vec, const double* c, double* out) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
+  if (n_vec < 0) return fail(STERN_ERR_INVALID_ARG, "n_vec must be >= 0");
+  if (n_vec == 0) return STERN_OK;
+  if (!c || !out) return fail(STERN_ERR_INVALID_ARG, "NULL array");
+  const int npw = S->hb.npw, K = S->hb.npw_pad, M = S->nocc_pad;
+  const int ns = choose_nsplit(M, n_vec, K, S->gemm64_wg);
+  // scratch: rows in column order [n][K], split-K partials [ns][n][M], C [n][M]
+  const size_t rows_b = (size_t)n_vec * K * sizeof(Z64);
+  const size_t part_b = (size_t)ns * n_vec * M * sizeof(Z64);
+  const size_t need = rows_b + part_b + (size_t)n_vec * M * sizeof(Z64);
+  if (need > (size_t)STERN_NOALLOC_SCRATCH_BYTES)
+    return fail(STERN_ERR_INVALID_ARG, "%d rows need %zu bytes of scratch; the limit is %zu", n_vec, need,
+                (size_t)STERN_NOALLOC_SCRATCH_BYTES);
+  Scope sc(S->device, &S->alloc);
+  void* scr = nullptr;
+  CHECKED(scratch_address(S->device, &scr));
+  unsigned char* base = static_cast<unsigned char*>(scr);
+  Z64* rows = reinterpret_cast<Z64*>(base);
+  Z64* part = reinterpret_cast<Z64*>(base + rows_b);
+  Z64* cmat = reinterpret_cast<Z64*>(base + rows_b + part_b);
+  hipStream_t st = S->stream;
+  // the padding entries of the rows take part in the reduce and must be zero
+  launch_fill_zero(rows, (size_t)n_vec * K, st);
+  launch_permute(reinterpret_cast<const Z64*>(c), npw, rows, K, S->perm.as<int>(), npw, n_vec, true, st);
+  launch_zgemm_reduce(S->psi.as<Z64>(), M, rows, K, nullptr, n_vec, K, part, ns, st);
+  launch_sum_parts(part, ns, n_vec, M, -1.0, cmat, st);
+  launch_zgemm_expand(S->psi.as<Z64>(), M, cmat, rows, K, nullptr, n_vec, K, st);
+  launch_permute(rows, K, reinterpret_cast<Z64*>(out), npw, S->perm.as<int>(), npw, n_vec, false, st);
+  return launch_check();
 }
 
 static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, double* dn_r, const stern_opts* opts,
