@@ -1,17 +1,24 @@
-"""Benchmark: converged Sternheimer solves per second of one chi0 apply on one GPU.
+"""Benchmark: converged Sternheimer solves per second of the chi0 apply on one GPU.
 
-A step is one stern_apply_chi0 call on the mid cell (L = 20 bohr, 64 atoms,
-25 Ry: 16,879 plane waves, 72^3 grid, 128 occupied bands x 64 band-limited
-fields = 8,192 Sternheimer solves, FP64 true residual <= 1e-8), inputs already
-resident in HBM. The headline path is the learned guess and preconditioner
-(trained beforehand, untimed, on two other seeded cells of the same model and
-size) with mixed-precision defect correction; the plain FP64 path is timed
-on the same cell as the baseline. Prints one JSON line with the throughput,
-the roofline of the dominant kernel (per-launch HIP events on the library's
-stream) and the CPU oracle timed on a bounded sample of the same workload.
+Headline workload: the large cell at full size (L = 32 bohr, 512 atoms, 30 Ry: 91,047 plane
+waves, 128^3 grid, 1,024 occupied bands). A step is one stern_apply_chi0 over 4 fields x 1,024
+bands = 4,096 Sternheimer solves (the one-GPU share of a 32-field Davidson block spread over 8
+GPUs), FP64 true residual <= 1e-8, inputs already resident in HBM. The headline path is fixed
+before anything is timed: the learned diagonal preconditioner (net trained, untimed, on fields
+4-5 of the same cell, disjoint from the timed fields 0-3) with mixed-precision defect correction
+(FP32 FFTs, split-BF16 MFMA GEMMs, FP64 outer residual). The plain FP64 path runs the same call
+as the baseline, with its own step count. The occupied states come from the input generator's
+GPU eigensolver (Chebyshev-filtered subspace iteration on the library's own H apply, untimed).
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
-                    [--path learned-mixed|mixed|fp64]
+Timed steps run without the per-launch profile; one extra profiled step of the headline path,
+the last apply of the run, gives the kernel breakdown and the roofline of the dominant kernel
+(HIP events on the library's stream). Secondary entries (fewer steps, same metric): the mid
+cell (72^3, 128 bands x 64 fields) and the 32 uneven cells of the batched workload in one
+stern_apply_chi0_many call. The CPU oracle is timed on a seeded uniform sample of the headline's
+(band, field) pairs, solved as one batch; its mean iterations are stated beside the GPU's.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--fp64-steps F] [--no-cpu-baseline]
+                    [--no-secondary] [--cpu-pairs P]
 """
 from __future__ import annotations
 
@@ -33,48 +40,281 @@ FP64_VALU_PEAK_TFS = 78.6    # MI355X FP64 vector
 ALU_KERNELS = {"plane_h32": FP32_VALU_PEAK_TFS, "plane_h": FP64_VALU_PEAK_TFS}
 MFMA_KERNELS = {"gemm_bf16": BF16_MFMA_PEAK_TFS, "pc_reduce": FP64_MFMA_PEAK_TFS, "pc_expand": FP64_MFMA_PEAK_TFS,
                 "kb_reduce": FP64_MFMA_PEAK_TFS, "kb_expand": FP64_MFMA_PEAK_TFS, "net": BF16_MFMA_PEAK_TFS}
+FFT_KERNELS = ("plane_h32", "x32", "plane_h", "xinv", "xfwd")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+METRIC = "converged Sternheimer solves/s at resid≤1e-8 (learned+mixed vs plain FP64)"
 
 
-def measured_traffic(kernel: str, algorithmic_bytes_per_launch: float):
+def log(msg):
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
+def measured_traffic(kernel: str, algorithmic_bytes_per_launch: float, workload: str):
     """HBM bytes per launch of `kernel` in this run: the ratio of measured (rocprofv3 FETCH_SIZE +
     WRITE_SIZE, calibrated on a plain copy) to algorithmic bytes over the same launches of a
-    committed counter run, times this run's algorithmic bytes per launch; None when the kernel
-    source has changed since the counters were taken."""
+    committed counter run of this workload, times this run's algorithmic bytes per launch; None
+    when there is no such run or the kernel source has changed since the counters were taken."""
     from paper_2607_14025_amd.rocprof_summary import source_hash
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    t = json.load(open(TRAFFIC_FILE)).get(kernel)
+    t = json.load(open(TRAFFIC_FILE)).get(f"{workload}:{kernel}")
     if not t or t.get("source_sha1") != source_hash(kernel) or not t.get("measured_over_algorithmic"):
         return None
     return t["measured_over_algorithmic"] * algorithmic_bytes_per_launch
 
 
-def cpu_baseline(wl, n_bands: int, tol: float):
-    """The oracle on `n_bands` solves (bands 0.. of field 0): RHS, PCG and dn."""
-    from oracle import OracleCell, apply_chi0
+def timed_steps(fn, steps, warmup, label):
+    """Runs fn() warmup times, then `steps` times between device synchronisations; returns
+    (solves/s over the timed steps, seconds, list of infos)."""
+    import torch
+    for w in range(warmup):
+        info = fn()
+        log(f"{label} warmup {w}: {info['n_converged']}/{info['n_solves']} converged in {info['wall_s']:.2f} s")
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        info = fn()
+        infos.append(info)
+        log(f"{label} step {k}: {info['n_converged']}/{info['n_solves']} converged, {info['wall_s']:.3f} s, "
+            f"mean iterations {info['total_iters'] / max(1, info['n_solves']):.1f}, max {info['max_iters']}, "
+            f"max true resid {info['max_true_resid']:.2e}, fallback {info['n_fallback']}")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    conv = sum(i["n_converged"] for i in infos)
+    return conv / dt, dt, infos
+
+
+def summary(infos, dt, value):
+    import numpy as np
+    return dict(solves_per_s=value, steps=len(infos), seconds=dt,
+                mean_iters=float(np.mean([i["total_iters"] / max(1, i["n_solves"]) for i in infos])),
+                max_iters=int(max(i["max_iters"] for i in infos)),
+                fallback_solves=int(sum(i["n_fallback"] for i in infos)),
+                max_true_resid=float(max(i["max_true_resid"] for i in infos)))
+
+
+def rel_err(a, ref):
+    n = ref.shape[0]
+    return ((a - ref).reshape(n, -1).norm(dim=1) / ref.reshape(n, -1).norm(dim=1)).max().item()
+
+
+def roofline(kern, workload):
+    dom = max(kern, key=lambda n: kern[n]["ms"])
+    d = kern[dom]
+    per_launch_s = d["ms"] / d["launches"] / 1e3
+    traffic = measured_traffic(dom, d["bytes"] / d["launches"], workload)
+    if dom in ALU_KERNELS or dom in MFMA_KERNELS:
+        peak = ALU_KERNELS.get(dom) or MFMA_KERNELS[dom]
+        achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
+        roof = dict(bound="alu" if dom in ALU_KERNELS else "mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
+                    frac=achieved / peak, traffic=traffic, kernel=dom,
+                    hbm_GBps=d["bytes"] / d["launches"] / per_launch_s / 1e9)
+        if dom == "gemm_bf16":
+            # the split-BF16 products issue three BF16 MFMA products per complex multiply-add
+            roof["bf16_mfma_TFLOPs_issued"] = 3.0 * achieved
+    else:
+        achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=traffic, kernel=dom)
+    roof["launches"] = d["launches"]
+    roof["ms_per_launch"] = d["ms"] / d["launches"]
+    roof["traffic_source"] = ("profiles/traffic.json: rocprofv3 FETCH_SIZE + WRITE_SIZE of this kernel on this "
+                              "workload, calibrated on a 1 GiB copy, as a ratio to the algorithmic bytes, scaled to "
+                              "this run's launches") if traffic is not None else None
+    return roof
+
+
+def breakdown(kern):
+    total_ms = sum(v["ms"] for v in kern.values())
+    return {n: dict(share=round(v["ms"] / total_ms, 4), launches=v["launches"],
+                    bytes_per_launch=round(v["bytes"] / v["launches"]), ms_per_launch=round(v["ms"] / v["launches"], 4),
+                    GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
+                    TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["flops"] > 0 else None)
+            for n, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
+
+
+def fft_stage(kern):
+    """HBM rate of the FFT stage (x pencils and yz planes) of the profiled step."""
+    ks = [k for k in FFT_KERNELS if k in kern]
+    ms = sum(kern[k]["ms"] for k in ks)
+    b = sum(kern[k]["bytes"] for k in ks)
+    if ms <= 0:
+        return None
+    gbs = b / (ms / 1e3) / 1e9
+    return dict(kernels=ks, ms=ms, algorithmic_GB=b / 1e9, GBps=gbs, frac_of_hbm_peak=gbs / HBM_PEAK_GBS,
+                target_frac=0.6)
+
+
+def cpu_baseline(wl, pairs, tol, gpu_x):
+    """The oracle on a seeded sample of the headline's (band, field) pairs, solved together as
+    one vectorised batch (RHS, projected Teter-PCG to true residual `tol`, dn), numpy/scipy FP64;
+    also the residual of the GPU's solutions of the same pairs under the oracle's operator."""
+    import numpy as np
+    from oracle import OracleCell, project
+    from oracle.sternheimer import band_kinetic, delta_n, pcg_solve, rhs
     spec = wl["spec"]
     cell = OracleCell(spec.L, spec.ecut, wl["pos"])
-    psi = cell.take(wl["psi"], wl["miller"])
+    psi = cell.take(wl["psi"].cpu().numpy() if hasattr(wl["psi"], "cpu") else wl["psi"], wl["miller"])
+    bands = [v for v, _ in pairs]
+    perts = [i for _, i in pairs]
+    tk = band_kinetic(cell, psi)
     t0 = time.perf_counter()
-    out = apply_chi0(cell, psi, wl["eps"], wl["dv"][:1], tol=tol, bands=range(n_bands), perts=[0])
+    b = rhs(cell, psi, wl["dv"], bands, perts)
+    xo, its, _ = pcg_solve(cell, psi, wl["eps"][bands], tk[bands], b, tol)
+    delta_n(cell, psi, xo, bands, perts, max(perts) + 1)
     dt = time.perf_counter() - t0
-    return dict(value=n_bands / dt, unit="solves/s", cores=len(os.sched_getaffinity(0)), kind="oracle",
-                sample=f"{n_bands} (band, field) pairs of the same cell (bands 0-{n_bands - 1} of field 0): "
-                       f"RHS + projected Teter-PCG to true residual {tol:g} + dn, numpy/scipy FP64, "
-                       f"{dt:.1f} s, mean {out['iters'].mean():.1f} CG iterations")
+    x = cell.take(gpu_x, wl["miller"])
+    px = project(psi, x)
+    ax = project(psi, cell.h_apply(px) - wl["eps"][bands][:, None] * px)
+    res = np.linalg.norm(b - ax, axis=1) / np.linalg.norm(b, axis=1)
+    dx = np.linalg.norm(x - xo, axis=1) / np.linalg.norm(xo, axis=1)
+    return dict(value=len(pairs) / dt, unit="solves/s", cores=len(os.sched_getaffinity(0)), kind="oracle",
+                sample=f"{len(pairs)} (band, field) pairs of the headline cell drawn uniformly with a seeded "
+                       f"generator: {pairs}; solved as one vectorised batch (RHS + projected Teter-PCG to true "
+                       f"residual {tol:g} + dn), numpy/scipy FP64, {dt:.1f} s",
+                mean_iters=float(np.mean(its)), iters=[int(i) for i in its],
+                gpu_x_true_resid_under_oracle_max=float(res.max()),
+                gpu_x_vs_oracle_x_rel_max=float(dx.max()))
+
+
+def large_entry(args, dev):
+    import numpy as np
+    import torch
+    from paper_2607_14025_amd import Model, STERN_FP64, STERN_MIXED
+    from synth.cells import LARGE
+    from synth.ground_gpu import large_workload
+    log("large cell: ground state on the GPU (Chebyshev-filtered subspace iteration on the library's H)")
+    wl = large_workload(LARGE, n_pert=8)
+    log(f"ground state: {wl['passes']} passes, {wl['wall_s']:.1f} s, gap {wl['gap']:.2e} Ha, "
+        f"max eigen-residual {wl['resid'].max():.2e}")
+    s = wl["system"]
+    s.set_occupied(wl["psi"], torch.from_numpy(wl["eps"]).to(dev))
+    dv_all = torch.from_numpy(wl["dv"]).to(dev)
+    dv = dv_all[:4].contiguous()
+    n_timed, tuned = s.autotune(n_vec=1024)
+    tune_ms = s.autotune_report()
+    log(f"autotuned {n_timed} kernel candidates: {tuned}")
+    log("training the learned preconditioner on fields 4-5")
+    model = Model(seed=0, device=0)
+    train = model.train([s], [dv_all[4:6].contiguous()], epochs=2, batch=16, lr=1e-3, max_solves=1024, tol=1e-10,
+                        seed=1, prec_epochs=4, prec_max_solves=512)
+    log(f"training done: {train}")
+    dn = torch.empty_like(dv)
+    ref = torch.empty_like(dv)
+
+    def call(prec, out, mdl=None, **kw):
+        return s.apply_chi0(dv, tol=args.tol, dn_out=out, precision=prec, model=mdl, prec_only=mdl is not None,
+                            **kw)[1]
+
+    # plain FP64 baseline (the training's FP64 solves have already run every FP64 kernel)
+    v64, t64, i64 = timed_steps(lambda: call(STERN_FP64, ref), args.fp64_steps, 0, "large fp64")
+    plain = summary(i64, t64, v64)
+    vmx, tmx, imx = timed_steps(lambda: call(STERN_MIXED, dn), 1, 0, "large mixed")
+    mixed = summary(imx, tmx, vmx)
+    mixed["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
+    # headline: learned preconditioner + mixed
+    vh, th, ih = timed_steps(lambda: call(STERN_MIXED, dn, model), args.steps, args.warmup, "large learnedK-mixed")
+    head = summary(ih, th, vh)
+    head["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
+    # pairs of the oracle sample: uniform over the step's 4,096 (band, field) pairs, seeded
+    rng = np.random.default_rng(np.random.SeedSequence([LARGE.config_id, 0, 7]))
+    pick = rng.choice(4 * s.n_occ, size=args.cpu_pairs, replace=False)
+    pairs = [(int(k % s.n_occ), int(k // s.n_occ)) for k in pick]
+    # the last apply of the run: the headline step once more with the per-launch profile
+    _, pinfo = s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=STERN_MIXED, model=model, prec_only=True,
+                            profile=True, samples=pairs)
+    torch.cuda.synchronize()
+    log(f"profiled step: {pinfo['wall_s']:.3f} s")
+    kern = pinfo["kernels"]
+    cfg = dict(workload=LARGE.name, L_bohr=LARGE.L, ecut_ry=LARGE.ecut, atoms=LARGE.n_atoms, n_pw=s.n_pw,
+               grid=s.fft_n, n_occ=s.n_occ, n_pert=4, solves_per_step=4 * s.n_occ, tol=args.tol,
+               share="4 of a 32-field Davidson block x all 1,024 bands: one GPU's share on 8 GPUs",
+               ground_state=dict(method="Chebyshev-filtered subspace iteration on the library's FP64 H apply",
+                                 passes=wl["passes"], seconds=wl["wall_s"], gap_Ha=wl["gap"],
+                                 max_eigen_residual=float(wl["resid"].max())),
+               autotuned=tuned, autotune_ms=tune_ms,
+               path="learned diagonal preconditioner (x0 = 0) from the BF16 MFMA conv net on the coarse grid, "
+                    "FP32 FFTs + split-BF16 MFMA GEMMs in FP64 defect correction; Teter FP64 PCG fallback",
+               headline=head, plain_fp64=plain, mixed=mixed,
+               training=dict(fields="4-5 of the same cell (timed: 0-3)", **train),
+               speedup_vs_plain_fp64=head["solves_per_s"] / plain["solves_per_s"],
+               mixed_speedup_vs_plain_fp64=mixed["solves_per_s"] / plain["solves_per_s"])
+    out = dict(value=vh, dt=th, steps=args.steps, cfg=cfg, kern=kern, wl=wl, pairs=pairs,
+               gpu_x=pinfo["samples"], roof=roofline(kern, LARGE.name), fft=fft_stage(kern))
+    model.close()
+    del dv_all, dv, dn, ref
+    return out, s
+
+
+def mid_entry(args, dev):
+    """Secondary: the mid cell (72^3, 128 bands x 64 fields), mixed and plain FP64."""
+    import numpy as np
+    import torch
+    from paper_2607_14025_amd import System, STERN_FP64, STERN_MIXED
+    from synth.cells import MID
+    from synth.inputs import load_workload
+    wl = load_workload(MID)
+    sp = wl["spec"]
+    s = System(sp.L, sp.ecut, wl["pos"], sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width, device=0)
+    s.set_occupied(torch.from_numpy(np.ascontiguousarray(wl["psi"])).to(dev), torch.from_numpy(wl["eps"]).to(dev))
+    s.autotune(n_vec=1024)
+    dv = torch.from_numpy(wl["dv"]).to(dev)
+    dn, ref = torch.empty_like(dv), torch.empty_like(dv)
+    v64, t64, i64 = timed_steps(lambda: s.apply_chi0(dv, tol=args.tol, dn_out=ref, precision=STERN_FP64)[1], 2, 1,
+                                "mid fp64")
+    vmx, tmx, imx = timed_steps(lambda: s.apply_chi0(dv, tol=args.tol, dn_out=dn, precision=STERN_MIXED)[1], 2, 1,
+                                "mid mixed")
+    r = dict(workload=sp.name, n_pw=s.n_pw, grid=s.fft_n, solves_per_step=dv.shape[0] * s.n_occ,
+             plain_fp64=summary(i64, t64, v64), mixed=summary(imx, tmx, vmx))
+    r["mixed"]["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
+    r["mixed_speedup_vs_plain_fp64"] = vmx / v64
+    s.close()
+    return r
+
+
+def batched_entry(args, dev):
+    """Secondary: the 32 uneven cells (L ~ U[10, 18], 8-48 atoms, 20 Ry, 16 fields each) in one
+    stern_apply_chi0_many call, mixed and plain FP64."""
+    import numpy as np
+    import torch
+    from paper_2607_14025_amd import System, STERN_FP64, STERN_MIXED, apply_chi0_many
+    from synth.cells import batched_specs
+    from synth.inputs import load_workload
+    systems, dvs = [], []
+    for sp0 in batched_specs(32):
+        w = load_workload(sp0)
+        sp = w["spec"]
+        s = System(sp.L, sp.ecut, w["pos"], sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width, device=0)
+        s.set_occupied(torch.from_numpy(np.ascontiguousarray(w["psi"])).to(dev), torch.from_numpy(w["eps"]).to(dev))
+        systems.append(s)
+        dvs.append(torch.from_numpy(w["dv"]).to(dev))
+    outs64 = [torch.empty_like(d) for d in dvs]
+    outs = [torch.empty_like(d) for d in dvs]
+    v64, t64, i64 = timed_steps(lambda: apply_chi0_many(systems, dvs, tol=args.tol, dn_outs=outs64,
+                                                        precision=STERN_FP64)[1], 2, 1, "batched fp64")
+    vmx, tmx, imx = timed_steps(lambda: apply_chi0_many(systems, dvs, tol=args.tol, dn_outs=outs,
+                                                        precision=STERN_MIXED)[1], 2, 1, "batched mixed")
+    err = max(rel_err(a, b) for a, b in zip(outs, outs64))
+    r = dict(workload="batched_32_cells_L10-18_8-48at_20Ry_16fields", systems=len(systems),
+             grids=sorted({s.fft_n for s in systems}), solves_per_step=i64[0]["n_solves"],
+             plain_fp64=summary(i64, t64, v64), mixed=summary(imx, tmx, vmx), mixed_speedup_vs_plain_fp64=vmx / v64)
+    r["mixed"]["dn_rel_err_vs_fp64"] = err
+    for s in systems:
+        s.close()
+    return r
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--cpu-bands", type=int, default=48)
+    ap.add_argument("--cpu-pairs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--path", choices=["learned-mixed", "mixed", "fp64"], default="learned-mixed")
-    ap.add_argument("--train-solves", type=int, default=8192)
+    ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -83,12 +323,7 @@ def main():
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-    from paper_2607_14025_amd import Model, System, STERN_FP64, STERN_MIXED, STERN_INNER_PROJECTED
-    from synth.cells import MID
-    from synth.inputs import load_workload
-
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.copy_calibration:
@@ -96,163 +331,30 @@ def main():
         b = torch.empty_like(a)
         torch.mul(a, 1.0, out=b)  # one elementwise kernel: reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
-        print("bench: copied 1 GiB device to device (counter reference)", file=sys.stderr, flush=True)
+        log("copied 1 GiB device to device (counter reference)")
         del a, b
-    print("bench: loading mid cell inputs", file=sys.stderr, flush=True)
-    wl = load_workload(MID)
-    spec = wl["spec"]
-
-    def make_system(w):
-        sp = w["spec"]
-        sy = System(sp.L, sp.ecut, w["pos"], sp.vloc_amp, sp.vloc_sigma, sp.kb_D, sp.kb_width, device=0)
-        sy.set_occupied(torch.from_numpy(np.ascontiguousarray(w["psi"])).to(dev), torch.from_numpy(w["eps"]).to(dev))
-        return sy
-
-    s = make_system(wl)
-    dv = torch.from_numpy(wl["dv"]).to(dev)
-    n_timed, tuned = s.autotune(n_vec=1024)  # setup, like init and set_occupied: not timed
-    tune_ms = s.autotune_report()
-    print(f"bench: autotuned {n_timed} kernel candidates: {tuned}; ms per candidate on 1,024 rows: {tune_ms}",
-          file=sys.stderr, flush=True)
-    dn = torch.empty_like(dv)
-    n_pert = dv.shape[0]
-    n_solves = n_pert * s.n_occ
-
-    model = None
-    train = None
-    if args.path == "learned-mixed":
-        print("bench: training the learned guess and preconditioner on two other mid cells", file=sys.stderr,
-              flush=True)
-        tr_sys, tr_dv = [], []
-        for sid in (1, 2):
-            w = load_workload(MID.with_system(sid))
-            tr_sys.append(make_system(w))
-            tr_dv.append(torch.from_numpy(w["dv"]).to(dev))
-        model = Model(seed=0, device=0)
-        train = model.train(tr_sys, tr_dv, epochs=4, batch=16, lr=1e-3, max_solves=args.train_solves, tol=1e-10,
-                            seed=1, prec_epochs=4)
-        for t in tr_sys:
-            t.close()
-        del tr_dv
-        torch.cuda.synchronize()
-        print(f"bench: training done: {train}", file=sys.stderr, flush=True)
-
-    def run(precision, steps, warmup, label, mdl=None, prec_only=False, inner_op=STERN_INNER_PROJECTED):
-        kw = dict(precision=precision, model=mdl, prec_only=prec_only, inner_op=inner_op)
-        for w in range(warmup):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, **kw)
-            print(f"bench: {label} warmup {w}: {info['n_converged']}/{info['n_solves']} converged in "
-                  f"{info['wall_s']:.2f} s", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        conv = 0
-        kern = {}
-        iters = []
-        fallback = 0
-        t0 = time.perf_counter()
-        for k in range(steps):
-            _, info = s.apply_chi0(dv, tol=args.tol, dn_out=dn, profile=True, **kw)
-            conv += info["n_converged"]
-            fallback += info["n_fallback"]
-            iters.append(info["total_iters"] / max(1, info["n_solves"]))
-            for name, v in info["kernels"].items():
-                a = kern.setdefault(name, dict(launches=0, ms=0.0, bytes=0.0, flops=0.0))
-                for f in a:
-                    a[f] += v[f]
-            print(f"bench: {label} step {k}: {info['n_converged']}/{info['n_solves']} converged, "
-                  f"{info['wall_s']:.3f} s, max true resid {info['max_true_resid']:.2e}, "
-                  f"fallback {info['n_fallback']}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        r = dict(value=conv / dt, dt=dt, kern=kern, iters=float(np.mean(iters)), fallback=fallback)
-        if label != "fp64":  # dn against the plain FP64 path at the same tolerance
-            s.apply_chi0(dv, tol=args.tol, dn_out=dn, **kw)
-            torch.cuda.synchronize()
-            r["dn_rel_err_vs_fp64"] = ((dn - ref).reshape(n_pert, -1).norm(dim=1)
-                                       / ref.reshape(n_pert, -1).norm(dim=1)).max().item()
-        return r
-
-    ref = torch.empty_like(dv)
-    s.apply_chi0(dv, tol=args.tol, dn_out=ref, precision=STERN_FP64)
-    torch.cuda.synchronize()
-    plain = run(STERN_FP64, args.steps, args.warmup, "fp64")
-    head = plain
-    mixed = learned = learned_fp64 = learned_k = None
-    if args.path in ("mixed", "learned-mixed"):
-        mixed = run(STERN_MIXED, args.steps, args.warmup, "mixed")
-        head = mixed
-    if args.path == "learned-mixed":
-        learned_fp64 = run(STERN_FP64, args.steps, args.warmup, "learned-fp64", model)
-        learned = run(STERN_MIXED, args.steps, args.warmup, "learned-mixed", model)
-        learned_k = run(STERN_MIXED, args.steps, args.warmup, "learnedK-mixed", model, prec_only=True)
-        head = learned_k if learned_k["value"] > learned["value"] else learned
-    value = head["value"]
-    dt = head["dt"]
-    kern = head["kern"]
-
-    dom = max(kern, key=lambda n: kern[n]["ms"])
-    d = kern[dom]
-    per_launch_s = d["ms"] / d["launches"] / 1e3
-    traffic = measured_traffic(dom, d["bytes"] / d["launches"])
-    if dom in ALU_KERNELS or dom in MFMA_KERNELS:
-        peak = ALU_KERNELS.get(dom) or MFMA_KERNELS[dom]
-        achieved = d["flops"] / d["launches"] / per_launch_s / 1e12
-        roof = dict(bound="alu" if dom in ALU_KERNELS else "mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
-                    frac=achieved / peak, traffic=traffic, kernel=dom,
-                    hbm_GBps=d["bytes"] / d["launches"] / per_launch_s / 1e9)
-    else:
-        achieved = d["bytes"] / d["launches"] / per_launch_s / 1e9
-        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=traffic, kernel=dom)
-    roof["launches"] = d["launches"]
-    roof["ms_per_launch"] = d["ms"] / d["launches"]
-    total_ms = sum(v["ms"] for v in kern.values())
-    breakdown = {n: dict(share=round(v["ms"] / total_ms, 4), launches=v["launches"],
-                         bytes_per_launch=round(v["bytes"] / v["launches"]), ms_per_launch=round(v["ms"] / v["launches"], 4),
-                         GBps=round(v["bytes"] / (v["ms"] / 1e3) / 1e9, 1) if v["ms"] > 0 else None,
-                         TFLOPs=round(v["flops"] / (v["ms"] / 1e3) / 1e12, 2) if v["flops"] > 0 else None)
-                 for n, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms"])}
-
+    secondary = {}
+    if not args.no_secondary:  # before the headline, so that its profiled step is the run's last apply
+        log("secondary: batched cells")
+        secondary["batched"] = batched_entry(args, dev)
+        log("secondary: mid cell")
+        secondary["mid"] = mid_entry(args, dev)
+        torch.cuda.empty_cache()
+    r, s = large_entry(args, dev)
+    cfg = r["cfg"]
+    if secondary:
+        cfg["secondary"] = secondary
+    cfg["fft_stage"] = r["fft"]
     cpu = None
     if not args.no_cpu_baseline:
-        print("bench: timing the CPU oracle sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(wl, args.cpu_bands, args.tol)
-
-    cfg = dict(workload=spec.name, L_bohr=spec.L, ecut_ry=spec.ecut, atoms=spec.n_atoms, n_pw=s.n_pw,
-               grid=s.fft_n, n_occ=s.n_occ, n_pert=n_pert, solves_per_step=n_solves, tol=args.tol, autotuned=tuned,
-               autotune_ms=tune_ms,
-               plain_fp64=dict(solves_per_s=plain["value"], mean_cg_iters=plain["iters"]))
-    if mixed is not None:
-        cfg.update(path="FP32 FFT + split-BF16 MFMA GEMMs in FP64 defect correction (fallback: FP64 PCG)",
-                   mixed=dict(solves_per_s=mixed["value"], mean_inner_iters=mixed["iters"],
-                              fallback_solves=mixed["fallback"], dn_rel_err_vs_fp64=mixed["dn_rel_err_vs_fp64"]),
-                   speedup_vs_plain_fp64=mixed["value"] / plain["value"])
-        dtype = "f32+bf16/f64"
-    if learned is not None:
-        which = ("learned diagonal preconditioner (x0 = 0)" if head is learned_k else
-                 "learned guess + learned diagonal preconditioner")
-        cfg.update(path=which + " from the BF16 MFMA conv net on the coarse grid, FP32 FFT + split-BF16 MFMA GEMMs "
-                            "in FP64 defect correction; Teter FP64 PCG fallback",
-                   learned_fp64=dict(solves_per_s=learned_fp64["value"], mean_cg_iters=learned_fp64["iters"],
-                                     fallback_solves=learned_fp64["fallback"],
-                                     dn_rel_err_vs_fp64=learned_fp64["dn_rel_err_vs_fp64"]),
-                   learned_mixed=dict(solves_per_s=learned["value"], mean_inner_iters=learned["iters"],
-                                      fallback_solves=learned["fallback"],
-                                      dn_rel_err_vs_fp64=learned["dn_rel_err_vs_fp64"]),
-                   learned_k_mixed=dict(solves_per_s=learned_k["value"], mean_inner_iters=learned_k["iters"],
-                                        fallback_solves=learned_k["fallback"],
-                                        dn_rel_err_vs_fp64=learned_k["dn_rel_err_vs_fp64"]),
-                   training=dict(cells="two other seeded mid cells (same L, Ecut, atom count)", **train),
-                   speedup_vs_plain_fp64=head["value"] / plain["value"])
-    if mixed is None:
-        cfg.update(path="plain FP64 projected Teter-PCG")
-        dtype = "f64"
-    line = dict(metric="converged Sternheimer solves/s at resid≤1e-8 (learned+mixed vs plain FP64)", value=value, unit="solves/s", n_gpus=1,
-                steps=args.steps, warmup=args.warmup, ms_per_step=dt / args.steps * 1e3, higher_is_better=True,
-                scaling="weak", vs_baseline=None, dtype=dtype, data="synthetic", config=cfg,
-                roofline=roof, cpu_baseline=cpu, kernels=breakdown)
+        log("timing the CPU oracle sample")
+        cpu = cpu_baseline(r["wl"], r["pairs"], args.tol, r["gpu_x"])
+        cpu["gpu_mean_iters_headline"] = cfg["headline"]["mean_iters"]
+    line = dict(metric=METRIC, value=r["value"], unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+                ms_per_step=r["dt"] / args.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f32+bf16/f64", data="synthetic", config=cfg, roofline=r["roof"], cpu_baseline=cpu,
+                kernels=breakdown(r["kern"]), kernels_steps=1)
     s.close()
-    if model is not None:
-        model.close()
     print(json.dumps(line), flush=True)
 
 

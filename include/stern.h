@@ -242,6 +242,52 @@ int stern_apply_chi0(stern_system* sys, int n_pert, const double* dv_r, double* 
 int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert, const double* const* dv_r,
                           double* const* dn_r, const stern_opts* opts, stern_stats* stats);
 
+/* ---- PDEP: the eigenpairs of the symmetrised response (Sec. II.A, eq. pdep) ----
+ * chi-bar0 = v^{1/2} chi0 v^{1/2}, v^{1/2}(G) = sqrt(4 pi) / |G|, acts on real
+ * potentials band-limited to |G|^2 < ecut_pot (G != 0: the long-range G = 0 part
+ * is the separate term of eq. pdep). A block Davidson iteration finds its n_eig
+ * lowest (most negative) eigenvalues lambda_a and eigenpotentials phi_a; every
+ * product chi-bar0 phi is one stern_apply_chi0 over a block of trial potentials
+ * (so with the chi0 options' precision, guess and tolerance). Converged pairs stay
+ * in the basis but add no new directions. The projected eigenproblem is solved on
+ * the host. Grids whose full FP64 yz plane does not fit in LDS (108^3, 128^3) are
+ * refused with STERN_ERR_UNSUPPORTED. */
+typedef struct {
+  int n_eig;            /* eigenpairs wanted (> 0) */
+  int block;            /* trial potentials per chi0 apply (0 = n_eig) */
+  int max_basis;        /* basis size before a restart from the Ritz vectors (0 = 4 n_eig) */
+  int max_iter;         /* Davidson iterations (0 = 50) */
+  double tol;           /* converged when ||chi-bar0 phi - lambda phi|| <= tol |lambda| (0 = 1e-6) */
+  double ecut_pot_ry;   /* sphere of the potentials, |G|^2 < ecut_pot (0 = ecut / 4) */
+  unsigned long long seed;  /* seeded random start */
+  const stern_opts* chi0;   /* options of every chi0 apply (mem_kind, band range, samples and
+                               profile are ignored) */
+} stern_pdep_opts;
+
+typedef struct {
+  int iterations;       /* Davidson iterations */
+  int n_converged;      /* of the n_eig wanted pairs */
+  int chi0_calls;       /* stern_apply_chi0 calls */
+  int basis_dim;        /* real dimension of the potential space (2 x half-space G count) */
+  long long total_solves;   /* Sternheimer solves over all chi0 calls */
+  long long total_cg_iters;
+  double max_rel_resid; /* max_a ||chi-bar0 phi_a - lambda_a phi_a|| / |lambda_a| */
+  double wall_s;
+} stern_pdep_stats;
+
+/* The potential sphere of stern_pdep_davidson: n_g nonzero G with |G|^2 < ecut_pot
+ * (0 = ecut / 4), both G and -G, in canonical order; miller (optional) receives
+ * their [n_g][3] Miller triples. Host only. */
+int stern_pdep_basis(const stern_system* sys, double ecut_pot_ry, int* n_g, int32_t* miller);
+/* eig [n_eig] receives the eigenvalues in ascending order; vec (optional, host)
+ * [n_eig][n_g] complex coefficients phi_a(G) over stern_pdep_basis's list
+ * (phi(-G) = conj phi(G), sum_G |phi(G)|^2 = 1). Needs set_occupied. Returns
+ * STERN_OK, STERN_WARN_NOT_CONVERGED (max_iter reached or the basis exhausted),
+ * STERN_ERR_STATE when a chi0 apply leaves a solve above its tolerance, or an
+ * error. Synchronous. */
+int stern_pdep_davidson(stern_system* sys, const stern_pdep_opts* opts, double* eig, double* vec,
+                        stern_pdep_stats* stats);
+
 /* ---- learned initial guess and diagonal preconditioner ----
  * A small 3-D convolutional net (3 periodic 3x3x3 layers, 16 channels, ReLU,
  * BF16 weights, FP32 accumulation) on the coarse (N/2)^3 grid, which holds the

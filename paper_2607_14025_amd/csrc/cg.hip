@@ -323,6 +323,16 @@ __global__ void k_set_flag(int* __restrict__ flag, const int* __restrict__ list,
   if (i < n) flag[list[i]] = value;
 }
 
+// complex field from a real one (zero imaginary part), and the real part of a complex one times scale
+__global__ void k_real_to_z(const double* __restrict__ in, Z64* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = zmk(in[i], 0.0);
+}
+__global__ void k_z_real(const Z64* __restrict__ in, double scale, double* __restrict__ out, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    out[i] = scale * in[i].re;
+}
+
 __global__ void k_ri(const double* __restrict__ in, Z64* __restrict__ out, size_t n) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
     out[i] = zmk(in[2 * i], in[2 * i + 1]);
@@ -655,6 +665,16 @@ void launch_fill_zero(Z64* p, size_t n, hipStream_t st) {
 }
 void launch_set_flag(int* flag, const int* list, int n, int value, hipStream_t st) {
   if (n > 0) k_set_flag<<<(n + 255) / 256, 256, 0, st>>>(flag, list, n, value);
+}
+void launch_real_to_z(const double* in, Z64* out, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  const size_t b = (n + 255) / 256;
+  k_real_to_z<<<(unsigned)(b > 65536 ? 65536 : b), 256, 0, st>>>(in, out, n);
+}
+void launch_z_real(const Z64* in, double scale, double* out, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  const size_t b = (n + 255) / 256;
+  k_z_real<<<(unsigned)(b > 65536 ? 65536 : b), 256, 0, st>>>(in, scale, out, n);
 }
 void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st) {
   if (n == 0) return;

@@ -1328,6 +1328,8 @@ void launch_plane_full_inv(const FftGeom& g, const Z64* pen, int nvec, Z64* out,
                    }));
 }
 
+bool plane_full_fwd_fits(int N, size_t lds) { return plane_lds_bytes(N, sizeof(Z64)) <= lds; }
+
 void launch_plane_full_fwd(const FftGeom& g, const Z64* in, int nvec, Z64* pen, hipStream_t st) {
   if (nvec <= 0) return;
   const size_t lds = plane_lds_bytes(g.N, sizeof(Z64));

@@ -10,6 +10,8 @@
 //   Re conj(a) x = (a_re, a_im) . (x_re, x_im),  Im conj(a) x = (a_re, a_im) . (x_im, -x_re)
 //   Re a c       = (a_re, a_im) . (c_re, -c_im), Im a c       = (a_re, a_im) . (c_im, c_re)
 // so no lane ever needs another lane's data.
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace stern {
@@ -73,18 +75,26 @@ constexpr int kThreads8 = 512;
 // the next step are loaded while this step's MFMAs run. Re C = A . X and
 // Im C = A' . X along the interleaved reduction index, with A' = (-a_im, a_re)
 // formed from A in registers.
+// Workgroups are numbered so that the row blocks of one (column block, split)
+// pair get consecutive slots of one XCD (the hardware hands workgroup L to XCD
+// L mod 8): they run together and share that pair's slice of X through the
+// XCD's L2 instead of each fetching it from HBM.
 __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __restrict__ Ahi,
                                                             const __bf16* __restrict__ Alo, int M_pad,
                                                             const Z32* __restrict__ X, int ldx,
                                                             const int* __restrict__ xidx, int ncols, int K,
-                                                            int kchunk, Z32* __restrict__ cpart) {
+                                                            int kchunk, Z32* __restrict__ cpart, int nmb, int nnb,
+                                                            int nsplit) {
   __shared__ bf16x8 xs[2][2][2][kWN * 4];  // [buffer][hi, lo][sub-step][column * 4 + group of 4 complex]
+  const int L = blockIdx.x, slot = L >> 3;
+  const int mb = slot % nmb, rest = (slot / nmb) * 8 + (L & 7);
+  if (rest >= nnb * nsplit) return;  // padding of the last group of XCD slots; no barrier passed yet
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int wm = wave & 3, wn = wave >> 2;
-  const int n0 = blockIdx.x * kWN;
-  const int split = blockIdx.y;
-  const int m0 = blockIdx.z * kWM + wm * 32;
+  const int n0 = (rest % nnb) * kWN;
+  const int split = rest / nnb;
+  const int m0 = mb * kWM + wm * 32;
   const bool live = m0 < M_pad;
   const int kb = split * kchunk;
   const int ke = min(K, kb + kchunk);
@@ -243,18 +253,24 @@ __device__ __forceinline__ bf16x8 swap_b(bf16x8 c) {
 // (128 x 128, fewer registers, 2 workgroups per CU); KB = 4, WN = 1 (256 x 64, 2 workgroups
 // per CU). With two workgroups on a CU one's Y update overlaps the other's products.
 // Re(a c) = a . (c_re, -c_im), Im(a c) = a . (c_im, c_re).
+// Workgroups are numbered so that the column blocks of one row block k get
+// consecutive slots of one XCD (workgroup L runs on XCD L mod 8) and share
+// that block's rows of A through the XCD's L2.
 template <int KB, bool PUPD, int WN>
 __global__ __launch_bounds__(256 * WN, KB == 4 ? 2 : 4) void k_expand_bf16s(const __bf16* __restrict__ ATh,
                                                             const __bf16* __restrict__ ATl, int M_pad, int K,
                                                             const __bf16* __restrict__ Cs, Z32* __restrict__ Y,
                                                             int ldy, const int* __restrict__ yidx, int ncols,
-                                                            Z32* __restrict__ P, const double* __restrict__ beta) {
+                                                            Z32* __restrict__ P, const double* __restrict__ beta,
+                                                            int nnb) {
+  const int L = blockIdx.x, slot = L >> 3;
+  const int nbk = slot % nnb, kblk = (slot / nnb) * 8 + (L & 7);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int wk = wave & 3, wn = wave >> 2;
-  const int k0 = blockIdx.x * (64 * KB) + wk * 16 * KB;
+  const int k0 = kblk * (64 * KB) + wk * 16 * KB;
   if (k0 >= K) return;  // K is a multiple of 64; no barrier below
-  const int n0 = blockIdx.y * (64 * WN) + wn * 64;
+  const int n0 = nbk * (64 * WN) + wn * 64;
   const size_t plane = (size_t)ncols * M_pad * 2;
   int nn[4];
   bool nv[4];
@@ -442,8 +458,10 @@ void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z
   if (ncols <= 0) return;
   int kchunk = (K + nsplit - 1) / nsplit;
   kchunk = (kchunk + 31) / 32 * 32;  // whole K steps of 32 complex; K is a multiple of 64
-  dim3 grid((ncols + kWN - 1) / kWN, nsplit, (M_pad + kWM - 1) / kWM);
-  k_reduce_bf16w<<<grid, kThreads8, 0, st>>>(Ahi, Alo, M_pad, X, ldx, xidx, ncols, K, kchunk, cpart);
+  const int nmb = (M_pad + kWM - 1) / kWM, nnb = (ncols + kWN - 1) / kWN;
+  const int groups = (nnb * nsplit + 7) / 8;  // groups of 8 (column block, split) pairs, one per XCD
+  k_reduce_bf16w<<<groups * 8 * nmb, kThreads8, 0, st>>>(Ahi, Alo, M_pad, X, ldx, xidx, ncols, K, kchunk, cpart,
+                                                          nmb, nnb, nsplit);
 }
 
 void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
@@ -456,20 +474,36 @@ void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, floa
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
                         const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P, const double* beta) {
   if (ncols <= 0) return;
-  const dim3 g2((K + 127) / 128, (ncols + kEN - 1) / kEN), g4((K + kET - 1) / kET, (ncols + kEN - 1) / kEN),
-      g41((K + kET - 1) / kET, (ncols + 63) / 64);
-  if (variant == 1 && P)
-    k_expand_bf16s<2, true, 2><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
-  else if (variant == 1)
-    k_expand_bf16s<2, false, 2><<<g2, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
-  else if (variant == 2 && P)
-    k_expand_bf16s<4, true, 1><<<g41, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
-  else if (variant == 2)
-    k_expand_bf16s<4, false, 1><<<g41, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
-  else if (P)
-    k_expand_bf16s<4, true, 2><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
-  else
-    k_expand_bf16s<4, false, 2><<<g4, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta);
+  // linear grid: ceil(row blocks / 8) groups x 8 XCD slots x column blocks
+  auto grid = [&](int rows, int cols) {
+    const int nkb = (K + rows - 1) / rows, nnb = (ncols + cols - 1) / cols;
+    return std::make_pair((unsigned)(((nkb + 7) / 8) * 8 * nnb), nnb);
+  };
+  if (variant == 1) {
+    const auto g = grid(128, kEN);
+    if (P)
+      k_expand_bf16s<2, true, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
+                                                                g.second);
+    else
+      k_expand_bf16s<2, false, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P,
+                                                                 beta, g.second);
+  } else if (variant == 2) {
+    const auto g = grid(kET, 64);
+    if (P)
+      k_expand_bf16s<4, true, 1><<<g.first, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
+                                                          g.second);
+    else
+      k_expand_bf16s<4, false, 1><<<g.first, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
+                                                           g.second);
+  } else {
+    const auto g = grid(kET, kEN);
+    if (P)
+      k_expand_bf16s<4, true, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
+                                                                g.second);
+    else
+      k_expand_bf16s<4, false, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P,
+                                                                 beta, g.second);
+  }
 }
 
 }  // namespace stern

@@ -111,6 +111,11 @@ void launch_permute(const Z64* in, int ld_in, Z64* out, int ld_out, const int* p
 void launch_fill_zero(Z64* p, size_t n, hipStream_t st);
 void launch_set_flag(int* flag, const int* list, int n, int value, hipStream_t st);
 void launch_ri_to_complex(const double* in, Z64* out, size_t n, hipStream_t st);
+// out = in + 0 i; out = scale Re(in) (grid fields of the PDEP potentials)
+void launch_real_to_z(const double* in, Z64* out, size_t n, hipStream_t st);
+void launch_z_real(const Z64* in, double scale, double* out, size_t n, hipStream_t st);
+// whether the full-plane FP64 forward transform of an N^3 grid fits in `lds` bytes of LDS
+bool plane_full_fwd_fits(int N, size_t lds);
 
 // ---- learned initial guess (coarse-grid 3-D conv net, learn.hip) ----
 constexpr int kNetChannels = 16;

@@ -1662,6 +1662,347 @@ int stern_apply_chi0_many(int n_sys, stern_system* const* sys, const int* n_pert
   return out;
 }
 
+// ---------------------------------------------------------- PDEP Davidson ----
+// Sec. II.A, eq. pdep: the lowest eigenpairs of chi-bar0 = v^{1/2} chi0 v^{1/2},
+// v^{1/2}(G) = sqrt(4 pi) / |G|, found iteratively, every chi-bar0 product being
+// one stern_apply_chi0 over a block of trial potentials.
+//
+// Potentials are real and band-limited to |G|^2 < ecut_pot, G != 0. They are
+// carried as real coordinates u in R^{2m}, m = number of half-space
+// representatives G_j: u[2j] = sqrt(2) Re c(G_j), u[2j + 1] = sqrt(2) Im c(G_j),
+// c(-G) = conj c(G), which makes sum_G |c(G)|^2 = |u|^2, so chi-bar0 is a real
+// symmetric matrix in these coordinates.
+
+namespace {
+
+// Eigenvalues (ascending) and eigenvectors (columns of V, row-major n x n) of a
+// real symmetric matrix by cyclic Jacobi rotations.
+static void jacobi_eigh(std::vector<double> A, int n, std::vector<double>& w, std::vector<double>& V) {
+  V.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a(i, j) * a(i, j);
+        if (i != j) off += a(i, j) * a(i, j);
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a(p, q);
+        if (std::fabs(apq) < 1e-300) continue;
+        // rotation angle that zeroes a(p, q): tan(2 t) = 2 apq / (aqq - app)
+        const double theta = 0.5 * (a(q, q) - a(p, p)) / apq;
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = a(k, p), akq = a(k, q);
+          a(k, p) = c * akp - sn * akq;
+          a(k, q) = sn * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = c * apk - sn * aqk;
+          a(q, k) = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = c * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + c * vkq;
+        }
+      }
+  }
+  std::vector<int> ord(n);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::sort(ord.begin(), ord.end(), [&](int i, int j) { return a(i, i) < a(j, j); });
+  w.resize(n);
+  std::vector<double> Vs((size_t)n * n);
+  for (int c = 0; c < n; ++c) {
+    w[c] = a(ord[c], ord[c]);
+    for (int k = 0; k < n; ++k) Vs[(size_t)k * n + c] = V[(size_t)k * n + ord[c]];
+  }
+  V.swap(Vs);
+}
+
+// Band-limited potentials of a system: canonical indices of each half-space
+// representative G_j and of -G_j in the wave-function sphere, and v^{1/2}(G_j);
+// `all` lists every G of the potential sphere (both signs), canonical order.
+struct PotBasis {
+  std::vector<int> rep, neg, all;
+  std::vector<double> vh;
+};
+
+static int pot_basis(const stern_system* S, double ecut_pot, PotBasis& pb) {
+  const HostBasis& hb = S->hb;
+  if (!(ecut_pot > 0) || ecut_pot > hb.ecut)
+    return fail(STERN_ERR_INVALID_ARG, "ecut_pot must be in (0, ecut] (got %g)", ecut_pot);
+  const double b2 = hb.b * hb.b;
+  for (int k = 0; k < hb.npw; ++k) {
+    const int x = hb.miller[3 * k], y = hb.miller[3 * k + 1], z = hb.miller[3 * k + 2];
+    const double g2 = b2 * (double)(x * x + y * y + z * z);
+    if (g2 == 0.0 || !(g2 < ecut_pot)) continue;
+    pb.all.push_back(k);
+    if (!(x > 0 || (x == 0 && y > 0) || (x == 0 && y == 0 && z > 0))) continue;
+    int kn = -1;  // -G sits in the same |n|^2 shell of the canonical order
+    for (int q = 0; q < hb.npw && kn < 0; ++q)
+      if (hb.miller[3 * q] == -x && hb.miller[3 * q + 1] == -y && hb.miller[3 * q + 2] == -z) kn = q;
+    if (kn < 0) return fail(STERN_ERR_INVALID_ARG, "-G of a potential G is missing from the sphere");
+    pb.rep.push_back(k);
+    pb.neg.push_back(kn);
+    pb.vh.push_back(std::sqrt(4.0 * M_PI / g2));
+  }
+  if (pb.rep.empty()) return fail(STERN_ERR_INVALID_ARG, "no nonzero G with |G|^2 < %g", ecut_pot);
+  return 0;
+}
+
+struct PdepWork {
+  DBuf rows, pen, zf, dv, dn;
+  void release() {
+    for (DBuf* d : {&rows, &pen, &zf, &dv, &dn}) d->release();
+  }
+};
+
+// W = chi-bar0 U for nb coordinate vectors U [nb][2m] (host), through one chi0 apply.
+static int pdep_apply(stern_system* S, const PotBasis& pb, const stern_opts& o, const double* U, int nb, double* W,
+               PdepWork& wk, long long& solves, long long& iters) {
+  const HostBasis& hb = S->hb;
+  const int K = hb.npw_pad, N = hb.N, m = (int)pb.rep.size();
+  const size_t n3 = (size_t)N * N * N;
+  hipStream_t st = S->stream;
+  CHECKED(wk.rows.ensure((size_t)nb * K * sizeof(Z64)));
+  CHECKED(wk.pen.ensure((size_t)nb * N * hb.ncol_pad * sizeof(Z64)));
+  CHECKED(wk.zf.ensure((size_t)nb * n3 * sizeof(Z64)));
+  CHECKED(wk.dv.ensure((size_t)nb * n3 * sizeof(double)));
+  CHECKED(wk.dn.ensure((size_t)nb * n3 * sizeof(double)));
+  // coefficients of v^{1/2} phi on the wave-function sphere (column order), zero elsewhere
+  std::vector<Z64> h((size_t)nb * K, zmk(0.0, 0.0));
+  const double r2 = 1.0 / std::sqrt(2.0);
+  for (int f = 0; f < nb; ++f)
+    for (int j = 0; j < m; ++j) {
+      const double re = pb.vh[j] * r2 * U[(size_t)f * 2 * m + 2 * j];
+      const double im = pb.vh[j] * r2 * U[(size_t)f * 2 * m + 2 * j + 1];
+      h[(size_t)f * K + hb.perm[pb.rep[j]]] = zmk(re, im);
+      h[(size_t)f * K + hb.perm[pb.neg[j]]] = zmk(re, -im);
+    }
+  HIPOK(hipMemcpyAsync(wk.rows.p, h.data(), h.size() * sizeof(Z64), hipMemcpyHostToDevice, st));
+  const FftGeom g = S->geom();
+  launch_xinv(g, wk.rows.as<Z64>(), nullptr, nb, wk.pen.as<Z64>(), st);
+  launch_plane_full_inv(g, wk.pen.as<Z64>(), nb, wk.zf.as<Z64>(), st);
+  launch_z_real(wk.zf.as<Z64>(), 1.0, wk.dv.as<double>(), (size_t)nb * n3, st);
+  CHECKED(launch_check());
+  HIPOK(hipStreamSynchronize(st));  // h is released on return
+  stern_opts oo = o;
+  oo.mem_kind = STERN_MEM_DEVICE;
+  oo.n_sample = 0;
+  oo.sample_pairs = nullptr;
+  oo.sample_x = nullptr;
+  oo.profile = 0;
+  oo.band_begin = 0;
+  oo.band_end = 0;
+  stern_stats cst;
+  std::memset(&cst, 0, sizeof cst);
+  const int rc = stern_apply_chi0(S, nb, wk.dv.as<double>(), wk.dn.as<double>(), &oo, &cst);
+  if (rc < 0) return rc;
+  if (rc == STERN_WARN_NOT_CONVERGED)
+    return fail(STERN_ERR_STATE, "a chi0 apply of the Davidson iteration left %d of %d solves above tol",
+                cst.n_solves - cst.n_converged, cst.n_solves);
+  solves += cst.n_solves;
+  iters += cst.total_iters;
+  // dn(G) on the sphere: forward planes of the real field, then the x pass scaled by 1/N^3
+  launch_real_to_z(wk.dn.as<double>(), wk.zf.as<Z64>(), (size_t)nb * n3, st);
+  launch_plane_full_fwd(g, wk.zf.as<Z64>(), nb, wk.pen.as<Z64>(), st);
+  launch_xfwd<double>(g, wk.pen.as<Z64>(), nullptr, nb, wk.rows.as<Z64>(), 2, nullptr, nullptr, 1.0 / (double)n3, st);
+  CHECKED(launch_check());
+  HIPOK(hipMemcpyAsync(h.data(), wk.rows.p, h.size() * sizeof(Z64), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  const double s2 = std::sqrt(2.0);
+  for (int f = 0; f < nb; ++f)
+    for (int j = 0; j < m; ++j) {
+      const Z64 v = h[(size_t)f * K + hb.perm[pb.rep[j]]];
+      W[(size_t)f * 2 * m + 2 * j] = s2 * pb.vh[j] * v.re;
+      W[(size_t)f * 2 * m + 2 * j + 1] = s2 * pb.vh[j] * v.im;
+    }
+  return 0;
+}
+
+static double dotv(const double* a, const double* b, int n) {
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += a[i] * b[i];
+  return s;
+}
+
+}  // namespace
+
+int stern_pdep_basis(const stern_system* S, double ecut_pot_ry, int* n_g, int32_t* miller) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  PotBasis pb;
+  CHECKED(pot_basis(S, ecut_pot_ry > 0 ? ecut_pot_ry : S->hb.ecut / 4.0, pb));
+  if (n_g) *n_g = (int)pb.all.size();
+  if (miller)
+    for (size_t k = 0; k < pb.all.size(); ++k)
+      for (int c = 0; c < 3; ++c) miller[3 * k + c] = S->hb.miller[3 * (size_t)pb.all[k] + c];
+  return STERN_OK;
+}
+
+int stern_pdep_davidson(stern_system* S, const stern_pdep_opts* o, double* eig, double* vec, stern_pdep_stats* stats) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!S || !o || !eig || !o->chi0) return fail(STERN_ERR_INVALID_ARG, "need a system, options, chi0 options and eig");
+  if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
+  const int ne = o->n_eig;
+  if (ne <= 0) return fail(STERN_ERR_INVALID_ARG, "n_eig must be > 0");
+  Scope sc(S->device, &S->alloc);
+  size_t lds_max = S->lds_max;
+  if (!plane_full_fwd_fits(S->hb.N, lds_max))
+    return fail(STERN_ERR_UNSUPPORTED, "the potential transforms of grid %d do not fit in LDS", S->hb.N);
+  PotBasis pb;
+  CHECKED(pot_basis(S, o->ecut_pot_ry > 0 ? o->ecut_pot_ry : S->hb.ecut / 4.0, pb));
+  const int m = (int)pb.rep.size(), dim = 2 * m;
+  if (ne > dim) return fail(STERN_ERR_INVALID_ARG, "n_eig %d exceeds the %d potentials of the basis", ne, dim);
+  const int nb = std::min(o->block > 0 ? o->block : ne, dim);
+  const int max_basis = std::min(dim, std::max(o->max_basis > 0 ? o->max_basis : 4 * ne, ne + nb));
+  const int max_iter = o->max_iter > 0 ? o->max_iter : 50;
+  const double tol = o->tol > 0 ? o->tol : 1e-6;
+  PdepWork wk;
+  long long solves = 0, cg_iters = 0;
+  int calls = 0;
+  std::vector<std::vector<double>> V, W;  // orthonormal basis and chi-bar0 of it
+  // orthonormalise x against V (twice) and normalise; false when nothing is left
+  auto orth = [&](std::vector<double>& x) -> bool {
+    const double n0 = std::sqrt(dotv(x.data(), x.data(), dim));
+    if (!(n0 > 0)) return false;
+    for (int pass = 0; pass < 2; ++pass)
+      for (const auto& v : V) {
+        const double c = dotv(v.data(), x.data(), dim);
+        for (int i = 0; i < dim; ++i) x[i] -= c * v[i];
+      }
+    const double n1 = std::sqrt(dotv(x.data(), x.data(), dim));
+    if (!(n1 > 1e-10 * n0)) return false;
+    for (double& e : x) e /= n1;
+    return true;
+  };
+  auto expand = [&](std::vector<std::vector<double>>& block) -> int {
+    std::vector<std::vector<double>> keep;
+    for (auto& x : block)
+      if (orth(x)) {
+        V.push_back(x);
+        keep.push_back(x);
+      }
+    const int n = (int)keep.size();
+    if (n == 0) return 0;
+    std::vector<double> U((size_t)n * dim), R((size_t)n * dim);
+    for (int f = 0; f < n; ++f) std::copy(keep[f].begin(), keep[f].end(), U.begin() + (size_t)f * dim);
+    const int rc = pdep_apply(S, pb, *o->chi0, U.data(), n, R.data(), wk, solves, cg_iters);
+    if (rc < 0) return rc;
+    ++calls;
+    for (int f = 0; f < n; ++f) W.emplace_back(R.begin() + (size_t)f * dim, R.begin() + (size_t)(f + 1) * dim);
+    return n;
+  };
+  int rc = 0;
+  {  // seeded random start
+    std::mt19937_64 rng(o->seed);
+    std::normal_distribution<double> nd(0.0, 1.0);
+    std::vector<std::vector<double>> block(nb, std::vector<double>(dim));
+    for (auto& x : block)
+      for (double& e : x) e = nd(rng);
+    rc = expand(block);
+  }
+  std::vector<double> theta, Y, res(ne, 0.0);
+  std::vector<std::vector<double>> X(ne), AX(ne);
+  int it = 0, nconv = 0;
+  for (; rc >= 0 && it < max_iter; ++it) {
+    const int k = (int)V.size();
+    std::vector<double> Hs((size_t)k * k);
+    for (int i = 0; i < k; ++i)
+      for (int j = 0; j <= i; ++j) {
+        const double h = 0.5 * (dotv(V[i].data(), W[j].data(), dim) + dotv(V[j].data(), W[i].data(), dim));
+        Hs[(size_t)i * k + j] = Hs[(size_t)j * k + i] = h;
+      }
+    jacobi_eigh(Hs, k, theta, Y);
+    const int nr = std::min(k, max_basis);  // Ritz pairs kept on a restart
+    std::vector<std::vector<double>> XR(std::min(k, std::max(ne, nr))), AXR(XR.size());
+    for (size_t a = 0; a < XR.size(); ++a) {
+      XR[a].assign(dim, 0.0);
+      AXR[a].assign(dim, 0.0);
+      for (int i = 0; i < k; ++i) {
+        const double y = Y[(size_t)i * k + a];
+        for (int d = 0; d < dim; ++d) {
+          XR[a][d] += y * V[i][d];
+          AXR[a][d] += y * W[i][d];
+        }
+      }
+    }
+    // residuals of the wanted pairs; unconverged ones give the next block
+    std::vector<std::vector<double>> block;
+    nconv = 0;
+    for (int a = 0; a < std::min(ne, k); ++a) {
+      std::vector<double> r(dim);
+      for (int d = 0; d < dim; ++d) r[d] = AXR[a][d] - theta[a] * XR[a][d];
+      res[a] = std::sqrt(dotv(r.data(), r.data(), dim));
+      if (res[a] <= tol * std::fabs(theta[a])) {
+        ++nconv;  // converged pairs add no directions (they stay in the basis, deflated)
+      } else if ((int)block.size() < nb) {
+        block.push_back(r);
+      }
+    }
+    if (nconv == ne && k >= ne) {
+      for (int a = 0; a < ne; ++a) {
+        X[a] = XR[a];
+        AX[a] = AXR[a];
+      }
+      break;
+    }
+    if (k + (int)block.size() > max_basis) {  // restart from the Ritz vectors
+      const int keep = std::max(ne, max_basis - nb);
+      V.assign(XR.begin(), XR.begin() + std::min<size_t>(keep, XR.size()));
+      W.assign(AXR.begin(), AXR.begin() + std::min<size_t>(keep, AXR.size()));
+    }
+    for (int a = 0; a < ne; ++a) {
+      X[a] = a < (int)XR.size() ? XR[a] : std::vector<double>(dim, 0.0);
+    }
+    rc = expand(block);
+    if (rc == 0 && nconv < ne) {  // no new direction survived: the basis is exhausted
+      rc = 0;
+      break;
+    }
+  }
+  wk.release();
+  if (rc < 0) return rc;
+  for (int a = 0; a < ne; ++a) eig[a] = a < (int)theta.size() ? theta[a] : 0.0;
+  if (vec) {  // complex coefficients over the whole potential sphere, canonical order
+    const size_t ng = pb.all.size();
+    std::vector<int> pos_of(S->hb.npw, -1);
+    for (size_t q = 0; q < ng; ++q) pos_of[pb.all[q]] = (int)q;
+    const double r2 = 1.0 / std::sqrt(2.0);
+    for (int a = 0; a < ne; ++a) {
+      double* out = vec + 2 * (size_t)a * ng;
+      std::fill(out, out + 2 * ng, 0.0);
+      for (int j = 0; j < m; ++j) {
+        const double re = r2 * X[a][2 * j], im = r2 * X[a][2 * j + 1];
+        const int p = pos_of[pb.rep[j]], q = pos_of[pb.neg[j]];
+        out[2 * p] = re;
+        out[2 * p + 1] = im;
+        out[2 * q] = re;
+        out[2 * q + 1] = -im;
+      }
+    }
+  }
+  if (stats) {
+    stats->iterations = it + 1;
+    stats->n_converged = nconv;
+    stats->chi0_calls = calls;
+    stats->total_solves = solves;
+    stats->total_cg_iters = cg_iters;
+    stats->basis_dim = dim;
+    double mr = 0.0;
+    for (int a = 0; a < ne; ++a) mr = std::max(mr, res[a] / std::max(std::fabs(eig[a]), 1e-300));
+    stats->max_rel_resid = mr;
+    stats->wall_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return nconv == ne ? STERN_OK : STERN_WARN_NOT_CONVERGED;
+}
+
 // ------------------------------------------------------------- autotuner ----
 
 const char* stern_autotune_report(void) { return g_tune_report.c_str(); }

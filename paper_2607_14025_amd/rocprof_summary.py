@@ -10,10 +10,9 @@
       HBM bytes per launch of one kernel from two --pmc runs (FETCH_SIZE, then WRITE_SIZE) of
       `bench.py --steps 1 --warmup 0 --copy-calibration`. Each counter is scaled by what it reads
       for the 1 GiB elementwise copy that run starts with. The kernel's last launches are matched
-      to the bench's final apply, which repeats the timed step's launches (the solve is
-      deterministic), and so to the bench's algorithmic bytes for them; the ratio
-      measured / algorithmic goes to TRAFFIC_JSON under LABEL, with the source hash bench.py
-      checks.
+      to the bench's final apply, its profiled headline step, and so to the bench's algorithmic
+      bytes for them; the ratio measured / algorithmic goes to TRAFFIC_JSON under
+      "WORKLOAD:LABEL", with the source hash bench.py checks.
 
   python3 -m paper_2607_14025_amd.rocprof_summary mfma CSV TITLE COMMAND [SIMDS] > summary.md
       MFMA use of the GEMM and net kernels from one --pmc run with SQ_INSTS_VALU_MFMA_MOPS_BF16,
@@ -61,6 +60,13 @@ def short_name(n: str) -> str:
     return n
 
 
+def matches(kernel: str, name: str) -> bool:
+    """Whether the trace name `name` is one of the kernels `kernel` lists ("a|b": any of a, b), as
+    a substring of its short name; a kernel class of the bench can span several kernels."""
+    sn = short_name(name)
+    return any(k in sn for k in kernel.split("|"))
+
+
 def stats(db: str, title: str, cmd: str) -> str:
     con = sqlite3.connect(db)
     rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
@@ -74,22 +80,21 @@ def stats(db: str, title: str, cmd: str) -> str:
 
 
 def launch_agreement(db: str, bench_log: str, label: str, kernel: str) -> str:
-    """rocprofv3 durations of the bench's timed launches of `kernel` against the bench's own
-    HIP-event time per launch. The head path runs last: its timed steps, then one untimed
-    apply with the same launches, so the timed ones are the kernel's last launches but one
-    step's worth."""
+    """rocprofv3 durations of the launches of `kernel` that the bench timed with HIP events
+    against the bench's own HIP-event time per launch. The bench's last apply is the headline
+    step with the per-launch profile, so those launches are the kernel's last ones."""
     bench = _bench_line(bench_log)
     k = bench["kernels"][label]
     n = int(k["launches"])
-    per_step = n // bench["steps"]
     con = sqlite3.connect(db)
     rows = [(dur, nm) for dur, nm in con.execute("select duration, name from kernels order by start")]
-    mine = [dur for dur, nm in rows if kernel in short_name(nm)]
-    timed = mine[len(mine) - per_step - n:len(mine) - per_step]
+    mine = [dur for dur, nm in rows if matches(kernel, nm)]
+    timed = mine[len(mine) - n:]
     avg_us = sum(timed) / len(timed) / 1e3  # durations are in ns
     return (f"Agreement for `{kernel}` ({label}, the kernel the bench's roofline reports): the bench's HIP "
-            f"events give {k['ms_per_launch'] * 1e3:.1f} us per launch over its {n} timed launches; this trace "
-            f"gives {avg_us:.1f} us for the same launches (ratio {avg_us / (k['ms_per_launch'] * 1e3):.3f}).\n")
+            f"events give {k['ms_per_launch'] * 1e3:.1f} us per launch over the {n} launches of its profiled "
+            f"step; this trace gives {avg_us:.1f} us for the same launches "
+            f"(ratio {avg_us / (k['ms_per_launch'] * 1e3):.3f}).\n")
 
 
 def _counter(path: str, counter: str):
@@ -121,8 +126,9 @@ def _bench_line(log: str) -> dict:
 def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w, traffic_json=None) -> str:
     bench = _bench_line(bench_log)
     k = bench["kernels"][label]
-    n_launch = int(k["launches"] // bench["steps"])
+    n_launch = int(k["launches"] // bench.get("kernels_steps", bench["steps"]))
     algo = float(k["bytes_per_launch"])
+    key = f"{bench['config']['workload']}:{label}"
     res = {}
     for name, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _counter(path, counter)
@@ -130,7 +136,7 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
         if not copy:
             raise SystemExit(f"{path}: no calibration copy kernel ({COPY_KERNEL})")
         scale = COPY_BYTES / (copy[0] * 1024.0)
-        mine = [v for _, n, v in rows if kernel in short_name(n)]
+        mine = [v for _, n, v in rows if matches(kernel, n)]
         if len(mine) < n_launch:
             raise SystemExit(f"{path}: {len(mine)} dispatches of {kernel}, the bench step has {n_launch}")
         last = mine[-n_launch:]
@@ -141,7 +147,7 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
     sha = source_hash(label)
     if traffic_json:
         t = json.load(open(traffic_json)) if os.path.exists(traffic_json) else {}
-        t[label] = dict(measured_over_algorithmic=ratio, source_sha1=sha, kernel=kernel, launches_matched=n_launch,
+        t[key] = dict(measured_over_algorithmic=ratio, source_sha1=sha, kernel=kernel, launches_matched=n_launch,
                         algorithmic_bytes_per_launch=algo, measured_bytes_per_launch=measured,
                         read_bytes_per_launch=res["fetch"]["bytes"], write_bytes_per_launch=res["write"]["bytes"])
         with open(traffic_json, "w") as fh:

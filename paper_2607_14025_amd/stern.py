@@ -29,7 +29,8 @@ STERN_MEM_DEVICE = 1
 EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_miller", "stern_set_occupied", "stern_apply_chi0",
             "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
-            "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error"]
+            "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
+            "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -95,6 +96,17 @@ class TrainStats(C.Structure):
                 ("wall_s", C.c_double)]
 
 
+class PdepOpts(C.Structure):
+    _fields_ = [("n_eig", C.c_int), ("block", C.c_int), ("max_basis", C.c_int), ("max_iter", C.c_int),
+                ("tol", C.c_double), ("ecut_pot_ry", C.c_double), ("seed", C.c_ulonglong), ("chi0", C.POINTER(Opts))]
+
+
+class PdepStats(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("n_converged", C.c_int), ("chi0_calls", C.c_int), ("basis_dim", C.c_int),
+                ("total_solves", C.c_longlong), ("total_cg_iters", C.c_longlong), ("max_rel_resid", C.c_double),
+                ("wall_s", C.c_double)]
+
+
 _lib = None
 
 
@@ -130,13 +142,17 @@ def lib():
         L.stern_autotune_report.restype = C.c_char_p
         L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        L.stern_apply_pc_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.stern_pdep_basis.argtypes = [C.c_void_p, C.c_double, P(C.c_int), P(C.c_int32)]
+        L.stern_pdep_davidson.argtypes = [C.c_void_p, P(PdepOpts), P(C.c_double), P(C.c_double), P(PdepStats)]
         L.stern_free.argtypes = [C.c_void_p]
         L.stern_free.restype = None
         L.stern_last_error.restype = C.c_char_p
         for name in ("stern_basis_info", "stern_init_system", "stern_query", "stern_get_miller", "stern_set_occupied",
                      "stern_apply_chi0", "stern_apply_chi0_many", "stern_apply_h", "stern_apply_pc",
                      "stern_model_create", "stern_model_train", "stern_model_num_params", "stern_model_get_weights",
-                     "stern_model_set_weights", "stern_model_fit_step", "stern_tunable", "stern_autotune"):
+                     "stern_model_set_weights", "stern_model_fit_step", "stern_tunable", "stern_autotune",
+                     "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -347,6 +363,43 @@ class System:
         if profile:
             info["kernels"] = _kernels(st)
         return dn_out, info
+
+    def apply_pc_noalloc(self, c, out=None):
+        """P_c c for complex128 CUDA rows without any allocation in the library (stern_apply_pc_noalloc);
+        enqueued on the system's stream, no synchronisation."""
+        import torch
+        if not c.is_cuda or not c.is_contiguous() or c.dtype != torch.complex128:
+            raise ValueError("rows must be a contiguous complex128 CUDA tensor")
+        c = c.reshape(-1, self.n_pw)
+        out = torch.empty_like(c) if out is None else out
+        _check(lib().stern_apply_pc_noalloc(self._h, c.shape[0], C.c_void_p(c.data_ptr()), C.c_void_p(out.data_ptr())))
+        return out
+
+    def pdep_basis(self, ecut_pot=0.0):
+        """Miller triples [n_g, 3] of the potential sphere |G|^2 < ecut_pot (0: ecut / 4), G != 0."""
+        n = C.c_int()
+        _check(lib().stern_pdep_basis(self._h, float(ecut_pot), C.byref(n), None))
+        mil = np.zeros((n.value, 3), dtype=np.int32)
+        _check(lib().stern_pdep_basis(self._h, float(ecut_pot), None, mil.ctypes.data_as(C.POINTER(C.c_int32))))
+        return mil
+
+    def pdep_davidson(self, n_eig, tol=1e-6, block=0, max_basis=0, max_iter=0, ecut_pot=0.0, seed=0,
+                      chi0_tol=1e-10, precision=STERN_FP64, model=None, prec_only=False, max_chi0_iter=0):
+        """Lowest eigenpairs of chi-bar0 = v^{1/2} chi0 v^{1/2} (stern_pdep_davidson).
+        Returns (eigenvalues [n_eig], coefficients [n_eig, n_g] over pdep_basis(ecut_pot), stats dict)."""
+        mil = self.pdep_basis(ecut_pot)
+        co = make_opts(chi0_tol, max_chi0_iter, precision, STERN_MEM_DEVICE, model=model, prec_only=prec_only)
+        o = PdepOpts(int(n_eig), int(block), int(max_basis), int(max_iter), float(tol), float(ecut_pot), int(seed),
+                     C.pointer(co))
+        eig = np.zeros(n_eig)
+        vec = np.zeros((n_eig, len(mil)), dtype=np.complex128)
+        st = PdepStats()
+        rc = _check(lib().stern_pdep_davidson(self._h, C.byref(o), eig.ctypes.data_as(C.POINTER(C.c_double)),
+                                              vec.ctypes.data_as(C.POINTER(C.c_double)), C.byref(st)))
+        info = dict(rc=rc, iterations=st.iterations, n_converged=st.n_converged, chi0_calls=st.chi0_calls,
+                    basis_dim=st.basis_dim, total_solves=st.total_solves, total_cg_iters=st.total_cg_iters,
+                    max_rel_resid=st.max_rel_resid, wall_s=st.wall_s, miller=mil)
+        return eig, vec, info
 
     def tunable(self, which, value=-1):
         """Query (value < 0) or set a kernel tunable (TUNE_*); returns its value."""
