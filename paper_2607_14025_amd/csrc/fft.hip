@@ -470,7 +470,9 @@ template <int N, class T, int W, int ZR>
 struct PlaneWCfg {
   static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
   static constexpr int RM = R1 > R2 ? R1 : R2;
-  static constexpr int QLD = N + 1;
+  // stride of the lines of Q: the smallest value above N that is 1 mod 32, so that lanes
+  // taking consecutive lines (and radix-R1 groups inside a line) fall on different banks
+  static constexpr int QLD = N + 1 + ((32 - (N + 1) % 32) + 1) % 32;
   static constexpr int NT = 64 * W;
   static constexpr int MAXZ = (ZR * RM + 63) / 64;         // items per lane in a z stage
 };
@@ -487,7 +489,7 @@ __device__ constexpr bool idle_range(int lo, int hi) {
 
 template <int N, class T, int W, int ZR>
 constexpr size_t planew_lds_bytes(int nza) {
-  return ((size_t)nza * (N + 1) + N + (size_t)W * N * ZR) * sizeof(Z<T>);
+  return ((size_t)nza * PlaneWCfg<N, T, W, ZR>::QLD + N + (size_t)W * N * ZR) * sizeof(Z<T>);
 }
 
 // orders the LDS accesses of one wave: stores above, loads below
@@ -519,6 +521,12 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   // this wave's y lines [f0, f0 + nl) and z-pass rows [y0w, y0w + nr)
   const int lpw = (nza + W - 1) / W;
   const int f0 = min(nza, wave * lpw), nl = min(nza, f0 + lpw) - f0;
+  // In the y passes that gather from and scatter to the pencils, consecutive lanes take
+  // consecutive lines: adjacent pencil columns in HBM and rows QLD apart in LDS. Items are
+  // numbered it = (index within the line) << lsh | (line - f0), with 2^lsh >= nl.
+  int lsh = 0;
+  while ((1 << lsh) < nl) ++lsh;
+  const int lmask = (1 << lsh) - 1;
   constexpr int RPW = (N + W - 1) / W;
   const int y0w = min(N, wave * RPW), nr = min(N, y0w + RPW) - y0w;
   const int* __restrict__ yc = g.ycol;
@@ -531,7 +539,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   // the first inverse-y item of this lane (it = lane), loaded one pair ahead
   Z<T> pre[R1];
   auto gather = [&](const Z<T>* tp, int it, Z<T>(&v)[R1]) {
-    const int j = it % R2, f = f0 + it / R2;
+    const int j = it >> lsh, f = f0 + (it & lmask);
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
       const int y = j + r * R2;
@@ -542,14 +550,16 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       }
     }
   };
-  if (PF && blockIdx.x < total && lane < nl * R2) gather(pencils(blockIdx.x), lane, pre);
+  const bool lane_item = lane < (R2 << lsh) && (lane & lmask) < nl;  // item it = lane exists
+  if (PF && blockIdx.x < total && lane_item) gather(pencils(blockIdx.x), lane, pre);
   for (long q = blockIdx.x; q < total; q += gridDim.x) {
     const int ix = (int)(q / nvec);
     Z<T>* tp = pencils(q);
     const T* __restrict__ vx = vt + (size_t)ix * N * N;
     // ---- inverse y on this wave's lines, in place in Q ----
-    for (int it = lane; it < nl * R2; it += 64) {
-      const int j = it % R2, f = f0 + it / R2;
+    for (int it = lane; it < (R2 << lsh); it += 64) {
+      if ((it & lmask) >= nl) continue;
+      const int j = it >> lsh, f = f0 + (it & lmask);
       Z<T> v[R1];
       if (PF && it == lane) {
 #pragma unroll
@@ -574,7 +584,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       for (int r = 0; r < R2; ++r) Q[f * QLD + j + r * R1] = v[r];
     }
     __syncthreads();
-    if (PF && q + gridDim.x < total && lane < nl * R2) gather(pencils(q + gridDim.x), lane, pre);  // in flight
+    if (PF && q + gridDim.x < total && lane_item) gather(pencils(q + gridDim.x), lane, pre);  // in flight
     // ---- z transforms of this wave's rows, ZR at a time ----
     for (int m0 = 0; m0 < nr; m0 += ZR) {
       const int nz = min(ZR, nr - m0), y0 = y0w + m0;
@@ -672,8 +682,9 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       for (int k1 = 0; k1 < R1; ++k1) Q[f * QLD + j + k1 * R2] = v[k1];
     }
     wave_sync();
-    for (int it = lane; it < nl * R1; it += 64) {
-      const int k1 = it % R1, f = f0 + it / R1;
+    for (int it = lane; it < (R1 << lsh); it += 64) {
+      if ((it & lmask) >= nl) continue;
+      const int k1 = it >> lsh, f = f0 + (it & lmask);
       Z<T> v[R2];
 #pragma unroll
       for (int jj = 0; jj < R2; ++jj) v[jj] = Q[f * QLD + k1 * R2 + jj];
