@@ -18,7 +18,7 @@ stern_apply_chi0_many call. The CPU oracle is timed on a seeded uniform sample o
 (band, field) pairs, solved as one batch; its mean iterations are stated beside the GPU's.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--fp64-steps F] [--no-cpu-baseline]
-                    [--no-secondary] [--cpu-pairs P]
+                    [--no-secondary] [--cpu-pairs P] [--headline-only] [--copy-calibration]
 """
 from __future__ import annotations
 
@@ -207,16 +207,19 @@ def large_entry(args, dev):
         return s.apply_chi0(dv, tol=args.tol, dn_out=out, precision=prec, model=mdl, prec_only=mdl is not None,
                             **kw)[1]
 
-    # plain FP64 baseline (the training's FP64 solves have already run every FP64 kernel)
-    v64, t64, i64 = timed_steps(lambda: call(STERN_FP64, ref), args.fp64_steps, 0, "large fp64")
-    plain = summary(i64, t64, v64)
-    vmx, tmx, imx = timed_steps(lambda: call(STERN_MIXED, dn), 1, 0, "large mixed")
-    mixed = summary(imx, tmx, vmx)
-    mixed["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
+    plain = mixed = None
+    if not args.headline_only:
+        # plain FP64 baseline (the training's FP64 solves have already run every FP64 kernel)
+        v64, t64, i64 = timed_steps(lambda: call(STERN_FP64, ref), args.fp64_steps, 0, "large fp64")
+        plain = summary(i64, t64, v64)
+        vmx, tmx, imx = timed_steps(lambda: call(STERN_MIXED, dn), 1, 0, "large mixed")
+        mixed = summary(imx, tmx, vmx)
+        mixed["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
     # headline: learned preconditioner + mixed
     vh, th, ih = timed_steps(lambda: call(STERN_MIXED, dn, model), args.steps, args.warmup, "large learnedK-mixed")
     head = summary(ih, th, vh)
-    head["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
+    if plain is not None:
+        head["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
     # pairs of the oracle sample: uniform over the step's 4,096 (band, field) pairs, seeded
     rng = np.random.default_rng(np.random.SeedSequence([LARGE.config_id, 0, 7]))
     pick = rng.choice(4 * s.n_occ, size=args.cpu_pairs, replace=False)
@@ -238,8 +241,8 @@ def large_entry(args, dev):
                     "FP32 FFTs + split-BF16 MFMA GEMMs in FP64 defect correction; Teter FP64 PCG fallback",
                headline=head, plain_fp64=plain, mixed=mixed,
                training=dict(fields="4-5 of the same cell (timed: 0-3)", **train),
-               speedup_vs_plain_fp64=head["solves_per_s"] / plain["solves_per_s"],
-               mixed_speedup_vs_plain_fp64=mixed["solves_per_s"] / plain["solves_per_s"])
+               speedup_vs_plain_fp64=head["solves_per_s"] / plain["solves_per_s"] if plain else None,
+               mixed_speedup_vs_plain_fp64=mixed["solves_per_s"] / plain["solves_per_s"] if plain else None)
     out = dict(value=vh, dt=th, steps=args.steps, cfg=cfg, kern=kern, wl=wl, pairs=pairs,
                gpu_x=pinfo["samples"], roof=roofline(kern, LARGE.name), fft=fft_stage(kern))
     model.close()
@@ -315,6 +318,8 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-secondary", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline path (setup, its steps and the profiled step): for profiler runs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for rocprofv3 FETCH_SIZE / WRITE_SIZE)")
     args = ap.parse_args()
@@ -334,6 +339,8 @@ def main():
         log("copied 1 GiB device to device (counter reference)")
         del a, b
     secondary = {}
+    if args.headline_only:
+        args.no_secondary = args.no_cpu_baseline = True
     if not args.no_secondary:  # before the headline, so that its profiled step is the run's last apply
         log("secondary: batched cells")
         secondary["batched"] = batched_entry(args, dev)

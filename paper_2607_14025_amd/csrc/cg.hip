@@ -385,8 +385,10 @@ __global__ __launch_bounds__(kCgThreads) void k_cg32_init2(Cg32State S, const in
 // flag 1 once ||r||^2 <= tol2 ||r0||^2. (r, z) is taken with z before any
 // projection: r stays in range(P_c), so it equals (r, P_c z).
 template <bool LK>
-__global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const int* __restrict__ act, double tol2) {
+__global__ __launch_bounds__(kCgThreads) void k_cg32_alpha(Cg32State S, const int* __restrict__ act, double tol2,
+                                                             const int* __restrict__ live) {
   __shared__ double sh[kCgThreads / 64];
+  if (live && (int)blockIdx.x >= *live) return;  // list entry past the live count (whole workgroup)
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
@@ -473,8 +475,9 @@ __device__ __forceinline__ double block_sum_a(double v, double* sh) {
 
 template <bool LK, int PER>
 __global__ __launch_bounds__(kAlphaThreads) void k_cg32_alpha_row(Cg32State S, const int* __restrict__ act,
-                                                                   double tol2) {
+                                                                   double tol2, const int* __restrict__ live) {
   __shared__ double sh[kAlphaThreads / 64];
+  if (live && (int)blockIdx.x >= *live) return;  // list entry past the live count (whole workgroup)
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
@@ -525,7 +528,9 @@ __global__ __launch_bounds__(kAlphaThreads) void k_cg32_alpha_row(Cg32State S, c
 }
 
 // p = z + beta p (beta from the alpha step)
-__global__ __launch_bounds__(kCgThreads) void k_cg32_beta(Cg32State S, const int* __restrict__ act) {
+__global__ __launch_bounds__(kCgThreads) void k_cg32_beta(Cg32State S, const int* __restrict__ act,
+                                                            const int* __restrict__ live) {
+  if (live && (int)blockIdx.x >= *live) return;  // list entry past the live count (whole workgroup)
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   if (S.flag[s] != 0) return;
   const size_t o = (size_t)s * S.npw_pad;
@@ -692,22 +697,64 @@ void launch_cg32_init(const Cg32State& s, const Z64* r64, const int* act, int n,
 void launch_cg32_init2(const Cg32State& s, const int* act, int n, hipStream_t st) {
   if (n > 0) k_cg32_init2<<<n, kCgThreads, 0, st>>>(s, act);
 }
-void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st) {
+void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st, const int* live) {
   if (n <= 0) return;
   if (s.npw_pad <= kAlphaThreads * kAlphaMaxPer) {  // the row fits in one workgroup's registers
     if (s.kprec)
-      k_cg32_alpha_row<true, kAlphaMaxPer><<<n, kAlphaThreads, 0, st>>>(s, act, tol2);
+      k_cg32_alpha_row<true, kAlphaMaxPer><<<n, kAlphaThreads, 0, st>>>(s, act, tol2, live);
     else
-      k_cg32_alpha_row<false, kAlphaMaxPer><<<n, kAlphaThreads, 0, st>>>(s, act, tol2);
+      k_cg32_alpha_row<false, kAlphaMaxPer><<<n, kAlphaThreads, 0, st>>>(s, act, tol2, live);
   } else if (s.kprec) {
-    k_cg32_alpha<true><<<n, kCgThreads, 0, st>>>(s, act, tol2);
+    k_cg32_alpha<true><<<n, kCgThreads, 0, st>>>(s, act, tol2, live);
   } else {
-    k_cg32_alpha<false><<<n, kCgThreads, 0, st>>>(s, act, tol2);
+    k_cg32_alpha<false><<<n, kCgThreads, 0, st>>>(s, act, tol2, live);
   }
 }
-void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st) {
-  if (n > 0) k_cg32_beta<<<n, kCgThreads, 0, st>>>(s, act);
+
+// In-place stable compaction of the active list by one workgroup of 1024 threads:
+// chunk by chunk, every entry of a chunk is read before any is written, and an
+// entry moves to its position among the kept ones, at or before where it was
+// read, so nothing is overwritten before it is read. The count is read by every
+// thread at the start and written by thread 0 after the last barrier.
+constexpr int kCompactThreads = 1024;
+__global__ __launch_bounds__(kCompactThreads) void k_compact(int* __restrict__ list, int* __restrict__ count,
+                                                             const int* __restrict__ flag) {
+  __shared__ int wsum[kCompactThreads / 64];
+  const int n = *count;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int base = 0;  // kept entries before the current chunk (the same in every thread)
+  for (int c0 = 0; c0 < n; c0 += kCompactThreads) {
+    const int i = c0 + threadIdx.x;
+    int s = 0, keep = 0;
+    if (i < n) {
+      s = list[i];
+      keep = flag[s] == 0;
+    }
+    const unsigned long long m = __ballot(keep);
+    const int before = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();  // every read of this chunk is done; the wave sums are visible
+    int off = base, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kCompactThreads / 64; ++w) {
+      off += w < wave ? wsum[w] : 0;
+      tot += wsum[w];
+    }
+    if (keep) list[off + before] = s;
+    base += tot;
+    __syncthreads();  // wsum is reused by the next chunk
+  }
+  if (threadIdx.x == 0) *count = base;
 }
+
+void launch_compact(int* list, int* count, const int* flag, hipStream_t st) {
+  k_compact<<<1, kCompactThreads, 0, st>>>(list, count, flag);
+}
+void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st, const int* live) {
+  if (n > 0) k_cg32_beta<<<n, kCgThreads, 0, st>>>(s, act, live);
+}
+__global__ void k_set_int(int* __restrict__ p, int v) { *p = v; }
+void launch_set_int(int* p, int v, hipStream_t st) { k_set_int<<<1, 1, 0, st>>>(p, v); }
 void launch_add_d(Z64* x, const Z32* d, int ld, const int* act, int n, hipStream_t st) {
   if (n > 0) k_add_d<<<n, 256, 0, st>>>(x, d, ld, act);
 }

@@ -150,6 +150,7 @@ __global__ __launch_bounds__(kXThreads) void k_xinv(const Z<T>* __restrict__ sph
   constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
   __shared__ Z<T> P[CB * LDX];
   __shared__ int bs[CB], bx[CB];
+  if (g.live && (int)blockIdx.y >= *g.live) return;  // vector not live (whole workgroup, before any barrier)
   const Z<T>* tw = twtab<T>(g);
   const int c0 = blockIdx.x * CB;
   const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
@@ -183,6 +184,7 @@ __global__ __launch_bounds__(kXThreads) void k_xfwd(const Z<T>* __restrict__ pen
   constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
   __shared__ Z<T> P[CB * LDX];
   __shared__ int bs[CB], bx[CB];
+  if (g.live && (int)blockIdx.y >= *g.live) return;  // vector not live (whole workgroup, before any barrier)
   const Z<T>* tw = twtab<T>(g);
   const int c0 = blockIdx.x * CB;
   const int vec = vidx ? vidx[blockIdx.y] : blockIdx.y;
@@ -342,6 +344,7 @@ __global__ __launch_bounds__((plane_nt<N, T>())) void k_plane_vloc(Z<T>* __restr
   T* VS = reinterpret_cast<T*>(smem_raw + ((size_t)N * LD + N) * sizeof(Z<T>));
   const int tid = threadIdx.x;
   const int nza = c.nza;
+  if (g.live) nvec = min(nvec, *g.live);  // pairs (plane, vector) of the live vectors only
   const long total = (long)N * nvec;
   const Z<T> zero = zmk(T(0), T(0));
   Z<T> pre[MAXA][R1];
@@ -530,6 +533,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   constexpr int RPW = (N + W - 1) / W;
   const int y0w = min(N, wave * RPW), nr = min(N, y0w + RPW) - y0w;
   const int* __restrict__ yc = g.ycol;
+  if (g.live) nvec = min(nvec, *g.live);  // pairs (plane, vector) of the live vectors only
   const long total = (long)N * nvec;
   auto pencils = [&](long q) {
     const int ix = (int)(q / nvec), b = (int)(q - (long)ix * nvec);

@@ -84,11 +84,13 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
                                                             const Z32* __restrict__ X, int ldx,
                                                             const int* __restrict__ xidx, int ncols, int K,
                                                             int kchunk, Z32* __restrict__ cpart, int nmb, int nnb,
-                                                            int nsplit) {
+                                                            int nsplit, const int* __restrict__ ncount) {
   __shared__ bf16x8 xs[2][2][2][kWN * 4];  // [buffer][hi, lo][sub-step][column * 4 + group of 4 complex]
   const int L = blockIdx.x, slot = L >> 3;
   const int mb = slot % nmb, rest = (slot / nmb) * 8 + (L & 7);
   if (rest >= nnb * nsplit) return;  // padding of the last group of XCD slots; no barrier passed yet
+  const int nlive = ncount ? min(ncols, *ncount) : ncols;  // ncols stays the stride of the partials
+  if ((rest % nnb) * kWN >= nlive) return;  // no live column in this block; no barrier passed yet
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, g = lane >> 4;
   const int wm = wave & 3, wn = wave >> 2;
@@ -101,7 +103,7 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
   // staging: thread -> (column tn, 8 complex from 8 tq): groups 2 tq and 2 tq + 1 of the step
   const int tn = threadIdx.x >> 2, tq = threadIdx.x & 3;
   const int ncol = n0 + tn;
-  const bool xval = ncol < ncols;
+  const bool xval = ncol < nlive;
   const Z32* xrow = X + (size_t)(xval ? (xidx ? xidx[ncol] : ncol) : 0) * ldx;
   const __bf16* ah[2];
   const __bf16* al[2];
@@ -198,7 +200,7 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
 #pragma unroll
   for (int nb = 0; nb < 4; ++nb) {
     const int n = n0 + wn * 64 + nb * 16 + l16;
-    if (n >= ncols) continue;
+    if (n >= nlive) continue;
     Z32* dst = cpart + ((size_t)split * ncols + n) * M_pad;
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -210,10 +212,10 @@ __global__ __launch_bounds__(kThreads8) void k_reduce_bf16w(const __bf16* __rest
 // C = scale * sum of the split partials, as bf16 hi and lo of (c_re, c_im):
 // Cs[0], Cs[1], each [ncols][2 M_pad] interleaved along m.
 __global__ void k_sum_split(const Z32* __restrict__ cpart, int nsplit, int ncols, int M_pad, float scale,
-                            __bf16* __restrict__ Cs) {
+                            __bf16* __restrict__ Cs, const int* __restrict__ live) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = ncols * M_pad;
-  if (i >= total) return;
+  if (i >= total || (live && i / M_pad >= *live)) return;
   float re = 0.f, im = 0.f;
   for (int s = 0; s < nsplit; ++s) {
     const Z32 v = cpart[(size_t)s * total + i];
@@ -262,7 +264,8 @@ __global__ __launch_bounds__(256 * WN, KB == 4 ? 2 : 4) void k_expand_bf16s(cons
                                                             const __bf16* __restrict__ Cs, Z32* __restrict__ Y,
                                                             int ldy, const int* __restrict__ yidx, int ncols,
                                                             Z32* __restrict__ P, const double* __restrict__ beta,
-                                                            int nnb) {
+                                                            int nnb, const int* __restrict__ live) {
+  const int nlive = live ? min(ncols, *live) : ncols;  // ncols stays the stride of C
   const int L = blockIdx.x, slot = L >> 3;
   const int nbk = slot % nnb, kblk = (slot / nnb) * 8 + (L & 7);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -271,13 +274,14 @@ __global__ __launch_bounds__(256 * WN, KB == 4 ? 2 : 4) void k_expand_bf16s(cons
   const int k0 = kblk * (64 * KB) + wk * 16 * KB;
   if (k0 >= K) return;  // K is a multiple of 64; no barrier below
   const int n0 = nbk * (64 * WN) + wn * 64;
+  if (n0 >= nlive) return;  // no live column for this wave
   const size_t plane = (size_t)ncols * M_pad * 2;
   int nn[4];
   bool nv[4];
 #pragma unroll
   for (int bj = 0; bj < 4; ++bj) {
     nn[bj] = n0 + 16 * bj + l16;
-    nv[bj] = nn[bj] < ncols;
+    nv[bj] = nn[bj] < nlive;
   }
   f32x4 dre[KB][4], dim_[KB][4];
 #pragma unroll
@@ -393,9 +397,11 @@ __device__ __forceinline__ void put_split(__bf16* __restrict__ Cs, size_t plane,
 // (H - eps) p. One workgroup per column n; output as k_sum_split writes it
 // for M_pad = Ma + Mb.
 __global__ void k_sum_proj(const Z32* __restrict__ cp_a, int ns_a, const Z32* __restrict__ cp_b, int ns_b,
-                           int ncols, int Ma, int Mb, float D, const Z32* __restrict__ G, __bf16* __restrict__ Cs) {
+                           int ncols, int Ma, int Mb, float D, const Z32* __restrict__ G, __bf16* __restrict__ Cs,
+                           const int* __restrict__ live) {
   extern __shared__ Z32 ca[];
   const int n = blockIdx.x, Mt = Ma + Mb;
+  if (live && n >= *live) return;  // whole workgroup, before its barrier
   const size_t plane = (size_t)ncols * Mt * 2, row = (size_t)n * Mt;
   for (int a = threadIdx.x; a < Ma; a += blockDim.x) {
     float re = 0.f, im = 0.f;
@@ -448,31 +454,32 @@ void launch_split_bf16_rows(const Z64* A, int M, int K, int row0, int Mt, __bf16
 }
 
 void launch_sum_proj32(const Z32* cp_a, int ns_a, const Z32* cp_b, int ns_b, int ncols, int Ma, int Mb, float D,
-                       const Z32* G, __bf16* Cs, hipStream_t st) {
+                       const Z32* G, __bf16* Cs, hipStream_t st, const int* live) {
   if (ncols <= 0) return;
-  k_sum_proj<<<ncols, 256, (size_t)Ma * sizeof(Z32), st>>>(cp_a, ns_a, cp_b, ns_b, ncols, Ma, Mb, D, G, Cs);
+  k_sum_proj<<<ncols, 256, (size_t)Ma * sizeof(Z32), st>>>(cp_a, ns_a, cp_b, ns_b, ncols, Ma, Mb, D, G, Cs, live);
 }
 
 void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,
-                        int ncols, int K, Z32* cpart, int nsplit, hipStream_t st) {
+                        int ncols, int K, Z32* cpart, int nsplit, hipStream_t st, const int* live) {
   if (ncols <= 0) return;
   int kchunk = (K + nsplit - 1) / nsplit;
   kchunk = (kchunk + 31) / 32 * 32;  // whole K steps of 32 complex; K is a multiple of 64
   const int nmb = (M_pad + kWM - 1) / kWM, nnb = (ncols + kWN - 1) / kWN;
   const int groups = (nnb * nsplit + 7) / 8;  // groups of 8 (column block, split) pairs, one per XCD
   k_reduce_bf16w<<<groups * 8 * nmb, kThreads8, 0, st>>>(Ahi, Alo, M_pad, X, ldx, xidx, ncols, K, kchunk, cpart,
-                                                          nmb, nnb, nsplit);
+                                                          nmb, nnb, nsplit, live);
 }
 
 void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
-                        hipStream_t st) {
+                        hipStream_t st, const int* live) {
   const int total = ncols * M_pad;
   if (total <= 0) return;
-  k_sum_split<<<(total + 255) / 256, 256, 0, st>>>(cpart, nsplit, ncols, M_pad, scale, Cs);
+  k_sum_split<<<(total + 255) / 256, 256, 0, st>>>(cpart, nsplit, ncols, M_pad, scale, Cs, live);
 }
 
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
-                        const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P, const double* beta) {
+                        const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P, const double* beta,
+                        const int* live) {
   if (ncols <= 0) return;
   // linear grid: ceil(row blocks / 8) groups x 8 XCD slots x column blocks
   auto grid = [&](int rows, int cols) {
@@ -483,26 +490,26 @@ void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const _
     const auto g = grid(128, kEN);
     if (P)
       k_expand_bf16s<2, true, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
-                                                                g.second);
+                                                                g.second, live);
     else
       k_expand_bf16s<2, false, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P,
-                                                                 beta, g.second);
+                                                                 beta, g.second, live);
   } else if (variant == 2) {
     const auto g = grid(kET, 64);
     if (P)
       k_expand_bf16s<4, true, 1><<<g.first, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
-                                                          g.second);
+                                                          g.second, live);
     else
       k_expand_bf16s<4, false, 1><<<g.first, 256, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
-                                                           g.second);
+                                                           g.second, live);
   } else {
     const auto g = grid(kET, kEN);
     if (P)
       k_expand_bf16s<4, true, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P, beta,
-                                                                g.second);
+                                                                g.second, live);
     else
       k_expand_bf16s<4, false, 2><<<g.first, kThreads8, 0, st>>>(ATh, ATl, M_pad, K, Cs, Y, ldy, yidx, ncols, P,
-                                                                 beta, g.second);
+                                                                 beta, g.second, live);
   }
 }
 

@@ -27,6 +27,9 @@ struct FftGeom {
   const double* g2h;        // [npw_pad] |G|^2 / 2 in column order (0 for padding)
   const Z64* tw64;          // [N] exp(-2 pi i m / N)
   const Z32* tw32;
+  // device count of the live vectors, or null: a launch sized for nvec vectors then covers only
+  // the first *live of them (the active list shrinks on the device between host polls)
+  const int* live = nullptr;
 };
 
 // columns per workgroup in the x-pencil passes: 32 FP32 or 16 FP64 columns, about the same
@@ -174,8 +177,13 @@ struct Cg32State {
 };
 void launch_cg32_init(const Cg32State& s, const Z64* r64, const int* act, int n, hipStream_t st);
 void launch_cg32_init2(const Cg32State& s, const int* act, int n, hipStream_t st);
-void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st);
-void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st);
+void launch_cg32_alpha(const Cg32State& s, const int* act, int n, double tol2, hipStream_t st,
+                       const int* live = nullptr);
+// in-place stable compaction of the active list: rows s = list[i], i < *count, with flag[s] == 0 keep
+// their order at the front and *count becomes their number (one workgroup)
+void launch_compact(int* list, int* count, const int* flag, hipStream_t st);
+void launch_cg32_beta(const Cg32State& s, const int* act, int n, hipStream_t st, const int* live = nullptr);
+void launch_set_int(int* p, int v, hipStream_t st);  // *p = v (device), as a kernel
 void launch_add_d(Z64* x, const Z32* d, int ld, const int* act, int n, hipStream_t st);
 void launch_outer_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st);
 void launch_row_norm2(const Z64* y, int ld, int n, double* out, hipStream_t st);
@@ -191,17 +199,19 @@ void launch_split_bf16_rows(const Z64* A, int M, int K, int row0, int Mt, __bf16
 // coefficients of the projected (H - eps) p over the stacked rows [KB (Ma); Psi (Mb)]:
 // rows a: D <beta_a|p>; rows Ma + b: -(<psi_b|q_loc> + sum_a G[a][b] D <beta_a|p>), G[a][b] = <psi_b|beta_a>
 void launch_sum_proj32(const Z32* cp_a, int ns_a, const Z32* cp_b, int ns_b, int ncols, int Ma, int Mb, float D,
-                       const Z32* G, __bf16* Cs, hipStream_t st);
+                       const Z32* G, __bf16* Cs, hipStream_t st, const int* live = nullptr);
 // C[n][m] partial = sum_k conj(A[m][k]) X[xidx[n]][k] (BF16 split operands, FP32 accumulation)
+// live (optional, device): only the first *live of the ncols columns are computed (ncols still
+// sets the grid and the strides of the partials and of C)
 void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,
-                        int ncols, int K, Z32* cpart, int nsplit, hipStream_t st);
+                        int ncols, int K, Z32* cpart, int nsplit, hipStream_t st, const int* live = nullptr);
 void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
-                        hipStream_t st);
+                        hipStream_t st, const int* live = nullptr);
 // Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A
 // Y += A C for the split-BF16 operands; variant 0: 256 x 128 tiles, 1: 128 x 128 tiles.
 // With P: Y is not written, P[s] = (Y[s] + A C) + beta[s] P[s] for s = yidx[n] instead.
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
                         const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P = nullptr,
-                        const double* beta = nullptr);
+                        const double* beta = nullptr, const int* live = nullptr);
 
 }  // namespace stern

@@ -174,6 +174,8 @@ struct stern_system {
   DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cpart2, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
       sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
   DBuf m_d, m_r, m_p, m_q, m_z, m_rz, m_rr0, m_beta, m_flag;  // mixed inner solve
+  DBuf m_cnt;                 // device count of the inner solve's active list (list_f)
+  const int* live = nullptr;  // while set, FP32 launches cover only the first *live list entries
   // coarse (N/2)^3 grid of the learned guess, when it holds the sphere
   bool have_coarse = false;
   HostBasis hbc;
@@ -212,6 +214,7 @@ struct stern_system {
     g.g2h = g2h.as<double>();
     g.tw64 = tw64.as<Z64>();
     g.tw32 = tw32.as<Z32>();
+    g.live = live;
     return g;
   }
 
@@ -248,7 +251,7 @@ struct stern_system {
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
-                   &band_feat, &projT_hi, &projT_lo, &proj_g, &cpart2};
+                   &band_feat, &projT_hi, &projT_lo, &proj_g, &cpart2, &m_cnt};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -383,13 +386,13 @@ int apply_psi32_rows(stern_system* S, const Z32* X, Z32* Y, const int* list, int
   __bf16* cm = S->cmat.as<__bf16>();
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (n + m), 8.0 * m * npw * n, [&] {
     launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, X, K, list, n, K, cp, ns,
-                       S->stream);
+                       S->stream, S->live);
   }));
   CHECKED(timed(S, STERN_K_SUM_PARTS, 8.0 * m * n * (ns + 1), 0.0,
-                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, scale, cm, S->stream); }));
+                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, scale, cm, S->stream, S->live); }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (2.0 * n + m), 8.0 * m * npw * n, [&] {
     launch_expand_bf16(S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), S->nocc_pad, cm, Y, K, list, n, K,
-                       S->gemm16_expand, S->stream);
+                       S->gemm16_expand, S->stream, nullptr, nullptr, S->live);
   }));
   return 0;
 }
@@ -405,13 +408,13 @@ int apply_pc32_update(stern_system* S, const Z32* Z, Z32* P, const double* beta,
   __bf16* cm = S->cmat.as<__bf16>();
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (n + m), 8.0 * m * npw * n, [&] {
     launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), S->nocc_pad, Z, K, list, n, K, cp, ns,
-                       S->stream);
+                       S->stream, S->live);
   }));
   CHECKED(timed(S, STERN_K_SUM_PARTS, 8.0 * m * n * (ns + 1), 0.0,
-                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, -1.f, cm, S->stream); }));
+                [&] { launch_sum_parts32(cp, ns, n, S->nocc_pad, -1.f, cm, S->stream, S->live); }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, 8.0 * npw * (3.0 * n + m), 8.0 * m * npw * n, [&] {
     launch_expand_bf16(S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), S->nocc_pad, cm, const_cast<Z32*>(Z), K,
-                       list, n, K, S->gemm16_expand, S->stream, P, beta);
+                       list, n, K, S->gemm16_expand, S->stream, P, beta, S->live);
   }));
   return 0;
 }
@@ -449,18 +452,20 @@ int apply_hproj32_rows(stern_system* S, const Z32* in, Z32* out, const int* list
   Z32 *cpa = S->cpart.as<Z32>(), *cpb = S->cpart2.as<Z32>();
   __bf16* cm = S->cmat.as<__bf16>();
   CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
-    launch_reduce_bf16(S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(), Ma, in, K, list, n, K, cpa, ns_a, S->stream);
+    launch_reduce_bf16(S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(), Ma, in, K, list, n, K, cpa, ns_a, S->stream,
+                       S->live);
   }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + m), 8.0 * m * npw * n, [&] {
     launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), Mb, out, K, list, n, K, cpb, ns_b,
-                       S->stream);
+                       S->stream, S->live);
   }));
   CHECKED(timed(S, STERN_K_SUM_PARTS, zb * n * (na * (ns_a + 1) + m * (ns_b + 1)), 8.0 * n * na * m, [&] {
-    launch_sum_proj32(cpa, ns_a, cpb, ns_b, n, Ma, Mb, (float)S->cell.D, S->proj_g.as<Z32>(), cm, S->stream);
+    launch_sum_proj32(cpa, ns_a, cpb, ns_b, n, Ma, Mb, (float)S->cell.D, S->proj_g.as<Z32>(), cm, S->stream,
+                      S->live);
   }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (2.0 * n + na + m), 8.0 * (na + m) * npw * n, [&] {
     launch_expand_bf16(S->projT_hi.as<__bf16>(), S->projT_lo.as<__bf16>(), S->proj_m, cm, out, K, list, n, K,
-                       S->gemm16_expand, S->stream);
+                       S->gemm16_expand, S->stream, nullptr, nullptr, S->live);
   }));
   return 0;
 }
@@ -490,13 +495,13 @@ int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, in
     __bf16* cm = S->cmat.as<__bf16>();
     CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (n + na), 8.0 * na * npw * n, [&] {
       launch_reduce_bf16(S->kb_hi.as<__bf16>(), S->kb_lo.as<__bf16>(), S->natoms_pad, in, K, list, n, K, cp, ns,
-                         S->stream);
+                         S->stream, S->live);
     }));
     CHECKED(timed(S, STERN_K_SUM_PARTS, zb * na * n * (ns + 1), 0.0,
-                  [&] { launch_sum_parts32(cp, ns, n, S->natoms_pad, (float)S->cell.D, cm, S->stream); }));
+                  [&] { launch_sum_parts32(cp, ns, n, S->natoms_pad, (float)S->cell.D, cm, S->stream, S->live); }));
     CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (2.0 * n + na), 8.0 * na * npw * n, [&] {
       launch_expand_bf16(S->kbT_hi.as<__bf16>(), S->kbT_lo.as<__bf16>(), S->natoms_pad, cm, out, K, list, n, K,
-                         S->gemm16_expand, S->stream);
+                         S->gemm16_expand, S->stream, nullptr, nullptr, S->live);
     }));
   }
   return 0;
@@ -542,6 +547,7 @@ int ensure_workspace32(stern_system* S, int ns) {
   for (DBuf* d : {&S->m_d, &S->m_r, &S->m_p, &S->m_q, &S->m_z}) CHECKED(d->ensure((size_t)ns * K * sizeof(Z32)));
   for (DBuf* d : {&S->m_rz, &S->m_rr0, &S->m_beta}) CHECKED(d->ensure((size_t)ns * sizeof(double)));
   CHECKED(S->m_flag.ensure((size_t)ns * sizeof(int)));
+  CHECKED(S->m_cnt.ensure(sizeof(int)));
   if (S->ws32_solves < ns) {
     for (DBuf* d : {&S->m_d, &S->m_r, &S->m_p, &S->m_q, &S->m_z})
       launch_fill_zero32(d->as<Z32>(), (size_t)ns * K, S->stream);
@@ -934,35 +940,46 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
     iact.clear();
     for (int s : act)
       if (h_iflag[s] == 0) iact.push_back(s);
+    // The active list (list_f) and its count (m_cnt) live on the device: every inner
+    // iteration ends with an in-place stable compaction, and its launches, sized for
+    // the count at the last poll, cover only the first *m_cnt entries. A window of
+    // check_every iterations (eager, or captured once into a hipGraph and replayed)
+    // needs one read of the count at its end and no other host round trip.
+    int ni = (int)iact.size();
+    int* F = S->list_f.as<int>();
+    int* cnt = S->m_cnt.as<int>();
+    if (ni > 0) {
+      HIPOK(hipMemcpyAsync(F, iact.data(), ni * sizeof(int), hipMemcpyHostToDevice, st));
+      launch_set_int(cnt, ni, st);
+    }
+    int cap = ni;  // the grids' bound: the count at the last poll
     int it = 0;
-    while (!iact.empty() && it < max_inner) {
-      const int ni = (int)iact.size();
-      HIPOK(hipMemcpyAsync(S->list_f.p, iact.data(), ni * sizeof(int), hipMemcpyHostToDevice, st));
-      const int* F = S->list_f.as<int>();
-      const int nsteps = std::min(check_every, max_inner - it);
-      CHECKED(run_steps(S, nsteps, use_graph && (it > 0 || outer > 0), [&]() -> int {
+    while (ni > 0 && it < max_inner) {
+      const int nsteps = S->prof_on ? 1 : std::min(check_every, max_inner - it);
+      S->live = cnt;
+      const int rc = run_steps(S, nsteps, use_graph && (it > 0 || outer > 0), [&]() -> int {
         if (projected) {
-          CHECKED(apply_hproj32_rows(S, c32.p, c32.q, F, ni, cs.eps));
+          CHECKED(apply_hproj32_rows(S, c32.p, c32.q, F, cap, cs.eps));
         } else {
-          CHECKED(apply_h32_rows(S, c32.p, c32.q, F, ni, cs.eps));
-          CHECKED(apply_psi32_rows(S, c32.p, c32.q, F, ni, (float)S->alpha_pv));
+          CHECKED(apply_h32_rows(S, c32.p, c32.q, F, cap, cs.eps));
+          CHECKED(apply_psi32_rows(S, c32.p, c32.q, F, cap, (float)S->alpha_pv));
         }
-        CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 7.0, 0.0,
-                      [&] { launch_cg32_alpha(c32, F, ni, inner_tol * inner_tol, st); }));
+        CHECKED(timed(S, STERN_K_CG32, vec32 * cap * 7.0, 0.0,
+                      [&] { launch_cg32_alpha(c32, F, cap, inner_tol * inner_tol, st, cnt); }));
         if (projected)  // p = P_c z + beta p
-          CHECKED(apply_pc32_update(S, c32.z, c32.p, c32.beta, F, ni));
+          CHECKED(apply_pc32_update(S, c32.z, c32.p, c32.beta, F, cap));
         else
-          CHECKED(timed(S, STERN_K_CG32, vec32 * ni * 3.0, 0.0, [&] { launch_cg32_beta(c32, F, ni, st); }));
+          CHECKED(timed(S, STERN_K_CG32, vec32 * cap * 3.0, 0.0, [&] { launch_cg32_beta(c32, F, cap, st, cnt); }));
+        CHECKED(timed(S, STERN_K_OTHER, 8.0 * cap, 0.0, [&] { launch_compact(F, cnt, c32.flag, st); }));
         return 0;
-      }));
+      });
+      S->live = nullptr;
+      CHECKED(rc);
       it += nsteps;
       CHECKED(launch_check());
-      HIPOK(hipMemcpyAsync(h_iflag.data(), c32.flag, ns32 * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipMemcpyAsync(&ni, cnt, sizeof(int), hipMemcpyDeviceToHost, st));
       HIPOK(hipStreamSynchronize(st));
-      std::vector<int> nxt;
-      for (int s : iact)
-        if (h_iflag[s] == 0) nxt.push_back(s);
-      iact.swap(nxt);
+      cap = std::min(cap, ni);
     }
     // FP64 update, re-orthogonalisation and true residual
     CHECKED(timed(S, STERN_K_CG, na * (2.0 * vecb + vec32), 0.0, [&] { launch_add_d(cs.x, c32.d, K, L, na, st); }));
