@@ -185,7 +185,7 @@ def large_entry(args, dev):
     from synth.cells import LARGE
     from synth.ground_gpu import large_workload
     log("large cell: ground state on the GPU (Chebyshev-filtered subspace iteration on the library's H)")
-    wl = large_workload(LARGE, n_pert=8)
+    wl = large_workload(LARGE, n_pert=8, verbose=True)  # a line per pass on stderr
     log(f"ground state: {wl['passes']} passes, {wl['wall_s']:.1f} s, gap {wl['gap']:.2e} Ha, "
         f"max eigen-residual {wl['resid'].max():.2e}")
     s = wl["system"]

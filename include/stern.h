@@ -379,8 +379,8 @@ int stern_model_fit_step(stern_model* m, int Nc, int n, const float* in, const f
  *                        for; 0 = built-in default (2048)
  *   STERN_TUNE_GEMM16_WG the same for the split-BF16 reduces; 0 = default (512)
  *   STERN_TUNE_GEMM16_EXPAND tile of the split-BF16 expand (Y += Psi C, B D P):
- *                        0 = 256 x 128 per workgroup, 1 = 128 x 128 (two per CU),
- *                        2 = 256 x 64 (two per CU) */
+ *                        0 = 256 x 128 per workgroup of 8 waves, 1 = 128 x 128 of
+ *                        16 waves, 2 = 128 x 128 of 8 waves */
 #define STERN_TUNE_PLANE64 0
 #define STERN_TUNE_PLANE32 1
 #define STERN_TUNE_GEMM64_WG 2

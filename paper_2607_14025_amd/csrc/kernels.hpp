@@ -207,8 +207,9 @@ void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z
                         int ncols, int K, Z32* cpart, int nsplit, hipStream_t st, const int* live = nullptr);
 void launch_sum_parts32(const Z32* cpart, int nsplit, int ncols, int M_pad, float scale, __bf16* Cs,
                         hipStream_t st, const int* live = nullptr);
-// Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A
-// Y += A C for the split-BF16 operands; variant 0: 256 x 128 tiles, 1: 128 x 128 tiles.
+// Y[yidx[n]][k] += sum_m A[m][k] C[n][m] from the transposed split copy of A (blocked
+// layout, as k_split_rows writes it) and C as launch_sum_parts32 / launch_sum_proj32 write it;
+// variant 0: 256 x 128 tiles of 8 waves, 1: 128 x 128 tiles of 16 waves, 2: 128 x 128 tiles of 8 waves.
 // With P: Y is not written, P[s] = (Y[s] + A C) + beta[s] P[s] for s = yidx[n] instead.
 void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const __bf16* Cs, Z32* Y, int ldy,
                         const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P = nullptr,

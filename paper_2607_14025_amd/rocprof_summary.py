@@ -14,6 +14,10 @@
       bytes for them; the ratio measured / algorithmic goes to TRAFFIC_JSON under
       "WORKLOAD:LABEL", with the source hash bench.py checks.
 
+  python3 -m paper_2607_14025_amd.rocprof_summary sq CSV TITLE COMMAND KERNEL > summary.md
+      SQ counters (VALU, SALU, LDS instructions and issue cycles, LDS bank conflicts, wave cycles)
+      of one kernel over the bench's final apply, per-dispatch means and their ratios.
+
   python3 -m paper_2607_14025_amd.rocprof_summary mfma CSV TITLE COMMAND [SIMDS] > summary.md
       MFMA use of the GEMM and net kernels from one --pmc run with SQ_INSTS_VALU_MFMA_MOPS_BF16,
       SQ_INSTS_VALU_MFMA_MOPS_F64, SQ_VALU_MFMA_BUSY_CYCLES and GRBM_GUI_ACTIVE over the bench's
@@ -43,6 +47,11 @@ KERNEL_SOURCES = {"plane_h": "fft.hip", "plane_h32": "fft.hip", "xinv": "fft.hip
                   "pc_expand": "gemm.hip", "kb_reduce": "gemm.hip", "kb_expand": "gemm.hip",
                   "sum_parts": "gemm.hip", "cg": "cg.hip", "cg32": "cg.hip", "gemm_bf16": "gemm_bf16.hip",
                   "net": "learn.hip"}
+
+# what the bench's algorithmic bytes per launch count, per kernel class
+ALGO_NOTE = {"plane_h32": "pencils read and written once, V_loc once",
+             "plane_h": "pencils read and written once, V_loc once",
+             "gemm_bf16": "the complex FP32 vectors and the projector block moved once each"}
 
 
 def source_hash(label: str) -> str:
@@ -186,7 +195,7 @@ def traffic(fetch_csv, write_csv, bench_log, label, kernel, title, cmd_f, cmd_w,
         f"| FETCH_SIZE {f['kib']:.0f} KiB, calibrated | {f['bytes'] / 1e6:.1f} MB |",
         f"| WRITE_SIZE {w['kib']:.0f} KiB, calibrated | {w['bytes'] / 1e6:.1f} MB |",
         f"| measured total | {measured / 1e6:.1f} MB |",
-        f"| algorithmic (pencils read and written once, V_loc once) | {algo / 1e6:.1f} MB |",
+        f"| algorithmic ({ALGO_NOTE.get(label, 'the bench bytes per launch')}) | {algo / 1e6:.1f} MB |",
         f"| measured / algorithmic | {ratio:.3f} |\n",
         f"Source `paper_2607_14025_amd/csrc/{KERNEL_SOURCES.get(label)}` sha1 prefix at measurement: {sha}\n",
         "All kernels of the run with more than 100 MB of traffic in total (calibrated, per dispatch). The counters "
@@ -255,6 +264,45 @@ def mfma(csv_path: str, title: str, cmd: str, simds: int = 1024, xcds: int = 8, 
     ] + rows) + "\n"
 
 
+def sq(csv_path: str, title: str, cmd: str, kernel: str) -> str:
+    """SQ counters of one kernel over the bench's final apply (the dispatches after the last but one
+    Delta n launch): per-dispatch means and the ratios that say what bounds it."""
+    per = {}
+    with open(csv_path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            d = per.setdefault(int(r["Dispatch_Id"]), {"name": r["Kernel_Name"]})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    order = sorted(per)
+    dn = [i for i in order if short_name(per[i]["name"]).startswith("k_plane_dn")]
+    if len(dn) < 2:
+        raise SystemExit(f"{csv_path}: fewer than two Delta n dispatches")
+    mine = [per[i] for i in order if dn[-2] < i <= dn[-1] and matches(kernel, per[i]["name"])]
+    if not mine:
+        raise SystemExit(f"{csv_path}: no dispatch of {kernel} in the final apply")
+    names = sorted(k for k in mine[0] if k != "name")
+    mean = {k: sum(d.get(k, 0.0) for d in mine) / len(mine) for k in names}
+    rows = ["| counter | mean per dispatch |", "|---|---:|"] + [f"| {k} | {mean[k]:.4g} |" for k in names]
+    notes = []
+    if mean.get("SQ_ACTIVE_INST_LDS"):
+        notes.append(f"LDS bank-conflict cycles per LDS-active cycle: "
+                     f"{mean.get('SQ_LDS_BANK_CONFLICT', 0.0) / mean['SQ_ACTIVE_INST_LDS']:.3f}")
+    if mean.get("SQ_INSTS_VALU"):
+        notes.append(f"SALU / VALU instructions: {mean.get('SQ_INSTS_SALU', 0.0) / mean['SQ_INSTS_VALU']:.3f}; "
+                     f"LDS / VALU instructions: {mean.get('SQ_INSTS_LDS', 0.0) / mean['SQ_INSTS_VALU']:.3f}")
+    if mean.get("SQ_WAVE_CYCLES"):
+        notes.append(f"VALU-issue cycles per wave cycle: "
+                     f"{mean.get('SQ_ACTIVE_INST_VALU', 0.0) / mean['SQ_WAVE_CYCLES']:.3f}; LDS-issue cycles per "
+                     f"wave cycle: {mean.get('SQ_ACTIVE_INST_LDS', 0.0) / mean['SQ_WAVE_CYCLES']:.3f}")
+    return "\n".join([
+        f"# {title}\n",
+        "Command (repository root, one MI355X, TMPDIR=/tmp):\n",
+        f"```\n{cmd}\n```\n",
+        f"`{kernel}`: {len(mine)} dispatches in the bench's final apply (between the last two Delta n launches). "
+        "SQ counters are summed over the shader engines by rocprofv3; the *_CYCLES counters count in units of "
+        "quad-cycles per the counter definitions, and their ratios compare like with like.\n",
+    ] + rows + [""] + [f"- {n}" for n in notes]) + "\n"
+
+
 def main(argv):
     if len(argv) >= 4 and argv[0] == "stats":
         sys.stdout.write(stats(argv[1], argv[2], argv[3]))
@@ -262,6 +310,8 @@ def main(argv):
             sys.stdout.write("\n" + launch_agreement(argv[1], argv[4], argv[5], argv[6]))
     elif len(argv) >= 9 and argv[0] == "traffic":
         sys.stdout.write(traffic(*argv[1:10]))
+    elif len(argv) >= 5 and argv[0] == "sq":
+        sys.stdout.write(sq(argv[1], argv[2], argv[3], argv[4]))
     elif len(argv) >= 4 and argv[0] == "mfma":
         sys.stdout.write(mfma(argv[1], argv[2], argv[3], *([int(argv[4])] if len(argv) > 4 else [])))
     else:

@@ -22,6 +22,7 @@ prepares inputs, like ground.py.
 from __future__ import annotations
 
 import math
+import sys
 import time
 
 import numpy as np
@@ -115,7 +116,7 @@ def chebyshev_eigs(apply_h, X, want: int, tol: float, degree: int = 20, max_pass
         if verbose:
             print(f"  chebyshev pass {passes}: max residual of the lowest {want} {res.max():.2e} "
                   f"(theta {th[0]:.4f} .. {th[-1]:.4f}, bound {b:.3f}), {time.perf_counter() - t0:.1f} s",
-                  flush=True)
+                  file=sys.stderr, flush=True)
         if res.max() <= tol:
             break
     return th, X, res, passes
@@ -157,7 +158,7 @@ def ground_state_gpu(spec: CellSpec, tol: float = 1e-9, buffer: int | None = Non
                         eps_lumo=float(th[sp.n_occ]), gap=gap, resid=res[:sp.n_occ].copy(), N=N, system=sysm,
                         passes=passes, wall_s=time.perf_counter() - t0)
         if verbose:
-            print(f"  gap {gap:.2e} < 1e-4 Ha, reseeding", flush=True)
+            print(f"  gap {gap:.2e} < 1e-4 Ha, reseeding", file=sys.stderr, flush=True)
         sysm.close()
     raise RuntimeError("no cell with a usable gap")
 
