@@ -478,6 +478,32 @@ struct PlaneWCfg {
   static constexpr int QLD = N + 1 + ((32 - (N + 1) % 32) + 1) % 32;
   static constexpr int NT = 64 * W;
   static constexpr int MAXZ = (ZR * RM + 63) / 64;         // items per lane in a z stage
+  // Per-wave z scratch: element (row, l) at row ZR + l plus a skew of ZR per group of R1
+  // rows (layout A, written by inverse stage 1) or of R2 rows (layout B, written by the
+  // middle stage). The writes of a stage put lanes R1 (or R2) rows apart, which without
+  // the skew is a multiple of the bank count; the reads of the next stage take
+  // consecutive rows of a group and stay contiguous.
+  static constexpr int SWS = N * ZR + (N / (R1 < R2 ? R1 : R2)) * ZR;  // elements per wave
+  __device__ static constexpr int swa(int row, int l) { return row * ZR + l + (row / R1) * ZR; }
+  __device__ static constexpr int swb(int row, int l) { return row * ZR + l + (row / R2) * ZR; }
+};
+
+// Waves per workgroup and z rows per round of the compact plane kernel. By default
+// 4 waves and ZR = 64 / max(R1, R2) rows, so the middle z stage fills the lanes; when
+// both radices are multiples of 8 (N = 128: 16 x 8), ZR = 64 / min(R1, R2) fills the
+// lanes of the two outer stages as well, with 8 waves to keep two per SIMD, if that
+// fits in LDS for the largest set of active z lines a grid of this size can have.
+template <int N, class T>
+struct PlaneShape {
+  static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
+  static constexpr int RM = R1 > R2 ? R1 : R2, RMIN = R1 < R2 ? R1 : R2;
+  static constexpr int ZR0 = RM >= 64 ? 1 : 64 / RM, ZRW = 64 / RMIN;
+  static constexpr int NZA_MAX = 2 * ((N - 1) / 4) + 1;
+  static constexpr size_t wide_lds =
+      ((size_t)NZA_MAX * PlaneWCfg<N, T, 8, ZRW>::QLD + N + 8 * (size_t)PlaneWCfg<N, T, 8, ZRW>::SWS) * sizeof(Z<T>);
+  static constexpr bool wide = R1 % 8 == 0 && R2 % 8 == 0 && RM < 64 && ZRW > ZR0 && wide_lds <= 160 * 1024;
+  static constexpr int W = wide ? 8 : 4;
+  static constexpr int ZR = wide ? ZRW : ZR0;
 };
 
 // Indices [lo, hi] of a y or z transform that no sphere function reaches on any grid
@@ -492,7 +518,7 @@ __device__ constexpr bool idle_range(int lo, int hi) {
 
 template <int N, class T, int W, int ZR>
 constexpr size_t planew_lds_bytes(int nza) {
-  return ((size_t)nza * PlaneWCfg<N, T, W, ZR>::QLD + N + (size_t)W * N * ZR) * sizeof(Z<T>);
+  return ((size_t)nza * PlaneWCfg<N, T, W, ZR>::QLD + N + (size_t)W * PlaneWCfg<N, T, W, ZR>::SWS) * sizeof(Z<T>);
 }
 
 // orders the LDS accesses of one wave: stores above, loads below
@@ -512,7 +538,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   Z<T>* Q = reinterpret_cast<Z<T>*>(smem_raw);
   Z<T>* tw = Q + (size_t)nza * QLD;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  Z<T>* Sw = tw + N + (size_t)wave * N * ZR;
+  Z<T>* Sw = tw + N + (size_t)wave * C::SWS;
   {
     const Z<T>* src = twtab<T>(g);
     for (int i = tid; i < N; i += C::NT) tw[i] = src[i];
@@ -616,7 +642,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
         }
         dft<R1, +1>(v);
 #pragma unroll
-        for (int r = 0; r < R1; ++r) Sw[(j * R1 + r) * ZR + l] = v[r];
+        for (int r = 0; r < R1; ++r) Sw[C::swa(j * R1 + r, l)] = v[r];
       }
       wave_sync();
       // inverse stage 2 (radix R2), x V, forward stage 1 of the reversed plan (radix R2)
@@ -628,7 +654,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
           const int l = it % ZR, j = it / ZR;
           if (it < ZR * R1 && l < nz) {
 #pragma unroll
-            for (int r = 0; r < R2; ++r) v[k][r] = Sw[(j + r * R1) * ZR + l];
+            for (int r = 0; r < R2; ++r) v[k][r] = Sw[C::swa(j + r * R1, l)];
           }
         }
         wave_sync();
@@ -645,7 +671,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
               v[k][r] = zscale(v[k][r], PF ? vreg[k][r] : vx[(size_t)(j + r * R1) * N + y0 + l]);
             dft<R2, -1>(v[k]);
 #pragma unroll
-            for (int r = 0; r < R2; ++r) Sw[(j * R2 + r) * ZR + l] = v[k][r];
+            for (int r = 0; r < R2; ++r) Sw[C::swb(j * R2 + r, l)] = v[k][r];
           }
         }
       }
@@ -656,7 +682,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
         if (l >= nz) continue;
         Z<T> v[R1];
 #pragma unroll
-        for (int r = 0; r < R1; ++r) v[r] = Sw[(j + r * R2) * ZR + l];
+        for (int r = 0; r < R1; ++r) v[r] = Sw[C::swb(j + r * R2, l)];
 #pragma unroll
         for (int r = 1; r < R1; ++r) v[r] = v[r] * twid<-1>(tw, r * j);
         dft<R1, -1>(v);
@@ -1262,9 +1288,7 @@ int blocks_per_cu(const void* kernel, int nt, size_t lds) {
 
 template <int NN, class T, bool PF>
 void launch_plane_hw_n(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, const T* vt, hipStream_t st) {
-  constexpr int W = 4;
-  constexpr int RM = PlaneWCfg<NN, T, W, 1>::RM;
-  constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
+  constexpr int W = PlaneShape<NN, T>::W, ZR = PlaneShape<NN, T>::ZR;
   const size_t lds = planew_lds_bytes<NN, T, W, ZR>(g.nza);
   const void* kp = (const void*)k_plane_hw<NN, T, W, ZR, PF>;
   const int per_cu = blocks_per_cu(kp, 64 * W, lds);
@@ -1289,9 +1313,10 @@ void launch_plane_hw(const FftGeom& g, Z<T>* pen, const int* vidx, int nvec, con
 size_t plane_hw_lds(int N, int nza, bool fp64) {
   size_t r = 0;
   STERN_DISPATCH_N(N, ({
-                     constexpr int RM = PlaneWCfg<NN, double, 4, 1>::RM;
-                     constexpr int ZR = RM >= 64 ? 1 : 64 / RM;
-                     r = fp64 ? planew_lds_bytes<NN, double, 4, ZR>(nza) : planew_lds_bytes<NN, float, 4, ZR>(nza);
+                     using S64 = PlaneShape<NN, double>;
+                     using S32 = PlaneShape<NN, float>;
+                     r = fp64 ? planew_lds_bytes<NN, double, S64::W, S64::ZR>(nza)
+                              : planew_lds_bytes<NN, float, S32::W, S32::ZR>(nza);
                    }));
   return r;
 }
