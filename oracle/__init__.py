@@ -23,6 +23,9 @@ Modules:
   closed_form  sum over all empty states, finite field, free-electron Lindhard sum
   net          one training step of the learned-start net (forward, loss, gradients, Adam)
                in float64 over BF16-rounded values, for checking the net's kernels
+  pdep         dense symmetrised response chi-bar0 in the real potential basis (PDEP)
+  frequency    the response at imaginary frequency i u: sum over states, dense shifted
+               solve, free-electron Lindhard sum at i u, residual of the shifted system
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: a brute-force lattice count, the real-space Gaussian sum, the dense
