@@ -133,6 +133,15 @@ typedef struct {
   const struct stern_model* model;
   /* STERN_MIXED only: operator of the inner solve, one of STERN_INNER_* (0 = projected) */
   int inner_op;
+  /* u >= 0: the response at imaginary frequency i u (Sec. II.A: the self-energy is evaluated at
+     many frequencies, Lanczos chains and full frequency, which need chi0 beyond zero frequency).
+     u > 0 solves (P_c (H - eps_v) P_c - i u) x = -P_c dV_i psi_v by conjugate orthogonal CG with
+     the bilinear form sum_G a(-G) b(G), in which the shifted operator is symmetric, and returns
+     dn_i = 4 Re sum_v conj(psi_v) x_{v,i}: for a real field the two frequency terms of chi0(i u)
+     are complex conjugates of each other, so one shifted solve per pair gives the real chi0(i u).
+     FP64 with Teter's preconditioner and a zero start only (STERN_ERR_UNSUPPORTED otherwise);
+     0 = the static response. */
+  double omega_imag;
 } stern_opts;
 
 /* Inner operators of the mixed solve (stern_opts.inner_op). The FP64 outer

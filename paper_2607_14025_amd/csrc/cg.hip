@@ -622,7 +622,160 @@ __global__ void k_fill_zero32(Z32* __restrict__ p, size_t n) {
     p[i] = zmk(0.f, 0.f);
 }
 
+// ---- conjugate orthogonal CG for the shifted systems of the response at imaginary frequency ----
+//
+// (P_c (H - eps_v) P_c - i u) x = b on range(P_c). The shifted operator is not Hermitian, but it
+// is symmetric in the bilinear form (a, b)_J = sum_G a(-G) b(G): H commutes with the map
+// a(G) -> conj a(-G) (a real local potential and projectors whose radial parts are real), so
+// does the projector on a complete occupied subspace of such an H, and so do the identity and
+// a preconditioner that depends on |G| only; an operator that commutes with that map is
+// symmetric in (., .)_J. Conjugate orthogonal CG (van der Vorst and Melissen, IEEE Trans. Magn.
+// 26, 706 (1990)) is CG with (., .)_J in place of the inner product: one operator apply per
+// iteration and complex scalars. negk[k] is the index of -G for the coefficient k (column
+// order; the padding maps to itself). The complex rho = (r, z)_J of solve s is (rz[s], rzi[s]).
+
+__device__ __forceinline__ Z64 block_sum_z(Z64 v, double* sh) {
+  const double re = block_sum(v.re, sh);
+  const double im = block_sum(v.im, sh);
+  return zmk(re, im);
+}
+__device__ __forceinline__ Z64 zdiv(Z64 a, Z64 b) {
+  const double d = b.re * b.re + b.im * b.im;
+  return zmk((a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d);
+}
+
+// p = z; rho = (r, z)_J, for solves whose flag equals `from` (0: start, 3: restart); flag -> 0
+__global__ __launch_bounds__(kCgThreads) void k_cocg_start(CgState S, const int* __restrict__ negk,
+                                                           double* __restrict__ rzi, const int* __restrict__ act,
+                                                           int from) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != from) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  Z64 rz = zmk(0.0, 0.0);
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 r = S.r[o + negk[k]], z = S.z[o + k];
+    rz = rz + r * z;
+    S.p[o + k] = z;
+  }
+  rz = block_sum_z(rz, sh);
+  if (threadIdx.x == 0) {
+    S.rz[s] = rz.re;
+    rzi[s] = rz.im;
+    S.flag[s] = 0;
+  }
+}
+
+// q holds P_c (H - eps) P_c p; with qs = q - i u p: alpha = rho / (p, qs)_J; x += alpha p;
+// r -= alpha qs; z = K r; flag 1 on ||r|| <= tol ||b|| (or a vanishing (p, qs)_J)
+template <bool LK>
+__global__ __launch_bounds__(kCgThreads) void k_cocg_alpha(CgState S, const int* __restrict__ negk,
+                                                           const double* __restrict__ rzi, double u,
+                                                           const int* __restrict__ act, double tol2) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  const int n = S.npw_pad;
+  Z64 pq = zmk(0.0, 0.0);
+  for (int k = threadIdx.x; k < n; k += kCgThreads) {
+    const Z64 p = S.p[o + k], q = S.q[o + k], pm = S.p[o + negk[k]];
+    pq = pq + pm * zmk(q.re + u * p.im, q.im - u * p.re);  // q - i u p
+  }
+  pq = block_sum_z(pq, sh);
+  const bool ok = pq.re != 0.0 || pq.im != 0.0;
+  const Z64 alpha = ok ? zdiv(zmk(S.rz[s], rzi[s]), pq) : zmk(0.0, 0.0);
+  const double iT = S.invT[s];
+  double rr = 0.0;
+  for (int k = threadIdx.x; k < n; k += kCgThreads) {
+    const Z64 p = S.p[o + k], q = S.q[o + k];
+    const Z64 qs = zmk(q.re + u * p.im, q.im - u * p.re);
+    const Z64 xn = S.x[o + k] + alpha * p;
+    const Z64 rn = S.r[o + k] - alpha * qs;
+    S.x[o + k] = xn;
+    S.r[o + k] = rn;
+    rr += rn.re * rn.re + rn.im * rn.im;
+    S.z[o + k] = zscale(rn, precond_eval<LK>(precond_load<LK>(S, s, k), iT));
+  }
+  rr = block_sum(rr, sh);
+  if (threadIdx.x == 0) {
+    S.rr[s] = rr;
+    S.iters[s] += 1;
+    if (rr <= tol2 * S.bb[s] || !ok) S.flag[s] = 1;
+  }
+}
+
+// beta = (r, z)_J new / old; p = z + beta p
+__global__ __launch_bounds__(kCgThreads) void k_cocg_beta(CgState S, const int* __restrict__ negk,
+                                                          double* __restrict__ rzi, const int* __restrict__ act) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 0) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  const int n = S.npw_pad;
+  Z64 rz = zmk(0.0, 0.0);
+  for (int k = threadIdx.x; k < n; k += kCgThreads) rz = rz + S.r[o + negk[k]] * S.z[o + k];
+  rz = block_sum_z(rz, sh);
+  const Z64 beta = zdiv(rz, zmk(S.rz[s], rzi[s]));
+  for (int k = threadIdx.x; k < n; k += kCgThreads) S.p[o + k] = S.z[o + k] + beta * S.p[o + k];
+  if (threadIdx.x == 0) {
+    S.rz[s] = rz.re;
+    rzi[s] = rz.im;
+  }
+}
+
+// For solves with flag 1: z holds P_c x and q holds P_c (H - eps) P_c x. The true residual
+// b - (q - i u z) is accepted (flag 2) or becomes the new r with z = K r (flag 3: restart)
+__global__ __launch_bounds__(kCgThreads) void k_cocg_true(CgState S, double u, const int* __restrict__ act,
+                                                          double tol) {
+  __shared__ double sh[kCgThreads / 64];
+  const int s = act ? act[blockIdx.x] : blockIdx.x;
+  if (S.flag[s] != 1) return;
+  const size_t o = (size_t)s * S.npw_pad;
+  double tt = 0.0;
+  for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+    const Z64 b = S.b[o + k], q = S.q[o + k], x = S.z[o + k];
+    const double re = b.re - q.re - u * x.im, im = b.im - q.im + u * x.re;
+    tt += re * re + im * im;
+  }
+  tt = block_sum(tt, sh);
+  const double bb = S.bb[s];
+  const bool ok = tt <= tol * tol * bb;
+  if (!ok) {
+    const double iT = S.invT[s];
+    for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
+      const Z64 b = S.b[o + k], q = S.q[o + k], x = S.z[o + k];
+      const Z64 r = zmk(b.re - q.re - u * x.im, b.im - q.im + u * x.re);
+      S.r[o + k] = r;
+      S.z[o + k] = zscale(r, precond(S, s, k, iT));
+    }
+  }
+  if (threadIdx.x == 0) {
+    S.tres[s] = sqrt(tt / bb);
+    S.flag[s] = ok ? 2 : 3;
+  }
+}
+
 }  // namespace
+
+void launch_cocg_start(const CgState& s, const int* negk, double* rzi, const int* act, int n, int from,
+                       hipStream_t st) {
+  if (n > 0) k_cocg_start<<<n, kCgThreads, 0, st>>>(s, negk, rzi, act, from);
+}
+void launch_cocg_alpha(const CgState& s, const int* negk, const double* rzi, double u, const int* act, int n,
+                       double tol2, hipStream_t st) {
+  if (n <= 0) return;
+  if (s.kprec)
+    k_cocg_alpha<true><<<n, kCgThreads, 0, st>>>(s, negk, rzi, u, act, tol2);
+  else
+    k_cocg_alpha<false><<<n, kCgThreads, 0, st>>>(s, negk, rzi, u, act, tol2);
+}
+void launch_cocg_beta(const CgState& s, const int* negk, double* rzi, const int* act, int n, hipStream_t st) {
+  if (n > 0) k_cocg_beta<<<n, kCgThreads, 0, st>>>(s, negk, rzi, act);
+}
+void launch_cocg_true(const CgState& s, double u, const int* act, int n, double tol, hipStream_t st) {
+  if (n > 0) k_cocg_true<<<n, kCgThreads, 0, st>>>(s, u, act, tol);
+}
 
 void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st) {
   if (n > 0) k_cg_init<<<n, kCgThreads, 0, st>>>(s, act, keep ? 1 : 0);

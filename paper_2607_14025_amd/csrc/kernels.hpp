@@ -108,6 +108,17 @@ void launch_cg_beta(const CgState& s, const int* act, int n, hipStream_t st);
 void launch_copy_rows(const Z64* src, Z64* dst, int ld, const int* act, int n, hipStream_t st);
 void launch_true_resid(const CgState& s, const int* act, int n, double tol, hipStream_t st);
 void launch_cg_restart(const CgState& s, const int* act, int n, hipStream_t st);
+// Conjugate orthogonal CG for (P_c (H - eps) P_c - i u) x = b (response at imaginary frequency):
+// negk [npw_pad] the index of -G of each coefficient; rzi [nbatch] the imaginary parts of the
+// per-solve (r, z)_J (real parts in CgState::rz). start: p = z, rho = (r, z)_J for the solves with
+// flag `from` (0 or 3), flag -> 0. alpha: q = P_c (H - eps) P_c p given. true: z = P_c x and
+// q = P_c (H - eps) P_c x given, flag 1 -> 2 (accepted) or 3 (restart from the true residual).
+void launch_cocg_start(const CgState& s, const int* negk, double* rzi, const int* act, int n, int from,
+                       hipStream_t st);
+void launch_cocg_alpha(const CgState& s, const int* negk, const double* rzi, double u, const int* act, int n,
+                       double tol2, hipStream_t st);
+void launch_cocg_beta(const CgState& s, const int* negk, double* rzi, const int* act, int n, hipStream_t st);
+void launch_cocg_true(const CgState& s, double u, const int* act, int n, double tol, hipStream_t st);
 // permutations between canonical and column order: out[v][perm[k]] = in[v][k] (scatter) or gather
 void launch_permute(const Z64* in, int ld_in, Z64* out, int ld_out, const int* perm, int npw, int nvec, bool scatter,
                     hipStream_t st);

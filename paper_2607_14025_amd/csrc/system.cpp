@@ -1,12 +1,14 @@
 // C ABI of the Sternheimer chi0 library: system setup, occupied states, the
 // batched projected-PCG driver and the density response.
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <numeric>
 #include <mutex>
 #include <random>
@@ -175,6 +177,8 @@ struct stern_system {
       sv_iters, sv_tres, list_act, list_f, pert_out, dv_dev, dn_dev, tmp_in, tmp_out;
   DBuf m_d, m_r, m_p, m_q, m_z, m_rz, m_rr0, m_beta, m_flag;  // mixed inner solve
   DBuf m_cnt;                 // device count of the inner solve's active list (list_f)
+  DBuf negk;                  // [npw_pad] index of -G of each coefficient (column order)
+  DBuf sv_rzi;                // [nbatch] imaginary parts of the shifted solves' (r, z)_J
   const int* live = nullptr;  // while set, FP32 launches cover only the first *live list entries
   // coarse (N/2)^3 grid of the learned guess, when it holds the sphere
   bool have_coarse = false;
@@ -251,7 +255,7 @@ struct stern_system {
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
-                   &band_feat, &projT_hi, &projT_lo, &proj_g, &cpart2, &m_cnt};
+                   &band_feat, &projT_hi, &projT_lo, &proj_g, &cpart2, &m_cnt, &negk, &sv_rzi};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -529,7 +533,7 @@ int ensure_workspace(stern_system* S, int ns) {
                                    cpart_capacity(S, S->natoms_pad, ns, (int)K))));
   CHECKED(S->cmat.ensure((size_t)ns * mp * sizeof(Z64)));
   CHECKED(S->cpart2.ensure(cpart_capacity(S, std::max(S->nocc_pad, 64), ns, (int)K)));
-  for (DBuf* d : {&S->sv_eps, &S->sv_invT, &S->sv_bb, &S->sv_rz, &S->sv_rr, &S->sv_tres})
+  for (DBuf* d : {&S->sv_eps, &S->sv_invT, &S->sv_bb, &S->sv_rz, &S->sv_rr, &S->sv_tres, &S->sv_rzi})
     CHECKED(d->ensure((size_t)ns * sizeof(double)));
   for (DBuf* d : {&S->sv_band, &S->sv_pert, &S->sv_flag, &S->sv_iters, &S->list_act, &S->list_f})
     CHECKED(d->ensure((size_t)ns * sizeof(int)));
@@ -893,6 +897,84 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
   return 0;
 }
 
+// Response at imaginary frequency i u: (P_c (H - eps_v) P_c - i u) x = b by preconditioned
+// conjugate orthogonal CG in FP64 (the shifted operator is symmetric in (a, b)_J =
+// sum_G a(-G) b(G); see the kernels). Same structure as run_pcg64: per-solve flags, the active
+// list compacted every check_every iterations, the FP64 true residual of the shifted system at
+// recurrence convergence, restart from it when it fails.
+int run_cocg64(stern_system* S, const CgState& cs, const std::vector<int>& list, double u, double tol, int max_iter,
+               int check_every, int& n_restart, double vecb) {
+  hipStream_t st = S->stream;
+  const int ns_all = S->ws_solves;
+  const int* negk = S->negk.as<int>();
+  double* rzi = S->sv_rzi.as<double>();
+  std::vector<int> h_flag(ns_all), act, flist;
+  if (list.empty()) return 0;
+  const int n0 = (int)list.size();
+  HIPOK(hipMemcpyAsync(S->list_act.p, list.data(), n0 * sizeof(int), hipMemcpyHostToDevice, st));
+  {
+    const int* L = S->list_act.as<int>();
+    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 4.0, 0.0, [&] { launch_cg_init(cs, L, n0, false, st); }));
+    CHECKED(apply_pc_rows(S, cs.z, L, n0));
+    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 3.0, 0.0, [&] { launch_cocg_start(cs, negk, rzi, L, n0, 0, st); }));
+  }
+  CHECKED(launch_check());
+  HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  for (int s : list)
+    if (h_flag[s] == 0) act.push_back(s);
+  int it = 0;
+  while (!act.empty()) {
+    const int na = (int)act.size();
+    HIPOK(hipMemcpyAsync(S->list_act.p, act.data(), na * sizeof(int), hipMemcpyHostToDevice, st));
+    const int* L = S->list_act.as<int>();
+    const int nsteps = std::min(check_every, max_iter - it);
+    for (int k = 0; k < nsteps; ++k) {
+      CHECKED(apply_h_rows(S, cs.p, cs.q, L, na, cs.eps));
+      CHECKED(apply_pc_rows(S, cs.q, L, na));
+      CHECKED(timed(S, STERN_K_CG, vecb * na * 8.0, 0.0,
+                    [&] { launch_cocg_alpha(cs, negk, rzi, u, L, na, tol * tol, st); }));
+      CHECKED(apply_pc_rows(S, cs.z, L, na));
+      CHECKED(timed(S, STERN_K_CG, vecb * na * 4.0, 0.0, [&] { launch_cocg_beta(cs, negk, rzi, L, na, st); }));
+    }
+    it += nsteps;
+    CHECKED(launch_check());
+    HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    const bool last = it >= max_iter;
+    flist.clear();
+    for (int s : act)
+      if (h_flag[s] == 1 || last) flist.push_back(s);
+    if (!flist.empty()) {
+      const int nf = (int)flist.size();
+      HIPOK(hipMemcpyAsync(S->list_f.p, flist.data(), nf * sizeof(int), hipMemcpyHostToDevice, st));
+      const int* F = S->list_f.as<int>();
+      if (last) launch_set_flag(cs.flag, F, nf, 1, st);  // final check on everything still running
+      launch_copy_rows(cs.x, cs.z, S->hb.npw_pad, F, nf, st);
+      CHECKED(apply_pc_rows(S, cs.z, F, nf));
+      CHECKED(apply_h_rows(S, cs.z, cs.q, F, nf, cs.eps));
+      CHECKED(apply_pc_rows(S, cs.q, F, nf));
+      launch_cocg_true(cs, u, F, nf, tol, st);
+      if (!last) {
+        CHECKED(apply_pc_rows(S, cs.z, F, nf));
+        launch_cocg_start(cs, negk, rzi, F, nf, 3, st);
+      }
+      CHECKED(launch_check());
+      HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns_all * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      if (!last)
+        for (int s : flist)
+          if (h_flag[s] == 0) ++n_restart;
+    }
+    if (last) break;
+    std::vector<int> nxt;
+    for (int s : act)
+      if (h_flag[s] != 2) nxt.push_back(s);
+    act.swap(nxt);
+  }
+  return 0;
+}
+
 // Mixed precision: FP64 defect correction around FP32/BF16 inner PCG solves.
 //   repeat: solve A d = r to inner_tol with FP32 FFTs and split-BF16 MFMA GEMMs
 //           (FP64 dots and scalars); x += d; x = P_c x (FP64); r = b - A x (FP64)
@@ -1133,6 +1215,20 @@ int stern_init_system(const stern_cell* cell, const stern_runtime* rt, stern_sys
     CHECKED(upload(S->zl, hb.zl.data(), hb.zl.size() * sizeof(int), st));
     CHECKED(upload(S->ycol, hb.ycol.data(), hb.ycol.size() * sizeof(int), st));
     CHECKED(upload(S->g2h, hb.g2h.data(), hb.g2h.size() * sizeof(double), st));
+    {  // -G of every coefficient in column order (the sphere is symmetric under G -> -G)
+      std::map<std::array<int32_t, 3>, int> canon;
+      for (int c = 0; c < hb.npw; ++c)
+        canon[{hb.miller[3 * c], hb.miller[3 * c + 1], hb.miller[3 * c + 2]}] = c;
+      std::vector<int> nk(hb.npw_pad);
+      for (int k = hb.npw; k < hb.npw_pad; ++k) nk[k] = k;
+      for (int c = 0; c < hb.npw; ++c) {
+        const auto it = canon.find({-hb.miller[3 * c], -hb.miller[3 * c + 1], -hb.miller[3 * c + 2]});
+        if (it == canon.end()) return fail(STERN_ERR_UNSUPPORTED, "the sphere is not symmetric under G -> -G");
+        nk[hb.perm[c]] = hb.perm[it->second];
+      }
+      CHECKED(upload(S->negk, nk.data(), nk.size() * sizeof(int), st));
+      HIPOK(hipStreamSynchronize(st));  // nk is released at the end of this block
+    }
     CHECKED(upload(S->perm, hb.perm.data(), hb.perm.size() * sizeof(int), st));
     std::vector<Z64> tw(hb.N);
     for (int m = 0; m < hb.N; ++m) {
@@ -1431,6 +1527,10 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->mem_kind != STERN_MEM_HOST && opts->mem_kind != STERN_MEM_DEVICE)
     return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
   if (!(opts->tol > 0)) return fail(STERN_ERR_INVALID_ARG, "tol must be > 0");
+  const double omega = opts->omega_imag;
+  if (!(omega >= 0.0) || !std::isfinite(omega)) return fail(STERN_ERR_INVALID_ARG, "omega_imag must be finite and >= 0");
+  if (omega > 0.0 && (opts->precision != STERN_FP64 || opts->guess != STERN_GUESS_ZERO))
+    return fail(STERN_ERR_UNSUPPORTED, "the response at imaginary frequency runs in FP64 from a zero start");
   const int v0 = opts->band_begin;
   const int v1 = opts->band_end > 0 ? opts->band_end : S->n_occ;
   if (v0 < 0 || v1 > S->n_occ || v0 >= v1) return fail(STERN_ERR_INVALID_ARG, "bad band range [%d, %d)", v0, v1);
@@ -1507,7 +1607,9 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
       CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected, opts->precision == STERN_MIXED, with_x0));
     std::vector<int> all(ns);
     for (int s = 0; s < ns; ++s) all[s] = s;
-    if (opts->precision == STERN_MIXED) {
+    if (omega > 0.0) {
+      CHECKED(run_cocg64(S, cs, all, omega, tol, max_iter, check_every, n_restart, vecb));
+    } else if (opts->precision == STERN_MIXED) {
       CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
                         use_graph, opts->inner_op));
     } else {

@@ -68,7 +68,7 @@ class Opts(C.Structure):
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
                 ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int), ("use_graph", C.c_int), ("model", C.c_void_p),
-                ("inner_op", C.c_int)]
+                ("inner_op", C.c_int), ("omega_imag", C.c_double)]
 
 
 NKERNEL = 17
@@ -202,8 +202,10 @@ def _torch_stream():
 
 
 def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
-              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False):
+              inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False,
+              omega_imag=0.0):
     o = Opts()
+    o.omega_imag = float(omega_imag)
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
@@ -320,12 +322,13 @@ class System:
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
                    samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False,
-                   model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False):
+                   model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False, omega_imag=0.0):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned.
         model: a trained Model for the learned guess and preconditioner (None: zero guess, Teter);
-        prec_only: with a model, use only its preconditioner (x0 = 0)."""
+        prec_only: with a model, use only its preconditioner (x0 = 0).
+        omega_imag: u > 0 gives chi0(i u) dv, the response at imaginary frequency i u (FP64 only)."""
         n_pert = dv_r.shape[0]
         dp, mk, k1 = _ptr(dv_r, False)
         if dn_out is None:
@@ -338,7 +341,7 @@ class System:
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
         o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
-                      use_graph, model, inner_op, prec_only)
+                      use_graph, model, inner_op, prec_only, omega_imag)
         keep = []
         sx = None
         if samples:
@@ -384,11 +387,14 @@ class System:
         return mil
 
     def pdep_davidson(self, n_eig, tol=1e-6, block=0, max_basis=0, max_iter=0, ecut_pot=0.0, seed=0,
-                      chi0_tol=1e-10, precision=STERN_FP64, model=None, prec_only=False, max_chi0_iter=0):
-        """Lowest eigenpairs of chi-bar0 = v^{1/2} chi0 v^{1/2} (stern_pdep_davidson).
+                      chi0_tol=1e-10, precision=STERN_FP64, model=None, prec_only=False, max_chi0_iter=0,
+                      omega_imag=0.0):
+        """Lowest eigenpairs of chi-bar0 = v^{1/2} chi0 v^{1/2} (stern_pdep_davidson), at imaginary
+        frequency i omega_imag when that is > 0.
         Returns (eigenvalues [n_eig], coefficients [n_eig, n_g] over pdep_basis(ecut_pot), stats dict)."""
         mil = self.pdep_basis(ecut_pot)
-        co = make_opts(chi0_tol, max_chi0_iter, precision, STERN_MEM_DEVICE, model=model, prec_only=prec_only)
+        co = make_opts(chi0_tol, max_chi0_iter, precision, STERN_MEM_DEVICE, model=model, prec_only=prec_only,
+                       omega_imag=omega_imag)
         o = PdepOpts(int(n_eig), int(block), int(max_basis), int(max_iter), float(tol), float(ecut_pot), int(seed),
                      C.pointer(co))
         eig = np.zeros(n_eig)
