@@ -473,9 +473,11 @@ template <int N, class T, int W, int ZR>
 struct PlaneWCfg {
   static constexpr int R1 = Plan<N>::R1, R2 = Plan<N>::R2;
   static constexpr int RM = R1 > R2 ? R1 : R2;
-  // stride of the lines of Q: the smallest value above N that is 1 mod 32, so that lanes
-  // taking consecutive lines (and radix-R1 groups inside a line) fall on different banks
-  static constexpr int QLD = N + 1 + ((32 - (N + 1) % 32) + 1) % 32;
+  // stride of the lines of Q. FP32: the smallest value above N that is 1 mod 32, so that lanes
+  // taking consecutive lines (and radix-R1 groups inside a line) fall on different banks. FP64
+  // (whose lanes take indices within a line): N + 1, which keeps the LDS of the FP64 kernel at
+  // 72^3 within two workgroups per CU.
+  static constexpr int QLD = sizeof(T) == 16 ? N + 1 : N + 1 + ((32 - (N + 1) % 32) + 1) % 32;
   static constexpr int NT = 64 * W;
   static constexpr int MAXZ = (ZR * RM + 63) / 64;         // items per lane in a z stage
   // Per-wave z scratch: element (row, l) at row ZR + l plus a skew of ZR per group of R1
@@ -483,9 +485,13 @@ struct PlaneWCfg {
   // middle stage). The writes of a stage put lanes R1 (or R2) rows apart, which without
   // the skew is a multiple of the bank count; the reads of the next stage take
   // consecutive rows of a group and stay contiguous.
-  static constexpr int SWS = N * ZR + (N / (R1 < R2 ? R1 : R2)) * ZR;  // elements per wave
-  __device__ static constexpr int swa(int row, int l) { return row * ZR + l + (row / R1) * ZR; }
-  __device__ static constexpr int swb(int row, int l) { return row * ZR + l + (row / R2) * ZR; }
+  // Only radices that are powers of two put those lanes a multiple of the bank count apart, and
+  // only for them the skew is a shift; other radices keep the plain layout (a division by 9 in
+  // the index of every scratch access cost the FP64 pass at 72^3 about a third of its speed).
+  static constexpr bool SKEW = (R1 & (R1 - 1)) == 0 && (R2 & (R2 - 1)) == 0;
+  static constexpr int SWS = N * ZR + (SKEW ? (N / (R1 < R2 ? R1 : R2)) * ZR : 0);  // elements per wave
+  __device__ static constexpr int swa(int row, int l) { return row * ZR + l + (SKEW ? (row / R1) * ZR : 0); }
+  __device__ static constexpr int swb(int row, int l) { return row * ZR + l + (SKEW ? (row / R2) * ZR : 0); }
 };
 
 // Waves per workgroup and z rows per round of the compact plane kernel. By default
@@ -550,12 +556,20 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   // this wave's y lines [f0, f0 + nl) and z-pass rows [y0w, y0w + nr)
   const int lpw = (nza + W - 1) / W;
   const int f0 = min(nza, wave * lpw), nl = min(nza, f0 + lpw) - f0;
-  // In the y passes that gather from and scatter to the pencils, consecutive lanes take
-  // consecutive lines: adjacent pencil columns in HBM and rows QLD apart in LDS. Items are
-  // numbered it = (index within the line) << lsh | (line - f0), with 2^lsh >= nl.
+  // In the y passes that gather from and scatter to the pencils, FP32 lanes take consecutive
+  // lines: adjacent pencil columns in HBM and rows QLD apart in LDS (measured on the FP32 pass
+  // at 128^3). Items are numbered it = (index within the line) << lsh | (line - f0), with
+  // 2^lsh >= nl. FP64 lanes take consecutive indices within a line, it = (line - f0) R + index.
+  constexpr bool LINE_FAST = sizeof(T) == 4;
   int lsh = 0;
   while ((1 << lsh) < nl) ++lsh;
   const int lmask = (1 << lsh) - 1;
+  // number of items of a gather or scatter pass whose items are transforms of radix R, and
+  // the (index, line) of item it (a slot with no line when LINE_FAST pads nl to 2^lsh)
+  auto n_items = [&](int R) { return LINE_FAST ? (R << lsh) : nl * R; };
+  auto item_ok = [&](int it) { return !LINE_FAST || (it & lmask) < nl; };
+  auto item_j = [&](int it, int R) { return LINE_FAST ? (it >> lsh) : it % R; };
+  auto item_f = [&](int it, int R) { return f0 + (LINE_FAST ? (it & lmask) : it / R); };
   constexpr int RPW = (N + W - 1) / W;
   const int y0w = min(N, wave * RPW), nr = min(N, y0w + RPW) - y0w;
   const int* __restrict__ yc = g.ycol;
@@ -569,7 +583,7 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
   // the first inverse-y item of this lane (it = lane), loaded one pair ahead
   Z<T> pre[R1];
   auto gather = [&](const Z<T>* tp, int it, Z<T>(&v)[R1]) {
-    const int j = it >> lsh, f = f0 + (it & lmask);
+    const int j = item_j(it, R2), f = item_f(it, R2);
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
       const int y = j + r * R2;
@@ -580,16 +594,16 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       }
     }
   };
-  const bool lane_item = lane < (R2 << lsh) && (lane & lmask) < nl;  // item it = lane exists
+  const bool lane_item = lane < n_items(R2) && item_ok(lane);  // item it = lane exists
   if (PF && blockIdx.x < total && lane_item) gather(pencils(blockIdx.x), lane, pre);
   for (long q = blockIdx.x; q < total; q += gridDim.x) {
     const int ix = (int)(q / nvec);
     Z<T>* tp = pencils(q);
     const T* __restrict__ vx = vt + (size_t)ix * N * N;
     // ---- inverse y on this wave's lines, in place in Q ----
-    for (int it = lane; it < (R2 << lsh); it += 64) {
-      if ((it & lmask) >= nl) continue;
-      const int j = it >> lsh, f = f0 + (it & lmask);
+    for (int it = lane; it < n_items(R2); it += 64) {
+      if (!item_ok(it)) continue;
+      const int j = item_j(it, R2), f = item_f(it, R2);
       Z<T> v[R1];
       if (PF && it == lane) {
 #pragma unroll
@@ -712,9 +726,9 @@ __global__ __launch_bounds__(64 * W) void k_plane_hw(Z<T>* __restrict__ pen, con
       for (int k1 = 0; k1 < R1; ++k1) Q[f * QLD + j + k1 * R2] = v[k1];
     }
     wave_sync();
-    for (int it = lane; it < (R1 << lsh); it += 64) {
-      if ((it & lmask) >= nl) continue;
-      const int k1 = it >> lsh, f = f0 + (it & lmask);
+    for (int it = lane; it < n_items(R1); it += 64) {
+      if (!item_ok(it)) continue;
+      const int k1 = item_j(it, R1), f = item_f(it, R1);
       Z<T> v[R2];
 #pragma unroll
       for (int jj = 0; jj < R2; ++jj) v[jj] = Q[f * QLD + k1 * R2 + jj];
