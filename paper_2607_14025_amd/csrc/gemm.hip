@@ -35,14 +35,12 @@ __global__ __launch_bounds__(kGemmThreads) void k_zgemm_reduce(const Z64* __rest
   const int ke = min(K, kb + kchunk);
   const Z64* ar[2];
   const Z64* xr[2];
-  bool xv[2];
 #pragma unroll
   for (int bi = 0; bi < 2; ++bi) ar[bi] = A + (size_t)(m0 + 16 * bi + l16) * K;
 #pragma unroll
   for (int bj = 0; bj < 2; ++bj) {
     const int n = n0 + 16 * bj + l16;
-    xv[bj] = n < ncols;
-    const int row = xv[bj] ? (xidx ? xidx[n] : n) : 0;
+    const int row = n < ncols ? (xidx ? xidx[n] : n) : (xidx ? xidx[0] : 0);
     xr[bj] = X + (size_t)row * ldx;
   }
   v4d cre[2][2], cim[2][2];
@@ -53,20 +51,34 @@ __global__ __launch_bounds__(kGemmThreads) void k_zgemm_reduce(const Z64* __rest
       cre[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
       cim[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
     }
-  const Z64 zero = zmk(0.0, 0.0);
-  for (int kc = kb; kc < ke; kc += 8) {
+  // The next step's fragments are loaded before this step's products (every load unconditional:
+  // columns past ncols read row 0, whose products are never stored), so they arrive while the
+  // products of this step run.
+  Z64 na0[2], na1[2], nx0[2], nx1[2];
+  auto load = [&](int kc) {
     const int k = kc + 2 * g;
-    Z64 a0[2], a1[2], x0[2], x1[2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
-      a0[bi] = ar[bi][k];
-      a1[bi] = ar[bi][k + 1];
+      na0[bi] = ar[bi][k];
+      na1[bi] = ar[bi][k + 1];
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      x0[bj] = xv[bj] ? xr[bj][k] : zero;
-      x1[bj] = xv[bj] ? xr[bj][k + 1] : zero;
+      nx0[bj] = xr[bj][k];
+      nx1[bj] = xr[bj][k + 1];
     }
+  };
+  if (kb < ke) load(kb);
+  for (int kc = kb; kc < ke; kc += 8) {
+    Z64 a0[2], a1[2], x0[2], x1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      a0[u] = na0[u];
+      a1[u] = na1[u];
+      x0[u] = nx0[u];
+      x1[u] = nx1[u];
+    }
+    load(min(kc + 8, ke - 8));  // the last step reloads itself, unused
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -131,21 +143,34 @@ __global__ __launch_bounds__(kGemmThreads) void k_zgemm_expand(const Z64* __rest
       dre[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
       dim_[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
     }
-  const Z64 zero = zmk(0.0, 0.0);
-  for (int m = 0; m < M_pad; m += 8) {
+  // next step's fragments loaded before this step's products; columns past ncols read column 0
+  Z64 na0[2], na1[2], nc0[2], nc1[2];
+  auto load = [&](int m) {
     const int mm = m + 2 * g;
-    Z64 a0[2], a1[2], c0[2], c1[2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
       const int kk = k0 + 16 * bi + l16;
-      a0[bi] = A[(size_t)mm * K + kk];
-      a1[bi] = A[(size_t)(mm + 1) * K + kk];
+      na0[bi] = A[(size_t)mm * K + kk];
+      na1[bi] = A[(size_t)(mm + 1) * K + kk];
     }
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) {
-      c0[bj] = nv[bj] ? C[(size_t)nn[bj] * M_pad + mm] : zero;
-      c1[bj] = nv[bj] ? C[(size_t)nn[bj] * M_pad + mm + 1] : zero;
+      const size_t o = (size_t)(nv[bj] ? nn[bj] : 0) * M_pad + mm;
+      nc0[bj] = C[o];
+      nc1[bj] = C[o + 1];
     }
+  };
+  load(0);
+  for (int m = 0; m < M_pad; m += 8) {
+    Z64 a0[2], a1[2], c0[2], c1[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      a0[u] = na0[u];
+      a1[u] = na1[u];
+      c0[u] = nc0[u];
+      c1[u] = nc1[u];
+    }
+    load(min(m + 8, M_pad - 8));  // the last step reloads itself, unused
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
