@@ -480,45 +480,30 @@ __device__ __forceinline__ void put_split(__bf16* __restrict__ Cs, size_t plane,
   Cs[plane + o + 1] = (__bf16)(im - (float)ih);
 }
 
-// Coefficients of (H - eps) p projected, for one expand over the stacked rows
-// [KB (Ma rows); Psi (Mb rows)], from the split partials of c_a = <beta_a|p>
-// and of <psi_b|q_loc>, q_loc the local part of (H - eps) p:
-//   rows a: D c_a;  rows Ma + b: -(<psi_b|q_loc> + sum_a G[a][b] D c_a),
-// G[a][b] = <psi_b|beta_a>, so that the Psi rows remove Psi^H of the whole
-// (H - eps) p. One workgroup per column n; output as k_sum_split writes it
-// for M_pad = Ma + Mb.
+// Coefficients of the projected (H - eps) p over the stacked rows [P_c KB (Ma); Psi (Mb)] from
+// the split partials of <beta_a|p> and of <psi_b|q_loc>, q_loc the local part of (H - eps) p:
+// rows a: D <beta_a|p>; rows Ma + b: -<psi_b|q_loc>. With P_c beta_a in the stacked matrix the
+// Psi rows need not remove Psi^H of the KB term. Output as k_sum_split writes it for M_pad = Ma + Mb.
 __global__ void k_sum_proj(const Z32* __restrict__ cp_a, int ns_a, const Z32* __restrict__ cp_b, int ns_b,
-                           int ncols, int Ma, int Mb, float D, const Z32* __restrict__ G, __bf16* __restrict__ Cs,
+                           int ncols, int Ma, int Mb, float D, __bf16* __restrict__ Cs,
                            const int* __restrict__ live) {
-  extern __shared__ Z32 ca[];
-  const int n = blockIdx.x, Mt = Ma + Mb;
-  if (live && n >= *live) return;  // whole workgroup, before its barrier
-  const size_t plane = (size_t)ncols * Mt * 2;
-  for (int a = threadIdx.x; a < Ma; a += blockDim.x) {
-    float re = 0.f, im = 0.f;
-    for (int s = 0; s < ns_a; ++s) {
-      const Z32 v = cp_a[((size_t)s * ncols + n) * Ma + a];
-      re += v.re;
-      im += v.im;
-    }
-    ca[a] = zmk(D * re, D * im);
-    put_split(Cs, plane, blk_index(a, n, ncols), D * re, D * im);
+  const int Mt = Ma + Mb;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ncols * Mt) return;
+  const int n = i / Mt, r = i - n * Mt;
+  if (live && n >= *live) return;
+  const bool kb = r < Ma;
+  const Z32* src = kb ? cp_a + (size_t)n * Ma + r : cp_b + (size_t)n * Mb + (r - Ma);
+  const size_t stride = (size_t)ncols * (kb ? Ma : Mb);
+  const int ns = kb ? ns_a : ns_b;
+  float re = 0.f, im = 0.f;
+  for (int s = 0; s < ns; ++s) {
+    const Z32 v = src[s * stride];
+    re += v.re;
+    im += v.im;
   }
-  __syncthreads();
-  for (int b = threadIdx.x; b < Mb; b += blockDim.x) {
-    float re = 0.f, im = 0.f;
-    for (int s = 0; s < ns_b; ++s) {
-      const Z32 v = cp_b[((size_t)s * ncols + n) * Mb + b];
-      re += v.re;
-      im += v.im;
-    }
-    for (int a = 0; a < Ma; ++a) {
-      const Z32 g = G[(size_t)a * Mb + b], c = ca[a];
-      re += g.re * c.re - g.im * c.im;
-      im += g.re * c.im + g.im * c.re;
-    }
-    put_split(Cs, plane, blk_index(Ma + b, n, ncols), -re, -im);
-  }
+  const float f = kb ? D : -1.f;
+  put_split(Cs, (size_t)ncols * Mt * 2, blk_index(r, n, ncols), f * re, f * im);
 }
 
 }  // namespace
@@ -545,9 +530,10 @@ void launch_split_bf16_rows(const Z64* A, int M, int K, int row0, int Mt, __bf16
 }
 
 void launch_sum_proj32(const Z32* cp_a, int ns_a, const Z32* cp_b, int ns_b, int ncols, int Ma, int Mb, float D,
-                       const Z32* G, __bf16* Cs, hipStream_t st, const int* live) {
-  if (ncols <= 0) return;
-  k_sum_proj<<<ncols, 256, (size_t)Ma * sizeof(Z32), st>>>(cp_a, ns_a, cp_b, ns_b, ncols, Ma, Mb, D, G, Cs, live);
+                       __bf16* Cs, hipStream_t st, const int* live) {
+  const int total = ncols * (Ma + Mb);
+  if (total <= 0) return;
+  k_sum_proj<<<(total + 255) / 256, 256, 0, st>>>(cp_a, ns_a, cp_b, ns_b, ncols, Ma, Mb, D, Cs, live);
 }
 
 void launch_reduce_bf16(const __bf16* Ahi, const __bf16* Alo, int M_pad, const Z32* X, int ldx, const int* xidx,

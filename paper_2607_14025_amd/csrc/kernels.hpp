@@ -207,10 +207,10 @@ void launch_split_bf16(const Z64* A, int M, int K, __bf16* hi, __bf16* lo, __bf1
 // the same into rows [row0, row0 + M) of a split matrix of Mt rows (row layout skipped when hi is null)
 void launch_split_bf16_rows(const Z64* A, int M, int K, int row0, int Mt, __bf16* hi, __bf16* lo, __bf16* thi,
                             __bf16* tlo, hipStream_t st);
-// coefficients of the projected (H - eps) p over the stacked rows [KB (Ma); Psi (Mb)]:
-// rows a: D <beta_a|p>; rows Ma + b: -(<psi_b|q_loc> + sum_a G[a][b] D <beta_a|p>), G[a][b] = <psi_b|beta_a>
+// coefficients of the projected (H - eps) p over the stacked rows [P_c KB (Ma); Psi (Mb)]:
+// rows a: D <beta_a|p>; rows Ma + b: -<psi_b|q_loc>, q_loc the local part of (H - eps) p
 void launch_sum_proj32(const Z32* cp_a, int ns_a, const Z32* cp_b, int ns_b, int ncols, int Ma, int Mb, float D,
-                       const Z32* G, __bf16* Cs, hipStream_t st, const int* live = nullptr);
+                       __bf16* Cs, hipStream_t st, const int* live = nullptr);
 // C[n][m] partial = sum_k conj(A[m][k]) X[xidx[n]][k] (BF16 split operands, FP32 accumulation)
 // live (optional, device): only the first *live of the ncols columns are computed (ncols still
 // sets the grid and the strides of the partials and of C)

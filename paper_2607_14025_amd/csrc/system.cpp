@@ -168,9 +168,9 @@ struct stern_system {
   DBuf psi, psi_r;
   // split BF16 copies of Psi and of the KB rows (row and transposed layouts)
   DBuf psi_hi, psi_lo, psiT_hi, psiT_lo, kb_hi, kb_lo, kbT_hi, kbT_lo;
-  // projected FP32 operator: transposed split of the stacked rows [KB (natoms_pad); Psi (nocc_pad)]
-  // and G[a][b] = <psi_b|beta_a> (FP32, [natoms_pad][nocc_pad]); proj_m = 0 without atoms
-  DBuf projT_hi, projT_lo, proj_g;
+  // projected FP32 operator: transposed split of the stacked rows [P_c KB (natoms_pad); Psi (nocc_pad)];
+  // proj_m = 0 without atoms
+  DBuf projT_hi, projT_lo;
   int proj_m = 0;
   // workspace
   DBuf wx, wr, wp, wq, wz, wb, pen, cpart, cpart2, cmat, sv_eps, sv_invT, sv_band, sv_pert, sv_bb, sv_rz, sv_rr, sv_flag,
@@ -255,7 +255,7 @@ struct stern_system {
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
-                   &band_feat, &projT_hi, &projT_lo, &proj_g, &cpart2, &m_cnt, &negk, &sv_rzi};
+                   &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -424,10 +424,10 @@ int apply_pc32_update(stern_system* S, const Z32* Z, Z32* P, const double* beta,
 }
 
 // out = P_c (H - eps_s) in for FP32 rows: FP32 FFTs, then one split-BF16 expand
-// over the stacked rows [KB; Psi] that adds the KB term and removes Psi^H of
-// the whole product. Psi^H of the KB term is G^T D <beta|in> with the
-// precomputed G = <psi_b|beta_a>, so the two reduces (KB rows against `in`,
-// Psi against the local part) are independent of each other.
+// over the stacked rows [P_c KB; Psi] that adds the projected KB term and removes
+// Psi^H of the local part. The KB rows are projected once at set-up, so the two
+// reduces (KB rows against `in`, Psi against the local part) are independent of
+// each other and the coefficients need no further product.
 int apply_h32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, int n, const double* eps_rows);
 int apply_hproj32_rows(stern_system* S, const Z32* in, Z32* out, const int* list, int n, const double* eps_rows) {
   if (n <= 0) return 0;
@@ -463,9 +463,8 @@ int apply_hproj32_rows(stern_system* S, const Z32* in, Z32* out, const int* list
     launch_reduce_bf16(S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(), Mb, out, K, list, n, K, cpb, ns_b,
                        S->stream, S->live);
   }));
-  CHECKED(timed(S, STERN_K_SUM_PARTS, zb * n * (na * (ns_a + 1) + m * (ns_b + 1)), 8.0 * n * na * m, [&] {
-    launch_sum_proj32(cpa, ns_a, cpb, ns_b, n, Ma, Mb, (float)S->cell.D, S->proj_g.as<Z32>(), cm, S->stream,
-                      S->live);
+  CHECKED(timed(S, STERN_K_SUM_PARTS, zb * n * (na * (ns_a + 1) + m * (ns_b + 1)), 0.0, [&] {
+    launch_sum_proj32(cpa, ns_a, cpb, ns_b, n, Ma, Mb, (float)S->cell.D, cm, S->stream, S->live);
   }));
   CHECKED(timed(S, STERN_K_GEMM_BF16, zb * npw * (2.0 * n + na + m), 8.0 * (na + m) * npw * n, [&] {
     launch_expand_bf16(S->projT_hi.as<__bf16>(), S->projT_lo.as<__bf16>(), S->proj_m, cm, out, K, list, n, K,
@@ -1352,7 +1351,8 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   CHECKED(upload(S->band_invT, S->invT.data(), n_occ * sizeof(double), st));
   CHECKED(S->psi.ensure((size_t)S->nocc_pad * K * sizeof(Z64)));
   launch_fill_zero(S->psi.as<Z64>(), (size_t)S->nocc_pad * K, st);
-  CHECKED(S->tmp_in.ensure((size_t)n_occ * npw * sizeof(Z64)));
+  // tmp_in also holds P_c KB below
+  CHECKED(S->tmp_in.ensure(std::max((size_t)n_occ * npw, (size_t)S->natoms_pad * K) * sizeof(Z64)));
   HIPOK(hipMemcpyAsync(S->tmp_in.p, hp, (size_t)n_occ * npw * sizeof(Z64), hipMemcpyHostToDevice, st));
   launch_permute(S->tmp_in.as<Z64>(), npw, S->psi.as<Z64>(), K, S->perm.as<int>(), npw, n_occ, true, st);
   const size_t psn = (size_t)S->nocc_pad * K * 2 * sizeof(__bf16);
@@ -1360,20 +1360,21 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   launch_split_bf16(S->psi.as<Z64>(), S->nocc_pad, K, S->psi_hi.as<__bf16>(), S->psi_lo.as<__bf16>(),
                     S->psiT_hi.as<__bf16>(), S->psiT_lo.as<__bf16>(), st);
   S->proj_m = 0;
-  if (S->n_atoms > 0) {  // stacked rows [KB; Psi] and G = Psi^H KB (FP64 GEMM, kept in FP32)
+  if (S->n_atoms > 0) {  // stacked rows [P_c KB; Psi], P_c beta_a = beta_a - sum_b psi_b <psi_b|beta_a> in FP64
     const int Ma = S->natoms_pad, Mb = S->nocc_pad, Mt = Ma + Mb;
     const size_t tn = (size_t)Mt * K * 2 * sizeof(__bf16);
     for (DBuf* d : {&S->projT_hi, &S->projT_lo}) CHECKED(d->ensure(tn));
     __bf16 *th = S->projT_hi.as<__bf16>(), *tl = S->projT_lo.as<__bf16>();
-    launch_split_bf16_rows(S->kb.as<Z64>(), Ma, K, 0, Mt, nullptr, nullptr, th, tl, st);
-    launch_split_bf16_rows(S->psi.as<Z64>(), Mb, K, Ma, Mt, nullptr, nullptr, th, tl, st);
+    Z64* pkb = S->tmp_in.as<Z64>();
+    HIPOK(hipMemcpyAsync(pkb, S->kb.p, (size_t)Ma * K * sizeof(Z64), hipMemcpyDeviceToDevice, st));
     const int ns = choose_nsplit(Mb, Ma, K, S->gemm64_wg);
     CHECKED(S->cpart.ensure((size_t)ns * Ma * Mb * sizeof(Z64)));
     CHECKED(S->cmat.ensure((size_t)Ma * Mb * sizeof(Z64)));
-    CHECKED(S->proj_g.ensure((size_t)Ma * Mb * sizeof(Z32)));
     launch_zgemm_reduce(S->psi.as<Z64>(), Mb, S->kb.as<Z64>(), K, nullptr, Ma, K, S->cpart.as<Z64>(), ns, st);
-    launch_sum_parts(S->cpart.as<Z64>(), ns, Ma, Mb, 1.0, S->cmat.as<Z64>(), st);
-    launch_to32(S->cmat.as<Z64>(), S->proj_g.as<Z32>(), (size_t)Ma * Mb, st);
+    launch_sum_parts(S->cpart.as<Z64>(), ns, Ma, Mb, -1.0, S->cmat.as<Z64>(), st);
+    launch_zgemm_expand(S->psi.as<Z64>(), Mb, S->cmat.as<Z64>(), pkb, K, nullptr, Ma, K, st);
+    launch_split_bf16_rows(pkb, Ma, K, 0, Mt, nullptr, nullptr, th, tl, st);
+    launch_split_bf16_rows(S->psi.as<Z64>(), Mb, K, Ma, Mt, nullptr, nullptr, th, tl, st);
     CHECKED(launch_check());
     S->proj_m = Mt;
   }
