@@ -59,6 +59,13 @@ extern "C" {
 #define STERN_GUESS_ZERO 0
 #define STERN_GUESS_LEARNED 1    /* learned x0 and learned diagonal preconditioner */
 #define STERN_GUESS_LEARNED_K 2  /* learned diagonal preconditioner only, x0 = 0 */
+/* warm start: every solve (v, i) starts from the solution of the same (v, i) kept by an earlier
+   call with keep_solutions set (same n_pert and band range, and no set_occupied since; else
+   STERN_ERR_STATE). The FP64 residual of the start decides: a start already within tol is a
+   converged solve with no iteration, one with ||r|| >= ||b|| is replaced by zero. For sequences
+   of related calls on the same fields: a frequency sweep of the response at i u, or a tighter
+   tolerance after a loose one. FP64, mixed and imaginary-frequency solves. */
+#define STERN_GUESS_PREVIOUS 3
 
 /* where pointer arguments live */
 #define STERN_MEM_HOST 0
@@ -103,7 +110,7 @@ typedef struct {
   double tol;          /* relative FP64 true residual ||b - A x|| / ||b|| to accept */
   int max_iter;        /* CG iterations per solve (0 = 1000) */
   int precision;       /* STERN_FP64 or STERN_MIXED */
-  int guess;           /* STERN_GUESS_ZERO, _LEARNED or _LEARNED_K (the last two need model) */
+  int guess;           /* STERN_GUESS_ZERO, _LEARNED, _LEARNED_K (these two need model) or _PREVIOUS */
   int mem_kind;        /* STERN_MEM_HOST or STERN_MEM_DEVICE for dv_r / dn_r */
   int band_begin;      /* solve bands [band_begin, band_end); band_end <= 0 means n_occ.
                           P_c always uses every occupied band; dn is the partial sum. */
@@ -139,9 +146,13 @@ typedef struct {
      the bilinear form sum_G a(-G) b(G), in which the shifted operator is symmetric, and returns
      dn_i = 4 Re sum_v conj(psi_v) x_{v,i}: for a real field the two frequency terms of chi0(i u)
      are complex conjugates of each other, so one shifted solve per pair gives the real chi0(i u).
-     FP64 with Teter's preconditioner and a zero start only (STERN_ERR_UNSUPPORTED otherwise);
-     0 = the static response. */
+     FP64 with Teter's preconditioner, from zero or from kept solutions (STERN_GUESS_PREVIOUS),
+     STERN_ERR_UNSUPPORTED otherwise; 0 = the static response. */
   double omega_imag;
+  /* nonzero: keep the solutions x of every (v, i) of this call on the device (n_pert x bands x
+     n_pw complex FP64, owned by the system until the next keeping call, set_occupied or
+     stern_free) as the starts of a later STERN_GUESS_PREVIOUS call */
+  int keep_solutions;
 } stern_opts;
 
 /* Inner operators of the mixed solve (stern_opts.inner_op). The FP64 outer

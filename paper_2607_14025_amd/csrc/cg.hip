@@ -82,35 +82,41 @@ __global__ __launch_bounds__(kCgThreads) void k_cg_init(CgState S, const int* __
   }
 }
 
-// r = b - q for a guess x, with q = A x given in FP64 (q32 == null) or FP32;
-// the guess is kept only if ||r|| is finite and below ||b||, else x = 0, r = b.
+// r = b - q + i u x for a guess x, with q = P_c (H - eps) P_c x given in FP64 (q32 == null) or
+// FP32 and u the imaginary frequency (0: the static system); the guess is kept only if ||r|| is
+// finite and below ||b|| by more than rounding (||r||^2 < (1 - 2^-40) ||b||^2: a zero guess, whose
+// ||r||^2 differs from ||b||^2 only by the order of the two sums, is always rejected), else
+// x = 0, r = b. With tol2 >= 0 a kept guess with ||r||^2 <= tol2 ||b||^2 is a converged solve
+// (flag 2, no iteration).
 __global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int* __restrict__ act,
-                                                            const Z32* __restrict__ q32, int* __restrict__ rejected) {
+                                                            const Z32* __restrict__ q32, int* __restrict__ rejected,
+                                                            double u, double tol2) {
   __shared__ double sh[kCgThreads / 64];
   const int s = act ? act[blockIdx.x] : blockIdx.x;
   const size_t o = (size_t)s * S.npw_pad;
-  auto qv = [&](int k) -> Z64 {
+  auto res = [&](int k) -> Z64 {
+    Z64 q;
     if (q32) {
       const Z32 v = q32[o + k];
-      return zmk((double)v.re, (double)v.im);
+      q = zmk((double)v.re, (double)v.im);
+    } else {
+      q = S.q[o + k];
     }
-    return S.q[o + k];
+    const Z64 b = S.b[o + k], x = S.x[o + k];
+    return zmk(b.re - q.re - u * x.im, b.im - q.im + u * x.re);
   };
   double rr = 0.0;
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 b = S.b[o + k], q = qv(k);
-    const double re = b.re - q.re, im = b.im - q.im;
-    rr += re * re + im * im;
+    const Z64 r = res(k);
+    rr += r.re * r.re + r.im * r.im;
   }
   rr = block_sum(rr, sh);
-  const bool ok = (rr == rr) && rr < S.bb[s];  // false for NaN
+  const bool ok = (rr == rr) && rr < (1.0 - 0x1p-40) * S.bb[s];  // false for NaN
   for (int k = threadIdx.x; k < S.npw_pad; k += kCgThreads) {
-    const Z64 b = S.b[o + k];
     if (ok) {
-      const Z64 q = qv(k);
-      S.r[o + k] = zmk(b.re - q.re, b.im - q.im);
+      S.r[o + k] = res(k);
     } else {
-      S.r[o + k] = b;
+      S.r[o + k] = S.b[o + k];
       S.x[o + k] = zmk(0.0, 0.0);
     }
   }
@@ -118,6 +124,7 @@ __global__ __launch_bounds__(kCgThreads) void k_guess_resid(CgState S, const int
     const bool zero_b = !(S.bb[s] > 0.0);  // b = 0: x = 0 is exact, nothing was rejected
     rejected[s] = (ok || zero_b) ? 0 : 1;
     S.tres[s] = ok ? sqrt(rr / S.bb[s]) : (zero_b ? 0.0 : 1.0);
+    if (ok && tol2 >= 0.0 && rr <= tol2 * S.bb[s]) S.flag[s] = 2;
   }
 }
 
@@ -780,8 +787,9 @@ void launch_cocg_true(const CgState& s, double u, const int* act, int n, double 
 void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st) {
   if (n > 0) k_cg_init<<<n, kCgThreads, 0, st>>>(s, act, keep ? 1 : 0);
 }
-void launch_guess_resid(const CgState& s, const int* act, int n, const Z32* q32, int* rejected, hipStream_t st) {
-  if (n > 0) k_guess_resid<<<n, kCgThreads, 0, st>>>(s, act, q32, rejected);
+void launch_guess_resid(const CgState& s, const int* act, int n, const Z32* q32, int* rejected, hipStream_t st,
+                        double u, double tol2) {
+  if (n > 0) k_guess_resid<<<n, kCgThreads, 0, st>>>(s, act, q32, rejected, u, tol2);
 }
 void launch_to32(const Z64* x, Z32* y, size_t n, hipStream_t st) {
   if (n == 0) return;

@@ -100,7 +100,10 @@ struct CgState {
   int npw_pad;
 };
 void launch_cg_init(const CgState& s, const int* act, int n, bool keep, hipStream_t st);
-void launch_guess_resid(const CgState& s, const int* act, int n, const Z32* q32, int* rejected, hipStream_t st);
+// r = b - A x + i u x for a guess x (A x in q, or q32 when not null); rejects guesses with ||r|| >= ||b||;
+// with tol2 >= 0, marks a guess with ||r||^2 <= tol2 ||b||^2 converged (flag 2)
+void launch_guess_resid(const CgState& s, const int* act, int n, const Z32* q32, int* rejected, hipStream_t st,
+                        double u = 0.0, double tol2 = -1.0);
 void launch_to32(const Z64* x, Z32* y, size_t n, hipStream_t st);
 void launch_cg_init2(const CgState& s, const int* act, int n, hipStream_t st);
 void launch_cg_alpha(const CgState& s, const int* act, int n, double tol2, hipStream_t st);

@@ -179,6 +179,10 @@ struct stern_system {
   DBuf m_cnt;                 // device count of the inner solve's active list (list_f)
   DBuf negk;                  // [npw_pad] index of -G of each coefficient (column order)
   DBuf sv_rzi;                // [nbatch] imaginary parts of the shifted solves' (r, z)_J
+  // solutions kept by a call with keep_solutions, [n_pert][bands][npw_pad] complex FP64, valid
+  // while keep_np > 0 for that call's field count and band range [keep_v0, keep_v1)
+  DBuf xkeep;
+  int keep_np = 0, keep_v0 = 0, keep_v1 = 0;
   const int* live = nullptr;  // while set, FP32 launches cover only the first *live list entries
   // coarse (N/2)^3 grid of the learned guess, when it holds the sphere
   bool have_coarse = false;
@@ -255,7 +259,7 @@ struct stern_system {
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
-                   &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi};
+                   &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi, &xkeep};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -754,6 +758,27 @@ int learned_guess(stern_system* S, const stern_model* M, CgState& cs, int ns, in
   return 0;
 }
 
+// Warm start of the solves [0, ns) of a batch from the kept solutions at row `row0`:
+// x = P_c x_kept, r = b - (P_c (H - eps) P_c - i u) x in FP64 (u = 0: the static system);
+// starts already within tol are marked converged, those with ||r|| >= ||b|| replaced by zero.
+int warm_start(stern_system* S, const CgState& cs, size_t row0, int ns, double u, double tol, int& n_rej) {
+  hipStream_t st = S->stream;
+  const int K = S->hb.npw_pad;
+  CHECKED(S->g_rej.ensure((size_t)S->ws_solves * sizeof(int)));
+  HIPOK(hipMemcpyAsync(cs.x, S->xkeep.as<Z64>() + row0 * K, (size_t)ns * K * sizeof(Z64), hipMemcpyDeviceToDevice,
+                       st));
+  CHECKED(apply_pc_rows(S, cs.x, nullptr, ns));
+  CHECKED(apply_h_rows(S, cs.x, cs.q, nullptr, ns, cs.eps));
+  CHECKED(apply_pc_rows(S, cs.q, nullptr, ns));
+  launch_guess_resid(cs, nullptr, ns, nullptr, S->g_rej.as<int>(), st, u, tol * tol);
+  CHECKED(launch_check());
+  std::vector<int> rej(ns);
+  HIPOK(hipMemcpyAsync(rej.data(), S->g_rej.p, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  for (int v : rej) n_rej += v;
+  return 0;
+}
+
 // Per-solve arrays, right-hand sides b = -P_c [dV psi_v] and x = 0, r = b for the
 // solves of perturbations [i0, i1) x bands [v0, v0 + nb) (row s = (i - i0) nb + v - v0).
 // A right-hand side P_c dV psi_v whose norm is at most this fraction of ||dV psi_v|| is
@@ -902,7 +927,7 @@ int run_pcg64(stern_system* S, const CgState& cs, const std::vector<int>& list, 
 // list compacted every check_every iterations, the FP64 true residual of the shifted system at
 // recurrence convergence, restart from it when it fails.
 int run_cocg64(stern_system* S, const CgState& cs, const std::vector<int>& list, double u, double tol, int max_iter,
-               int check_every, int& n_restart, double vecb) {
+               int check_every, int& n_restart, double vecb, bool keep_x = false) {
   hipStream_t st = S->stream;
   const int ns_all = S->ws_solves;
   const int* negk = S->negk.as<int>();
@@ -913,7 +938,7 @@ int run_cocg64(stern_system* S, const CgState& cs, const std::vector<int>& list,
   HIPOK(hipMemcpyAsync(S->list_act.p, list.data(), n0 * sizeof(int), hipMemcpyHostToDevice, st));
   {
     const int* L = S->list_act.as<int>();
-    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 4.0, 0.0, [&] { launch_cg_init(cs, L, n0, false, st); }));
+    CHECKED(timed(S, STERN_K_CG, vecb * n0 * 4.0, 0.0, [&] { launch_cg_init(cs, L, n0, keep_x, st); }));
     CHECKED(apply_pc_rows(S, cs.z, L, n0));
     CHECKED(timed(S, STERN_K_CG, vecb * n0 * 3.0, 0.0, [&] { launch_cocg_start(cs, negk, rzi, L, n0, 0, st); }));
   }
@@ -1316,6 +1341,7 @@ int stern_set_occupied(stern_system* S, int n_occ, const double* psi, const doub
   if (n_occ <= 0 || !psi || !eps) return fail(STERN_ERR_INVALID_ARG, "need n_occ > 0, psi and eps");
   if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
   Scope sc(S->device, &S->alloc);
+  S->keep_np = 0;  // kept solutions belong to the previous occupied states
   const HostBasis& hb = S->hb;
   hipStream_t st = S->stream;
   const int npw = hb.npw, K = hb.npw_pad, N = hb.N;
@@ -1518,9 +1544,12 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->inner_tol < 0 || opts->max_outer < 0) return fail(STERN_ERR_INVALID_ARG, "bad inner_tol / max_outer");
   if (opts->inner_op != STERN_INNER_PROJECTED && opts->inner_op != STERN_INNER_SHIFTED)
     return fail(STERN_ERR_INVALID_ARG, "inner_op %d is not one of STERN_INNER_*", opts->inner_op);
-  if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED && opts->guess != STERN_GUESS_LEARNED_K)
-    return fail(STERN_ERR_INVALID_ARG, "guess must be STERN_GUESS_ZERO, STERN_GUESS_LEARNED or STERN_GUESS_LEARNED_K");
-  if (opts->guess != STERN_GUESS_ZERO) {
+  if (opts->guess != STERN_GUESS_ZERO && opts->guess != STERN_GUESS_LEARNED && opts->guess != STERN_GUESS_LEARNED_K &&
+      opts->guess != STERN_GUESS_PREVIOUS)
+    return fail(STERN_ERR_INVALID_ARG, "guess must be one of STERN_GUESS_*");
+  const bool learned = opts->guess == STERN_GUESS_LEARNED || opts->guess == STERN_GUESS_LEARNED_K;
+  const bool warm = opts->guess == STERN_GUESS_PREVIOUS;
+  if (learned) {
     if (!opts->model) return fail(STERN_ERR_INVALID_ARG, "a learned start needs a model");
     if (!S->have_coarse) return fail(STERN_ERR_UNSUPPORTED, "grid %d has no coarse grid for the learned guess", S->hb.N);
     if (opts->model->device != S->device) return fail(STERN_ERR_INVALID_ARG, "model and system on different devices");
@@ -1530,11 +1559,14 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (!(opts->tol > 0)) return fail(STERN_ERR_INVALID_ARG, "tol must be > 0");
   const double omega = opts->omega_imag;
   if (!(omega >= 0.0) || !std::isfinite(omega)) return fail(STERN_ERR_INVALID_ARG, "omega_imag must be finite and >= 0");
-  if (omega > 0.0 && (opts->precision != STERN_FP64 || opts->guess != STERN_GUESS_ZERO))
-    return fail(STERN_ERR_UNSUPPORTED, "the response at imaginary frequency runs in FP64 from a zero start");
+  if (omega > 0.0 && (opts->precision != STERN_FP64 || learned))
+    return fail(STERN_ERR_UNSUPPORTED, "the response at imaginary frequency runs in FP64 with Teter's preconditioner");
   const int v0 = opts->band_begin;
   const int v1 = opts->band_end > 0 ? opts->band_end : S->n_occ;
   if (v0 < 0 || v1 > S->n_occ || v0 >= v1) return fail(STERN_ERR_INVALID_ARG, "bad band range [%d, %d)", v0, v1);
+  if (warm && (S->keep_np != n_pert || S->keep_v0 != v0 || S->keep_v1 != v1))
+    return fail(STERN_ERR_STATE, "no kept solutions for %d fields x bands [%d, %d) (kept: %d x [%d, %d))", n_pert, v0,
+                v1, S->keep_np, S->keep_v0, S->keep_v1);
   if (opts->n_sample < 0 || (opts->n_sample > 0 && (!opts->sample_pairs || !opts->sample_x)))
     return fail(STERN_ERR_INVALID_ARG, "bad sample request");
   for (int k = 0; k < opts->n_sample; ++k) {
@@ -1589,6 +1621,11 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     dv_dev = S->dv_dev.as<double>();
     dn_dev = S->dn_dev.as<double>();
   }
+  const bool keep = opts->keep_solutions != 0;
+  if (keep) {  // invalid until every batch has stored its solutions
+    if (!warm) S->keep_np = 0;
+    CHECKED(S->xkeep.ensure((size_t)n_pert * nb * K * sizeof(Z64)));
+  }
   CgState cs = cg_state(S);
   const FftGeom g = S->geom();
   std::vector<int> all_iters, all_flag;
@@ -1602,20 +1639,28 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
     const int i1 = std::min(n_pert, i0 + per);
     const int ns = (i1 - i0) * nb;
     CHECKED(setup_batch(S, i0, i1, v0, nb, dv_dev, vecb));
-    const bool guess = opts->guess != STERN_GUESS_ZERO;
-    const bool with_x0 = opts->guess == STERN_GUESS_LEARNED;
-    if (guess)
+    const bool with_x0 = opts->guess == STERN_GUESS_LEARNED || warm;
+    if (learned)
       CHECKED(learned_guess(S, opts->model, cs, ns, n_rejected, opts->precision == STERN_MIXED, with_x0));
-    std::vector<int> all(ns);
-    for (int s = 0; s < ns; ++s) all[s] = s;
+    if (warm) CHECKED(warm_start(S, cs, (size_t)i0 * nb, ns, omega, tol, n_rejected));
+    std::vector<int> all;
+    if (warm) {  // starts already within tol are done
+      HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      for (int s = 0; s < ns; ++s)
+        if (h_flag[s] != 2) all.push_back(s);
+    } else {
+      all.resize(ns);
+      for (int s = 0; s < ns; ++s) all[s] = s;
+    }
     if (omega > 0.0) {
-      CHECKED(run_cocg64(S, cs, all, omega, tol, max_iter, check_every, n_restart, vecb));
+      CHECKED(run_cocg64(S, cs, all, omega, tol, max_iter, check_every, n_restart, vecb, warm));
     } else if (opts->precision == STERN_MIXED) {
       CHECKED(run_mixed(S, cs, all, tol, inner_tol, max_outer, max_iter, check_every, n_restart, n_fallback, vecb,
                         use_graph, opts->inner_op));
     } else {
       CHECKED(run_pcg64(S, cs, all, tol, max_iter, check_every, n_restart, vecb, use_graph, with_x0));
-      if (guess) {  // solves the learned start did not bring below tol: Teter-PCG from zero
+      if (learned || warm) {  // solves the start did not bring below tol: Teter-PCG from zero
         HIPOK(hipMemcpyAsync(h_flag.data(), cs.flag, ns * sizeof(int), hipMemcpyDeviceToHost, st));
         HIPOK(hipStreamSynchronize(st));
         std::vector<int> rest;
@@ -1629,6 +1674,9 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
         }
       }
     }
+    if (keep)
+      HIPOK(hipMemcpyAsync(S->xkeep.as<Z64>() + (size_t)i0 * nb * K, cs.x, (size_t)ns * K * sizeof(Z64),
+                           hipMemcpyDeviceToDevice, st));
     // dn_i = 4/Omega Re sum_v conj(psi_v(r)) x_{v,i}(r)
     CHECKED(timed(S, STERN_K_XINV, ns * (vecb + (double)N * hb.ncol * 16.0), 0.0,
                   [&] { launch_xinv(g, cs.x, nullptr, ns, S->pen.as<Z64>(), st); }));
@@ -1663,6 +1711,11 @@ static int apply_chi0_impl(stern_system* S, int n_pert, const double* dv_r, doub
   if (opts->mem_kind == STERN_MEM_HOST)
     HIPOK(hipMemcpyAsync(dn_r, dn_dev, (size_t)n_pert * n3 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
+  if (keep) {
+    S->keep_np = n_pert;
+    S->keep_v0 = v0;
+    S->keep_v1 = v1;
+  }
   if (stats) {
     for (int k = 0; k < STERN_NKERNEL; ++k) {
       stats->kernel_launches[k] = 0;

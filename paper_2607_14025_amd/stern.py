@@ -21,6 +21,7 @@ STERN_MIXED = 1
 STERN_GUESS_ZERO = 0
 STERN_GUESS_LEARNED = 1
 STERN_GUESS_LEARNED_K = 2
+STERN_GUESS_PREVIOUS = 3
 STERN_INNER_PROJECTED = 0
 STERN_INNER_SHIFTED = 1
 STERN_MEM_HOST = 0
@@ -68,7 +69,7 @@ class Opts(C.Structure):
                 ("check_every", C.c_int), ("n_sample", C.c_int), ("sample_pairs", C.POINTER(C.c_int)),
                 ("sample_x", C.POINTER(C.c_double)), ("profile", C.c_int), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int), ("use_graph", C.c_int), ("model", C.c_void_p),
-                ("inner_op", C.c_int), ("omega_imag", C.c_double)]
+                ("inner_op", C.c_int), ("omega_imag", C.c_double), ("keep_solutions", C.c_int)]
 
 
 NKERNEL = 17
@@ -203,13 +204,18 @@ def _torch_stream():
 
 def make_opts(tol, max_iter, precision, mem_kind, band_range=None, max_batch=0, check_every=0, profile=False,
               inner_tol=0.0, max_outer=0, use_graph=False, model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False,
-              omega_imag=0.0):
+              omega_imag=0.0, keep_solutions=False, warm_start=False):
+    if warm_start and model is not None:
+        raise ValueError("a warm start and a learned guess exclude each other")
     o = Opts()
     o.omega_imag = float(omega_imag)
+    o.keep_solutions = 1 if keep_solutions else 0
     o.tol = float(tol)
     o.max_iter = int(max_iter)
     o.precision = int(precision)
     o.guess = STERN_GUESS_ZERO if model is None else (STERN_GUESS_LEARNED_K if prec_only else STERN_GUESS_LEARNED)
+    if warm_start:
+        o.guess = STERN_GUESS_PREVIOUS
     o.model = None if model is None else model._h
     o.inner_op = int(inner_op)
     o.mem_kind = mem_kind
@@ -322,13 +328,17 @@ class System:
 
     def apply_chi0(self, dv_r, tol=1e-8, dn_out=None, max_iter=0, band_range=None, max_batch=0, check_every=0,
                    samples=None, precision=STERN_FP64, profile=False, inner_tol=0.0, max_outer=0, use_graph=False,
-                   model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False, omega_imag=0.0):
+                   model=None, inner_op=STERN_INNER_PROJECTED, prec_only=False, omega_imag=0.0,
+                   keep_solutions=False, warm_start=False):
         """dn = chi0 dv for dv [n_pert, N, N, N]; returns (dn, info dict).
 
         samples: optional list of (band, pert) pairs whose solution vectors are returned.
         model: a trained Model for the learned guess and preconditioner (None: zero guess, Teter);
         prec_only: with a model, use only its preconditioner (x0 = 0).
-        omega_imag: u > 0 gives chi0(i u) dv, the response at imaginary frequency i u (FP64 only)."""
+        omega_imag: u > 0 gives chi0(i u) dv, the response at imaginary frequency i u (FP64 only).
+        keep_solutions: keep every solution on the device for a later warm start;
+        warm_start: start every solve from the solution kept by an earlier call with the same
+        field count and band range (STERN_GUESS_PREVIOUS)."""
         n_pert = dv_r.shape[0]
         dp, mk, k1 = _ptr(dv_r, False)
         if dn_out is None:
@@ -341,7 +351,7 @@ class System:
         if mk != mk2:
             raise ValueError("dv and dn must both be host or both device arrays")
         o = make_opts(tol, max_iter, precision, mk, band_range, max_batch, check_every, profile, inner_tol, max_outer,
-                      use_graph, model, inner_op, prec_only, omega_imag)
+                      use_graph, model, inner_op, prec_only, omega_imag, keep_solutions, warm_start)
         keep = []
         sx = None
         if samples:

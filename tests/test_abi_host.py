@@ -69,3 +69,35 @@ def test_invalid_arguments_rejected():
     rc = L.stern_apply_chi0(None, 1, None, None, None, None)
     assert rc == -1
     L.stern_free(None)  # NULL-safe
+
+
+def test_ctypes_structs_match_the_c_header(tmp_path):
+    """Every ctypes mirror of a stern.h struct has the C compiler's size and field offsets."""
+    import shutil
+    import subprocess
+    from paper_2607_14025_amd import stern
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    pairs = {"stern_cell": stern.Cell, "stern_runtime": stern.Runtime, "stern_opts": stern.Opts,
+             "stern_stats": stern.Stats, "stern_train_opts": stern.TrainOpts, "stern_train_stats": stern.TrainStats,
+             "stern_pdep_opts": stern.PdepOpts, "stern_pdep_stats": stern.PdepStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "stern.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    subprocess.run(["gcc", "-std=c11", "-I", inc, str(src), "-o", str(exe)], check=True)
+    got = {}
+    for line in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n"):
+        if line:
+            c, k, v = line.split()
+            got[(c, k)] = int(v)
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f in py._fields_:
+            assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
