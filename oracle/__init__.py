@@ -26,6 +26,9 @@ Modules:
   pdep         dense symmetrised response chi-bar0 in the real potential basis (PDEP)
   frequency    the response at imaginary frequency i u: sum over states, dense shifted
                solve, free-electron Lindhard sum at i u, residual of the shifted system
+  liouville    TDDFT Liouville superoperator in the Tamm-Dancoff approximation (Hartree
+               kernel): grid route, transition-basis matrix, free-electron matrix by hand,
+               residual of the Z-vector system
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: a brute-force lattice count, the real-space Gaussian sum, the dense

@@ -1,0 +1,119 @@
+"""Liouville superoperator of TDDFT in the Tamm-Dancoff approximation (TEST INFRASTRUCTURE ONLY).
+
+Sec. II.C.1, eq. bse_tddft: the excitation energies w_s solve (D + K1e - K1d) A_s = w_s A_s over
+auxiliary orbitals A_s = {a_{s,v}}, one per occupied band, with Delta gamma_s = sum_v |a_{s,v}><psi_v|.
+The paper names the three terms (D: electron-hole energy differences; K1e, K1d: exchange and direct
+electron-hole interaction) but not their formulas. The reading here is closed-shell singlet
+excitations with the Hartree kernel: the model Hamiltonian carries no exchange-correlation
+functional, so K1d = 0, as in TDDFT with a semilocal functional, and
+
+    (D A)_v   = P_c (H - eps_v) a_v,
+    (K1e A)_v = 2 P_c [ V[rho_A] psi_v ],   rho_A(r) = sum_v' conj(psi_v'(r)) a_v'(r),
+    V[rho](r) = int rho(r') / |r - r'| dr' = sum_{q != 0} (4 pi / |q|^2) rho(q) e^{i q.r},
+
+rho(q) = Omega^-1 int rho e^{-i q.r}, on the A with a_v in range(P_c) (inputs are projected first).
+rho_A is band-limited to the 4 Ecut sphere, which the grid holds exactly, so the grid route has no
+aliasing. <B|K1e A> = 2 Omega sum_{q != 0} (4 pi / |q|^2) conj(rho_B(q)) rho_A(q): the operator is
+Hermitian in <A|B> = sum_v <a_v|b_v>, and positive definite when the gap is open.
+
+Routes, pinned against each other and against closed forms:
+* liouville_apply: the grid route above (FFTs of the oracle cell);
+* casida_tda: the matrix in the transition basis {a_v' = delta_vv' psi_c} from a full
+  diagonalisation, L_{vc,v'c'} = (eps_c - eps_v) delta + 2 Omega sum_q (4 pi/|q|^2) conj(rho_vc(q)) rho_v'c'(q)
+  with rho_vc = conj(psi_v) psi_c;
+* free_electron_tda: for plane-wave occupied and empty states k, the same matrix written out by
+  hand: (|k_c|^2 - |k_v|^2)/2 on the diagonal plus 8 pi / (Omega |q|^2) between transitions with the
+  same momentum transfer q = k_c - k_v.
+liouville_residual measures a solution of L z = b under liouville_apply, for the Z-vector solve.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.fft as sfft
+
+from .model import OracleCell, sphere_miller, WORKERS
+from .sternheimer import project
+
+
+def coulomb_q(cell: OracleCell):
+    """Miller indices [n_q, 3] of the 4 Ecut sphere without q = 0, and 4 pi / |q|^2 on them."""
+    mq = sphere_miller(cell.L, 4.0 * cell.ecut)
+    mq = mq[np.any(mq != 0, axis=1)]
+    q2 = np.sum((mq * cell.b) ** 2, axis=1)
+    return mq, 4.0 * math.pi / q2
+
+
+def hartree_grid(cell: OracleCell, rho_r: np.ndarray) -> np.ndarray:
+    """V[rho](r_j) for complex band-limited densities rho_r [n, N, N, N]."""
+    N = cell.N
+    mq, vq = coulomb_q(cell)
+    ix, iy, iz = (mq[:, 0] % N, mq[:, 1] % N, mq[:, 2] % N)
+    rq = sfft.fftn(rho_r, axes=(1, 2, 3), workers=WORKERS, norm="forward")  # rho(q)
+    box = np.zeros_like(rq)
+    box[:, ix, iy, iz] = vq[None, :] * rq[:, ix, iy, iz]
+    return sfft.ifftn(box, axes=(1, 2, 3), workers=WORKERS, norm="forward")  # sum_q V(q) e^{i q r}
+
+
+def liouville_apply(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, A: np.ndarray) -> np.ndarray:
+    """(D + K1e) A for A [n_exc, n_occ, npw] (oracle order); psi [n_occ, npw], eps [n_occ]."""
+    A = np.asarray(A, dtype=np.complex128)
+    n_exc, n_occ, npw = A.shape
+    Ap = project(psi, A.reshape(-1, npw)).reshape(n_exc, n_occ, npw)
+    out = np.empty_like(Ap)
+    psi_r = cell.to_grid(psi)                                    # psi~_v(r) = sqrt(Omega) psi_v(r)
+    for e in range(n_exc):
+        d = cell.h_apply(Ap[e]) - eps[:, None] * Ap[e]
+        a_r = cell.to_grid(Ap[e])
+        rho = np.sum(np.conj(psi_r) * a_r, axis=0)[None] / cell.omega
+        v = hartree_grid(cell, rho)[0]
+        k = 2.0 * cell.from_grid(v[None] * psi_r)
+        out[e] = project(psi, d + k)
+    return out
+
+
+def liouville_residual(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, b: np.ndarray, z: np.ndarray) -> np.ndarray:
+    """||b - L z|| / ||b|| per excitation (norms over all bands)."""
+    r = b - liouville_apply(cell, psi, eps, z)
+    n = b.shape[0]
+    return np.linalg.norm(r.reshape(n, -1), axis=1) / np.linalg.norm(b.reshape(n, -1), axis=1)
+
+
+def casida_tda(cell: OracleCell, n_occ: int):
+    """Dense L in the transition basis t = v * n_emp + c from a full diagonalisation of H.
+    Returns (L [n_occ n_emp, n_occ n_emp], occupied psi, eps_occ, empty psi, eps_emp)."""
+    e, U = np.linalg.eigh(cell.h_dense())
+    psi = U.T
+    occ, emp = psi[:n_occ], psi[n_occ:]
+    eo, ee = e[:n_occ], e[n_occ:]
+    n_emp = emp.shape[0]
+    N = cell.N
+    mq, vq = coulomb_q(cell)
+    ix, iy, iz = (mq[:, 0] % N, mq[:, 1] % N, mq[:, 2] % N)
+    occ_r = cell.to_grid(occ)
+    emp_r = cell.to_grid(emp)
+    rho_q = np.empty((n_occ, n_emp, len(vq)), dtype=np.complex128)
+    for v in range(n_occ):
+        rv = np.conj(occ_r[v])[None] * emp_r / cell.omega        # rho_vc(r), physical normalisation
+        rq = sfft.fftn(rv, axes=(1, 2, 3), workers=WORKERS, norm="forward")
+        rho_q[v] = rq[:, ix, iy, iz]
+    R = rho_q.reshape(n_occ * n_emp, -1)
+    L = 2.0 * cell.omega * (R.conj() * vq[None, :]) @ R.T
+    L[np.diag_indices_from(L)] += (ee[None, :] - eo[:, None]).reshape(-1)
+    return L, occ, eo, emp, ee
+
+
+def free_electron_tda(cell: OracleCell, occ_idx, emp_idx) -> np.ndarray:
+    """Hand-written L for plane-wave states (basis indices of the oracle cell): transitions
+    t = (occ_idx[v], emp_idx[c]) in the order v * len(emp_idx) + c."""
+    k = cell.miller
+    trans = [(v, c) for v in occ_idx for c in emp_idx]
+    L = np.zeros((len(trans), len(trans)))
+    for a, (v, c) in enumerate(trans):
+        qa = k[c] - k[v]
+        L[a, a] = 0.5 * (cell.g2[c] - cell.g2[v])
+        for b, (w, d) in enumerate(trans):
+            if np.array_equal(k[d] - k[w], qa):
+                L[a, b] += 8.0 * math.pi / (cell.omega * float(np.sum((qa * cell.b) ** 2)))
+    return L
