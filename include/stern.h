@@ -438,6 +438,31 @@ int stern_apply_h(stern_system* sys, int n_vec, const double* c, const double* s
  * set_occupied. Synchronous. */
 int stern_apply_pc(stern_system* sys, int n_vec, const double* c, double* out, int mem_kind);
 
+/* ---- TDDFT Liouville superoperator (Sec. II.C.1, eq. bse_tddft) ----
+ * Excitations are sets of auxiliary orbitals A = {a_v}, one per occupied band (Delta gamma =
+ * sum_v |a_v><psi_v|), stored as n_exc x n_occ rows of n_pw complex coefficients in canonical
+ * order ([n_exc][n_occ][n_pw], interleaved re, im). The paper names the terms of the Liouville
+ * superoperator but not their formulas; here: Tamm-Dancoff, closed-shell singlet excitations,
+ * Hartree kernel (the model Hamiltonian has no exchange-correlation functional, so K1d = 0):
+ *   (L A)_v = P_c (H - eps_v) a_v + 2 P_c [ V[rho_A] psi_v ],  rho_A = sum_v conj(psi_v) a_v,
+ *   V[rho](r) = sum_{0 < |q|^2 <= 4 Ecut} (4 pi / |q|^2) rho(q) e^{i q.r},
+ * applied to P_c A. L is Hermitian in <A|B> = sum_v <a_v|b_v> and positive definite when the gap
+ * is open. FP64 throughout; grids up to 96^3 (STERN_ERR_UNSUPPORTED above: the Hartree stage
+ * keeps whole FP64 planes in LDS). STERN_ERR_STATE before set_occupied.
+ *
+ * out = L A, host or device arrays per mem_kind (they may not overlap). Synchronous. */
+int stern_liouville_apply(stern_system* sys, int n_exc, const double* a, double* out, int mem_kind);
+
+/* Linear systems L z_e = b_e of the Liouville superoperator, as the Z-vector equations of
+ * excited-state forces pose them (Sec. II.C.2), for n_exc right-hand sides b [n_exc][n_occ][n_pw]
+ * (projected on range(P_c) first): preconditioned CG with one block (all band rows) per
+ * excitation, Teter's diagonal per band, from z = 0, at most max_iter (0 = 1000) iterations,
+ * accepted on the true residual ||b - L z|| <= tol ||b|| (norms over all bands). iters and resid
+ * (host, n_exc each) may be NULL. Returns STERN_OK, STERN_WARN_NOT_CONVERGED (z written) or an
+ * error. Synchronous. */
+int stern_liouville_solve(stern_system* sys, int n_exc, const double* b, double* z, double tol, int max_iter,
+                          int mem_kind, int* iters, double* resid);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): out = P_c c as
  * stern_apply_pc computes it (the same kernels, so bitwise the same result),

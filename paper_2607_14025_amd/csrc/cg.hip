@@ -763,6 +763,54 @@ __global__ __launch_bounds__(kCgThreads) void k_cocg_true(CgState S, double u, c
   }
 }
 
+// ---- block vectors of the Liouville solve: one block = the nb band rows of one excitation ----
+
+// out[row] = sum_k conj(a[row][k]) b[row][k], fixed order
+__global__ __launch_bounds__(kCgThreads) void k_row_dot(const Z64* __restrict__ a, const Z64* __restrict__ b, int ld,
+                                                        Z64* __restrict__ out) {
+  __shared__ double sh[kCgThreads / 64];
+  const size_t o = (size_t)blockIdx.x * ld;
+  Z64 d = zmk(0.0, 0.0);
+  for (int k = threadIdx.x; k < ld; k += kCgThreads) {
+    const Z64 x = a[o + k], y = b[o + k];
+    d.re += x.re * y.re + x.im * y.im;
+    d.im += x.re * y.im - x.im * y.re;
+  }
+  d = block_sum_z(d, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = d;
+}
+
+// y[row] += c[row / nb] x[row]
+__global__ __launch_bounds__(kCgThreads) void k_blk_axpy(Z64* __restrict__ y, const Z64* __restrict__ x,
+                                                         const Z64* __restrict__ c, int nb, int ld) {
+  const Z64 a = c[blockIdx.x / nb];
+  const size_t o = (size_t)blockIdx.x * ld;
+  for (int k = threadIdx.x; k < ld; k += kCgThreads) {
+    const Z64 v = x[o + k], w = y[o + k];
+    y[o + k] = zmk(w.re + a.re * v.re - a.im * v.im, w.im + a.re * v.im + a.im * v.re);
+  }
+}
+
+// p[row] = z[row] + c[row / nb] p[row]
+__global__ __launch_bounds__(kCgThreads) void k_blk_xpby(Z64* __restrict__ p, const Z64* __restrict__ z,
+                                                         const Z64* __restrict__ c, int nb, int ld) {
+  const Z64 a = c[blockIdx.x / nb];
+  const size_t o = (size_t)blockIdx.x * ld;
+  for (int k = threadIdx.x; k < ld; k += kCgThreads) {
+    const Z64 v = p[o + k], w = z[o + k];
+    p[o + k] = zmk(w.re + a.re * v.re - a.im * v.im, w.im + a.re * v.im + a.im * v.re);
+  }
+}
+
+// z[row][k] = K_v(G) r[row][k], Teter's K with T_v of band v = row mod nb
+__global__ __launch_bounds__(kCgThreads) void k_teter_rows(const Z64* __restrict__ r, Z64* __restrict__ z,
+                                                           const double* __restrict__ g2h,
+                                                           const double* __restrict__ invT, int nb, int ld) {
+  const double iT = invT[blockIdx.x % nb];
+  const size_t o = (size_t)blockIdx.x * ld;
+  for (int k = threadIdx.x; k < ld; k += kCgThreads) z[o + k] = zscale(r[o + k], teter(g2h[k], iT));
+}
+
 }  // namespace
 
 void launch_cocg_start(const CgState& s, const int* negk, double* rzi, const int* act, int n, int from,
@@ -934,4 +982,18 @@ void launch_fill_zero32(Z32* p, size_t n, hipStream_t st) {
   if (blocks > 65536) blocks = 65536;
   k_fill_zero32<<<(unsigned)blocks, 256, 0, st>>>(p, n);
 }
+void launch_row_dot(const Z64* a, const Z64* b, int ld, int nrows, Z64* out, hipStream_t st) {
+  if (nrows > 0) k_row_dot<<<nrows, kCgThreads, 0, st>>>(a, b, ld, out);
+}
+void launch_blk_axpy(Z64* y, const Z64* x, const Z64* c, int nb, int ld, int nrows, hipStream_t st) {
+  if (nrows > 0) k_blk_axpy<<<nrows, kCgThreads, 0, st>>>(y, x, c, nb, ld);
+}
+void launch_blk_xpby(Z64* p, const Z64* z, const Z64* c, int nb, int ld, int nrows, hipStream_t st) {
+  if (nrows > 0) k_blk_xpby<<<nrows, kCgThreads, 0, st>>>(p, z, c, nb, ld);
+}
+void launch_teter_rows(const Z64* r, Z64* z, const double* g2h, const double* invT, int nb, int ld, int nrows,
+                       hipStream_t st) {
+  if (nrows > 0) k_teter_rows<<<nrows, kCgThreads, 0, st>>>(r, z, g2h, invT, nb, ld);
+}
+
 }  // namespace stern

@@ -229,4 +229,21 @@ void launch_expand_bf16(const __bf16* ATh, const __bf16* ATl, int M_pad, const _
                         const int* yidx, int ncols, int K, int variant, hipStream_t st, Z32* P = nullptr,
                         const double* beta = nullptr, const int* live = nullptr);
 
+// ---- TDDFT Liouville apply and its block solve (tddft.hip, cg.hip) ----
+// rho[e] = scale sum_v conj(psi_r[v]) a_r[e nb + v] on full N^3 grids (n3 points each)
+void launch_band_density(const Z64* psi_r, const Z64* a_r, int n_exc, int nb, size_t n3, double scale, Z64* rho,
+                         hipStream_t st);
+// c[n][k] *= fac / g2h[k] for nvec rows of K coefficients, zero where g2h = 0
+void launch_coulomb(Z64* c, const double* g2h, int K, int nvec, double fac, hipStream_t st);
+// out[e nb + v] = v_r[e] psi_r[v] on full grids (n_exc nb <= 65535 rows)
+void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t n3, Z64* out, hipStream_t st);
+void launch_add(Z64* y, const Z64* x, size_t n, hipStream_t st);
+// per-row conj(a) . b; y[row] += c[row / nb] x[row]; p[row] = z[row] + c[row / nb] p[row];
+// z = Teter K_v r with T_v of band row mod nb
+void launch_row_dot(const Z64* a, const Z64* b, int ld, int nrows, Z64* out, hipStream_t st);
+void launch_blk_axpy(Z64* y, const Z64* x, const Z64* c, int nb, int ld, int nrows, hipStream_t st);
+void launch_blk_xpby(Z64* p, const Z64* z, const Z64* c, int nb, int ld, int nrows, hipStream_t st);
+void launch_teter_rows(const Z64* r, Z64* z, const double* g2h, const double* invT, int nb, int ld, int nrows,
+                       hipStream_t st);
+
 }  // namespace stern

@@ -190,6 +190,12 @@ struct stern_system {
   DBuf c_col_start, c_col_len, c_col_xmin, c_col_pos, c_zl, c_ycol, c_tw64, psi_c, c_pen, c_field, net_a0, net_a1,
       net_a2, net_out, g_rej, net_feat, net_coef, kprec, band_eps, band_invT, band_feat;
   int ws_solves = 0, ws32_solves = 0;
+  // 4 Ecut sphere on the same grid (densities and the Hartree potential of the Liouville apply),
+  // built at its first use, and the Liouville work buffers
+  bool have_dens = false;
+  HostBasis hbd;
+  DBuf d_col_start, d_col_len, d_col_xmin, d_col_pos, d_zl, d_ycol, d_g2h;
+  DBuf lv_ar, lv_rho, lv_rhog, lv_pend, lv_k, lv_eps, lv_dot, lv_coef;
 
   // per-launch event profile (opts->profile)
   struct Rec {
@@ -226,6 +232,29 @@ struct stern_system {
     return g;
   }
 
+  FftGeom geom_d() const {
+    FftGeom g;
+    g.N = hbd.N;
+    g.npw = hbd.npw;
+    g.npw_pad = hbd.npw_pad;
+    g.ncol = hbd.ncol;
+    g.ncol_pad = hbd.ncol_pad;
+    g.nza = hbd.nza;
+    g.col_start = d_col_start.as<int>();
+    g.col_len = d_col_len.as<int>();
+    g.col_xmin = d_col_xmin.as<int>();
+    g.col_pos = d_col_pos.as<int>();
+    g.zl = d_zl.as<int>();
+    g.ycol = d_ycol.as<int>();
+    g.zact_lo = hbd.zact_lo;
+    g.zact_hi = hbd.zact_hi;
+    g.n_cu = n_cu;
+    g.g2h = d_g2h.as<double>();
+    g.tw64 = tw64.as<Z64>();  // same grid
+    g.tw32 = nullptr;
+    return g;
+  }
+
   FftGeom geom_c() const {
     FftGeom g;
     g.N = hbc.N;
@@ -259,7 +288,9 @@ struct stern_system {
                    &m_rr0,     &m_flag,   &c_col_start, &c_col_len, &c_col_xmin, &c_col_pos, &c_zl, &c_ycol,
                    &c_tw64,    &psi_c,    &c_pen,   &c_field,  &net_a0,  &net_a1,   &net_a2,   &net_out,
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
-                   &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi, &xkeep};
+                   &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi, &xkeep,
+                   &d_col_start, &d_col_len, &d_col_xmin, &d_col_pos, &d_zl, &d_ycol, &d_g2h, &lv_ar, &lv_rho,
+                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -1466,6 +1497,230 @@ int stern_apply_h(stern_system* S, int n_vec, const double* c, const double* shi
   CHECKED(apply_h_rows(S, S->wp.as<Z64>(), S->wq.as<Z64>(), nullptr, n_vec, S->sv_eps.as<double>()));
   CHECKED(launch_check());
   return rows_out(S, n_vec, S->wq.as<Z64>(), nullptr, out, mem_kind);
+}
+
+// ---- TDDFT Liouville superoperator (Tamm-Dancoff, Hartree kernel) ----------
+
+// the 4 Ecut sphere on the system's grid: transition densities and the Hartree potential
+static int ensure_density_geom(stern_system* S) {
+  if (S->have_dens) return 0;
+  const HostBasis& hb = S->hb;
+  if (plane_lds_bytes(hb.N, sizeof(Z64)) > S->lds_max)
+    return fail(STERN_ERR_UNSUPPORTED, "grid %d: the Liouville apply needs full FP64 planes in LDS (N <= 96)", hb.N);
+  CellParams pd;
+  pd.L = hb.L;
+  pd.ecut = 4.0 * hb.ecut;
+  pd.fft_n = hb.N;
+  const std::string e = build_basis(pd, S->hbd, true);
+  if (!e.empty()) return fail(STERN_ERR_UNSUPPORTED, "density sphere: %s", e.c_str());
+  const HostBasis& d = S->hbd;
+  hipStream_t st = S->stream;
+  CHECKED(upload(S->d_col_start, d.col_start.data(), d.col_start.size() * sizeof(int), st));
+  CHECKED(upload(S->d_col_len, d.col_len.data(), d.col_len.size() * sizeof(int), st));
+  CHECKED(upload(S->d_col_xmin, d.col_xmin.data(), d.col_xmin.size() * sizeof(int), st));
+  CHECKED(upload(S->d_col_pos, d.col_pos.data(), d.col_pos.size() * sizeof(int), st));
+  CHECKED(upload(S->d_zl, d.zl.data(), d.zl.size() * sizeof(int), st));
+  CHECKED(upload(S->d_ycol, d.ycol.data(), d.ycol.size() * sizeof(int), st));
+  CHECKED(upload(S->d_g2h, d.g2h.data(), d.g2h.size() * sizeof(double), st));
+  HIPOK(hipStreamSynchronize(st));
+  S->have_dens = true;
+  return 0;
+}
+
+// excitations per chunk of the grid stage: ce nb full grids of a_r and their pencils in flight
+static int liouville_chunk(const stern_system* S, int n_exc) {
+  const size_t n3 = (size_t)S->hb.N * S->hb.N * S->hb.N, nb = S->n_occ;
+  const size_t per = nb * (n3 + (size_t)S->hb.N * S->hb.ncol_pad + S->hb.npw_pad) * sizeof(Z64);
+  const size_t budget = (size_t)2 << 30;
+  int ce = (int)std::max<size_t>(1, budget / per);
+  ce = std::min(ce, std::max(1, 65535 / (int)nb));  // rows of one grid launch
+  return std::min(ce, n_exc);
+}
+
+// out = L A for n_exc excitations of n_occ band rows each (column order, stride npw_pad; A in
+// range(P_c)): out_v = P_c [ (H - eps_v) a_v + 2 V[rho_A] psi_v ], rho_A = sum_v conj(psi_v) a_v,
+// V[rho] = sum_{0 < |q|^2 <= 4 Ecut} 4 pi / |q|^2 rho(q) e^{i q.r}.
+static int liouville_rows(stern_system* S, const Z64* A, Z64* out, int n_exc) {
+  const HostBasis& hb = S->hb;
+  const int nb = S->n_occ, K = hb.npw_pad, N = hb.N, n = n_exc * nb;
+  const size_t n3 = (size_t)N * N * N;
+  hipStream_t st = S->stream;
+  const FftGeom g = S->geom(), gd = S->geom_d();
+  const int Kd = S->hbd.npw_pad;
+  const int ce = liouville_chunk(S, n_exc);
+  CHECKED(S->lv_ar.ensure((size_t)ce * nb * n3 * sizeof(Z64)));
+  CHECKED(S->lv_rho.ensure((size_t)ce * n3 * sizeof(Z64)));
+  CHECKED(S->lv_rhog.ensure((size_t)ce * Kd * sizeof(Z64)));
+  CHECKED(S->lv_pend.ensure((size_t)ce * N * S->hbd.ncol_pad * sizeof(Z64)));
+  CHECKED(S->lv_k.ensure((size_t)n * K * sizeof(Z64)));
+  CHECKED(S->lv_eps.ensure((size_t)n * sizeof(double)));
+  {
+    std::vector<double> e(n);
+    for (int r = 0; r < n; ++r) e[r] = S->eps[r % nb];
+    HIPOK(hipMemcpyAsync(S->lv_eps.p, e.data(), n * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPOK(hipStreamSynchronize(st));
+  }
+  // D A
+  CHECKED(apply_h_rows(S, A, out, nullptr, n, S->lv_eps.as<double>()));
+  // K1e A, ce excitations at a time
+  Z64* ar = S->lv_ar.as<Z64>();
+  Z64* rho = S->lv_rho.as<Z64>();
+  Z64* kt = S->lv_k.as<Z64>();
+  launch_fill_zero(kt, (size_t)n * K, st);  // the padding entries are added to out below
+  for (int e0 = 0; e0 < n_exc; e0 += ce) {
+    const int c = std::min(ce, n_exc - e0), m = c * nb;
+    const Z64* Ae = A + (size_t)e0 * nb * K;
+    for (int r0 = 0; r0 < m; r0 += S->ws_solves) {  // pencils hold ws_solves rows
+      const int rm = std::min(S->ws_solves, m - r0);
+      launch_xinv(g, Ae + (size_t)r0 * K, nullptr, rm, S->pen.as<Z64>(), st);
+      launch_plane_full_inv(g, S->pen.as<Z64>(), rm, ar + (size_t)r0 * n3, st);
+    }
+    launch_band_density(S->psi_r.as<Z64>(), ar, c, nb, n3, 1.0 / hb.omega, rho, st);
+    launch_plane_full_fwd(gd, rho, c, S->lv_pend.as<Z64>(), st);
+    launch_xfwd<double>(gd, S->lv_pend.as<Z64>(), nullptr, c, S->lv_rhog.as<Z64>(), 2, nullptr, nullptr,
+                        1.0 / (double)n3, st);
+    // 2 x 4 pi / |q|^2 = 4 pi / (|q|^2 / 2): the factor 2 of the singlet exchange term folded in
+    launch_coulomb(S->lv_rhog.as<Z64>(), gd.g2h, Kd, c, 4.0 * 3.14159265358979323846, st);
+    launch_xinv(gd, S->lv_rhog.as<Z64>(), nullptr, c, S->lv_pend.as<Z64>(), st);
+    launch_plane_full_inv(gd, S->lv_pend.as<Z64>(), c, rho, st);
+    launch_grid_mul(rho, S->psi_r.as<Z64>(), c, nb, n3, ar, st);
+    for (int r0 = 0; r0 < m; r0 += S->ws_solves) {
+      const int rm = std::min(S->ws_solves, m - r0);
+      launch_plane_full_fwd(g, ar + (size_t)r0 * n3, rm, S->pen.as<Z64>(), st);
+      launch_xfwd<double>(g, S->pen.as<Z64>(), nullptr, rm, kt + ((size_t)e0 * nb + r0) * K, 2, nullptr, nullptr,
+                          1.0 / (double)n3, st);
+    }
+  }
+  launch_add(out, kt, (size_t)n * K, st);
+  CHECKED(apply_pc_rows(S, out, nullptr, n));
+  return launch_check();
+}
+
+static int liouville_setup(stern_system* S, int n_exc) {
+  if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");
+  if (n_exc <= 0) return fail(STERN_ERR_INVALID_ARG, "n_exc must be > 0");
+  CHECKED(ensure_density_geom(S));
+  const int nb = S->n_occ;
+  // pencils for whole excitations' rows at a time (the chunk), and the six block vectors of the solve
+  CHECKED(ensure_workspace(S, std::max(S->ws_solves, std::max(n_exc * nb, liouville_chunk(S, n_exc) * nb))));
+  return 0;
+}
+
+int stern_liouville_apply(stern_system* S, int n_exc, const double* a, double* out, int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!a || !out) return fail(STERN_ERR_INVALID_ARG, "NULL array");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  Scope sc(S->device, &S->alloc);
+  CHECKED(liouville_setup(S, n_exc));
+  const int n = n_exc * S->n_occ;
+  CHECKED(rows_in(S, n, a, mem_kind, S->wp));
+  CHECKED(apply_pc_rows(S, S->wp.as<Z64>(), nullptr, n));
+  CHECKED(liouville_rows(S, S->wp.as<Z64>(), S->wq.as<Z64>(), n_exc));
+  return rows_out(S, n, S->wq.as<Z64>(), nullptr, out, mem_kind);
+}
+
+// per-excitation sums of the per-row dots conj(a) . b (bands in order)
+static int block_dots(stern_system* S, const Z64* a, const Z64* b, int n_exc, std::vector<Z64>& out) {
+  const int nb = S->n_occ, n = n_exc * nb;
+  launch_row_dot(a, b, S->hb.npw_pad, n, S->lv_dot.as<Z64>(), S->stream);
+  std::vector<Z64> h(n);
+  HIPOK(hipMemcpyAsync(h.data(), S->lv_dot.p, n * sizeof(Z64), hipMemcpyDeviceToHost, S->stream));
+  HIPOK(hipStreamSynchronize(S->stream));
+  out.assign(n_exc, zmk(0.0, 0.0));
+  for (int e = 0; e < n_exc; ++e)
+    for (int v = 0; v < nb; ++v) out[e] = out[e] + h[(size_t)e * nb + v];
+  return 0;
+}
+
+static int upload_coef(stern_system* S, const std::vector<Z64>& c) {
+  HIPOK(hipMemcpyAsync(S->lv_coef.p, c.data(), c.size() * sizeof(Z64), hipMemcpyHostToDevice, S->stream));
+  HIPOK(hipStreamSynchronize(S->stream));  // c may be released or changed on return
+  return 0;
+}
+
+// z = P_c K r per band row (Teter's K with the band's T_v)
+static int precond_rows(stern_system* S, const Z64* r, Z64* z, int n) {
+  launch_teter_rows(r, z, S->g2h.as<double>(), S->band_invT.as<double>(), S->n_occ, S->hb.npw_pad, n, S->stream);
+  return apply_pc_rows(S, z, nullptr, n);
+}
+
+// L z = b by preconditioned CG, one block (all band rows) per excitation: L is Hermitian and,
+// with the gap open, positive definite on range(P_c)^n_occ; the block inner product sums the
+// band rows. Converged when the recurrence residual meets tol, then judged by the true one.
+int stern_liouville_solve(stern_system* S, int n_exc, const double* b, double* z, double tol, int max_iter,
+                          int mem_kind, int* iters, double* resid) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!b || !z) return fail(STERN_ERR_INVALID_ARG, "NULL array");
+  if (!(tol > 0)) return fail(STERN_ERR_INVALID_ARG, "tol must be > 0");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  Scope sc(S->device, &S->alloc);
+  CHECKED(liouville_setup(S, n_exc));
+  const int nb = S->n_occ, n = n_exc * nb, K = S->hb.npw_pad;
+  const int mi = max_iter > 0 ? max_iter : 1000;
+  hipStream_t st = S->stream;
+  CHECKED(S->lv_dot.ensure((size_t)n * sizeof(Z64)));
+  CHECKED(S->lv_coef.ensure((size_t)n_exc * sizeof(Z64)));
+  Z64 *X = S->wx.as<Z64>(), *R = S->wr.as<Z64>(), *P = S->wp.as<Z64>(), *Q = S->wq.as<Z64>(), *Zv = S->wz.as<Z64>(),
+      *B = S->wb.as<Z64>();
+  CHECKED(rows_in(S, n, b, mem_kind, S->wb));
+  CHECKED(apply_pc_rows(S, B, nullptr, n));
+  launch_fill_zero(X, (size_t)n * K, st);
+  HIPOK(hipMemcpyAsync(R, B, (size_t)n * K * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+  CHECKED(precond_rows(S, R, Zv, n));
+  HIPOK(hipMemcpyAsync(P, Zv, (size_t)n * K * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+  std::vector<Z64> d;
+  CHECKED(block_dots(S, B, B, n_exc, d));
+  std::vector<double> bb(n_exc), rz(n_exc);
+  for (int e = 0; e < n_exc; ++e) bb[e] = d[e].re;
+  CHECKED(block_dots(S, R, Zv, n_exc, d));
+  for (int e = 0; e < n_exc; ++e) rz[e] = d[e].re;
+  std::vector<int> it(n_exc, 0);
+  std::vector<char> done(n_exc, 0);
+  for (int e = 0; e < n_exc; ++e) done[e] = !(bb[e] > 0.0);  // b = 0: z = 0
+  std::vector<Z64> c(n_exc);
+  for (int k = 0; k < mi; ++k) {
+    bool any = false;
+    for (int e = 0; e < n_exc; ++e) any |= !done[e];
+    if (!any) break;
+    CHECKED(liouville_rows(S, P, Q, n_exc));
+    CHECKED(block_dots(S, P, Q, n_exc, d));
+    for (int e = 0; e < n_exc; ++e) c[e] = zmk(done[e] || !(d[e].re > 0.0) ? 0.0 : rz[e] / d[e].re, 0.0);
+    CHECKED(upload_coef(S, c));
+    launch_blk_axpy(X, P, S->lv_coef.as<Z64>(), nb, K, n, st);
+    for (int e = 0; e < n_exc; ++e) c[e].re = -c[e].re;
+    CHECKED(upload_coef(S, c));
+    launch_blk_axpy(R, Q, S->lv_coef.as<Z64>(), nb, K, n, st);
+    CHECKED(block_dots(S, R, R, n_exc, d));
+    for (int e = 0; e < n_exc; ++e)
+      if (!done[e]) {
+        ++it[e];
+        if (d[e].re <= tol * tol * bb[e]) done[e] = 1;
+      }
+    CHECKED(precond_rows(S, R, Zv, n));
+    CHECKED(block_dots(S, R, Zv, n_exc, d));
+    for (int e = 0; e < n_exc; ++e) {
+      c[e] = zmk(done[e] || !(rz[e] > 0.0) ? 0.0 : d[e].re / rz[e], 0.0);
+      rz[e] = d[e].re;
+    }
+    CHECKED(upload_coef(S, c));
+    launch_blk_xpby(P, Zv, S->lv_coef.as<Z64>(), nb, K, n, st);
+  }
+  // true residual b - L x
+  CHECKED(liouville_rows(S, X, Q, n_exc));
+  HIPOK(hipMemcpyAsync(R, B, (size_t)n * K * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+  for (int e = 0; e < n_exc; ++e) c[e] = zmk(-1.0, 0.0);
+  CHECKED(upload_coef(S, c));
+  launch_blk_axpy(R, Q, S->lv_coef.as<Z64>(), nb, K, n, st);
+  CHECKED(block_dots(S, R, R, n_exc, d));
+  bool all_ok = true;
+  for (int e = 0; e < n_exc; ++e) {
+    const double res = bb[e] > 0.0 ? std::sqrt(std::max(0.0, d[e].re) / bb[e]) : 0.0;
+    all_ok &= res <= tol;
+    if (resid) resid[e] = res;
+    if (iters) iters[e] = it[e];
+  }
+  CHECKED(rows_out(S, n, X, nullptr, z, mem_kind));
+  return all_ok ? STERN_OK : STERN_WARN_NOT_CONVERGED;
 }
 
 int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int mem_kind) {

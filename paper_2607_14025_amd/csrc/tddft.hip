@@ -1,0 +1,95 @@
+// Grid kernels of the TDDFT Liouville apply (Tamm-Dancoff, Hartree kernel; Sec. II.C.1,
+// eq. bse_tddft): the band-summed transition densities rho_e = sum_v conj(psi_v) a_{e,v}, the
+// Coulomb factor on the 4 Ecut sphere, and the products V_e psi_v. All of it is streaming work on
+// full N^3 grids (one read and one write per point and band), so the kernels are plain
+// grid-stride loops with coalesced complex FP64 accesses; the FFTs between them are the
+// library's pencil and plane kernels.
+#include "kernels.hpp"
+
+namespace stern {
+
+namespace {
+
+constexpr int kGridThreads = 256;
+
+// rho[e][j] = scale sum_v conj(psi_r[v][j]) a_r[e nb + v][j], bands summed in order
+__global__ __launch_bounds__(kGridThreads) void k_band_density(const Z64* __restrict__ psi_r,
+                                                               const Z64* __restrict__ a_r, int nb, size_t n3,
+                                                               double scale, Z64* __restrict__ rho) {
+  const int e = blockIdx.y;
+  const Z64* ae = a_r + (size_t)e * nb * n3;
+  for (size_t j = (size_t)blockIdx.x * kGridThreads + threadIdx.x; j < n3; j += (size_t)gridDim.x * kGridThreads) {
+    double re = 0.0, im = 0.0;
+    for (int v = 0; v < nb; ++v) {
+      const Z64 p = psi_r[(size_t)v * n3 + j], a = ae[(size_t)v * n3 + j];
+      re += p.re * a.re + p.im * a.im;
+      im += p.re * a.im - p.im * a.re;
+    }
+    rho[(size_t)e * n3 + j] = zmk(scale * re, scale * im);
+  }
+}
+
+// c[i] *= fac / g2h[i mod K]; zero where g2h = 0 (G = 0 and the padding, whatever they held)
+__global__ __launch_bounds__(kGridThreads) void k_coulomb(Z64* __restrict__ c, const double* __restrict__ g2h, int K,
+                                                          size_t total, double fac) {
+  for (size_t i = (size_t)blockIdx.x * kGridThreads + threadIdx.x; i < total; i += (size_t)gridDim.x * kGridThreads) {
+    const double h = g2h[i % K];
+    const Z64 v = c[i];
+    c[i] = h > 0.0 ? zmk(fac / h * v.re, fac / h * v.im) : zmk(0.0, 0.0);
+  }
+}
+
+// out[e nb + v][j] = v_r[e][j] psi_r[v][j]
+__global__ __launch_bounds__(kGridThreads) void k_grid_mul(const Z64* __restrict__ v_r, const Z64* __restrict__ psi_r,
+                                                           int nb, size_t n3, Z64* __restrict__ out) {
+  const int row = blockIdx.y, e = row / nb, v = row - e * nb;
+  const Z64* ve = v_r + (size_t)e * n3;
+  const Z64* pv = psi_r + (size_t)v * n3;
+  Z64* o = out + (size_t)row * n3;
+  for (size_t j = (size_t)blockIdx.x * kGridThreads + threadIdx.x; j < n3; j += (size_t)gridDim.x * kGridThreads) {
+    const Z64 a = ve[j], p = pv[j];
+    o[j] = zmk(a.re * p.re - a.im * p.im, a.re * p.im + a.im * p.re);
+  }
+}
+
+// y[i] += x[i]
+__global__ __launch_bounds__(kGridThreads) void k_add(Z64* __restrict__ y, const Z64* __restrict__ x, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kGridThreads + threadIdx.x; i < n; i += (size_t)gridDim.x * kGridThreads) {
+    const Z64 a = y[i], b = x[i];
+    y[i] = zmk(a.re + b.re, a.im + b.im);
+  }
+}
+
+unsigned grid_blocks(size_t n, int per_row_rows) {
+  // enough workgroups to fill the chip several times over, fewer when a launch has many rows
+  const size_t want = std::max<size_t>(1, 2048 / (size_t)std::max(1, per_row_rows));
+  return (unsigned)std::max<size_t>(1, std::min<size_t>((n + kGridThreads - 1) / kGridThreads, want));
+}
+
+}  // namespace
+
+void launch_band_density(const Z64* psi_r, const Z64* a_r, int n_exc, int nb, size_t n3, double scale, Z64* rho,
+                         hipStream_t st) {
+  if (n_exc <= 0 || nb <= 0) return;
+  dim3 grid(grid_blocks(n3, n_exc), n_exc);
+  k_band_density<<<grid, kGridThreads, 0, st>>>(psi_r, a_r, nb, n3, scale, rho);
+}
+
+void launch_coulomb(Z64* c, const double* g2h, int K, int nvec, double fac, hipStream_t st) {
+  const size_t total = (size_t)K * nvec;
+  if (total == 0) return;
+  k_coulomb<<<grid_blocks(total, 1), kGridThreads, 0, st>>>(c, g2h, K, total, fac);
+}
+
+void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t n3, Z64* out, hipStream_t st) {
+  if (n_exc <= 0 || nb <= 0) return;
+  dim3 grid(grid_blocks(n3, n_exc * nb), n_exc * nb);
+  k_grid_mul<<<grid, kGridThreads, 0, st>>>(v_r, psi_r, nb, n3, out);
+}
+
+void launch_add(Z64* y, const Z64* x, size_t n, hipStream_t st) {
+  if (n == 0) return;
+  k_add<<<grid_blocks(n, 1), kGridThreads, 0, st>>>(y, x, n);
+}
+
+}  // namespace stern

@@ -31,7 +31,8 @@ EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_m
             "stern_apply_chi0_many", "stern_model_create", "stern_model_train", "stern_model_num_params",
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
-            "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc"]
+            "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc", "stern_liouville_apply",
+            "stern_liouville_solve"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -144,6 +145,9 @@ def lib():
         L.stern_apply_h.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
+        L.stern_liouville_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        L.stern_liouville_solve.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
+                                            P(C.c_int), P(C.c_double)]
         L.stern_pdep_basis.argtypes = [C.c_void_p, C.c_double, P(C.c_int), P(C.c_int32)]
         L.stern_pdep_davidson.argtypes = [C.c_void_p, P(PdepOpts), P(C.c_double), P(C.c_double), P(PdepStats)]
         L.stern_free.argtypes = [C.c_void_p]
@@ -473,6 +477,32 @@ class System:
         _check(lib().stern_apply_pc(self._h, c.shape[0], C.c_void_p(c.ctypes.data), C.c_void_p(out.ctypes.data),
                                     STERN_MEM_HOST))
         return out
+
+    def _exc_rows(self, a):
+        a = np.ascontiguousarray(a, dtype=np.complex128)
+        if a.ndim != 3 or a.shape[1] != self.n_occ or a.shape[2] != self.n_pw:
+            raise ValueError(f"excitations must be [n_exc, {self.n_occ}, {self.n_pw}] complex")
+        return a
+
+    def liouville_apply(self, a):
+        """L A of the TDDFT Liouville superoperator (stern_liouville_apply) for a [n_exc, n_occ, n_pw]."""
+        a = self._exc_rows(a)
+        out = np.empty_like(a)
+        _check(lib().stern_liouville_apply(self._h, a.shape[0], C.c_void_p(a.ctypes.data),
+                                           C.c_void_p(out.ctypes.data), STERN_MEM_HOST))
+        return out
+
+    def liouville_solve(self, b, tol=1e-10, max_iter=0):
+        """z with L z = b (stern_liouville_solve); returns (z, iterations [n_exc], true residuals [n_exc], rc)."""
+        b = self._exc_rows(b)
+        z = np.empty_like(b)
+        it = np.zeros(b.shape[0], dtype=np.int32)
+        res = np.zeros(b.shape[0])
+        rc = _check(lib().stern_liouville_solve(self._h, b.shape[0], C.c_void_p(b.ctypes.data), C.c_void_p(z.ctypes.data),
+                                                float(tol), int(max_iter), STERN_MEM_HOST,
+                                                it.ctypes.data_as(C.POINTER(C.c_int)),
+                                                res.ctypes.data_as(C.POINTER(C.c_double))))
+        return z, it, res, rc
 
 
 class Model:

@@ -1,0 +1,152 @@
+"""TDDFT Liouville superoperator through the C ABI (stern_liouville_apply, stern_liouville_solve)
+against the oracle: the grid route on the tiny cell, the transition-basis matrix of a full
+diagonalisation on a micro cell, the free-electron closed form, and the Z-vector solve against the
+oracle's residual and a dense solve."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import OracleCell
+from oracle.liouville import casida_tda, liouville_apply, liouville_residual
+
+pytestmark = pytest.mark.gpu
+
+MICRO_L, MICRO_ECUT, MICRO_OCC = 8.0, 6.0, 4
+
+
+def _system(*args, **kw):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2607_14025_amd import System
+    return System(*args, **kw)
+
+
+@pytest.fixture(scope="module")
+def tiny_sys(tiny_system):
+    sp, gs = tiny_system["spec"], tiny_system["gs"]
+    s = _system(sp.L, sp.ecut, gs["pos"])
+    s.set_occupied(gs["psi"], gs["eps"])
+    yield s
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def micro():
+    pos = np.random.default_rng(7).uniform(0.0, MICRO_L, size=(3, 3))
+    cell = OracleCell(MICRO_L, MICRO_ECUT, pos)
+    L, occ, eo, emp, ee = casida_tda(cell, MICRO_OCC)
+    s = _system(MICRO_L, MICRO_ECUT, pos)
+    mil = s.miller()
+    s.set_occupied(cell.give(occ, mil), eo)
+    yield dict(cell=cell, L=L, occ=occ, eo=eo, emp=emp, sys=s, mil=mil)
+    s.close()
+
+
+def _to_oracle(cell, rows, mil):
+    n_e, nb, npw = rows.shape
+    return cell.take(rows.reshape(-1, npw), mil).reshape(n_e, nb, npw)
+
+
+def _to_lib(cell, rows, mil):
+    n_e, nb, npw = rows.shape
+    return cell.give(rows.reshape(-1, npw), mil).reshape(n_e, nb, npw)
+
+
+def test_apply_matches_oracle_on_the_tiny_cell(tiny_system, tiny_sys):
+    """Random excitations with occupied components (the apply projects them out first)."""
+    t = tiny_system
+    cell, mil = t["cell"], t["gs"]["miller"]
+    nb, npw = tiny_sys.n_occ, tiny_sys.n_pw
+    rng = np.random.default_rng(21)
+    a = rng.standard_normal((3, nb, npw)) + 1j * rng.standard_normal((3, nb, npw))
+    print(f"case: tiny cell, 3 excitations x {nb} bands, grid {tiny_sys.fft_n}", flush=True)
+    out = tiny_sys.liouville_apply(a)
+    ref = liouville_apply(cell, t["psi"], t["eps"], _to_oracle(cell, a, mil))
+    got = _to_oracle(cell, out, mil)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print(f"  max rel error {err:.2e}")
+    assert err <= 1e-12
+
+
+def test_apply_matches_the_transition_matrix(micro):
+    cell, L, emp, s, mil = micro["cell"], micro["L"], micro["emp"], micro["sys"], micro["mil"]
+    n_emp = emp.shape[0]
+    cols = np.random.default_rng(3).choice(L.shape[0], size=8, replace=False)
+    A = np.zeros((len(cols), MICRO_OCC, cell.npw), dtype=np.complex128)
+    for k, t in enumerate(cols):
+        v, c = divmod(int(t), n_emp)
+        A[k, v] = emp[c]
+    print(f"case: micro cell, grid {s.fft_n}, {MICRO_OCC} bands, {n_emp} empty states", flush=True)
+    out = _to_oracle(cell, s.liouville_apply(_to_lib(cell, A, mil)), mil)
+    for k, t in enumerate(cols):
+        col = (out[k] @ emp.conj().T).reshape(-1)
+        assert np.abs(col - L[:, t]).max() <= 1e-11 * np.abs(L).max()
+
+
+def test_free_electron_closed_form():
+    """One occupied plane wave G = 0: L A = (|G|^2/2 + 8 pi / (Omega |G|^2)) A for A = e^{i G.r}."""
+    cell = OracleCell(MICRO_L, MICRO_ECUT, np.zeros((0, 3)), amp=0.0, D=0.0)
+    s = _system(MICRO_L, MICRO_ECUT, np.zeros((0, 3)), vloc_amp=0.0, kb_D=0.0)
+    mil = s.miller()
+    psi = np.zeros((1, cell.npw), dtype=np.complex128)
+    psi[0, 0] = 1.0                                     # oracle index 0 is G = 0
+    s.set_occupied(cell.give(psi, mil), np.zeros(1))
+    cs = [1, 7, 20, cell.npw - 1]
+    A = np.zeros((len(cs), 1, cell.npw), dtype=np.complex128)
+    for k, c in enumerate(cs):
+        A[k, 0, c] = 1.0
+    out = _to_oracle(cell, s.liouville_apply(_to_lib(cell, A, mil)), mil)
+    s.close()
+    for k, c in enumerate(cs):
+        w = 0.5 * cell.g2[c] + 8.0 * math.pi / (cell.omega * cell.g2[c])
+        ref = np.zeros(cell.npw, dtype=np.complex128)
+        ref[c] = w
+        assert np.abs(out[k, 0] - ref).max() <= 1e-12 * w
+
+
+def test_solve_meets_the_oracle_residual(tiny_system, tiny_sys):
+    t = tiny_system
+    cell, mil = t["cell"], t["gs"]["miller"]
+    nb, npw = tiny_sys.n_occ, tiny_sys.n_pw
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal((2, nb, npw)) + 1j * rng.standard_normal((2, nb, npw))
+    print("case: tiny cell, 2 Z-vector systems", flush=True)
+    z, it, res, rc = tiny_sys.liouville_solve(b, tol=1e-11)
+    print(f"  iterations {it}, true residuals {res}")
+    assert rc == 0 and (res <= 1e-11).all()
+    bo = _to_oracle(cell, tiny_sys.apply_pc(b.reshape(-1, npw)).reshape(b.shape), mil)
+    ro = liouville_residual(cell, t["psi"], t["eps"], bo, _to_oracle(cell, z, mil))
+    print(f"  oracle residuals {ro}")
+    assert (ro <= 2e-11).all()
+
+
+def test_solve_matches_a_dense_solve(micro):
+    cell, L, emp, s, mil = micro["cell"], micro["L"], micro["emp"], micro["sys"], micro["mil"]
+    n_emp = emp.shape[0]
+    rng = np.random.default_rng(13)
+    y = rng.standard_normal((2, L.shape[0])) + 1j * rng.standard_normal((2, L.shape[0]))
+    b = np.stack([(yy.reshape(MICRO_OCC, n_emp) @ emp) for yy in y])
+    zref = np.stack([(np.linalg.solve(L, yy).reshape(MICRO_OCC, n_emp) @ emp) for yy in y])
+    z, it, res, rc = s.liouville_solve(_to_lib(cell, b, mil), tol=1e-12)
+    print(f"micro cell: iterations {it}, true residuals {res}")
+    assert rc == 0
+    zo = _to_oracle(cell, z, mil)
+    for e in range(2):
+        assert np.linalg.norm(zo[e] - zref[e]) <= 1e-10 * np.linalg.norm(zref[e])
+
+
+def test_rejects_bad_requests(tiny_system):
+    sp, gs = tiny_system["spec"], tiny_system["gs"]
+    s = _system(sp.L, sp.ecut, gs["pos"])
+    with pytest.raises(RuntimeError):  # before set_occupied
+        from paper_2607_14025_amd.stern import lib
+        import ctypes as C
+        a = np.zeros((1, 2, s.n_pw), dtype=np.complex128)
+        from paper_2607_14025_amd.stern import _check, STERN_MEM_HOST
+        _check(lib().stern_liouville_apply(s._h, 1, C.c_void_p(a.ctypes.data), C.c_void_p(a.ctypes.data),
+                                           STERN_MEM_HOST))
+    s.set_occupied(gs["psi"], gs["eps"])
+    with pytest.raises(ValueError):
+        s.liouville_apply(np.zeros((1, s.n_occ + 1, s.n_pw), dtype=np.complex128))
+    s.close()
