@@ -463,6 +463,20 @@ int stern_liouville_apply(stern_system* sys, int n_exc, const double* a, double*
 int stern_liouville_solve(stern_system* sys, int n_exc, const double* b, double* z, double tol, int max_iter,
                           int mem_kind, int* iters, double* resid);
 
+/* The n_eig lowest excitation energies w_s of eq. bse_tddft and their auxiliary orbitals by block
+ * Davidson (Sec. II.C.1; WEST shares one Davidson between this operator and chi-bar0, Sec. IV):
+ * the basis stays on the device, Rayleigh-Ritz through FP64 GEMMs and Jacobi rotations of the
+ * projected Hermitian matrix on the host, corrections P_c K (L x - w x) with Teter's K per band,
+ * converged pairs kept in the basis without new directions, and when the basis would exceed
+ * max_basis a restart from its lowest max(n_eig, max_basis / 2) Ritz vectors. Converged when
+ * ||L x - w x|| <= tol |w| (||x|| = 1 over all bands).
+ * block (0 = n_eig) new directions per iteration, max_basis (0 = max(8 n_eig, n_eig + 4 block)),
+ * max_iter (0 = 200), seed of the random start. eig [n_eig] ascending (host); vec (host, may be
+ * NULL) [n_eig][n_occ][n_pw] canonical order; n_iter, max_resid (host) may be NULL. Returns
+ * STERN_OK, STERN_WARN_NOT_CONVERGED (max_iter reached or the basis exhausted) or an error. */
+int stern_liouville_davidson(stern_system* sys, int n_eig, int block, int max_basis, int max_iter, double tol,
+                             unsigned long long seed, double* eig, double* vec, int* n_iter, double* max_resid);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): out = P_c c as
  * stern_apply_pc computes it (the same kernels, so bitwise the same result),

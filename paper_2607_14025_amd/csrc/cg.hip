@@ -802,6 +802,17 @@ __global__ __launch_bounds__(kCgThreads) void k_blk_xpby(Z64* __restrict__ p, co
   }
 }
 
+// y[row] *= c[row / nb]
+__global__ __launch_bounds__(kCgThreads) void k_blk_scale(Z64* __restrict__ y, const Z64* __restrict__ c, int nb,
+                                                          int ld) {
+  const Z64 a = c[blockIdx.x / nb];
+  const size_t o = (size_t)blockIdx.x * ld;
+  for (int k = threadIdx.x; k < ld; k += kCgThreads) {
+    const Z64 w = y[o + k];
+    y[o + k] = zmk(a.re * w.re - a.im * w.im, a.re * w.im + a.im * w.re);
+  }
+}
+
 // z[row][k] = K_v(G) r[row][k], Teter's K with T_v of band v = row mod nb
 __global__ __launch_bounds__(kCgThreads) void k_teter_rows(const Z64* __restrict__ r, Z64* __restrict__ z,
                                                            const double* __restrict__ g2h,
@@ -990,6 +1001,9 @@ void launch_blk_axpy(Z64* y, const Z64* x, const Z64* c, int nb, int ld, int nro
 }
 void launch_blk_xpby(Z64* p, const Z64* z, const Z64* c, int nb, int ld, int nrows, hipStream_t st) {
   if (nrows > 0) k_blk_xpby<<<nrows, kCgThreads, 0, st>>>(p, z, c, nb, ld);
+}
+void launch_blk_scale(Z64* y, const Z64* c, int nb, int ld, int nrows, hipStream_t st) {
+  if (nrows > 0) k_blk_scale<<<nrows, kCgThreads, 0, st>>>(y, c, nb, ld);
 }
 void launch_teter_rows(const Z64* r, Z64* z, const double* g2h, const double* invT, int nb, int ld, int nrows,
                        hipStream_t st) {

@@ -245,5 +245,6 @@ void launch_blk_axpy(Z64* y, const Z64* x, const Z64* c, int nb, int ld, int nro
 void launch_blk_xpby(Z64* p, const Z64* z, const Z64* c, int nb, int ld, int nrows, hipStream_t st);
 void launch_teter_rows(const Z64* r, Z64* z, const double* g2h, const double* invT, int nb, int ld, int nrows,
                        hipStream_t st);
+void launch_blk_scale(Z64* y, const Z64* c, int nb, int ld, int nrows, hipStream_t st);  // y[row] *= c[row / nb]
 
 }  // namespace stern

@@ -196,6 +196,7 @@ struct stern_system {
   HostBasis hbd;
   DBuf d_col_start, d_col_len, d_col_xmin, d_col_pos, d_zl, d_ycol, d_g2h;
   DBuf lv_ar, lv_rho, lv_rhog, lv_pend, lv_k, lv_eps, lv_dot, lv_coef;
+  DBuf dv_V, dv_W, dv_X, dv_LX, dv_T, dv_LT, dv_part, dv_cm;  // Liouville Davidson
 
   // per-launch event profile (opts->profile)
   struct Rec {
@@ -290,7 +291,8 @@ struct stern_system {
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
                    &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi, &xkeep,
                    &d_col_start, &d_col_len, &d_col_xmin, &d_col_pos, &d_zl, &d_ycol, &d_g2h, &lv_ar, &lv_rho,
-                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef};
+                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef, &dv_V, &dv_W, &dv_X, &dv_LX,
+                   &dv_T, &dv_LT, &dv_part, &dv_cm};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
     events.clear();
@@ -1721,6 +1723,257 @@ int stern_liouville_solve(stern_system* S, int n_exc, const double* b, double* z
   }
   CHECKED(rows_out(S, n, X, nullptr, z, mem_kind));
   return all_ok ? STERN_OK : STERN_WARN_NOT_CONVERGED;
+}
+
+// Eigenpairs of a small Hermitian matrix by cyclic Jacobi rotations (host): A [n][n] row-major,
+// w ascending, V [n][n] with the eigenvectors as columns. Each rotation first takes the phase of
+// a_pq into the q column, then zeroes the now real off-diagonal pair as in the real case.
+static void jacobi_zheev(std::vector<std::complex<double>> A, int n, std::vector<double>& w,
+                         std::vector<std::complex<double>>& V) {
+  using cd = std::complex<double>;
+  V.assign((size_t)n * n, cd(0.0, 0.0));
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> cd& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += std::norm(a(i, j));
+        if (i != j) off += std::norm(a(i, j));
+      }
+    if (off <= 1e-30 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double r = std::abs(a(p, q));
+        if (r < 1e-300) continue;
+        const cd ph = a(p, q) / r;  // e^{i phi}
+        const double th = 0.5 * (a(q, q).real() - a(p, p).real()) / r;
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        // U = diag(1, e^{-i phi}) [[c, s], [-s, c]]: A <- U^H A U, V <- V U
+        const cd upp = c, upq = s, uqp = -s * std::conj(ph), uqq = c * std::conj(ph);
+        for (int k = 0; k < n; ++k) {  // columns
+          const cd x = a(k, p), y = a(k, q);
+          a(k, p) = x * upp + y * uqp;
+          a(k, q) = x * upq + y * uqq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows
+          const cd x = a(p, k), y = a(q, k);
+          a(p, k) = std::conj(upp) * x + std::conj(uqp) * y;
+          a(q, k) = std::conj(upq) * x + std::conj(uqq) * y;
+        }
+        a(p, q) = a(q, p) = 0.0;
+        a(p, p) = a(p, p).real();
+        a(q, q) = a(q, q).real();
+        for (int k = 0; k < n; ++k) {
+          const cd x = V[(size_t)k * n + p], y = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = x * upp + y * uqp;
+          V[(size_t)k * n + q] = x * upq + y * uqq;
+        }
+      }
+  }
+  std::vector<int> ord(n);
+  for (int i = 0; i < n; ++i) ord[i] = i;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return a(x, x).real() < a(y, y).real(); });
+  std::vector<std::complex<double>> Vs((size_t)n * n);
+  w.resize(n);
+  for (int j = 0; j < n; ++j) {
+    w[j] = a(ord[j], ord[j]).real();
+    for (int k = 0; k < n; ++k) Vs[(size_t)k * n + j] = V[(size_t)k * n + ord[j]];
+  }
+  V.swap(Vs);
+}
+
+// C[n][i] = <V_i | X_n> for the cap basis rows of V and nx rows of X, rows of length Lt (FP64 MFMA
+// reduce), on the host
+static int dav_vh_x(stern_system* S, const Z64* V, int cap, const Z64* X, int nx, int Lt, std::vector<Z64>& C) {
+  hipStream_t st = S->stream;
+  const int ns = choose_nsplit(cap, nx, Lt, S->gemm64_wg);
+  CHECKED(S->dv_part.ensure((size_t)ns * nx * cap * sizeof(Z64)));
+  CHECKED(S->dv_cm.ensure((size_t)nx * cap * sizeof(Z64)));
+  launch_zgemm_reduce(V, cap, X, Lt, nullptr, nx, Lt, S->dv_part.as<Z64>(), ns, st);
+  launch_sum_parts(S->dv_part.as<Z64>(), ns, nx, cap, 1.0, S->dv_cm.as<Z64>(), st);
+  C.resize((size_t)nx * cap);
+  HIPOK(hipMemcpyAsync(C.data(), S->dv_cm.p, C.size() * sizeof(Z64), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  return launch_check();
+}
+
+// Y[n] += sum_i V_i C[n][i] (FP64 MFMA expand) for ny rows of length Lt
+static int dav_v_c(stern_system* S, const Z64* V, int cap, const std::vector<Z64>& C, Z64* Y, int ny, int Lt) {
+  hipStream_t st = S->stream;
+  CHECKED(S->dv_cm.ensure((size_t)ny * cap * sizeof(Z64)));
+  HIPOK(hipMemcpyAsync(S->dv_cm.p, C.data(), (size_t)ny * cap * sizeof(Z64), hipMemcpyHostToDevice, st));
+  launch_zgemm_expand(V, cap, S->dv_cm.as<Z64>(), Y, Lt, nullptr, ny, Lt, st);
+  HIPOK(hipStreamSynchronize(st));  // C may change on return
+  return launch_check();
+}
+
+// T (nt vectors) orthogonalised against the m basis vectors of V (two classical Gram-Schmidt
+// passes through the GEMMs) and among themselves (modified Gram-Schmidt), normalised; vectors
+// that lose all but 1e-8 of their norm are dropped. Returns the number kept (packed first).
+static int dav_orth(stern_system* S, const Z64* V, int cap, int m, Z64* T, int nt, int Lt, int& kept) {
+  hipStream_t st = S->stream;
+  const int nb = S->n_occ;
+  std::vector<Z64> d, C;
+  CHECKED(block_dots(S, T, T, nt, d));
+  std::vector<double> n0(nt);
+  for (int j = 0; j < nt; ++j) n0[j] = std::sqrt(std::max(0.0, d[j].re));
+  for (int pass = 0; pass < 2 && m > 0; ++pass) {
+    CHECKED(dav_vh_x(S, V, cap, T, nt, Lt, C));
+    for (auto& c : C) c = zmk(-c.re, -c.im);
+    CHECKED(dav_v_c(S, V, cap, C, T, nt, Lt));
+  }
+  kept = 0;
+  std::vector<Z64> c1(1);
+  for (int j = 0; j < nt; ++j) {
+    Z64* tj = T + (size_t)j * Lt;
+    for (int i = 0; i < kept; ++i) {
+      const Z64* ti = T + (size_t)i * Lt;
+      CHECKED(block_dots(S, ti, tj, 1, d));
+      c1[0] = zmk(-d[0].re, -d[0].im);
+      CHECKED(upload_coef(S, c1));
+      launch_blk_axpy(tj, ti, S->lv_coef.as<Z64>(), nb, S->hb.npw_pad, nb, st);
+    }
+    CHECKED(block_dots(S, tj, tj, 1, d));
+    const double nn = std::sqrt(std::max(0.0, d[0].re));
+    if (!(nn > 1e-8 * n0[j])) continue;
+    // unit norm, into slot `kept`
+    Z64* tk = T + (size_t)kept * Lt;
+    if (tk != tj) HIPOK(hipMemcpyAsync(tk, tj, (size_t)Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+    c1[0] = zmk(1.0 / nn, 0.0);
+    CHECKED(upload_coef(S, c1));
+    launch_blk_scale(tk, S->lv_coef.as<Z64>(), nb, S->hb.npw_pad, nb, st);
+    ++kept;
+  }
+  return launch_check();
+}
+
+// Lowest n_eig eigenpairs of the Liouville superoperator (eq. bse_tddft) by block Davidson with
+// the basis on the device: Rayleigh-Ritz through the FP64 GEMMs, Jacobi on the host, corrections
+// P_c K r with Teter's K per band, converged pairs kept in the basis without new directions,
+// restart from the Ritz vectors when the basis is full.
+int stern_liouville_davidson(stern_system* S, int n_eig, int block, int max_basis, int max_iter, double tol,
+                             unsigned long long seed, double* eig, double* vec, int* n_iter, double* max_resid) {
+  using cd = std::complex<double>;
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (n_eig <= 0 || !eig) return fail(STERN_ERR_INVALID_ARG, "need n_eig > 0 and eig");
+  if (!(tol > 0)) return fail(STERN_ERR_INVALID_ARG, "tol must be > 0");
+  const int bl = block > 0 ? block : n_eig;
+  const int mb = max_basis > 0 ? max_basis : std::max(8 * n_eig, n_eig + 4 * bl);
+  if (mb < n_eig + bl) return fail(STERN_ERR_INVALID_ARG, "max_basis %d < n_eig + block = %d", mb, n_eig + bl);
+  const int mi = max_iter > 0 ? max_iter : 200;
+  Scope sc(S->device, &S->alloc);
+  const int n_start = std::max(n_eig, bl);
+  CHECKED(liouville_setup(S, std::max(n_start, bl)));
+  const int nb = S->n_occ, K = S->hb.npw_pad, npw = S->hb.npw;
+  const int Lt = nb * K;
+  const int cap = (mb + 63) / 64 * 64;
+  hipStream_t st = S->stream;
+  CHECKED(S->lv_dot.ensure((size_t)std::max(mb, n_start) * nb * sizeof(Z64)));
+  CHECKED(S->lv_coef.ensure((size_t)std::max(mb, n_start) * sizeof(Z64)));
+  for (DBuf* d : {&S->dv_V, &S->dv_W}) {
+    CHECKED(d->ensure((size_t)cap * Lt * sizeof(Z64)));
+    launch_fill_zero(d->as<Z64>(), (size_t)cap * Lt, st);
+  }
+  for (DBuf* d : {&S->dv_X, &S->dv_LX, &S->dv_T}) {
+    CHECKED(d->ensure((size_t)std::max(n_start, n_eig) * Lt * sizeof(Z64)));
+    launch_fill_zero(d->as<Z64>(), (size_t)std::max(n_start, n_eig) * Lt, st);
+  }
+  // corrections (block) and, at a restart, the new basis and its L image (up to mb each)
+  CHECKED(S->dv_LT.ensure((size_t)(std::max(n_start, bl) + 2 * mb) * Lt * sizeof(Z64)));
+  Z64 *V = S->dv_V.as<Z64>(), *W = S->dv_W.as<Z64>(), *X = S->dv_X.as<Z64>(), *LX = S->dv_LX.as<Z64>(),
+      *T = S->dv_T.as<Z64>();
+  // seeded random start, shaped by P_c K
+  {
+    std::mt19937_64 rng(seed);
+    std::normal_distribution<double> nd;
+    std::vector<double> h((size_t)n_start * nb * npw * 2);
+    for (auto& x : h) x = nd(rng);
+    CHECKED(rows_in(S, n_start * nb, h.data(), STERN_MEM_HOST, S->wr));
+    CHECKED(precond_rows(S, S->wr.as<Z64>(), T, n_start * nb));
+  }
+  int m = 0, kept = 0;
+  CHECKED(dav_orth(S, V, cap, m, T, n_start, Lt, kept));
+  HIPOK(hipMemcpyAsync(V, T, (size_t)kept * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+  CHECKED(liouville_rows(S, V, W, kept));
+  m = kept;
+  std::vector<double> theta, rn(n_eig, 0.0);
+  std::vector<cd> Y;
+  std::vector<Z64> C, d;
+  bool all_conv = false;
+  int it = 0;
+  for (; it < mi; ++it) {
+    // Rayleigh-Ritz on the m basis vectors
+    CHECKED(dav_vh_x(S, V, cap, W, m, Lt, C));  // C[n][i] = <v_i|w_n> = H[i][n]
+    std::vector<cd> H((size_t)m * m);
+    for (int i = 0; i < m; ++i)
+      for (int n = 0; n < m; ++n) {
+        const Z64 a = C[(size_t)n * cap + i], b = C[(size_t)i * cap + n];
+        H[(size_t)i * m + n] = 0.5 * (cd(a.re, a.im) + std::conj(cd(b.re, b.im)));
+      }
+    jacobi_zheev(H, m, theta, Y);
+    // Ritz vectors X = V Y and L X = W Y for the n_eig lowest
+    std::vector<Z64> Cy((size_t)n_eig * cap, zmk(0.0, 0.0));
+    for (int n = 0; n < n_eig; ++n)
+      for (int i = 0; i < m; ++i) Cy[(size_t)n * cap + i] = zmk(Y[(size_t)i * m + n].real(), Y[(size_t)i * m + n].imag());
+    launch_fill_zero(X, (size_t)n_eig * Lt, st);
+    launch_fill_zero(LX, (size_t)n_eig * Lt, st);
+    CHECKED(dav_v_c(S, V, cap, Cy, X, n_eig, Lt));
+    CHECKED(dav_v_c(S, W, cap, Cy, LX, n_eig, Lt));
+    // residuals r = L x - theta x into T
+    HIPOK(hipMemcpyAsync(T, LX, (size_t)n_eig * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+    std::vector<Z64> c(n_eig);
+    for (int n = 0; n < n_eig; ++n) c[n] = zmk(-theta[n], 0.0);
+    CHECKED(upload_coef(S, c));
+    launch_blk_axpy(T, X, S->lv_coef.as<Z64>(), nb, K, n_eig * nb, st);
+    CHECKED(block_dots(S, T, T, n_eig, d));
+    std::vector<int> todo;
+    for (int n = 0; n < n_eig; ++n) {
+      rn[n] = std::sqrt(std::max(0.0, d[n].re));
+      if (!(rn[n] <= tol * std::fabs(theta[n]))) todo.push_back(n);
+    }
+    if (todo.empty()) {
+      all_conv = true;
+      break;
+    }
+    // corrections P_c K r of the unconverged pairs, packed at the front of T
+    const int nt = std::min((int)todo.size(), bl);
+    for (int j = 0; j < nt; ++j)
+      if (todo[j] != j)
+        HIPOK(hipMemcpyAsync(T + (size_t)j * Lt, T + (size_t)todo[j] * Lt, (size_t)Lt * sizeof(Z64),
+                             hipMemcpyDeviceToDevice, st));
+    CHECKED(precond_rows(S, T, S->dv_LT.as<Z64>(), nt * nb));
+    HIPOK(hipMemcpyAsync(T, S->dv_LT.p, (size_t)nt * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+    if (m + nt > mb) {  // thick restart: the lowest nk Ritz vectors (at least n_eig, half the basis)
+      const int nk = std::min(m, std::max(n_eig, mb / 2));
+      std::vector<Z64> Ck((size_t)nk * cap, zmk(0.0, 0.0));
+      for (int n = 0; n < nk; ++n)
+        for (int i = 0; i < m; ++i)
+          Ck[(size_t)n * cap + i] = zmk(Y[(size_t)i * m + n].real(), Y[(size_t)i * m + n].imag());
+      Z64 *Vn = S->dv_LT.as<Z64>() + (size_t)nt * Lt, *Wn = Vn + (size_t)nk * Lt;
+      launch_fill_zero(Vn, (size_t)2 * nk * Lt, st);
+      CHECKED(dav_v_c(S, V, cap, Ck, Vn, nk, Lt));
+      CHECKED(dav_v_c(S, W, cap, Ck, Wn, nk, Lt));
+      HIPOK(hipMemcpyAsync(V, Vn, (size_t)nk * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+      HIPOK(hipMemcpyAsync(W, Wn, (size_t)nk * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+      launch_fill_zero(V + (size_t)nk * Lt, (size_t)(cap - nk) * Lt, st);
+      launch_fill_zero(W + (size_t)nk * Lt, (size_t)(cap - nk) * Lt, st);
+      m = nk;
+    }
+    CHECKED(dav_orth(S, V, cap, m, T, nt, Lt, kept));
+    if (kept == 0) break;  // no new direction: the basis is exhausted
+    HIPOK(hipMemcpyAsync(V + (size_t)m * Lt, T, (size_t)kept * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+    CHECKED(liouville_rows(S, V + (size_t)m * Lt, W + (size_t)m * Lt, kept));
+    m += kept;
+  }
+  for (int n = 0; n < n_eig; ++n) eig[n] = theta[n];
+  double mr = 0.0;
+  for (int n = 0; n < n_eig; ++n) mr = std::max(mr, rn[n] / std::max(std::fabs(theta[n]), 1e-300));
+  if (n_iter) *n_iter = it;
+  if (max_resid) *max_resid = mr;
+  if (vec) CHECKED(rows_out(S, n_eig * nb, X, nullptr, vec, STERN_MEM_HOST));
+  return all_conv ? STERN_OK : STERN_WARN_NOT_CONVERGED;
 }
 
 int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int mem_kind) {

@@ -32,7 +32,7 @@ EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_m
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
             "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc", "stern_liouville_apply",
-            "stern_liouville_solve"]
+            "stern_liouville_solve", "stern_liouville_davidson"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -148,6 +148,8 @@ def lib():
         L.stern_liouville_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_liouville_solve.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
                                             P(C.c_int), P(C.c_double)]
+        L.stern_liouville_davidson.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
+                                               C.c_ulonglong, P(C.c_double), C.c_void_p, P(C.c_int), P(C.c_double)]
         L.stern_pdep_basis.argtypes = [C.c_void_p, C.c_double, P(C.c_int), P(C.c_int32)]
         L.stern_pdep_davidson.argtypes = [C.c_void_p, P(PdepOpts), P(C.c_double), P(C.c_double), P(PdepStats)]
         L.stern_free.argtypes = [C.c_void_p]
@@ -503,6 +505,18 @@ class System:
                                                 it.ctypes.data_as(C.POINTER(C.c_int)),
                                                 res.ctypes.data_as(C.POINTER(C.c_double))))
         return z, it, res, rc
+
+    def liouville_davidson(self, n_eig, tol=1e-8, block=0, max_basis=0, max_iter=0, seed=0):
+        """Lowest excitation energies of the Liouville superoperator (stern_liouville_davidson).
+        Returns (w [n_eig], auxiliary orbitals [n_eig, n_occ, n_pw], stats dict)."""
+        w = np.zeros(n_eig)
+        vec = np.zeros((n_eig, self.n_occ, self.n_pw), dtype=np.complex128)
+        it = C.c_int()
+        mr = C.c_double()
+        rc = _check(lib().stern_liouville_davidson(self._h, int(n_eig), int(block), int(max_basis), int(max_iter),
+                                                   float(tol), int(seed), w.ctypes.data_as(C.POINTER(C.c_double)),
+                                                   C.c_void_p(vec.ctypes.data), C.byref(it), C.byref(mr)))
+        return w, vec, dict(rc=rc, n_iter=it.value, max_resid=mr.value)
 
 
 class Model:

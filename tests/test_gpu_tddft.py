@@ -1,7 +1,8 @@
-"""TDDFT Liouville superoperator through the C ABI (stern_liouville_apply, stern_liouville_solve)
-against the oracle: the grid route on the tiny cell, the transition-basis matrix of a full
-diagonalisation on a micro cell, the free-electron closed form, and the Z-vector solve against the
-oracle's residual and a dense solve."""
+"""TDDFT Liouville superoperator through the C ABI (stern_liouville_apply, stern_liouville_solve,
+stern_liouville_davidson) against the oracle: the grid route on the tiny cell, the transition-basis
+matrix of a full diagonalisation on a micro cell, the free-electron closed form, the Z-vector solve
+against the oracle's residual and a dense solve, and the Davidson excitation energies against the
+dense spectrum, a degenerate free-electron shell and the oracle's operator."""
 import math
 
 import numpy as np
@@ -150,3 +151,52 @@ def test_rejects_bad_requests(tiny_system):
     with pytest.raises(ValueError):
         s.liouville_apply(np.zeros((1, s.n_occ + 1, s.n_pw), dtype=np.complex128))
     s.close()
+
+
+def test_davidson_matches_the_dense_spectrum(micro):
+    cell, L, s, mil = micro["cell"], micro["L"], micro["sys"], micro["mil"]
+    ref = np.linalg.eigvalsh(L)
+    n = 5
+    print(f"case: micro cell Davidson, {n} lowest of {L.shape[0]} excitations", flush=True)
+    w, vec, info = s.liouville_davidson(n, tol=1e-9, seed=3)
+    print("  w", w, "ref", ref[:n], info)
+    assert info["rc"] == 0
+    assert np.abs(w - ref[:n]).max() <= 1e-10 * ref[n - 1]
+    xo = _to_oracle(cell, vec, mil)
+    lx = liouville_apply(cell, micro["occ"], micro["eo"], xo)
+    for k in range(n):
+        assert np.linalg.norm(lx[k] - w[k] * xo[k]) <= 1e-8 * w[k]
+
+
+def test_davidson_free_electron_degenerate_shell():
+    """One occupied plane wave: the six transitions to the first shell |G| = 2 pi / L share
+    w = |G|^2 / 2 + 8 pi / (Omega |G|^2), below the next shell's."""
+    cell = OracleCell(MICRO_L, MICRO_ECUT, np.zeros((0, 3)), amp=0.0, D=0.0)
+    s = _system(MICRO_L, MICRO_ECUT, np.zeros((0, 3)), vloc_amp=0.0, kb_D=0.0)
+    psi = np.zeros((1, cell.npw), dtype=np.complex128)
+    psi[0, 0] = 1.0
+    s.set_occupied(cell.give(psi, s.miller()), np.zeros(1))
+    w, _, info = s.liouville_davidson(6, tol=1e-10, seed=1)
+    s.close()
+    g2 = cell.b ** 2
+    ref = 0.5 * g2 + 8.0 * math.pi / (cell.omega * g2)
+    print("free-electron shell", w, "closed form", ref, info)
+    assert info["rc"] == 0
+    assert np.abs(w - ref).max() <= 1e-12 * ref
+
+
+def test_davidson_pairs_satisfy_the_oracle_operator(tiny_system, tiny_sys):
+    t = tiny_system
+    cell, mil = t["cell"], t["gs"]["miller"]
+    n = 4
+    print(f"case: tiny cell Davidson, {n} lowest", flush=True)
+    w, vec, info = tiny_sys.liouville_davidson(n, tol=1e-8, block=4, seed=2)
+    print("  w", w, info)
+    assert info["rc"] == 0
+    gap = t["eps"][tiny_sys.n_occ - 1]
+    xo = _to_oracle(cell, vec, mil)
+    lx = liouville_apply(cell, t["psi"], t["eps"], xo)
+    for k in range(n):
+        assert np.linalg.norm(lx[k] - w[k] * xo[k]) <= 2e-8 * w[k]
+        assert abs(np.linalg.norm(xo[k]) - 1.0) <= 1e-10
+    assert np.all(np.diff(w) >= -1e-12) and w[0] > 0
