@@ -272,8 +272,46 @@ def mid_entry(args, dev):
              plain_fp64=summary(i64, t64, v64), mixed=summary(imx, tmx, vmx))
     r["mixed"]["dn_rel_err_vs_fp64"] = rel_err(dn, ref)
     r["mixed_speedup_vs_plain_fp64"] = vmx / v64
+    r["tddft"] = tddft_entry(s)
     s.close()
     return r
+
+
+def tddft_entry(s, n_exc=8, reps=3):
+    """The Liouville superoperator of TDDFT (Tamm-Dancoff, Hartree kernel) on the same system:
+    applies of n_exc excitations on device arrays, the lowest excitation energies by Davidson, and
+    Z-vector solves. The grid stage's algorithmic bytes per excitation: n_occ full grids written
+    (a_v(r)), read twice (density, products) and written once more (V psi_v), plus psi_v(r) read
+    twice: 6 n_occ N^3 complex FP64 values."""
+    import torch
+    g = torch.Generator(device="cpu").manual_seed(5)
+    shape = (n_exc, s.n_occ, s.n_pw)
+    a = torch.complex(torch.randn(shape, generator=g, dtype=torch.float64),
+                      torch.randn(shape, generator=g, dtype=torch.float64)).to("cuda")
+    s.liouville_apply(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        s.liouville_apply(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    grid_bytes = 6.0 * s.n_occ * s.fft_n ** 3 * 16 * n_exc
+    log(f"tddft: L apply of {n_exc} excitations {dt * 1e3:.1f} ms")
+    t0 = time.perf_counter()
+    w, _, dinfo = s.liouville_davidson(4, tol=1e-4, seed=1)
+    tdav = time.perf_counter() - t0
+    log(f"tddft: Davidson {dinfo['n_iter']} iterations, {tdav:.2f} s, w {w}")
+    b = a[:2].cpu().numpy()
+    t0 = time.perf_counter()
+    _, it, res, rc = s.liouville_solve(b, tol=1e-8)
+    tsol = time.perf_counter() - t0
+    log(f"tddft: Z-vector solves {it.tolist()} iterations, {tsol:.2f} s, residuals {res.tolist()}")
+    return dict(apply=dict(n_exc=n_exc, ms=dt * 1e3, excitations_per_s=n_exc / dt,
+                           grid_GB=grid_bytes / 1e9, grid_GBps_whole_apply=grid_bytes / dt / 1e9),
+                davidson=dict(n_eig=4, tol=1e-4, iterations=dinfo["n_iter"], seconds=tdav, rc=dinfo["rc"],
+                              w_Ha=[float(x) for x in w]),
+                zvector=dict(n_exc=2, tol=1e-8, iterations=[int(x) for x in it], seconds=tsol, rc=int(rc),
+                             true_resid=[float(x) for x in res]))
 
 
 def batched_entry(args, dev):

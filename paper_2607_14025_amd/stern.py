@@ -487,7 +487,18 @@ class System:
         return a
 
     def liouville_apply(self, a):
-        """L A of the TDDFT Liouville superoperator (stern_liouville_apply) for a [n_exc, n_occ, n_pw]."""
+        """L A of the TDDFT Liouville superoperator (stern_liouville_apply) for a [n_exc, n_occ, n_pw]:
+        a host array, or a contiguous complex128 CUDA tensor (the result is then one too)."""
+        if _is_torch(a):
+            import torch
+            if (not a.is_cuda or not a.is_contiguous() or a.dtype != torch.complex128 or a.dim() != 3
+                    or a.shape[1] != self.n_occ or a.shape[2] != self.n_pw):
+                raise ValueError(f"device excitations must be a contiguous complex128 CUDA tensor "
+                                 f"[n_exc, {self.n_occ}, {self.n_pw}]")
+            out = torch.empty_like(a)
+            _check(lib().stern_liouville_apply(self._h, a.shape[0], C.c_void_p(a.data_ptr()),
+                                               C.c_void_p(out.data_ptr()), STERN_MEM_DEVICE))
+            return out
         a = self._exc_rows(a)
         out = np.empty_like(a)
         _check(lib().stern_liouville_apply(self._h, a.shape[0], C.c_void_p(a.ctypes.data),
