@@ -1120,9 +1120,11 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
       HIPOK(hipStreamSynchronize(st));
       cap = std::min(cap, ni);
     }
-    // FP64 update, re-orthogonalisation and true residual
+    // FP64 update and true residual. x keeps the occupied components the inner solves leave (at
+    // the level of their split-BF16 projections); on them P_c (H - eps) acts as P_c Psi (E - eps)
+    // = 0 up to the ground state's eigen-residual, so the residual needs no projection of x, which
+    // is projected once after the last step.
     CHECKED(timed(S, STERN_K_CG, na * (2.0 * vecb + vec32), 0.0, [&] { launch_add_d(cs.x, c32.d, K, L, na, st); }));
-    CHECKED(apply_pc_rows(S, cs.x, L, na));
     CHECKED(apply_h_rows(S, cs.x, cs.q, L, na, cs.eps));
     CHECKED(apply_pc_rows(S, cs.q, L, na));
     CHECKED(timed(S, STERN_K_CG, na * 3.0 * vecb, 0.0, [&] { launch_outer_resid(cs, L, na, tol, st); }));
@@ -1133,6 +1135,12 @@ int run_mixed(stern_system* S, const CgState& cs, const std::vector<int>& list, 
     for (int s : act)
       if (h_flag[s] != 2) nxt.push_back(s);
     act.swap(nxt);
+  }
+  {  // the solutions in range(P_c) (those falling back below restart from zero)
+    const int n = (int)list.size();
+    HIPOK(hipMemcpyAsync(S->list_act.p, list.data(), n * sizeof(int), hipMemcpyHostToDevice, st));
+    CHECKED(apply_pc_rows(S, cs.x, S->list_act.as<int>(), n));
+    HIPOK(hipStreamSynchronize(st));  // list_act is rewritten by the fallback
   }
   if (!act.empty()) {  // Teter-preconditioned FP64 PCG from zero
     n_fallback += (int)act.size();
