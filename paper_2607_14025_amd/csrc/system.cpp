@@ -1034,9 +1034,9 @@ int run_cocg64(stern_system* S, const CgState& cs, const std::vector<int>& list,
 
 // Mixed precision: FP64 defect correction around FP32/BF16 inner PCG solves.
 //   repeat: solve A d = r to inner_tol with FP32 FFTs and split-BF16 MFMA GEMMs
-//           (FP64 dots and scalars); x += d; x = P_c x (FP64); r = b - A x (FP64)
-//   until ||r|| <= tol ||b||; solves still above tol after max_outer steps are
-//   re-solved by FP64 PCG from zero.
+//           (FP64 dots and scalars); x += d; r = b - A x (FP64)
+//   until ||r|| <= tol ||b||; then x = P_c x (FP64); solves still above tol after
+//   max_outer steps are re-solved by FP64 PCG from zero.
 // Inner operators (inner_op):
 //  projected: q = P_c (H - eps) p and z = P_c K r. The alpha step takes the new
 //    (r, z) before z is projected, which equals (r, P_c z) as r stays in
