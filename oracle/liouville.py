@@ -16,6 +16,15 @@ rho_A is band-limited to the 4 Ecut sphere, which the grid holds exactly, so the
 aliasing. <B|K1e A> = 2 Omega sum_{q != 0} (4 pi / |q|^2) conj(rho_B(q)) rho_A(q): the operator is
 Hermitian in <A|B> = sum_v <a_v|b_v>, and positive definite when the gap is open.
 
+Hybrid functionals add the direct term with a fraction alpha of bare exchange, built from the
+Coulomb integrals of occupied pairs (eq. tau_u):
+
+    (K1d A)_v = alpha P_c sum_v' tau_{v'v}(r) a_v'(r),   tau_{v'v} = V[conj(psi_v') psi_v],
+
+so that L = D + K1e - K1d. <B|K1d A> = alpha sum_{v,v'} int conj(b_v) tau_{v'v} a_v' is Hermitian, as
+tau_{vv'} = conj(tau_{v'v}); for plane-wave states it couples transitions with the same momentum
+transfer by alpha 4 pi / (Omega |k_v - k_v'|^2) (v != v'; q = 0 omitted, as in V).
+
 Routes, pinned against each other and against closed forms:
 * liouville_apply: the grid route above (FFTs of the oracle cell);
 * casida_tda: the matrix in the transition basis {a_v' = delta_vv' psi_c} from a full
@@ -56,32 +65,41 @@ def hartree_grid(cell: OracleCell, rho_r: np.ndarray) -> np.ndarray:
     return sfft.ifftn(box, axes=(1, 2, 3), workers=WORKERS, norm="forward")  # sum_q V(q) e^{i q r}
 
 
-def liouville_apply(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, A: np.ndarray) -> np.ndarray:
-    """(D + K1e) A for A [n_exc, n_occ, npw] (oracle order); psi [n_occ, npw], eps [n_occ]."""
+def liouville_apply(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, A: np.ndarray,
+                    alpha_x: float = 0.0) -> np.ndarray:
+    """(D + K1e - K1d) A for A [n_exc, n_occ, npw] (oracle order); psi [n_occ, npw], eps [n_occ];
+    alpha_x the fraction of bare exchange in K1d (0: none)."""
     A = np.asarray(A, dtype=np.complex128)
     n_exc, n_occ, npw = A.shape
     Ap = project(psi, A.reshape(-1, npw)).reshape(n_exc, n_occ, npw)
     out = np.empty_like(Ap)
     psi_r = cell.to_grid(psi)                                    # psi~_v(r) = sqrt(Omega) psi_v(r)
+    tau = None
+    if alpha_x != 0.0:                                           # tau[v', v] = V[conj(psi_v') psi_v]
+        tau = np.stack([hartree_grid(cell, np.conj(psi_r) * psi_r[v][None] / cell.omega) for v in range(n_occ)], 1)
     for e in range(n_exc):
         d = cell.h_apply(Ap[e]) - eps[:, None] * Ap[e]
         a_r = cell.to_grid(Ap[e])
         rho = np.sum(np.conj(psi_r) * a_r, axis=0)[None] / cell.omega
         v = hartree_grid(cell, rho)[0]
         k = 2.0 * cell.from_grid(v[None] * psi_r)
+        if tau is not None:
+            k -= alpha_x * cell.from_grid(np.einsum("wvxyz,wxyz->vxyz", tau, a_r))
         out[e] = project(psi, d + k)
     return out
 
 
-def liouville_residual(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, b: np.ndarray, z: np.ndarray) -> np.ndarray:
+def liouville_residual(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, b: np.ndarray, z: np.ndarray,
+                       alpha_x: float = 0.0) -> np.ndarray:
     """||b - L z|| / ||b|| per excitation (norms over all bands)."""
-    r = b - liouville_apply(cell, psi, eps, z)
+    r = b - liouville_apply(cell, psi, eps, z, alpha_x)
     n = b.shape[0]
     return np.linalg.norm(r.reshape(n, -1), axis=1) / np.linalg.norm(b.reshape(n, -1), axis=1)
 
 
-def casida_tda(cell: OracleCell, n_occ: int):
-    """Dense L in the transition basis t = v * n_emp + c from a full diagonalisation of H.
+def casida_tda(cell: OracleCell, n_occ: int, alpha_x: float = 0.0):
+    """Dense L in the transition basis t = v * n_emp + c from a full diagonalisation of H, with
+    alpha_x of bare exchange: L_{vc,v'c'} -= alpha_x Omega sum_q (4 pi/|q|^2) conj(rho_{c'c}(q)) rho_{v'v}(q).
     Returns (L [n_occ n_emp, n_occ n_emp], occupied psi, eps_occ, empty psi, eps_emp)."""
     e, U = np.linalg.eigh(cell.h_dense())
     psi = U.T
@@ -101,10 +119,23 @@ def casida_tda(cell: OracleCell, n_occ: int):
     R = rho_q.reshape(n_occ * n_emp, -1)
     L = 2.0 * cell.omega * (R.conj() * vq[None, :]) @ R.T
     L[np.diag_indices_from(L)] += (ee[None, :] - eo[:, None]).reshape(-1)
+    if alpha_x != 0.0:
+        def pair_q(a_r, b_r):                                   # rho_ab(q) for rho_ab = conj(a) b
+            out = np.empty((a_r.shape[0], b_r.shape[0], len(vq)), dtype=np.complex128)
+            for i in range(a_r.shape[0]):
+                rq = sfft.fftn(np.conj(a_r[i])[None] * b_r / cell.omega, axes=(1, 2, 3), workers=WORKERS,
+                               norm="forward")
+                out[i] = rq[:, ix, iy, iz]
+            return out
+        Rvv = pair_q(occ_r, occ_r)                              # [v', v, q]
+        Rcc = pair_q(emp_r, emp_r)                              # [c', c, q]
+        # K1d[(v,c),(v',c')] = Omega sum_q conj(rho_{c'c}(q)) w(q) rho_{v'v}(q)
+        K = cell.omega * np.einsum("dcq,q,wvq->vcwd", Rcc.conj(), vq, Rvv, optimize=True)
+        L -= alpha_x * K.reshape(n_occ * n_emp, n_occ * n_emp)
     return L, occ, eo, emp, ee
 
 
-def free_electron_tda(cell: OracleCell, occ_idx, emp_idx) -> np.ndarray:
+def free_electron_tda(cell: OracleCell, occ_idx, emp_idx, alpha_x: float = 0.0) -> np.ndarray:
     """Hand-written L for plane-wave states (basis indices of the oracle cell): transitions
     t = (occ_idx[v], emp_idx[c]) in the order v * len(emp_idx) + c."""
     k = cell.miller
@@ -116,4 +147,7 @@ def free_electron_tda(cell: OracleCell, occ_idx, emp_idx) -> np.ndarray:
         for b, (w, d) in enumerate(trans):
             if np.array_equal(k[d] - k[w], qa):
                 L[a, b] += 8.0 * math.pi / (cell.omega * float(np.sum((qa * cell.b) ** 2)))
+                if w != v:
+                    dk = k[v] - k[w]
+                    L[a, b] -= alpha_x * 4.0 * math.pi / (cell.omega * float(np.sum((dk * cell.b) ** 2)))
     return L

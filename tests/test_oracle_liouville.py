@@ -121,3 +121,43 @@ def test_occupied_components_of_the_input_are_removed(micro):
     a = liouville_apply(cell, occ, micro["eo"], A)
     b = liouville_apply(cell, occ, micro["eo"], A + extra)
     assert np.max(np.abs(a - b)) <= 1e-12 * np.max(np.abs(a))
+
+
+ALPHA = 0.25
+
+
+def test_closed_shell_with_exchange_matches_the_hand_written_matrix():
+    """The direct term of bare exchange: grid route against momentum conservation written out."""
+    cell = free_cell()
+    order = np.argsort(cell.g2, kind="stable")
+    occ_idx = list(order[:7])
+    emp_idx = list(order[7:40])
+    psi = unit_rows(cell, occ_idx)
+    eps = 0.5 * cell.g2[occ_idx]
+    ref = free_electron_tda(cell, occ_idx, emp_idx, ALPHA)
+    assert np.abs(ref - free_electron_tda(cell, occ_idx, emp_idx)).max() > 1e-3   # the term is there
+    n_t = len(occ_idx) * len(emp_idx)
+    A = np.zeros((n_t, len(occ_idx), cell.npw), dtype=np.complex128)
+    for t in range(n_t):
+        v, c = divmod(t, len(emp_idx))
+        A[t, v, emp_idx[c]] = 1.0
+    out = liouville_apply(cell, psi, eps, A, ALPHA)
+    got = out[:, :, emp_idx].reshape(n_t, n_t).T
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def test_model_cell_with_exchange_grid_route_matches_transition_matrix(micro):
+    cell, occ, emp = micro["cell"], micro["occ"], micro["emp"]
+    L, _, _, _, _ = casida_tda(cell, MICRO_OCC, ALPHA)
+    assert np.max(np.abs(L - L.conj().T)) <= 1e-12 * np.max(np.abs(L))
+    assert np.abs(L - micro["L"]).max() > 1e-4
+    n_emp = emp.shape[0]
+    cols = np.random.default_rng(4).choice(L.shape[0], size=6, replace=False)
+    A = np.zeros((len(cols), MICRO_OCC, cell.npw), dtype=np.complex128)
+    for k, t in enumerate(cols):
+        v, c = divmod(int(t), n_emp)
+        A[k, v] = emp[c]
+    out = liouville_apply(cell, occ, micro["eo"], A, ALPHA)
+    for k, t in enumerate(cols):
+        col = (out[k] @ emp.conj().T).reshape(-1)
+        assert np.max(np.abs(col - L[:, t])) <= 1e-11 * np.max(np.abs(L))
