@@ -443,7 +443,8 @@ int stern_apply_pc(stern_system* sys, int n_vec, const double* c, double* out, i
  * sum_v |a_v><psi_v|), stored as n_exc x n_occ rows of n_pw complex coefficients in canonical
  * order ([n_exc][n_occ][n_pw], interleaved re, im). The paper names the terms of the Liouville
  * superoperator but not their formulas; here: Tamm-Dancoff, closed-shell singlet excitations,
- * Hartree kernel (the model Hamiltonian has no exchange-correlation functional, so K1d = 0):
+ * Hartree kernel (the model Hamiltonian has no exchange-correlation functional, so K1d = 0 unless
+ * a fraction of bare exchange is set, stern_liouville_set_kernel):
  *   (L A)_v = P_c (H - eps_v) a_v + 2 P_c [ V[rho_A] psi_v ],  rho_A = sum_v conj(psi_v) a_v,
  *   V[rho](r) = sum_{0 < |q|^2 <= 4 Ecut} (4 pi / |q|^2) rho(q) e^{i q.r},
  * applied to P_c A. L is Hermitian in <A|B> = sum_v <a_v|b_v> and positive definite when the gap
@@ -452,6 +453,14 @@ int stern_apply_pc(stern_system* sys, int n_vec, const double* c, double* out, i
  *
  * out = L A, host or device arrays per mem_kind (they may not overlap). Synchronous. */
 int stern_liouville_apply(stern_system* sys, int n_exc, const double* a, double* out, int mem_kind);
+
+/* Hybrid TDDFT: a fraction alpha_x in [0, 1] of bare exchange in the direct term (Sec. II.C.1,
+ * the Coulomb integrals of occupied pairs of eq. tau_u), used by every later Liouville call on
+ * this system (0, the default, leaves K1d = 0):
+ *   (K1d A)_v = alpha_x P_c sum_w tau_{wv} a_w,   tau_{wv}(r) = V[conj(psi_w) psi_v](r),
+ * with V as above (q = 0 omitted), and L = D + K1e - K1d. Each apply then forms the n_occ^2
+ * pair potentials again (n_occ Poisson solves per band). STERN_ERR_INVALID_ARG outside [0, 1]. */
+int stern_liouville_set_kernel(stern_system* sys, double alpha_x);
 
 /* Linear systems L z_e = b_e of the Liouville superoperator, as the Z-vector equations of
  * excited-state forces pose them (Sec. II.C.2), for n_exc right-hand sides b [n_exc][n_occ][n_pw]

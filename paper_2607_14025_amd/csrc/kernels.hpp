@@ -235,8 +235,13 @@ void launch_band_density(const Z64* psi_r, const Z64* a_r, int n_exc, int nb, si
                          hipStream_t st);
 // c[n][k] *= fac / g2h[k] for nvec rows of K coefficients, zero where g2h = 0
 void launch_coulomb(Z64* c, const double* g2h, int K, int nvec, double fac, hipStream_t st);
-// out[e nb + v] = v_r[e] psi_r[v] on full grids (n_exc nb <= 65535 rows)
-void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t n3, Z64* out, hipStream_t st);
+// out[e nb + v] = v_r[e] psi_r[v] - alpha acc[e nb + v] (acc may be null) on full grids (n_exc nb <= 65535 rows)
+void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t n3, const Z64* acc, double alpha,
+                     Z64* out, hipStream_t st);
+// out[w] = scale conj(psi_r[w]) psi_r[v] for w < nb
+void launch_pair_density(const Z64* psi_r, int v, int nb, size_t n3, double scale, Z64* out, hipStream_t st);
+// acc[e nb + v] = sum_{w < nb} tau[w] a_r[e nb + w] for e < n_exc
+void launch_exch_acc(const Z64* tau, const Z64* a_r, int n_exc, int nb, int v, size_t n3, Z64* acc, hipStream_t st);
 void launch_add(Z64* y, const Z64* x, size_t n, hipStream_t st);
 // per-row conj(a) . b; y[row] += c[row / nb] x[row]; p[row] = z[row] + c[row / nb] p[row];
 // z = Teter K_v r with T_v of band row mod nb

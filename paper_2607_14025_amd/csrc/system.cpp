@@ -195,7 +195,8 @@ struct stern_system {
   bool have_dens = false;
   HostBasis hbd;
   DBuf d_col_start, d_col_len, d_col_xmin, d_col_pos, d_zl, d_ycol, d_g2h;
-  DBuf lv_ar, lv_rho, lv_rhog, lv_pend, lv_k, lv_eps, lv_dot, lv_coef;
+  DBuf lv_ar, lv_rho, lv_rhog, lv_pend, lv_k, lv_eps, lv_dot, lv_coef, lv_tau, lv_acc;
+  double lv_alpha = 0.0;  // fraction of bare exchange in the direct term K1d
   DBuf dv_V, dv_W, dv_X, dv_LX, dv_T, dv_LT, dv_part, dv_cm;  // Liouville Davidson
 
   // per-launch event profile (opts->profile)
@@ -291,7 +292,7 @@ struct stern_system {
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
                    &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi, &xkeep,
                    &d_col_start, &d_col_len, &d_col_xmin, &d_col_pos, &d_zl, &d_ycol, &d_g2h, &lv_ar, &lv_rho,
-                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef, &dv_V, &dv_W, &dv_X, &dv_LX,
+                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef, &lv_tau, &lv_acc, &dv_V, &dv_W, &dv_X, &dv_LX,
                    &dv_T, &dv_LT, &dv_part, &dv_cm};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -1547,21 +1548,42 @@ static int liouville_chunk(const stern_system* S, int n_exc) {
   return std::min(ce, n_exc);
 }
 
+// n full grids (in place) -> fac / (|q|^2 / 2) times their components on the 4 Ecut sphere,
+// zero at q = 0, back on the grid: the Hartree potential for fac = 2 pi
+static void potential_grids(stern_system* S, Z64* buf, int n, double fac) {
+  const FftGeom gd = S->geom_d();
+  const size_t n3 = (size_t)gd.N * gd.N * gd.N;
+  hipStream_t st = S->stream;
+  launch_plane_full_fwd(gd, buf, n, S->lv_pend.as<Z64>(), st);
+  launch_xfwd<double>(gd, S->lv_pend.as<Z64>(), nullptr, n, S->lv_rhog.as<Z64>(), 2, nullptr, nullptr, 1.0 / (double)n3,
+                      st);
+  launch_coulomb(S->lv_rhog.as<Z64>(), gd.g2h, gd.npw_pad, n, fac, st);
+  launch_xinv(gd, S->lv_rhog.as<Z64>(), nullptr, n, S->lv_pend.as<Z64>(), st);
+  launch_plane_full_inv(gd, S->lv_pend.as<Z64>(), n, buf, st);
+}
+
 // out = L A for n_exc excitations of n_occ band rows each (column order, stride npw_pad; A in
-// range(P_c)): out_v = P_c [ (H - eps_v) a_v + 2 V[rho_A] psi_v ], rho_A = sum_v conj(psi_v) a_v,
+// range(P_c)): out_v = P_c [ (H - eps_v) a_v + 2 V[rho_A] psi_v - alpha sum_w tau_{wv} a_w ],
+// rho_A = sum_v conj(psi_v) a_v, tau_{wv} = V[conj(psi_w) psi_v] (eq. tau_u),
 // V[rho] = sum_{0 < |q|^2 <= 4 Ecut} 4 pi / |q|^2 rho(q) e^{i q.r}.
 static int liouville_rows(stern_system* S, const Z64* A, Z64* out, int n_exc) {
   const HostBasis& hb = S->hb;
   const int nb = S->n_occ, K = hb.npw_pad, N = hb.N, n = n_exc * nb;
   const size_t n3 = (size_t)N * N * N;
   hipStream_t st = S->stream;
-  const FftGeom g = S->geom(), gd = S->geom_d();
+  const FftGeom g = S->geom();
   const int Kd = S->hbd.npw_pad;
   const int ce = liouville_chunk(S, n_exc);
+  const bool exch = S->lv_alpha != 0.0;
+  const int np = std::max(ce, exch ? nb : 0);  // grids through the potential stage at once
   CHECKED(S->lv_ar.ensure((size_t)ce * nb * n3 * sizeof(Z64)));
   CHECKED(S->lv_rho.ensure((size_t)ce * n3 * sizeof(Z64)));
-  CHECKED(S->lv_rhog.ensure((size_t)ce * Kd * sizeof(Z64)));
-  CHECKED(S->lv_pend.ensure((size_t)ce * N * S->hbd.ncol_pad * sizeof(Z64)));
+  CHECKED(S->lv_rhog.ensure((size_t)np * Kd * sizeof(Z64)));
+  CHECKED(S->lv_pend.ensure((size_t)np * N * S->hbd.ncol_pad * sizeof(Z64)));
+  if (exch) {
+    CHECKED(S->lv_tau.ensure((size_t)nb * n3 * sizeof(Z64)));
+    CHECKED(S->lv_acc.ensure((size_t)ce * nb * n3 * sizeof(Z64)));
+  }
   CHECKED(S->lv_k.ensure((size_t)n * K * sizeof(Z64)));
   CHECKED(S->lv_eps.ensure((size_t)n * sizeof(double)));
   {
@@ -1585,15 +1607,17 @@ static int liouville_rows(stern_system* S, const Z64* A, Z64* out, int n_exc) {
       launch_xinv(g, Ae + (size_t)r0 * K, nullptr, rm, S->pen.as<Z64>(), st);
       launch_plane_full_inv(g, S->pen.as<Z64>(), rm, ar + (size_t)r0 * n3, st);
     }
+    constexpr double kPi = 3.14159265358979323846;
+    if (exch)  // sum_w tau_{wv} a_w of every band v, the pair potentials one band v at a time
+      for (int v = 0; v < nb; ++v) {
+        launch_pair_density(S->psi_r.as<Z64>(), v, nb, n3, 1.0 / hb.omega, S->lv_tau.as<Z64>(), st);
+        potential_grids(S, S->lv_tau.as<Z64>(), nb, 2.0 * kPi);
+        launch_exch_acc(S->lv_tau.as<Z64>(), ar, c, nb, v, n3, S->lv_acc.as<Z64>(), st);
+      }
     launch_band_density(S->psi_r.as<Z64>(), ar, c, nb, n3, 1.0 / hb.omega, rho, st);
-    launch_plane_full_fwd(gd, rho, c, S->lv_pend.as<Z64>(), st);
-    launch_xfwd<double>(gd, S->lv_pend.as<Z64>(), nullptr, c, S->lv_rhog.as<Z64>(), 2, nullptr, nullptr,
-                        1.0 / (double)n3, st);
     // 2 x 4 pi / |q|^2 = 4 pi / (|q|^2 / 2): the factor 2 of the singlet exchange term folded in
-    launch_coulomb(S->lv_rhog.as<Z64>(), gd.g2h, Kd, c, 4.0 * 3.14159265358979323846, st);
-    launch_xinv(gd, S->lv_rhog.as<Z64>(), nullptr, c, S->lv_pend.as<Z64>(), st);
-    launch_plane_full_inv(gd, S->lv_pend.as<Z64>(), c, rho, st);
-    launch_grid_mul(rho, S->psi_r.as<Z64>(), c, nb, n3, ar, st);
+    potential_grids(S, rho, c, 4.0 * kPi);
+    launch_grid_mul(rho, S->psi_r.as<Z64>(), c, nb, n3, exch ? S->lv_acc.as<Z64>() : nullptr, S->lv_alpha, ar, st);
     for (int r0 = 0; r0 < m; r0 += S->ws_solves) {
       const int rm = std::min(S->ws_solves, m - r0);
       launch_plane_full_fwd(g, ar + (size_t)r0 * n3, rm, S->pen.as<Z64>(), st);
@@ -1614,6 +1638,13 @@ static int liouville_setup(stern_system* S, int n_exc) {
   // pencils for whole excitations' rows at a time (the chunk), and the six block vectors of the solve
   CHECKED(ensure_workspace(S, std::max(S->ws_solves, std::max(n_exc * nb, liouville_chunk(S, n_exc) * nb))));
   return 0;
+}
+
+int stern_liouville_set_kernel(stern_system* S, double alpha_x) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!(alpha_x >= 0.0 && alpha_x <= 1.0)) return fail(STERN_ERR_INVALID_ARG, "alpha_x must lie in [0, 1]");
+  S->lv_alpha = alpha_x;
+  return STERN_OK;
 }
 
 int stern_liouville_apply(stern_system* S, int n_exc, const double* a, double* out, int mem_kind) {

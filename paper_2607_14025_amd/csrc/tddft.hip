@@ -1,6 +1,8 @@
-// Grid kernels of the TDDFT Liouville apply (Tamm-Dancoff, Hartree kernel; Sec. II.C.1,
-// eq. bse_tddft): the band-summed transition densities rho_e = sum_v conj(psi_v) a_{e,v}, the
-// Coulomb factor on the 4 Ecut sphere, and the products V_e psi_v. All of it is streaming work on
+// Grid kernels of the TDDFT Liouville apply (Tamm-Dancoff; Sec. II.C.1, eq. bse_tddft): the
+// band-summed transition densities rho_e = sum_v conj(psi_v) a_{e,v}, the Coulomb factor on the
+// 4 Ecut sphere, the products V_e psi_v, and for the bare-exchange direct term the occupied pair
+// densities conj(psi_w) psi_v whose potentials are the integrals tau_{wv} of eq. tau_u and the
+// sums sum_w tau_{wv} a_{e,w}. All of it is streaming work on
 // full N^3 grids (one read and one write per point and band), so the kernels are plain
 // grid-stride loops with coalesced complex FP64 accesses; the FFTs between them are the
 // library's pencil and plane kernels.
@@ -39,16 +41,53 @@ __global__ __launch_bounds__(kGridThreads) void k_coulomb(Z64* __restrict__ c, c
   }
 }
 
-// out[e nb + v][j] = v_r[e][j] psi_r[v][j]
+// out[e nb + v][j] = v_r[e][j] psi_r[v][j] (- alpha acc[e nb + v][j] when acc is given)
 __global__ __launch_bounds__(kGridThreads) void k_grid_mul(const Z64* __restrict__ v_r, const Z64* __restrict__ psi_r,
-                                                           int nb, size_t n3, Z64* __restrict__ out) {
+                                                           int nb, size_t n3, const Z64* __restrict__ acc,
+                                                           double alpha, Z64* __restrict__ out) {
   const int row = blockIdx.y, e = row / nb, v = row - e * nb;
   const Z64* ve = v_r + (size_t)e * n3;
   const Z64* pv = psi_r + (size_t)v * n3;
+  const Z64* ac = acc ? acc + (size_t)row * n3 : nullptr;
   Z64* o = out + (size_t)row * n3;
   for (size_t j = (size_t)blockIdx.x * kGridThreads + threadIdx.x; j < n3; j += (size_t)gridDim.x * kGridThreads) {
     const Z64 a = ve[j], p = pv[j];
-    o[j] = zmk(a.re * p.re - a.im * p.im, a.re * p.im + a.im * p.re);
+    Z64 r = zmk(a.re * p.re - a.im * p.im, a.re * p.im + a.im * p.re);
+    if (ac) {
+      const Z64 c = ac[j];
+      r = zmk(r.re - alpha * c.re, r.im - alpha * c.im);
+    }
+    o[j] = r;
+  }
+}
+
+// pair densities of one occupied orbital with all of them: out[w][j] = scale conj(psi_r[w][j]) psi_r[v][j]
+__global__ __launch_bounds__(kGridThreads) void k_pair_density(const Z64* __restrict__ psi_r, int v, size_t n3,
+                                                               double scale, Z64* __restrict__ out) {
+  const int w = blockIdx.y;
+  const Z64* pw = psi_r + (size_t)w * n3;
+  const Z64* pv = psi_r + (size_t)v * n3;
+  Z64* o = out + (size_t)w * n3;
+  for (size_t j = (size_t)blockIdx.x * kGridThreads + threadIdx.x; j < n3; j += (size_t)gridDim.x * kGridThreads) {
+    const Z64 a = pw[j], b = pv[j];
+    o[j] = zmk(scale * (a.re * b.re + a.im * b.im), scale * (a.re * b.im - a.im * b.re));
+  }
+}
+
+// acc[e nb + v][j] = sum_w tau[w][j] a_r[e nb + w][j], w in order (tau[w] = tau_{wv} of one band v)
+__global__ __launch_bounds__(kGridThreads) void k_exch_acc(const Z64* __restrict__ tau, const Z64* __restrict__ a_r,
+                                                           int nb, int v, size_t n3, Z64* __restrict__ acc) {
+  const int e = blockIdx.y;
+  const Z64* ae = a_r + (size_t)e * nb * n3;
+  Z64* o = acc + ((size_t)e * nb + v) * n3;
+  for (size_t j = (size_t)blockIdx.x * kGridThreads + threadIdx.x; j < n3; j += (size_t)gridDim.x * kGridThreads) {
+    double re = 0.0, im = 0.0;
+    for (int w = 0; w < nb; ++w) {
+      const Z64 t = tau[(size_t)w * n3 + j], a = ae[(size_t)w * n3 + j];
+      re += t.re * a.re - t.im * a.im;
+      im += t.re * a.im + t.im * a.re;
+    }
+    o[j] = zmk(re, im);
   }
 }
 
@@ -81,10 +120,23 @@ void launch_coulomb(Z64* c, const double* g2h, int K, int nvec, double fac, hipS
   k_coulomb<<<grid_blocks(total, 1), kGridThreads, 0, st>>>(c, g2h, K, total, fac);
 }
 
-void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t n3, Z64* out, hipStream_t st) {
+void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t n3, const Z64* acc, double alpha,
+                     Z64* out, hipStream_t st) {
   if (n_exc <= 0 || nb <= 0) return;
   dim3 grid(grid_blocks(n3, n_exc * nb), n_exc * nb);
-  k_grid_mul<<<grid, kGridThreads, 0, st>>>(v_r, psi_r, nb, n3, out);
+  k_grid_mul<<<grid, kGridThreads, 0, st>>>(v_r, psi_r, nb, n3, acc, alpha, out);
+}
+
+void launch_pair_density(const Z64* psi_r, int v, int nb, size_t n3, double scale, Z64* out, hipStream_t st) {
+  if (nb <= 0) return;
+  dim3 grid(grid_blocks(n3, nb), nb);
+  k_pair_density<<<grid, kGridThreads, 0, st>>>(psi_r, v, n3, scale, out);
+}
+
+void launch_exch_acc(const Z64* tau, const Z64* a_r, int n_exc, int nb, int v, size_t n3, Z64* acc, hipStream_t st) {
+  if (n_exc <= 0 || nb <= 0) return;
+  dim3 grid(grid_blocks(n3, n_exc), n_exc);
+  k_exch_acc<<<grid, kGridThreads, 0, st>>>(tau, a_r, nb, v, n3, acc);
 }
 
 void launch_add(Z64* y, const Z64* x, size_t n, hipStream_t st) {

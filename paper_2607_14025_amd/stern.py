@@ -32,7 +32,7 @@ EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_m
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
             "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc", "stern_liouville_apply",
-            "stern_liouville_solve", "stern_liouville_davidson"]
+            "stern_liouville_solve", "stern_liouville_davidson", "stern_liouville_set_kernel"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -146,6 +146,7 @@ def lib():
         L.stern_apply_pc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_apply_pc_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.stern_liouville_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
+        L.stern_liouville_set_kernel.argtypes = [C.c_void_p, C.c_double]
         L.stern_liouville_solve.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
                                             P(C.c_int), P(C.c_double)]
         L.stern_liouville_davidson.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
@@ -485,6 +486,10 @@ class System:
         if a.ndim != 3 or a.shape[1] != self.n_occ or a.shape[2] != self.n_pw:
             raise ValueError(f"excitations must be [n_exc, {self.n_occ}, {self.n_pw}] complex")
         return a
+
+    def liouville_set_kernel(self, alpha_x):
+        """Fraction of bare exchange in the Liouville direct term (stern_liouville_set_kernel)."""
+        _check(lib().stern_liouville_set_kernel(self._h, float(alpha_x)))
 
     def liouville_apply(self, a):
         """L A of the TDDFT Liouville superoperator (stern_liouville_apply) for a [n_exc, n_occ, n_pw]:

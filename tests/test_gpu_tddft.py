@@ -200,3 +200,57 @@ def test_davidson_pairs_satisfy_the_oracle_operator(tiny_system, tiny_sys):
         assert np.linalg.norm(lx[k] - w[k] * xo[k]) <= 2e-8 * w[k]
         assert abs(np.linalg.norm(xo[k]) - 1.0) <= 1e-10
     assert np.all(np.diff(w) >= -1e-12) and w[0] > 0
+
+
+ALPHA = 0.25
+
+
+def test_exchange_apply_matches_oracle_on_the_tiny_cell(tiny_system):
+    t = tiny_system
+    sp, gs = t["spec"], t["gs"]
+    cell, mil = t["cell"], gs["miller"]
+    s = _system(sp.L, sp.ecut, gs["pos"])
+    s.set_occupied(gs["psi"], gs["eps"])
+    s.liouville_set_kernel(ALPHA)
+    nb, npw = s.n_occ, s.n_pw
+    rng = np.random.default_rng(22)
+    a = rng.standard_normal((2, nb, npw)) + 1j * rng.standard_normal((2, nb, npw))
+    print(f"case: tiny cell with alpha_x = {ALPHA}, 2 excitations", flush=True)
+    out = _to_oracle(cell, s.liouville_apply(a), mil)
+    ref = liouville_apply(cell, t["psi"], t["eps"], _to_oracle(cell, a, mil), ALPHA)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    print(f"  max rel error {err:.2e}")
+    assert err <= 1e-12
+    z, it, res, rc = s.liouville_solve(a, tol=1e-10)
+    bo = _to_oracle(cell, s.apply_pc(a.reshape(-1, npw)).reshape(a.shape), mil)
+    ro = liouville_residual(cell, t["psi"], t["eps"], bo, _to_oracle(cell, z, mil), ALPHA)
+    print(f"  Z-vector iterations {it}, oracle residuals {ro}")
+    assert rc == 0 and (ro <= 2e-10).all()
+    with pytest.raises(RuntimeError):
+        s.liouville_set_kernel(1.5)
+    s.close()
+
+
+def test_exchange_davidson_matches_the_dense_spectrum():
+    pos = np.random.default_rng(7).uniform(0.0, MICRO_L, size=(3, 3))
+    cell = OracleCell(MICRO_L, MICRO_ECUT, pos)
+    L, occ, eo, emp, _ = casida_tda(cell, MICRO_OCC, ALPHA)
+    s = _system(MICRO_L, MICRO_ECUT, pos)
+    mil = s.miller()
+    s.set_occupied(cell.give(occ, mil), eo)
+    s.liouville_set_kernel(ALPHA)
+    n_emp = emp.shape[0]
+    cols = np.random.default_rng(9).choice(L.shape[0], size=6, replace=False)
+    A = np.zeros((len(cols), MICRO_OCC, cell.npw), dtype=np.complex128)
+    for k, t in enumerate(cols):
+        v, c = divmod(int(t), n_emp)
+        A[k, v] = emp[c]
+    out = _to_oracle(cell, s.liouville_apply(_to_lib(cell, A, mil)), mil)
+    for k, t in enumerate(cols):
+        assert np.abs((out[k] @ emp.conj().T).reshape(-1) - L[:, t]).max() <= 1e-11 * np.abs(L).max()
+    ref = np.linalg.eigvalsh(L)
+    w, _, info = s.liouville_davidson(5, tol=1e-9, seed=3)
+    s.close()
+    print("micro cell with exchange: w", w, "ref", ref[:5], info)
+    assert info["rc"] == 0
+    assert np.abs(w - ref[:5]).max() <= 1e-10 * ref[4]
