@@ -486,6 +486,23 @@ int stern_liouville_solve(stern_system* sys, int n_exc, const double* b, double*
 int stern_liouville_davidson(stern_system* sys, int n_eig, int block, int max_basis, int max_iter, double tol,
                              unsigned long long seed, double* eig, double* vec, int* n_iter, double* max_resid);
 
+/* Absorption spectra by Lanczos (Sec. II.C.1: over a broad range of energies without the
+ * excitation energies or their orbitals): the Hermitian Lanczos chain of L from d_v = P_c dV psi_v,
+ * all bands of one real field dV [N^3] (the perturbation that couples to the light, e.g. a long-
+ * wavelength potential; host or device per mem_kind). q_0 = d / ||d||; for k = 0 .. n_steps - 1:
+ * w = L q_k - beta_{k-1} q_{k-1}, alpha_k = <q_k|w>, w -= alpha_k q_k, beta_k = ||w||,
+ * q_{k+1} = w / beta_k (inner products over all bands, no reorthogonalisation). Writes alpha and
+ * beta [n_steps] and norm2 = ||d||^2 (host); a chain that closes early is padded with zeros.
+ * STERN_ERR_INVALID_ARG if d = 0. Synchronous. */
+int stern_liouville_lanczos(stern_system* sys, const double* dv, int n_steps, double* alpha, double* beta,
+                            double* norm2, int mem_kind);
+
+/* S(w) = -Im <d|(w + i eta - L)^{-1}|d> / pi from a Lanczos chain, as the continued fraction
+ * norm2 / (z - alpha_0 - beta_0^2 / (z - alpha_1 - ...)), z = w + i eta, closed after the last step
+ * (host only; eta > 0). */
+int stern_lanczos_spectrum(int n_steps, const double* alpha, const double* beta, double norm2, int n_omega,
+                           const double* omega, double eta, double* out);
+
 /* For callers that cannot allocate device memory (code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc): out = P_c c as
  * stern_apply_pc computes it (the same kernels, so bitwise the same result),

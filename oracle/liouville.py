@@ -151,3 +151,41 @@ def free_electron_tda(cell: OracleCell, occ_idx, emp_idx, alpha_x: float = 0.0) 
                     dk = k[v] - k[w]
                     L[a, b] -= alpha_x * 4.0 * math.pi / (cell.omega * float(np.sum((dk * cell.b) ** 2)))
     return L
+
+
+def lanczos_chain(Lmat: np.ndarray, d: np.ndarray, n_steps: int):
+    """Hermitian Lanczos on a dense matrix from d: alpha [n], beta [n] (beta[k] couples steps k and
+    k+1) and ||d||^2; plain three-term recurrence, no reorthogonalisation, in the order it is written:
+    q_0 = d/||d||, w = L q_k - beta_{k-1} q_{k-1}, alpha_k = <q_k|w>, w -= alpha_k q_k,
+    beta_k = ||w||, q_{k+1} = w / beta_k."""
+    nrm2 = float(np.vdot(d, d).real)
+    q_prev = np.zeros_like(d)
+    q = d / np.sqrt(nrm2)
+    alpha, beta = np.zeros(n_steps), np.zeros(n_steps)
+    b_prev = 0.0
+    for k in range(n_steps):
+        w = Lmat @ q - b_prev * q_prev
+        alpha[k] = np.vdot(q, w).real
+        w = w - alpha[k] * q
+        beta[k] = np.linalg.norm(w)
+        q_prev, q, b_prev = q, w / beta[k], beta[k]
+    return alpha, beta, nrm2
+
+
+def spectrum_from_chain(alpha, beta, nrm2, omega, eta):
+    """-Im <d|(w + i eta - L)^{-1}|d> / pi from a Lanczos chain, by the continued fraction
+    nrm2 / (z - a_0 - b_0^2 / (z - a_1 - b_1^2 / ...)), z = w + i eta, closed after the last step."""
+    z = np.asarray(omega, dtype=np.float64) + 1j * eta
+    g = np.zeros_like(z)
+    for k in range(len(alpha) - 1, -1, -1):
+        tail = beta[k] ** 2 * g if k < len(alpha) - 1 else 0.0
+        g = 1.0 / (z - alpha[k] - tail)
+    return -(nrm2 * g).imag / np.pi
+
+
+def spectrum_exact(Lmat: np.ndarray, d: np.ndarray, omega, eta):
+    """-Im <d|(w + i eta - L)^{-1}|d> / pi from the eigenpairs of the dense L."""
+    w, U = np.linalg.eigh(Lmat)
+    amp = np.abs(U.conj().T @ d) ** 2
+    z = np.asarray(omega, dtype=np.float64)[:, None] + 1j * eta
+    return -(amp[None, :] / (z - w[None, :])).sum(axis=1).imag / np.pi

@@ -2015,6 +2015,85 @@ int stern_liouville_davidson(stern_system* S, int n_eig, int block, int max_basi
   return all_conv ? STERN_OK : STERN_WARN_NOT_CONVERGED;
 }
 
+// Lanczos chain of the Liouville superoperator from d_v = P_c dV psi_v of one field (Sec. II.C.1:
+// absorption spectra without the excitation energies): q_0 = d / ||d||, w = L q_k - beta_{k-1} q_{k-1},
+// alpha_k = <q_k|w>, w -= alpha_k q_k, beta_k = ||w||, q_{k+1} = w / beta_k; inner products over all
+// bands. Plain three-term recurrence, no reorthogonalisation.
+int stern_liouville_lanczos(stern_system* S, const double* dv, int n_steps, double* alpha, double* beta, double* norm2,
+                            int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (!dv || !alpha || !beta || !norm2 || n_steps <= 0) return fail(STERN_ERR_INVALID_ARG, "bad arguments");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  Scope sc(S->device, &S->alloc);
+  CHECKED(liouville_setup(S, 1));
+  const int nb = S->n_occ, K = S->hb.npw_pad, N = S->hb.N;
+  const size_t n3 = (size_t)N * N * N;
+  hipStream_t st = S->stream;
+  CHECKED(S->lv_dot.ensure((size_t)nb * sizeof(Z64)));
+  CHECKED(S->lv_coef.ensure(sizeof(Z64)));
+  const double* dvd = dv;
+  if (mem_kind == STERN_MEM_HOST) {
+    CHECKED(S->dv_dev.ensure(n3 * sizeof(double)));
+    HIPOK(hipMemcpyAsync(S->dv_dev.p, dv, n3 * sizeof(double), hipMemcpyHostToDevice, st));
+    dvd = S->dv_dev.as<double>();
+  }
+  // d_v = -b_v of the Sternheimer right-hand sides of this field (the sign leaves the chain unchanged)
+  CHECKED(setup_batch(S, 0, 1, 0, nb, dvd, (double)S->hb.npw * sizeof(Z64)));
+  const CgState cs = cg_state(S);
+  Z64 *Qp = S->wx.as<Z64>(), *Q = S->wp.as<Z64>(), *Wv = S->wq.as<Z64>();
+  std::vector<Z64> d;
+  CHECKED(block_dots(S, cs.b, cs.b, 1, d));
+  *norm2 = d[0].re;
+  if (!(d[0].re > 0.0)) return fail(STERN_ERR_INVALID_ARG, "the field gives P_c dV psi_v = 0 for every band");
+  launch_fill_zero(Qp, (size_t)nb * K, st);
+  HIPOK(hipMemcpyAsync(Q, cs.b, (size_t)nb * K * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+  std::vector<Z64> c(1, zmk(1.0 / std::sqrt(d[0].re), 0.0));
+  CHECKED(upload_coef(S, c));
+  launch_blk_scale(Q, S->lv_coef.as<Z64>(), nb, K, nb, st);
+  double bprev = 0.0;
+  for (int k = 0; k < n_steps; ++k) {
+    CHECKED(liouville_rows(S, Q, Wv, 1));
+    c[0] = zmk(-bprev, 0.0);
+    CHECKED(upload_coef(S, c));
+    launch_blk_axpy(Wv, Qp, S->lv_coef.as<Z64>(), nb, K, nb, st);
+    CHECKED(block_dots(S, Q, Wv, 1, d));
+    alpha[k] = d[0].re;
+    c[0] = zmk(-alpha[k], 0.0);
+    CHECKED(upload_coef(S, c));
+    launch_blk_axpy(Wv, Q, S->lv_coef.as<Z64>(), nb, K, nb, st);
+    CHECKED(block_dots(S, Wv, Wv, 1, d));
+    beta[k] = std::sqrt(std::max(0.0, d[0].re));
+    if (k + 1 == n_steps) break;
+    if (!(beta[k] > 0.0)) {  // an invariant subspace: the chain ends exactly here
+      for (int j = k + 1; j < n_steps; ++j) alpha[j] = beta[j] = 0.0;
+      break;
+    }
+    std::swap(Qp, Q);  // q_{k-1} <- q_k
+    HIPOK(hipMemcpyAsync(Q, Wv, (size_t)nb * K * sizeof(Z64), hipMemcpyDeviceToDevice, st));
+    c[0] = zmk(1.0 / beta[k], 0.0);
+    CHECKED(upload_coef(S, c));
+    launch_blk_scale(Q, S->lv_coef.as<Z64>(), nb, K, nb, st);
+    bprev = beta[k];
+  }
+  return launch_check();
+}
+
+int stern_lanczos_spectrum(int n_steps, const double* alpha, const double* beta, double norm2, int n_omega,
+                           const double* omega, double eta, double* out) {
+  if (n_steps <= 0 || n_omega < 0 || !alpha || !beta || (n_omega > 0 && (!omega || !out)) || !(eta > 0.0))
+    return fail(STERN_ERR_INVALID_ARG, "bad arguments");
+  for (int i = 0; i < n_omega; ++i) {
+    const std::complex<double> z(omega[i], eta);
+    std::complex<double> g = 0.0;
+    for (int k = n_steps - 1; k >= 0; --k) {
+      const std::complex<double> tail = k < n_steps - 1 ? beta[k] * beta[k] * g : 0.0;
+      g = 1.0 / (z - alpha[k] - tail);
+    }
+    out[i] = -norm2 * g.imag() / 3.14159265358979323846;
+  }
+  return STERN_OK;
+}
+
 int stern_apply_pc(stern_system* S, int n_vec, const double* c, double* out, int mem_kind) {
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   if (!S->have_occ) return fail(STERN_ERR_STATE, "set_occupied has not been called");

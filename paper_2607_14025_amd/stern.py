@@ -32,7 +32,8 @@ EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_m
             "stern_model_get_weights", "stern_model_set_weights", "stern_model_free", "stern_model_fit_step", "stern_tunable",
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
             "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc", "stern_liouville_apply",
-            "stern_liouville_solve", "stern_liouville_davidson", "stern_liouville_set_kernel"]
+            "stern_liouville_solve", "stern_liouville_davidson", "stern_liouville_set_kernel",
+            "stern_liouville_lanczos", "stern_lanczos_spectrum"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -147,6 +148,10 @@ def lib():
         L.stern_apply_pc_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.stern_liouville_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_liouville_set_kernel.argtypes = [C.c_void_p, C.c_double]
+        L.stern_liouville_lanczos.argtypes = [C.c_void_p, C.c_void_p, C.c_int, P(C.c_double), P(C.c_double),
+                                              P(C.c_double), C.c_int]
+        L.stern_lanczos_spectrum.argtypes = [C.c_int, P(C.c_double), P(C.c_double), C.c_double, C.c_int,
+                                             P(C.c_double), C.c_double, P(C.c_double)]
         L.stern_liouville_solve.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_double, C.c_int, C.c_int,
                                             P(C.c_int), P(C.c_double)]
         L.stern_liouville_davidson.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double,
@@ -486,6 +491,28 @@ class System:
         if a.ndim != 3 or a.shape[1] != self.n_occ or a.shape[2] != self.n_pw:
             raise ValueError(f"excitations must be [n_exc, {self.n_occ}, {self.n_pw}] complex")
         return a
+
+    def liouville_lanczos(self, dv, n_steps):
+        """Lanczos chain of the Liouville superoperator from P_c dV psi_v (stern_liouville_lanczos) for
+        one real field dv [N, N, N] (host); returns (alpha, beta, ||d||^2)."""
+        dv = np.ascontiguousarray(dv, dtype=np.float64)
+        a, b, n2 = np.zeros(n_steps), np.zeros(n_steps), C.c_double()
+        _check(lib().stern_liouville_lanczos(self._h, C.c_void_p(dv.ctypes.data), int(n_steps),
+                                             a.ctypes.data_as(C.POINTER(C.c_double)),
+                                             b.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n2), STERN_MEM_HOST))
+        return a, b, n2.value
+
+    @staticmethod
+    def lanczos_spectrum(alpha, beta, norm2, omega, eta):
+        """-Im <d|(w + i eta - L)^{-1}|d> / pi from a chain (stern_lanczos_spectrum)."""
+        a = np.ascontiguousarray(alpha, dtype=np.float64)
+        b = np.ascontiguousarray(beta, dtype=np.float64)
+        om = np.ascontiguousarray(omega, dtype=np.float64)
+        out = np.zeros_like(om)
+        P = C.POINTER(C.c_double)
+        _check(lib().stern_lanczos_spectrum(len(a), a.ctypes.data_as(P), b.ctypes.data_as(P), float(norm2), len(om),
+                                            om.ctypes.data_as(P), float(eta), out.ctypes.data_as(P)))
+        return out
 
     def liouville_set_kernel(self, alpha_x):
         """Fraction of bare exchange in the Liouville direct term (stern_liouville_set_kernel)."""

@@ -254,3 +254,29 @@ def test_exchange_davidson_matches_the_dense_spectrum():
     print("micro cell with exchange: w", w, "ref", ref[:5], info)
     assert info["rc"] == 0
     assert np.abs(w - ref[:5]).max() <= 1e-10 * ref[4]
+
+
+def test_lanczos_chain_matches_the_dense_chain(micro):
+    """The GPU chain from P_c dV psi_v against the same recurrence on the transition-basis matrix, and
+    its continued fraction against the eigen-sum at the bottom of the spectrum."""
+    from oracle.liouville import lanczos_chain, spectrum_exact
+    from oracle.sternheimer import rhs
+    cell, L, occ, emp, s = micro["cell"], micro["L"], micro["occ"], micro["emp"], micro["sys"]
+    N = cell.N
+    dv = np.random.default_rng(17).standard_normal((N, N, N))
+    k = 12
+    print(f"case: micro cell Lanczos, {k} steps", flush=True)
+    a, b, n2 = s.liouville_lanczos(dv, k)
+    bt = rhs(cell, occ, dv[None], list(range(MICRO_OCC)), [0] * MICRO_OCC)
+    d = (bt @ emp.conj().T).reshape(-1)
+    ao, bo, n2o = lanczos_chain(L, d, k)
+    print("  alpha", a[:4], ao[:4], "beta", b[:4], bo[:4])
+    assert abs(n2 - n2o) <= 1e-12 * n2o
+    assert np.abs(a - ao).max() <= 1e-9 * np.abs(ao).max()
+    assert np.abs(b - bo).max() <= 1e-9 * np.abs(bo).max()
+    a60, b60, n2 = s.liouville_lanczos(dv, 60)
+    om = np.linspace(0.0, 0.25, 101)
+    sp = s.lanczos_spectrum(a60, b60, n2, om, 0.02)
+    ex = spectrum_exact(L, d, om, 0.02)
+    print(f"  spectrum max rel difference {np.abs(sp - ex).max() / np.abs(ex).max():.2e}")
+    assert np.abs(sp - ex).max() <= 1e-6 * np.abs(ex).max()

@@ -161,3 +161,31 @@ def test_model_cell_with_exchange_grid_route_matches_transition_matrix(micro):
     for k, t in enumerate(cols):
         col = (out[k] @ emp.conj().T).reshape(-1)
         assert np.max(np.abs(col - L[:, t])) <= 1e-11 * np.max(np.abs(L))
+
+
+def test_lanczos_chain_reproduces_moments_and_the_low_energy_spectrum(micro):
+    """k steps of the chain reproduce the moments <d|L^j|d>, j < 2k, exactly (those of its tridiagonal
+    matrix); its continued fraction equals the eigen-sum where the chain has converged (the bottom of
+    the spectrum), and the eigen-sum integrates to ||d||^2."""
+    from oracle.liouville import lanczos_chain, spectrum_exact, spectrum_from_chain
+    L = micro["L"]
+    d = np.random.default_rng(2).standard_normal(L.shape[0]).astype(np.complex128)
+    k = 8
+    a, b, n2 = lanczos_chain(L, d, k)
+    T = np.diag(a) + np.diag(b[:-1], 1) + np.diag(b[:-1], -1)
+    v, e1 = d.copy(), np.eye(k)[0]
+    t = e1.copy()
+    for j in range(2 * k):
+        mom = np.vdot(d, v).real
+        assert abs(n2 * t[0] - mom) <= 1e-9 * abs(mom), j
+        v = L @ v
+        t = T @ t
+    a, b, n2 = lanczos_chain(L, d, 60)
+    om = np.linspace(0.0, 0.25, 101)
+    eta = 0.02
+    s_ch = spectrum_from_chain(a, b, n2, om, eta)
+    s_ex = spectrum_exact(L, d, om, eta)
+    assert np.abs(s_ch - s_ex).max() <= 1e-8 * np.abs(s_ex).max()
+    wide = np.linspace(-200.0, 200.0, 400001)
+    total = np.trapezoid(spectrum_exact(L, d, wide, 0.5), wide)
+    assert abs(total - n2) <= 5e-3 * n2
