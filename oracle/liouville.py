@@ -25,6 +25,15 @@ so that L = D + K1e - K1d. <B|K1d A> = alpha sum_{v,v'} int conj(b_v) tau_{v'v} 
 tau_{vv'} = conj(tau_{v'v}); for plane-wave states it couples transitions with the same momentum
 transfer by alpha 4 pi / (Omega |k_v - k_v'|^2) (v != v'; q = 0 omitted, as in V).
 
+BSE replaces the bare interaction of the direct term by the screened W of eq. tau. With the PDEP
+eigenpairs of chi-bar0 (Sec. II.A, eq. pdep), W = v + sum_a (v^{1/2} phi_a) lambda_a / (1 - lambda_a)
+(v^{1/2} phi_a)^T on the span of the phi_a. Here the direct term takes the interaction
+alpha v + sum_a w_a c_a w_a^T for real grid potentials w_a and weights c_a, acting as
+V_W[rho](r) = alpha V[rho](r) + sum_a w_a(r) c_a <w_a, rho>, <f, g> = N^-3 sum_j f(r_j) g(r_j);
+screening_from_chibar0 builds w_a = v^{1/2} g_a and c_a = lambda_a / (1 - lambda_a) from the dense
+chi-bar0 of oracle/pdep.py (g_a its eigenfunctions, normalised to a unit cell average of g_a^2),
+and alpha = 1 with them is BSE's W.
+
 Routes, pinned against each other and against closed forms:
 * liouville_apply: the grid route above (FFTs of the oracle cell);
 * casida_tda: the matrix in the transition basis {a_v' = delta_vv' psi_c} from a full
@@ -65,18 +74,38 @@ def hartree_grid(cell: OracleCell, rho_r: np.ndarray) -> np.ndarray:
     return sfft.ifftn(box, axes=(1, 2, 3), workers=WORKERS, norm="forward")  # sum_q V(q) e^{i q r}
 
 
+def screened_grid(cell: OracleCell, rho_r: np.ndarray, alpha_x: float, screen) -> np.ndarray:
+    """alpha V[rho] + sum_a w_a c_a <w_a, rho> for densities rho_r [n, N, N, N]; screen = (w [m, N, N, N], c [m])."""
+    out = alpha_x * hartree_grid(cell, rho_r) if alpha_x != 0.0 else np.zeros_like(rho_r)
+    if screen is not None:
+        w, c = screen
+        N3 = cell.N ** 3
+        proj = np.einsum("axyz,nxyz->na", w, rho_r) / N3          # <w_a, rho_n>
+        out = out + np.einsum("axyz,na->nxyz", w, proj * c[None, :])
+    return out
+
+
+def screening_from_chibar0(cell: OracleCell, M: np.ndarray, fields: np.ndarray, vh: np.ndarray):
+    """(w [2m, N, N, N], c [2m]) of W - v from the dense chi-bar0 M in the real basis fields [2m, N, N, N]
+    with v^{1/2} vh [2m] (oracle/pdep.py): w_a = sum_j U_ja vh_j f_j, c_a = lambda_a / (1 - lambda_a)."""
+    lam, U = np.linalg.eigh(0.5 * (M + M.T))
+    w = np.einsum("ja,jxyz->axyz", U * vh[:, None], fields)
+    return w, lam / (1.0 - lam)
+
+
 def liouville_apply(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, A: np.ndarray,
-                    alpha_x: float = 0.0) -> np.ndarray:
+                    alpha_x: float = 0.0, screen=None) -> np.ndarray:
     """(D + K1e - K1d) A for A [n_exc, n_occ, npw] (oracle order); psi [n_occ, npw], eps [n_occ];
-    alpha_x the fraction of bare exchange in K1d (0: none)."""
+    K1d with the interaction alpha_x v + sum_a w_a c_a w_a^T (screen = (w, c) or None)."""
     A = np.asarray(A, dtype=np.complex128)
     n_exc, n_occ, npw = A.shape
     Ap = project(psi, A.reshape(-1, npw)).reshape(n_exc, n_occ, npw)
     out = np.empty_like(Ap)
     psi_r = cell.to_grid(psi)                                    # psi~_v(r) = sqrt(Omega) psi_v(r)
     tau = None
-    if alpha_x != 0.0:                                           # tau[v', v] = V[conj(psi_v') psi_v]
-        tau = np.stack([hartree_grid(cell, np.conj(psi_r) * psi_r[v][None] / cell.omega) for v in range(n_occ)], 1)
+    if alpha_x != 0.0 or screen is not None:                     # tau[v', v] = V_W[conj(psi_v') psi_v]
+        tau = np.stack([screened_grid(cell, np.conj(psi_r) * psi_r[v][None] / cell.omega, alpha_x, screen)
+                        for v in range(n_occ)], 1)
     for e in range(n_exc):
         d = cell.h_apply(Ap[e]) - eps[:, None] * Ap[e]
         a_r = cell.to_grid(Ap[e])
@@ -84,22 +113,24 @@ def liouville_apply(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, A: np.nd
         v = hartree_grid(cell, rho)[0]
         k = 2.0 * cell.from_grid(v[None] * psi_r)
         if tau is not None:
-            k -= alpha_x * cell.from_grid(np.einsum("wvxyz,wxyz->vxyz", tau, a_r))
+            k -= cell.from_grid(np.einsum("wvxyz,wxyz->vxyz", tau, a_r))
         out[e] = project(psi, d + k)
     return out
 
 
 def liouville_residual(cell: OracleCell, psi: np.ndarray, eps: np.ndarray, b: np.ndarray, z: np.ndarray,
-                       alpha_x: float = 0.0) -> np.ndarray:
+                       alpha_x: float = 0.0, screen=None) -> np.ndarray:
     """||b - L z|| / ||b|| per excitation (norms over all bands)."""
-    r = b - liouville_apply(cell, psi, eps, z, alpha_x)
+    r = b - liouville_apply(cell, psi, eps, z, alpha_x, screen)
     n = b.shape[0]
     return np.linalg.norm(r.reshape(n, -1), axis=1) / np.linalg.norm(b.reshape(n, -1), axis=1)
 
 
-def casida_tda(cell: OracleCell, n_occ: int, alpha_x: float = 0.0):
-    """Dense L in the transition basis t = v * n_emp + c from a full diagonalisation of H, with
-    alpha_x of bare exchange: L_{vc,v'c'} -= alpha_x Omega sum_q (4 pi/|q|^2) conj(rho_{c'c}(q)) rho_{v'v}(q).
+def casida_tda(cell: OracleCell, n_occ: int, alpha_x: float = 0.0, screen=None):
+    """Dense L in the transition basis t = v * n_emp + c from a full diagonalisation of H, with the
+    direct term of the interaction alpha_x v + sum_a w_a c_a w_a^T:
+    L_{vc,v'c'} -= alpha_x Omega sum_q (4 pi/|q|^2) conj(rho_{c'c}(q)) rho_{v'v}(q)
+                   + Omega sum_a c_a <w_a, rho_{cc'}> <w_a, rho_{v'v}>.
     Returns (L [n_occ n_emp, n_occ n_emp], occupied psi, eps_occ, empty psi, eps_emp)."""
     e, U = np.linalg.eigh(cell.h_dense())
     psi = U.T
@@ -119,7 +150,7 @@ def casida_tda(cell: OracleCell, n_occ: int, alpha_x: float = 0.0):
     R = rho_q.reshape(n_occ * n_emp, -1)
     L = 2.0 * cell.omega * (R.conj() * vq[None, :]) @ R.T
     L[np.diag_indices_from(L)] += (ee[None, :] - eo[:, None]).reshape(-1)
-    if alpha_x != 0.0:
+    if alpha_x != 0.0 or screen is not None:
         def pair_q(a_r, b_r):                                   # rho_ab(q) for rho_ab = conj(a) b
             out = np.empty((a_r.shape[0], b_r.shape[0], len(vq)), dtype=np.complex128)
             for i in range(a_r.shape[0]):
@@ -130,8 +161,14 @@ def casida_tda(cell: OracleCell, n_occ: int, alpha_x: float = 0.0):
         Rvv = pair_q(occ_r, occ_r)                              # [v', v, q]
         Rcc = pair_q(emp_r, emp_r)                              # [c', c, q]
         # K1d[(v,c),(v',c')] = Omega sum_q conj(rho_{c'c}(q)) w(q) rho_{v'v}(q)
-        K = cell.omega * np.einsum("dcq,q,wvq->vcwd", Rcc.conj(), vq, Rvv, optimize=True)
-        L -= alpha_x * K.reshape(n_occ * n_emp, n_occ * n_emp)
+        K = alpha_x * cell.omega * np.einsum("dcq,q,wvq->vcwd", Rcc.conj(), vq, Rvv, optimize=True)
+        if screen is not None:
+            w, cw = screen
+            wq = sfft.fftn(w, axes=(1, 2, 3), workers=WORKERS, norm="forward")[:, ix, iy, iz]  # w_a(q)
+            pc = np.einsum("aq,cdq->acd", wq.conj(), Rcc)                            # <w_a, rho_{cc'}>
+            pv = np.einsum("aq,wvq->awv", wq.conj(), Rvv)                            # <w_a, rho_{v'v}>
+            K += cell.omega * np.einsum("a,acd,awv->vcwd", cw, pc, pv, optimize=True)
+        L -= K.reshape(n_occ * n_emp, n_occ * n_emp)
     return L, occ, eo, emp, ee
 
 

@@ -189,3 +189,60 @@ def test_lanczos_chain_reproduces_moments_and_the_low_energy_spectrum(micro):
     wide = np.linspace(-200.0, 200.0, 400001)
     total = np.trapezoid(spectrum_exact(L, d, wide, 0.5), wide)
     assert abs(total - n2) <= 5e-3 * n2
+
+
+@pytest.fixture(scope="module")
+def screening(micro):
+    """W - v from the dense chi-bar0 of the micro cell (potentials |G|^2 < Ecut / 4)."""
+    from oracle.closed_form import sum_over_states
+    from oracle.liouville import screening_from_chibar0
+    from oracle.pdep import basis_fields, potential_reps, vhalf
+    cell = micro["cell"]
+    reps = potential_reps(cell.L, cell.ecut / 4.0)
+    f = basis_fields(cell, reps)
+    vh = vhalf(cell, reps)
+    _, _, _, dn = sum_over_states(cell, MICRO_OCC, vh[:, None, None, None] * f)
+    m = len(vh)
+    M = (f.reshape(m, -1) @ dn.reshape(m, -1).T) / cell.N ** 3 * vh[:, None]
+    w, c = screening_from_chibar0(cell, M, f, vh)
+    return dict(M=M, f=f, vh=vh, w=w, c=c)
+
+
+def test_screening_equals_the_inverse_dielectric_matrix(micro, screening):
+    """sum_a w_a c_a <w_a, .> from the eigenpairs = v^{1/2} ((1 - M)^{-1} - 1) v^{1/2} by a dense solve,
+    on the real basis functions (no eigen-decomposition on this side)."""
+    cell = micro["cell"]
+    M, f, vh, w, c = (screening[k] for k in ("M", "f", "vh", "w", "c"))
+    m = len(vh)
+    N3 = cell.N ** 3
+    proj = np.einsum("axyz,jxyz->ja", w, f) / N3
+    got = np.einsum("ja,a,ka->jk", proj, c, proj)                       # <f_j, dW f_k>_N
+    Ms = 0.5 * (M + M.T)
+    ref = vh[:, None] * (np.linalg.solve(np.eye(m) - Ms, np.eye(m)) - np.eye(m)) * vh[None, :]
+    assert np.abs(got - ref).max() <= 1e-10 * np.abs(ref).max()
+    assert np.all(c <= 0.0) and np.all(c > -1.0)                        # screening lowers W
+
+
+def test_screened_grid_route_matches_transition_matrix(micro, screening):
+    """BSE's W (alpha = 1 plus the screening): grid route against the transition-basis matrix."""
+    from oracle.liouville import screened_grid
+    cell, occ, emp = micro["cell"], micro["occ"], micro["emp"]
+    scr = (screening["w"], screening["c"])
+    L, _, _, _, _ = casida_tda(cell, MICRO_OCC, 1.0, scr)
+    L1, _, _, _, _ = casida_tda(cell, MICRO_OCC, 1.0)
+    assert np.max(np.abs(L - L.conj().T)) <= 1e-12 * np.max(np.abs(L))
+    assert np.abs(L - L1).max() > 1e-4                                   # the screening changes L
+    n_emp = emp.shape[0]
+    cols = np.random.default_rng(6).choice(L.shape[0], size=6, replace=False)
+    A = np.zeros((len(cols), MICRO_OCC, cell.npw), dtype=np.complex128)
+    for k, t in enumerate(cols):
+        v, c = divmod(int(t), n_emp)
+        A[k, v] = emp[c]
+    out = liouville_apply(cell, occ, micro["eo"], A, 1.0, scr)
+    for k, t in enumerate(cols):
+        col = (out[k] @ emp.conj().T).reshape(-1)
+        assert np.max(np.abs(col - L[:, t])) <= 1e-11 * np.max(np.abs(L))
+    # no screening weight: the bare-exchange route
+    rho = np.random.default_rng(1).standard_normal((2, cell.N, cell.N, cell.N)).astype(np.complex128)
+    zero = (screening["w"], np.zeros_like(screening["c"]))
+    assert np.abs(screened_grid(cell, rho, 0.3, zero) - screened_grid(cell, rho, 0.3, None)).max() <= 1e-15
