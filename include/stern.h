@@ -462,6 +462,17 @@ int stern_liouville_apply(stern_system* sys, int n_exc, const double* a, double*
  * pair potentials again (n_occ Poisson solves per band). STERN_ERR_INVALID_ARG outside [0, 1]. */
 int stern_liouville_set_kernel(stern_system* sys, double alpha_x);
 
+/* BSE: the screened interaction of eq. tau in the direct term, as a low-rank addition to the bare
+ * part set by stern_liouville_set_kernel:
+ *   V_W[rho](r) = alpha_x V[rho](r) + sum_a w_a(r) c_a <w_a, rho>,  <f, g> = N^-3 sum_j f(r_j) g(r_j),
+ *   tau_{wv} = V_W[conj(psi_w) psi_v],  (K1d A)_v = P_c sum_w tau_{wv} a_w,
+ * for n real potentials w [n][N^3] (grid order of the fields of stern_apply_chi0) and weights c [n],
+ * host or device per mem_kind (copied). With the PDEP eigenpairs (lambda_a, phi_a) of Sec. II.A
+ * (eq. pdep) normalised to a unit cell average of phi_a^2, w_a = v^{1/2} phi_a and
+ * c_a = lambda_a / (1 - lambda_a) give W = v + v^{1/2} ((1 - chi-bar0)^{-1} - 1) v^{1/2} on their span,
+ * and alpha_x = 1 makes K1d BSE's direct term. n = 0 removes the screening. */
+int stern_liouville_set_screening(stern_system* sys, int n, const double* w, const double* c, int mem_kind);
+
 /* Linear systems L z_e = b_e of the Liouville superoperator, as the Z-vector equations of
  * excited-state forces pose them (Sec. II.C.2), for n_exc right-hand sides b [n_exc][n_occ][n_pw]
  * (projected on range(P_c) first): preconditioned CG with one block (all band rows) per

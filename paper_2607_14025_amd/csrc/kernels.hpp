@@ -240,6 +240,11 @@ void launch_grid_mul(const Z64* v_r, const Z64* psi_r, int n_exc, int nb, size_t
                      Z64* out, hipStream_t st);
 // out[w] = scale conj(psi_r[w]) psi_r[v] for w < nb
 void launch_pair_density(const Z64* psi_r, int v, int nb, size_t n3, double scale, Z64* out, hipStream_t st);
+// proj[r][a] = N^-3 sum_j w[a][j] rho[r][j] for n real potentials w and nrows complex grids rho
+void launch_scr_proj(const Z64* rho, const double* w, int n, int nrows, size_t n3, Z64* proj, hipStream_t st);
+// tau[r] += sum_a w[a] c[a] proj[r][a]
+void launch_scr_add(Z64* tau, const double* w, const Z64* proj, const double* c, int n, int nrows, size_t n3,
+                    hipStream_t st);
 // acc[e nb + v] = sum_{w < nb} tau[w] a_r[e nb + w] for e < n_exc
 void launch_exch_acc(const Z64* tau, const Z64* a_r, int n_exc, int nb, int v, size_t n3, Z64* acc, hipStream_t st);
 void launch_add(Z64* y, const Z64* x, size_t n, hipStream_t st);

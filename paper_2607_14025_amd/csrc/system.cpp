@@ -197,6 +197,9 @@ struct stern_system {
   DBuf d_col_start, d_col_len, d_col_xmin, d_col_pos, d_zl, d_ycol, d_g2h;
   DBuf lv_ar, lv_rho, lv_rhog, lv_pend, lv_k, lv_eps, lv_dot, lv_coef, lv_tau, lv_acc;
   double lv_alpha = 0.0;  // fraction of bare exchange in the direct term K1d
+  // screening of the direct term: n_scr real potentials [n_scr][N^3] and weights, and projections
+  int n_scr = 0;
+  DBuf scr_w, scr_c, scr_proj;
   DBuf dv_V, dv_W, dv_X, dv_LX, dv_T, dv_LT, dv_part, dv_cm;  // Liouville Davidson
 
   // per-launch event profile (opts->profile)
@@ -292,7 +295,7 @@ struct stern_system {
                    &g_rej,     &net_feat, &net_coef, &kprec,  &v_t,     &v_t32,    &band_eps, &band_invT,
                    &band_feat, &projT_hi, &projT_lo, &cpart2, &m_cnt, &negk, &sv_rzi, &xkeep,
                    &d_col_start, &d_col_len, &d_col_xmin, &d_col_pos, &d_zl, &d_ycol, &d_g2h, &lv_ar, &lv_rho,
-                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef, &lv_tau, &lv_acc, &dv_V, &dv_W, &dv_X, &dv_LX,
+                   &lv_rhog, &lv_pend, &lv_k, &lv_eps, &lv_dot, &lv_coef, &lv_tau, &lv_acc, &scr_w, &scr_c, &scr_proj, &dv_V, &dv_W, &dv_X, &dv_LX,
                    &dv_T, &dv_LT, &dv_part, &dv_cm};
     for (DBuf* d : all) d->release();
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
@@ -1574,7 +1577,7 @@ static int liouville_rows(stern_system* S, const Z64* A, Z64* out, int n_exc) {
   const FftGeom g = S->geom();
   const int Kd = S->hbd.npw_pad;
   const int ce = liouville_chunk(S, n_exc);
-  const bool exch = S->lv_alpha != 0.0;
+  const bool exch = S->lv_alpha != 0.0 || S->n_scr > 0;
   const int np = std::max(ce, exch ? nb : 0);  // grids through the potential stage at once
   CHECKED(S->lv_ar.ensure((size_t)ce * nb * n3 * sizeof(Z64)));
   CHECKED(S->lv_rho.ensure((size_t)ce * n3 * sizeof(Z64)));
@@ -1583,6 +1586,7 @@ static int liouville_rows(stern_system* S, const Z64* A, Z64* out, int n_exc) {
   if (exch) {
     CHECKED(S->lv_tau.ensure((size_t)nb * n3 * sizeof(Z64)));
     CHECKED(S->lv_acc.ensure((size_t)ce * nb * n3 * sizeof(Z64)));
+    if (S->n_scr > 0) CHECKED(S->scr_proj.ensure((size_t)nb * S->n_scr * sizeof(Z64)));
   }
   CHECKED(S->lv_k.ensure((size_t)n * K * sizeof(Z64)));
   CHECKED(S->lv_eps.ensure((size_t)n * sizeof(double)));
@@ -1610,14 +1614,20 @@ static int liouville_rows(stern_system* S, const Z64* A, Z64* out, int n_exc) {
     constexpr double kPi = 3.14159265358979323846;
     if (exch)  // sum_w tau_{wv} a_w of every band v, the pair potentials one band v at a time
       for (int v = 0; v < nb; ++v) {
-        launch_pair_density(S->psi_r.as<Z64>(), v, nb, n3, 1.0 / hb.omega, S->lv_tau.as<Z64>(), st);
-        potential_grids(S, S->lv_tau.as<Z64>(), nb, 2.0 * kPi);
-        launch_exch_acc(S->lv_tau.as<Z64>(), ar, c, nb, v, n3, S->lv_acc.as<Z64>(), st);
+        Z64* tau = S->lv_tau.as<Z64>();
+        launch_pair_density(S->psi_r.as<Z64>(), v, nb, n3, 1.0 / hb.omega, tau, st);
+        if (S->n_scr > 0)
+          launch_scr_proj(tau, S->scr_w.as<double>(), S->n_scr, nb, n3, S->scr_proj.as<Z64>(), st);
+        potential_grids(S, tau, nb, 2.0 * kPi * S->lv_alpha);  // alpha V[rho]
+        if (S->n_scr > 0)
+          launch_scr_add(tau, S->scr_w.as<double>(), S->scr_proj.as<Z64>(), S->scr_c.as<double>(), S->n_scr, nb, n3,
+                         st);
+        launch_exch_acc(tau, ar, c, nb, v, n3, S->lv_acc.as<Z64>(), st);
       }
     launch_band_density(S->psi_r.as<Z64>(), ar, c, nb, n3, 1.0 / hb.omega, rho, st);
     // 2 x 4 pi / |q|^2 = 4 pi / (|q|^2 / 2): the factor 2 of the singlet exchange term folded in
     potential_grids(S, rho, c, 4.0 * kPi);
-    launch_grid_mul(rho, S->psi_r.as<Z64>(), c, nb, n3, exch ? S->lv_acc.as<Z64>() : nullptr, S->lv_alpha, ar, st);
+    launch_grid_mul(rho, S->psi_r.as<Z64>(), c, nb, n3, exch ? S->lv_acc.as<Z64>() : nullptr, 1.0, ar, st);
     for (int r0 = 0; r0 < m; r0 += S->ws_solves) {
       const int rm = std::min(S->ws_solves, m - r0);
       launch_plane_full_fwd(g, ar + (size_t)r0 * n3, rm, S->pen.as<Z64>(), st);
@@ -1644,6 +1654,31 @@ int stern_liouville_set_kernel(stern_system* S, double alpha_x) {
   if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
   if (!(alpha_x >= 0.0 && alpha_x <= 1.0)) return fail(STERN_ERR_INVALID_ARG, "alpha_x must lie in [0, 1]");
   S->lv_alpha = alpha_x;
+  return STERN_OK;
+}
+
+int stern_liouville_set_screening(stern_system* S, int n, const double* w, const double* c, int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (n < 0 || (n > 0 && (!w || !c))) return fail(STERN_ERR_INVALID_ARG, "need n >= 0, w and c");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  Scope sc(S->device, &S->alloc);
+  S->n_scr = 0;
+  if (n == 0) return STERN_OK;
+  const size_t n3 = (size_t)S->hb.N * S->hb.N * S->hb.N;
+  std::vector<double> hc(n);
+  if (mem_kind == STERN_MEM_DEVICE)
+    HIPOK(hipMemcpy(hc.data(), c, n * sizeof(double), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(hc.data(), c, n * sizeof(double));
+  for (double x : hc)
+    if (!std::isfinite(x)) return fail(STERN_ERR_INVALID_ARG, "screening weights must be finite");
+  CHECKED(S->scr_w.ensure((size_t)n * n3 * sizeof(double)));
+  CHECKED(S->scr_c.ensure((size_t)n * sizeof(double)));
+  HIPOK(hipMemcpyAsync(S->scr_w.p, w, (size_t)n * n3 * sizeof(double),
+                       mem_kind == STERN_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, S->stream));
+  HIPOK(hipMemcpyAsync(S->scr_c.p, hc.data(), n * sizeof(double), hipMemcpyHostToDevice, S->stream));
+  HIPOK(hipStreamSynchronize(S->stream));
+  S->n_scr = n;
   return STERN_OK;
 }
 

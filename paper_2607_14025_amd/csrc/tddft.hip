@@ -99,6 +99,60 @@ __global__ __launch_bounds__(kGridThreads) void k_add(Z64* __restrict__ y, const
   }
 }
 
+// proj[r][a] = N^-3 sum_j w[a][j] rho[r][j] (one workgroup per (a, r), fixed order)
+__global__ __launch_bounds__(kGridThreads) void k_scr_proj(const Z64* __restrict__ rho, const double* __restrict__ w,
+                                                           int n, size_t n3, Z64* __restrict__ proj) {
+  __shared__ double sre[kGridThreads / 64], sim[kGridThreads / 64];
+  const int a = blockIdx.x, r = blockIdx.y;
+  const Z64* x = rho + (size_t)r * n3;
+  const double* wa = w + (size_t)a * n3;
+  double re = 0.0, im = 0.0;
+  for (size_t j = threadIdx.x; j < n3; j += kGridThreads) {
+    const double f = wa[j];
+    const Z64 v = x[j];
+    re += f * v.re;
+    im += f * v.im;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    re += __shfl_xor(re, o);
+    im += __shfl_xor(im, o);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) {
+    sre[wave] = re;
+    sim[wave] = im;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tr = 0.0, ti = 0.0;
+    for (int k = 0; k < kGridThreads / 64; ++k) {
+      tr += sre[k];
+      ti += sim[k];
+    }
+    proj[(size_t)r * n + a] = zmk(tr / (double)n3, ti / (double)n3);
+  }
+}
+
+// tau[r][j] += sum_a w[a][j] c[a] proj[r][a]
+__global__ __launch_bounds__(kGridThreads) void k_scr_add(Z64* __restrict__ tau, const double* __restrict__ w,
+                                                          const Z64* __restrict__ proj, const double* __restrict__ c,
+                                                          int n, size_t n3) {
+  const int r = blockIdx.y;
+  Z64* t = tau + (size_t)r * n3;
+  const Z64* p = proj + (size_t)r * n;
+  for (size_t j = (size_t)blockIdx.x * kGridThreads + threadIdx.x; j < n3; j += (size_t)gridDim.x * kGridThreads) {
+    double re = 0.0, im = 0.0;
+    for (int a = 0; a < n; ++a) {
+      const double f = w[(size_t)a * n3 + j] * c[a];
+      re += f * p[a].re;
+      im += f * p[a].im;
+    }
+    const Z64 v = t[j];
+    t[j] = zmk(v.re + re, v.im + im);
+  }
+}
+
 unsigned grid_blocks(size_t n, int per_row_rows) {
   // enough workgroups to fill the chip several times over, fewer when a launch has many rows
   const size_t want = std::max<size_t>(1, 2048 / (size_t)std::max(1, per_row_rows));
@@ -142,6 +196,17 @@ void launch_exch_acc(const Z64* tau, const Z64* a_r, int n_exc, int nb, int v, s
 void launch_add(Z64* y, const Z64* x, size_t n, hipStream_t st) {
   if (n == 0) return;
   k_add<<<grid_blocks(n, 1), kGridThreads, 0, st>>>(y, x, n);
+}
+
+void launch_scr_proj(const Z64* rho, const double* w, int n, int nrows, size_t n3, Z64* proj, hipStream_t st) {
+  if (n <= 0 || nrows <= 0) return;
+  k_scr_proj<<<dim3(n, nrows), kGridThreads, 0, st>>>(rho, w, n, n3, proj);
+}
+
+void launch_scr_add(Z64* tau, const double* w, const Z64* proj, const double* c, int n, int nrows, size_t n3,
+                    hipStream_t st) {
+  if (n <= 0 || nrows <= 0) return;
+  k_scr_add<<<dim3(grid_blocks(n3, nrows), nrows), kGridThreads, 0, st>>>(tau, w, proj, c, n, n3);
 }
 
 }  // namespace stern

@@ -33,7 +33,7 @@ EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_m
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
             "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc", "stern_liouville_apply",
             "stern_liouville_solve", "stern_liouville_davidson", "stern_liouville_set_kernel",
-            "stern_liouville_lanczos", "stern_lanczos_spectrum"]
+            "stern_liouville_lanczos", "stern_lanczos_spectrum", "stern_liouville_set_screening"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -148,6 +148,7 @@ def lib():
         L.stern_apply_pc_noalloc.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]
         L.stern_liouville_apply.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_liouville_set_kernel.argtypes = [C.c_void_p, C.c_double]
+        L.stern_liouville_set_screening.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_int]
         L.stern_liouville_lanczos.argtypes = [C.c_void_p, C.c_void_p, C.c_int, P(C.c_double), P(C.c_double),
                                               P(C.c_double), C.c_int]
         L.stern_lanczos_spectrum.argtypes = [C.c_int, P(C.c_double), P(C.c_double), C.c_double, C.c_int,
@@ -513,6 +514,19 @@ class System:
         _check(lib().stern_lanczos_spectrum(len(a), a.ctypes.data_as(P), b.ctypes.data_as(P), float(norm2), len(om),
                                             om.ctypes.data_as(P), float(eta), out.ctypes.data_as(P)))
         return out
+
+    def liouville_set_screening(self, w=None, c=None):
+        """Screened direct term (stern_liouville_set_screening): real potentials w [n, N, N, N] and
+        weights c [n] (host); None removes the screening."""
+        if w is None:
+            _check(lib().stern_liouville_set_screening(self._h, 0, None, None, STERN_MEM_HOST))
+            return
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        if w.shape[0] != c.shape[0] or w[0].size != self.fft_n ** 3:
+            raise ValueError("w must be [n, N, N, N] and c [n]")
+        _check(lib().stern_liouville_set_screening(self._h, w.shape[0], C.c_void_p(w.ctypes.data),
+                                                   C.c_void_p(c.ctypes.data), STERN_MEM_HOST))
 
     def liouville_set_kernel(self, alpha_x):
         """Fraction of bare exchange in the Liouville direct term (stern_liouville_set_kernel)."""

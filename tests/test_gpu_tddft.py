@@ -280,3 +280,41 @@ def test_lanczos_chain_matches_the_dense_chain(micro):
     ex = spectrum_exact(L, d, om, 0.02)
     print(f"  spectrum max rel difference {np.abs(sp - ex).max() / np.abs(ex).max():.2e}")
     assert np.abs(sp - ex).max() <= 1e-6 * np.abs(ex).max()
+
+
+def test_bse_screened_direct_term_matches_the_dense_matrix(micro):
+    """BSE's W = v + sum_a w_a c_a w_a^T (w_a, c_a from the oracle's dense chi-bar0 of the micro cell)
+    with alpha = 1: apply against the transition-basis matrix, Davidson against its spectrum."""
+    from oracle.closed_form import sum_over_states
+    from oracle.liouville import screening_from_chibar0
+    from oracle.pdep import basis_fields, potential_reps, vhalf
+    cell, occ, emp, s, mil = micro["cell"], micro["occ"], micro["emp"], micro["sys"], micro["mil"]
+    reps = potential_reps(cell.L, cell.ecut / 4.0)
+    f = basis_fields(cell, reps)
+    vh = vhalf(cell, reps)
+    _, _, _, dn = sum_over_states(cell, MICRO_OCC, vh[:, None, None, None] * f)
+    m = len(vh)
+    M = (f.reshape(m, -1) @ dn.reshape(m, -1).T) / cell.N ** 3 * vh[:, None]
+    w, c = screening_from_chibar0(cell, M, f, vh)
+    L, _, _, _, _ = casida_tda(cell, MICRO_OCC, 1.0, (w, c))
+    print(f"case: micro cell BSE, {m} screening potentials", flush=True)
+    s.liouville_set_kernel(1.0)
+    s.liouville_set_screening(w, c)
+    try:
+        n_emp = emp.shape[0]
+        cols = np.random.default_rng(12).choice(L.shape[0], size=6, replace=False)
+        A = np.zeros((len(cols), MICRO_OCC, cell.npw), dtype=np.complex128)
+        for k, t in enumerate(cols):
+            v, cc = divmod(int(t), n_emp)
+            A[k, v] = emp[cc]
+        out = _to_oracle(cell, s.liouville_apply(_to_lib(cell, A, mil)), mil)
+        for k, t in enumerate(cols):
+            assert np.abs((out[k] @ emp.conj().T).reshape(-1) - L[:, t]).max() <= 1e-11 * np.abs(L).max()
+        ref = np.linalg.eigvalsh(L)
+        wv, _, info = s.liouville_davidson(5, tol=1e-9, seed=3)
+        print("  w", wv, "ref", ref[:5], info)
+        assert info["rc"] == 0
+        assert np.abs(wv - ref[:5]).max() <= 1e-10 * ref[4]
+    finally:
+        s.liouville_set_kernel(0.0)
+        s.liouville_set_screening(None)
