@@ -308,6 +308,13 @@ int stern_pdep_basis(const stern_system* sys, double ecut_pot_ry, int* n_g, int3
 int stern_pdep_davidson(stern_system* sys, const stern_pdep_opts* opts, double* eig, double* vec,
                         stern_pdep_stats* stats);
 
+/* The eigenpotentials of stern_pdep_davidson on the grid, w_a(r) = sum_G v^{1/2}(G) phi_a(G) e^{i G.r}
+ * (real; v^{1/2}(G) = sqrt(4 pi) / |G|), for n coefficient rows vec [n][n_g] over the basis of
+ * ecut_pot_ry (0 = ecut / 4) as stern_pdep_davidson writes them; w [n][N^3] in the grid order of
+ * the fields of stern_apply_chi0, host or device per mem_kind. With c_a = lambda_a / (1 - lambda_a)
+ * they are the screening of stern_liouville_set_screening (BSE's W, eq. tau). Synchronous. */
+int stern_pdep_potentials(stern_system* sys, int n, const double* vec, double ecut_pot_ry, double* w, int mem_kind);
+
 /* ---- learned initial guess and diagonal preconditioner ----
  * A small 3-D convolutional net (3 periodic 3x3x3 layers, 16 channels, ReLU,
  * BF16 weights, FP32 accumulation) on the coarse (N/2)^3 grid, which holds the

@@ -2680,6 +2680,48 @@ int stern_pdep_basis(const stern_system* S, double ecut_pot_ry, int* n_g, int32_
   return STERN_OK;
 }
 
+int stern_pdep_potentials(stern_system* S, int n, const double* vec, double ecut_pot_ry, double* w, int mem_kind) {
+  if (!S) return fail(STERN_ERR_INVALID_ARG, "system is NULL");
+  if (n <= 0 || !vec || !w) return fail(STERN_ERR_INVALID_ARG, "need n > 0, vec and w");
+  if (mem_kind != STERN_MEM_HOST && mem_kind != STERN_MEM_DEVICE) return fail(STERN_ERR_INVALID_ARG, "bad mem_kind");
+  const HostBasis& hb = S->hb;
+  if (!plane_full_fwd_fits(hb.N, S->lds_max))
+    return fail(STERN_ERR_UNSUPPORTED, "the potential transforms of grid %d do not fit in LDS", hb.N);
+  Scope sc(S->device, &S->alloc);
+  PotBasis pb;
+  CHECKED(pot_basis(S, ecut_pot_ry > 0 ? ecut_pot_ry : hb.ecut / 4.0, pb));
+  const int ng = (int)pb.all.size(), K = hb.npw_pad, N = hb.N;
+  const size_t n3 = (size_t)N * N * N;
+  std::vector<double> hv((size_t)n * ng * 2);
+  if (mem_kind == STERN_MEM_DEVICE)
+    HIPOK(hipMemcpy(hv.data(), vec, hv.size() * sizeof(double), hipMemcpyDeviceToHost));
+  else
+    std::memcpy(hv.data(), vec, hv.size() * sizeof(double));
+  // v^{1/2}(G) phi_a(G) on the wave-function sphere (column order), zero elsewhere
+  std::vector<Z64> h((size_t)n * K, zmk(0.0, 0.0));
+  for (int a = 0; a < n; ++a)
+    for (int k = 0; k < ng; ++k) {
+      const int c = pb.all[k];
+      const double x = hb.miller[3 * (size_t)c], y = hb.miller[3 * (size_t)c + 1], z = hb.miller[3 * (size_t)c + 2];
+      const double vh = std::sqrt(4.0 * 3.14159265358979323846) / (hb.b * std::sqrt(x * x + y * y + z * z));
+      h[(size_t)a * K + hb.perm[c]] = zmk(vh * hv[2 * ((size_t)a * ng + k)], vh * hv[2 * ((size_t)a * ng + k) + 1]);
+    }
+  hipStream_t st = S->stream;
+  CHECKED(ensure_workspace(S, std::max(S->ws_solves, n)));
+  CHECKED(S->tmp_in.ensure((size_t)n * n3 * sizeof(Z64)));
+  CHECKED(S->dv_dev.ensure((size_t)n * n3 * sizeof(double)));
+  HIPOK(hipMemcpyAsync(S->wp.p, h.data(), h.size() * sizeof(Z64), hipMemcpyHostToDevice, st));
+  const FftGeom g = S->geom();
+  launch_xinv(g, S->wp.as<Z64>(), nullptr, n, S->pen.as<Z64>(), st);
+  launch_plane_full_inv(g, S->pen.as<Z64>(), n, S->tmp_in.as<Z64>(), st);
+  launch_z_real(S->tmp_in.as<Z64>(), 1.0, S->dv_dev.as<double>(), (size_t)n * n3, st);
+  CHECKED(launch_check());
+  HIPOK(hipMemcpyAsync(w, S->dv_dev.p, (size_t)n * n3 * sizeof(double),
+                       mem_kind == STERN_MEM_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));  // h is released on return
+  return STERN_OK;
+}
+
 int stern_pdep_davidson(stern_system* S, const stern_pdep_opts* o, double* eig, double* vec, stern_pdep_stats* stats) {
   const auto t0 = std::chrono::steady_clock::now();
   if (!S || !o || !eig || !o->chi0) return fail(STERN_ERR_INVALID_ARG, "need a system, options, chi0 options and eig");

@@ -33,7 +33,8 @@ EXPORTED = ["stern_basis_info", "stern_init_system", "stern_query", "stern_get_m
             "stern_autotune", "stern_autotune_report", "stern_apply_h", "stern_apply_pc", "stern_free", "stern_last_error",
             "stern_pdep_basis", "stern_pdep_davidson", "stern_apply_pc_noalloc", "stern_liouville_apply",
             "stern_liouville_solve", "stern_liouville_davidson", "stern_liouville_set_kernel",
-            "stern_liouville_lanczos", "stern_lanczos_spectrum", "stern_liouville_set_screening"]
+            "stern_liouville_lanczos", "stern_lanczos_spectrum", "stern_liouville_set_screening",
+            "stern_pdep_potentials"]
 
 TUNE_PLANE64 = 0
 TUNE_PLANE32 = 1
@@ -159,6 +160,7 @@ def lib():
                                                C.c_ulonglong, P(C.c_double), C.c_void_p, P(C.c_int), P(C.c_double)]
         L.stern_pdep_basis.argtypes = [C.c_void_p, C.c_double, P(C.c_int), P(C.c_int32)]
         L.stern_pdep_davidson.argtypes = [C.c_void_p, P(PdepOpts), P(C.c_double), P(C.c_double), P(PdepStats)]
+        L.stern_pdep_potentials.argtypes = [C.c_void_p, C.c_int, C.c_void_p, C.c_double, C.c_void_p, C.c_int]
         L.stern_free.argtypes = [C.c_void_p]
         L.stern_free.restype = None
         L.stern_last_error.restype = C.c_char_p
@@ -514,6 +516,14 @@ class System:
         _check(lib().stern_lanczos_spectrum(len(a), a.ctypes.data_as(P), b.ctypes.data_as(P), float(norm2), len(om),
                                             om.ctypes.data_as(P), float(eta), out.ctypes.data_as(P)))
         return out
+
+    def pdep_potentials(self, vec, ecut_pot=0.0):
+        """v^{1/2} phi_a on the grid [n, N, N, N] for PDEP coefficient rows vec [n, n_g] (stern_pdep_potentials)."""
+        vec = np.ascontiguousarray(np.atleast_2d(vec), dtype=np.complex128)
+        w = np.zeros((vec.shape[0], self.fft_n, self.fft_n, self.fft_n))
+        _check(lib().stern_pdep_potentials(self._h, vec.shape[0], C.c_void_p(vec.ctypes.data), float(ecut_pot),
+                                           C.c_void_p(w.ctypes.data), STERN_MEM_HOST))
+        return w
 
     def liouville_set_screening(self, w=None, c=None):
         """Screened direct term (stern_liouville_set_screening): real potentials w [n, N, N, N] and

@@ -318,3 +318,37 @@ def test_bse_screened_direct_term_matches_the_dense_matrix(micro):
     finally:
         s.liouville_set_kernel(0.0)
         s.liouville_set_screening(None)
+
+
+def test_pdep_eigenpotentials_feed_the_bse_screening(micro):
+    """PDEP eigenpairs from the library (stern_pdep_davidson) -> grid potentials (stern_pdep_potentials,
+    against the same sum done by numpy) -> BSE screening; the apply equals the oracle's with the same
+    potentials and weights."""
+    cell, occ, s, mil = micro["cell"], micro["occ"], micro["sys"], micro["mil"]
+    n = 6
+    eig, vec, info = s.pdep_davidson(n, tol=1e-8, chi0_tol=1e-11, seed=4)
+    print("case: micro cell PDEP -> screening; eigenvalues", eig, flush=True)
+    assert info["n_converged"] == n
+    w = s.pdep_potentials(vec)
+    gm = s.pdep_basis()
+    idx = cell.index_of(gm)
+    vh = np.sqrt(4.0 * np.pi) / (cell.b * np.sqrt(np.sum(gm.astype(np.float64) ** 2, axis=1)))
+    coef = np.zeros((n, cell.npw), dtype=np.complex128)
+    coef[:, idx] = vh[None, :] * vec
+    w_np = cell.to_grid(coef)
+    assert np.abs(w_np.imag).max() <= 1e-13 * np.abs(w_np.real).max()
+    assert np.abs(w - w_np.real).max() <= 1e-12 * np.abs(w_np.real).max()
+    c = eig / (1.0 - eig)
+    s.liouville_set_kernel(1.0)
+    s.liouville_set_screening(w, c)
+    try:
+        rng = np.random.default_rng(31)
+        a = rng.standard_normal((2, MICRO_OCC, cell.npw)) + 1j * rng.standard_normal((2, MICRO_OCC, cell.npw))
+        out = _to_oracle(cell, s.liouville_apply(_to_lib(cell, a, mil)), mil)
+        ref = liouville_apply(cell, occ, micro["eo"], a, 1.0, (w_np.real, c))
+        err = np.abs(out - ref).max() / np.abs(ref).max()
+        print(f"  BSE apply with the PDEP screening: max rel error {err:.2e}")
+        assert err <= 1e-12
+    finally:
+        s.liouville_set_kernel(0.0)
+        s.liouville_set_screening(None)
