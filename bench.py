@@ -279,8 +279,8 @@ def mid_entry(args, dev):
 
 def tddft_entry(s, n_exc=8, reps=3):
     """The Liouville superoperator of TDDFT (Tamm-Dancoff, Hartree kernel) on the same system:
-    applies of n_exc excitations on device arrays, the lowest excitation energies by Davidson, and
-    Z-vector solves. The grid stage's algorithmic bytes per excitation: n_occ full grids written
+    applies of n_exc excitations on device arrays, the lowest excitation energies by Davidson,
+    Z-vector solves, and a Lanczos chain with its absorption spectrum. The grid stage's algorithmic bytes per excitation: n_occ full grids written
     (a_v(r)), read twice (density, products) and written once more (V psi_v), plus psi_v(r) read
     twice: 6 n_occ N^3 complex FP64 values."""
     import torch
@@ -306,12 +306,24 @@ def tddft_entry(s, n_exc=8, reps=3):
     _, it, res, rc = s.liouville_solve(b, tol=1e-8)
     tsol = time.perf_counter() - t0
     log(f"tddft: Z-vector solves {it.tolist()} iterations, {tsol:.2f} s, residuals {res.tolist()}")
+    import numpy as np
+    N = s.fft_n
+    j = np.arange(N) * (2.0 * np.pi / N)
+    dvl = np.cos(j)[:, None, None] * np.ones((1, N, N))  # the longest wave along x
+    t0 = time.perf_counter()
+    al, be, n2 = s.liouville_lanczos(dvl, 100)
+    tlan = time.perf_counter() - t0
+    om = np.linspace(0.0, 3.0, 601)
+    spec = s.lanczos_spectrum(al, be, n2, om, 0.01)
+    log(f"tddft: Lanczos 100 steps {tlan:.2f} s, spectrum peak at {om[int(np.argmax(spec))]:.3f} Ha")
     return dict(apply=dict(n_exc=n_exc, ms=dt * 1e3, excitations_per_s=n_exc / dt,
                            grid_GB=grid_bytes / 1e9, grid_GBps_whole_apply=grid_bytes / dt / 1e9),
                 davidson=dict(n_eig=4, tol=1e-4, block=8, max_basis=64, iterations=dinfo["n_iter"], seconds=tdav, rc=dinfo["rc"],
                               w_Ha=[float(x) for x in w]),
                 zvector=dict(n_exc=2, tol=1e-8, iterations=[int(x) for x in it], seconds=tsol, rc=int(rc),
-                             true_resid=[float(x) for x in res]))
+                             true_resid=[float(x) for x in res]),
+                lanczos=dict(field="cos(2 pi x / L)", steps=100, seconds=tlan, ms_per_step=tlan / 100 * 1e3,
+                             eta_Ha=0.01, peak_Ha=float(om[int(np.argmax(spec))])))
 
 
 def batched_entry(args, dev):
