@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libstern.so")
-SOURCES = ["fft.hip", "gemm.hip", "gemm_bf16.hip", "cg.hip", "learn.hip", "tddft.hip", "basis.cpp", "system.cpp"]
+SOURCES = ["fft.hip", "gemm.hip", "gemm_bf16.hip", "cg.hip", "learn.hip", "tddft.hip", "basis.cpp", "hostla.cpp", "system.cpp"]
 
 # Packed FP32 instructions are disabled for every HIP source.
 HIP_FLAGS = [
