@@ -101,3 +101,20 @@ def test_ctypes_structs_match_the_c_header(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for f in py._fields_:
             assert got[(cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
+
+
+def test_lanczos_spectrum_is_the_oracle_continued_fraction():
+    """stern_lanczos_spectrum (host code) against the oracle's continued fraction of the same chain,
+    and its argument checks."""
+    _lib_or_skip()
+    from oracle.liouville import spectrum_from_chain
+    rng = np.random.default_rng(4)
+    a = rng.uniform(0.05, 2.0, 40)
+    b = rng.uniform(0.01, 0.5, 40)
+    om = np.linspace(-0.5, 3.0, 301)
+    for eta in (0.005, 0.05):
+        got = stern.System.lanczos_spectrum(a, b, 2.5, om, eta)
+        ref = spectrum_from_chain(a, b, 2.5, om, eta)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    with pytest.raises(stern.SternError):
+        stern.System.lanczos_spectrum(a, b, 2.5, om, 0.0)
