@@ -10,6 +10,11 @@
  *     dn_i(r) = 4 Re sum_v conj(psi_v(r)) x_{v,i}(r)       (2 spin x 2 c.c.)
  *
  * solved by projected preconditioned CG (Teter-Payne-Allan diagonal) from zero.
+ * The same solves serve the steps around it: the mixed-precision and learned
+ * starts, the response at imaginary frequency and warm starts (stern_opts), the
+ * PDEP Davidson on chi-bar0 (Sec. II.A, eq. pdep), and the TDDFT/BSE Liouville
+ * superoperator of Sec. II.C.1 (eq. bse_tddft) with its Z-vector solves, its
+ * Davidson for excitation energies and its Lanczos spectra.
  *
  * Model Hamiltonian (input stand-in for the ground-state code of the paper's
  * workflow, Sec. II): cubic cell of edge L (bohr), Gamma point, plane waves
