@@ -1912,6 +1912,8 @@ int stern_liouville_davidson(stern_system* S, int n_eig, int block, int max_basi
   }
   int m = 0, kept = 0;
   CHECKED(dav_orth(S, V, cap, m, T, n_start, Lt, kept));
+  if (kept < n_eig)  // the start spans fewer directions than pairs asked for (a smaller space)
+    return fail(STERN_ERR_INVALID_ARG, "only %d independent start vectors for %d eigenpairs", kept, n_eig);
   HIPOK(hipMemcpyAsync(V, T, (size_t)kept * Lt * sizeof(Z64), hipMemcpyDeviceToDevice, st));
   CHECKED(liouville_rows(S, V, W, kept));
   m = kept;
