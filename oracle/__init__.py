@@ -27,8 +27,10 @@ Modules:
   frequency    the response at imaginary frequency i u: sum over states, dense shifted
                solve, free-electron Lindhard sum at i u, residual of the shifted system
   liouville    TDDFT Liouville superoperator in the Tamm-Dancoff approximation (Hartree
-               kernel): grid route, transition-basis matrix, free-electron matrix by hand,
-               residual of the Z-vector system
+               kernel, bare-exchange and screened direct terms): grid route, transition-basis
+               matrix, free-electron matrix by hand, residual of the Z-vector system, Lanczos
+               chain and spectra
+  deflation    the Sternheimer solve with known lowest empty states taken out in closed form
 
 Pins (tests/test_oracle_*.py) tie each function to something other than
 itself: a brute-force lattice count, the real-space Gaussian sum, the dense
